@@ -1,0 +1,253 @@
+"""Plain FP64 CPU oracle for the decorated-particle (Scovel-Weinstein, k = 2) cycle.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously-correct reference the HIP
+path is checked against.  Only the test suite, the smoke check and the CPU-baseline leg
+of the benchmark may import it; the product path never does.  It shares no code with the
+HIP library: it imports NumPy and nothing else.
+
+Everything below is written from the paper (arXiv 2605.21794, "A Structure-Preserving
+Decorated Particle Method for the Vlasov-Poisson System"), Section 5 "Discretization in
+space and time", in the normalised 1D1V setting e = m = eps0 = 1 on the periodic
+domain [0, L).
+
+Readings taken where the paper is silent (each is also listed in the design doc):
+  * finite elements are P1 (degree k = 1) on a uniform periodic mesh of Ng elements,
+    h = L / Ng, element e = [e h, (e+1) h), nodes q_j = j h, node Ng == node 0;
+  * a particle sitting exactly on a node belongs to the element on its right;
+  * the second derivative phi_h'' needed by the dipole equation (eq. sw-evolution) is
+    taken from the lumped-mass L2 projection of the element-constant field E_h onto
+    P1, then differentiated on each element ("auxiliary projection step");
+  * "leapfrog as in standard PIC" is read as the kick-drift-kick Strang splitting of
+    H_h = H_kin + H_field, each sub-flow solved exactly (derived from the 1D bracket,
+    eq. lp1d): the kick freezes (Q, p*) and moves (P, q*), the drift freezes (P, q*)
+    and moves (Q, p*).
+
+Functions and the passages they follow:
+  cell_index          -- locating Q in the mesh (P1 local support; half-open elements)
+  deposit             -- eq. rhs-assembly (monopole + dipole load vector b)
+  neutralize          -- eq. neutrality / zero-mean background (b - mean(b))
+  poisson_solve       -- eq. lin-sys with the gauge 1^T Phi = 0
+  element_field       -- E_e = -phi_h' on each element (field read from the basis)
+  projected_curvature -- phi_h'' via the lumped L2 projection (reading above)
+  kick, drift         -- exact sub-flows of eq. sw-evolution split as above
+  diagnostics         -- eq. Hh (discrete Hamiltonian), eq. Eamp, charge, momentum
+  sort_perm           -- chunked stable counting sort by cell (a layout step of the
+                         GPU path; its meaning is fixed here, not by the paper)
+  run                 -- the whole cycle, one field solve per step
+
+parity unpinned: the choice of projection for phi_h'' (no printed value in the paper
+discriminates between projections); every other function is pinned by the tests in
+tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "inv_h", "cell_index", "deposit", "neutralize", "poisson_eigenvalues",
+    "poisson_solve", "element_field", "projected_curvature", "solve_field",
+    "kick", "drift", "wrap", "diagnostics", "sort_perm", "step", "run",
+]
+
+
+def inv_h(L: float, ng: int) -> float:
+    """1/h = Ng / L, one FP64 division (uniform periodic mesh, Section 5)."""
+    return float(ng) / float(L)
+
+
+def cell_index(Q, L: float, ng: int):
+    """Element index i and local coordinate s of each position.
+
+    x = Q * (Ng / L) in FP64 (FP32 inputs are promoted exactly); i = floor(x) clamped to
+    [0, Ng-1] (a position rounding onto L lands in the last element); s = x - i clipped
+    to [0, 1].  Elements are half-open, so a particle on node j is in element j.
+    """
+    x = np.asarray(Q, dtype=np.float64) * inv_h(L, ng)
+    i = np.floor(x).astype(np.int64)
+    i = np.minimum(np.maximum(i, 0), ng - 1)
+    s = np.clip(x - i, 0.0, 1.0)
+    return i, s
+
+
+def deposit(Q, ps, psi, L: float, ng: int):
+    """Load vector b_j = sum_a [psi*_a phi_j(Q_a) - p*_a phi_j'(Q_a)] (eq. rhs-assembly).
+
+    On element i the two P1 hats that do not vanish are phi_i = 1 - s and
+    phi_{i+1} = s, with slopes -1/h and +1/h.  So particle a adds
+    psi*(1 - s) + p*/h to node i and psi* s - p*/h to node i+1 (mod Ng).
+    The result still contains the full monopole charge: sum_j b_j = sum_a psi*_a.
+    """
+    ps = np.asarray(ps, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    i, s = cell_index(Q, L, ng)
+    ih = inv_h(L, ng)
+    w_left = psi * (1.0 - s) + ps * ih
+    w_right = psi * s - ps * ih
+    b = np.bincount(i, weights=w_left, minlength=ng)
+    b = b + np.bincount((i + 1) % ng, weights=w_right, minlength=ng)
+    return b
+
+
+def neutralize(b):
+    """Subtract the uniform background (eq. neutrality: n0 L = sum psi*).
+
+    The background's load on node j is n0 * integral(phi_j) = n0 h, and
+    n0 h = (sum_a psi*_a) / Ng = mean(b) because the hats sum to one.  The paper notes the
+    background drops out against zero-mean test functions; removing the mean makes the
+    load consistent with the singular stiffness matrix.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    return b - b.mean()
+
+
+def poisson_eigenvalues(L: float, ng: int):
+    """Eigenvalues of the periodic P1 stiffness matrix A = (1/h) circ(-1, 2, -1).
+
+    A is circulant, so its eigenvectors are the discrete Fourier modes and
+    lambda_m = (2/h) (1 - cos(2 pi m / Ng)); lambda_0 = 0 spans the kernel {1}.
+    """
+    h = float(L) / ng
+    m = np.arange(ng)
+    return (2.0 / h) * (1.0 - np.cos(2.0 * np.pi * m / ng))
+
+
+def poisson_solve(bt, L: float):
+    """Phi with A Phi = b~ and 1^T Phi = 0 (eq. lin-sys with the zero-mean gauge).
+
+    The circulant A is diagonal in the Fourier basis; the gauge removes mode 0.  The FFT
+    is a library primitive standing in for that diagonalisation.
+    """
+    bt = np.asarray(bt, dtype=np.float64)
+    ng = bt.shape[0]
+    lam = poisson_eigenvalues(L, ng)
+    bh = np.fft.fft(bt)
+    ph = np.zeros_like(bh)
+    ph[1:] = bh[1:] / lam[1:]
+    return np.fft.ifft(ph).real
+
+
+def element_field(Phi, L: float):
+    """E_e = -phi_h' on element e = -(Phi_{e+1} - Phi_e) / h (field from the basis)."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    ng = Phi.shape[0]
+    return -(np.roll(Phi, -1) - Phi) * inv_h(L, ng)
+
+
+def projected_curvature(E, L: float):
+    """phi_h'' per element from the lumped L2 projection of E_h onto P1.
+
+    The lumped projection of an element-constant function onto P1 on a uniform mesh is
+    the nodal average E_n_j = (E_{j-1} + E_j) / 2.  Projected phi_h' is -E_n, so on
+    element e: phi_h'' = g_e = -(E_n_{e+1} - E_n_e) / h.
+    """
+    E = np.asarray(E, dtype=np.float64)
+    ng = E.shape[0]
+    En = 0.5 * (np.roll(E, 1) + E)
+    return -(np.roll(En, -1) - En) * inv_h(L, ng)
+
+
+def solve_field(Q, ps, psi, L: float, ng: int):
+    """Deposit, neutralise, solve; returns dict with b, bt, Phi, E, g, W."""
+    b = deposit(Q, ps, psi, L, ng)
+    bt = neutralize(b)
+    Phi = poisson_solve(bt, L)
+    E = element_field(Phi, L)
+    g = projected_curvature(E, L)
+    h = float(L) / ng
+    W = 0.5 * h * np.sum(E * E)
+    return {"b": b, "bt": bt, "Phi": Phi, "E": E, "g": g, "W": W}
+
+
+def kick(Q, P, qs, ps, E, g, L: float, tau: float):
+    """Exact flow of H_field = (1/2) Phi^T A Phi for time tau.
+
+    Q and p* (hence b, Phi, E, g) are frozen, so
+        P  <- P  + tau * E[i]            (dP/dt  = -phi_h'(Q)),
+        q* <- q* + tau * p* * g[i]       (dq*/dt =  p* phi_h''(Q)),
+    with the products evaluated left to right.
+    """
+    ng = np.asarray(E).shape[0]
+    i, _ = cell_index(Q, L, ng)
+    P = np.asarray(P, dtype=np.float64) + tau * E[i]
+    qs = np.asarray(qs, dtype=np.float64) + tau * np.asarray(ps, dtype=np.float64) * g[i]
+    return P, qs
+
+
+def wrap(Qn, L: float):
+    """Bring Q + dt P back into [0, L): add L if negative, then subtract L if >= L.
+
+    Valid when |dt P| < L (checked by the caller)."""
+    Qn = np.asarray(Qn, dtype=np.float64).copy()
+    Qn = np.where(Qn < 0.0, Qn + L, Qn)
+    Qn = np.where(Qn >= L, Qn - L, Qn)
+    return Qn
+
+
+def drift(Q, P, qs, ps, L: float, tau: float):
+    """Exact flow of H_kin = sum (psi* P^2 / 2 + q* P) for time tau.
+
+    P and q* are frozen, so Q <- Q + tau P (periodic wrap) and p* <- p* - tau q*.
+    """
+    Qn = wrap(np.asarray(Q, dtype=np.float64) + tau * np.asarray(P, dtype=np.float64), L)
+    psn = np.asarray(ps, dtype=np.float64) - tau * np.asarray(qs, dtype=np.float64)
+    return Qn, psn
+
+
+def diagnostics(P, qs, psi, fld, L: float):
+    """FP64 invariants: K, W, H (eq. Hh), charge, momentum, E_amp (eq. Eamp), E mode 1.
+
+    K = sum psi* P^2 / 2 + q* P; W = (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2;
+    momentum = sum (psi* P + q*) (first p-moment of the ansatz); charge = sum psi*;
+    E_amp = sqrt((1/L) int E^2) = sqrt(2 W / L);
+    E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng).
+    """
+    P = np.asarray(P, dtype=np.float64)
+    qs = np.asarray(qs, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    E = fld["E"]
+    ng = E.shape[0]
+    K = float(np.sum(0.5 * psi * P * P + qs * P))
+    W = float(fld["W"])
+    e1 = np.sum(E * np.exp(-2j * np.pi * np.arange(ng) / ng)) / ng
+    return {
+        "K": K, "W": W, "H": K + W,
+        "charge": float(np.sum(psi)),
+        "momentum": float(np.sum(psi * P + qs)),
+        "e_amp": float(np.sqrt(2.0 * W / L)),
+        "e1_re": float(e1.real), "e1_im": float(e1.imag),
+    }
+
+
+def sort_perm(cells, chunk: int):
+    """Chunked stable sort permutation: within each chunk of `chunk` particles, order by
+    cell index, ties kept in original order.  perm[k] is the source index of slot k."""
+    cells = np.asarray(cells)
+    n = cells.shape[0]
+    out = np.empty(n, dtype=np.int64)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        out[c0:c1] = c0 + np.argsort(cells[c0:c1], kind="stable")
+    return out
+
+
+def step(state, fld, L: float, ng: int, dt: float):
+    """One kick(dt/2) - drift(dt) - [deposit, solve] - kick(dt/2) step."""
+    Q, P, qs, ps, psi = state
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt)
+    Q, ps = drift(Q, P, qs, ps, L, dt)
+    fld = solve_field(Q, ps, psi, L, ng)
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt)
+    return (Q, P, qs, ps, psi), fld
+
+
+def run(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, record=True):
+    """Run nsteps KDK steps from the given state.  Returns (state, field, history),
+    where history is a list of diagnostics dicts at t = 0, dt, ..., nsteps dt."""
+    state = tuple(np.asarray(a, dtype=np.float64).copy() for a in (Q, P, qs, ps, psi))
+    fld = solve_field(state[0], state[3], state[4], L, ng)
+    hist = [diagnostics(state[1], state[2], state[4], fld, L)] if record else []
+    for _ in range(nsteps):
+        state, fld = step(state, fld, L, ng, dt)
+        if record:
+            hist.append(diagnostics(state[1], state[2], state[4], fld, L))
+    return state, fld, hist
