@@ -1,0 +1,225 @@
+/*
+ * vp.h -- C ABI of the MI355X (gfx950) decorated-particle Vlasov-Poisson library.
+ *
+ * The library advances decorated particles of the Scovel-Weinstein monopole-dipole model
+ * (k = 2) for the normalised 1D1V periodic Vlasov-Poisson system (e = m = eps0 = 1) as
+ * discretised in Section 5 of arXiv 2605.21794: P1 continuous-Galerkin potential on a
+ * uniform periodic mesh of Ng elements over [0, L), load vector of eq. rhs-assembly,
+ * stiffness system of eq. lin-sys with the zero-mean gauge, equations of motion of
+ * eq. sw-evolution, advanced by the kick-drift-kick splitting of the discrete Hamiltonian
+ * of eq. Hh.  Each particle carries (Q, P, q*, p*, psi*): position, velocity, momentum
+ * dipole, spatial dipole, weight (the tuple of Section 4).
+ *
+ * Conventions shared by every entry point
+ *   - All pointers to particle or workspace memory are DEVICE pointers on the current HIP
+ *     device; host pointers are named host_*.  No call takes ownership of caller memory:
+ *     particle arrays and workspaces are borrowed from vp_create / vp_admit until
+ *     vp_destroy / vp_retire and must stay allocated and untouched by other work until then.
+ *   - Particle arrays are five separate contiguous arrays (structure of arrays) of n
+ *     elements each, float64 for VP_FP64 and float32 for VP_FP32_COMP and VP_FP32.
+ *     Positions must lie in [0, L) on entry; psi* is never written.
+ *   - Work is enqueued asynchronously on the stream given at creation (a hipStream_t
+ *     passed as void*, NULL for the null stream) unless a function says it synchronises.
+ *   - Every function returns a vp_status; on failure nothing is enqueued and
+ *     vp_last_error() returns a thread-local message.  A handle is not thread-safe.
+ *   - Grid sizes Ng are powers of two in [VP_MIN_NG, VP_MAX_NG].
+ */
+#ifndef VP_H_
+#define VP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VP_ABI_VERSION 1
+#define VP_MIN_NG 8
+#define VP_MAX_NG 1024
+#define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
+#define VP_MAX_SORT_CHUNK_F64 2048 /* particles per sorted chunk, float64 state */
+#define VP_MAX_ACC_COPIES 32       /* spread copies of the global load accumulator */
+
+typedef enum vp_status {
+  VP_OK = 0,
+  VP_ERR_ARG = 1,        /* invalid argument or configuration */
+  VP_ERR_HIP = 2,        /* a HIP runtime call failed */
+  VP_ERR_NONFINITE = 3,  /* a diagnostic came out NaN or Inf (the values are still returned) */
+  VP_ERR_STATE = 4,      /* call not valid in the handle's current state (e.g. empty slot) */
+  VP_ERR_RANGE = 5       /* requested history records are no longer (or not yet) stored */
+} vp_status;
+
+typedef enum vp_precision {
+  VP_FP64 = 0,       /* float64 state; float64 loads accumulated in LDS and globally      */
+  VP_FP32_COMP = 1,  /* float32 state; per-particle arithmetic in float64; loads summed in
+                        LDS as float32 (hi, lo) pairs with two-sum error capture, block
+                        totals added in float64                                           */
+  VP_FP32 = 2        /* float32 state, float32 arithmetic and float32 accumulation
+                        (naive reference for the precision study)                         */
+} vp_precision;
+/* In every mode the neutralising mean subtraction, the Poisson solve and all
+ * diagnostics (K, W, H, charge, momentum) are computed in float64 on the GPU. */
+
+typedef struct vp_config {
+  int64_t n;           /* decorated particles, >= 1 */
+  int32_t ng;          /* mesh elements (= nodes), power of two in [8, 1024] */
+  int32_t precision;   /* vp_precision */
+  double L;            /* domain length, > 0 */
+  double dt;           /* time step, > 0 */
+  int32_t sort_every;  /* vp_step sorts particles by cell every this many steps; 0 = never */
+  int32_t sort_chunk;  /* particles per sorted chunk (<= VP_MAX_SORT_CHUNK_*); 0 = max */
+  int32_t hist_cap;    /* per-step diagnostic records kept on the device (ring); >= 1 */
+  int32_t reserved;    /* must be 0 */
+} vp_config;
+
+typedef struct vp_particles {
+  void* Q;    /* position in [0, L)                    */
+  void* P;    /* velocity (momentum, m = 1)            */
+  void* qs;   /* q*: momentum dipole                   */
+  void* ps;   /* p*: spatial dipole                    */
+  void* psi;  /* psi*: weight, read only               */
+} vp_particles;
+
+typedef struct vp_diag {
+  int64_t step;     /* steps taken by vp_step since creation / admission */
+  double t;         /* step * dt */
+  double K;         /* sum psi* P^2 / 2 + q* P  (kinetic part of eq. Hh)          */
+  double W;         /* (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2 (field part of eq. Hh) */
+  double H;         /* K + W */
+  double charge;    /* sum psi* */
+  double momentum;  /* sum psi* P + q* */
+  double e_amp;     /* sqrt((1/L) int E^2) (eq. Eamp) = sqrt(2 W / L) */
+  double e1_re;     /* (1/Ng) sum_e E_e exp(-2 pi i e / Ng), real part */
+  double e1_im;     /*   ... imaginary part */
+} vp_diag;
+
+/* Launch shape of the particle kernels; chosen by vp_tune or set by the caller. */
+typedef struct vp_tuning {
+  int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 (256 threads) */
+  int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..32 */
+  int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
+  int32_t graph_steps;  /* steps per captured graph, 1..256 */
+} vp_tuning;
+
+typedef struct vp_handle vp_handle;
+
+/* ---------------------------------------------------------------- sizing and lifetime */
+
+/* Bytes of device workspace one instance with this configuration needs (grid
+ * accumulators, field arrays, FFT tables, diagnostic history).  Validates *cfg. */
+vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out);
+
+/* Single-instance handle: an engine with one slot, slot 0 admitted with (cfg, parts,
+ * workspace).  Enqueues the initial deposit and Poisson solve (field at t = 0).
+ * workspace: device memory of vp_workspace_bytes(cfg) bytes, 256-byte aligned.
+ * stream: hipStream_t as void*.  Errors: VP_ERR_ARG (cfg, null or misaligned pointers),
+ * VP_ERR_HIP. */
+vp_status vp_create(const vp_config* cfg, vp_particles parts, void* workspace,
+                    void* stream, vp_handle** out);
+
+/* Engine with max_slots empty slots, all of one precision (for batches and serving). */
+vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream,
+                           vp_handle** out);
+
+/* Batched handle: engine with n_inst slots admitted from the arrays (one entry each). */
+vp_status vp_create_batch(int32_t n_inst, const vp_config* cfgs, const vp_particles* parts,
+                          void* const* workspaces, void* stream, vp_handle** out);
+
+/* Put an instance into an empty slot; enqueues its initial deposit and solve.  The
+ * precision in cfg must equal the engine's.  Errors: VP_ERR_ARG, VP_ERR_STATE (slot in
+ * use or out of range), VP_ERR_HIP. */
+vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particles parts,
+                   void* workspace);
+
+/* Remove an instance: synchronises the stream, applies its pending half-kick so the
+ * particle arrays hold the state at integer time step*dt, and releases the slot.  The
+ * caller's buffers are then free to reuse.  Errors: VP_ERR_STATE (empty slot). */
+vp_status vp_retire(vp_handle* h, int32_t slot);
+
+/* Synchronises the stream and frees the library's own device tables.  Caller buffers are
+ * left untouched (a pending half-kick is NOT applied; call vp_sync_state first). */
+vp_status vp_destroy(vp_handle* h);
+
+/* ---------------------------------------------------------------- primitive steps
+ * The unfused reference composition of one kick-drift-kick step (Section 5):
+ *   vp_gather_push(h, dt/2, dt); vp_deposit(h); vp_poisson(h); vp_gather_push(h, dt/2, 0).
+ * Each acts on every occupied slot and leaves the step counter alone. */
+
+/* Load vector b_j = sum_a [psi*_a phi_j(Q_a) - p*_a phi_j'(Q_a)] (eq. rhs-assembly) of the
+ * current positions and dipoles, added into each instance's accumulator (which
+ * vp_poisson consumes and clears). */
+vp_status vp_deposit(vp_handle* h);
+
+/* Poisson solve (eq. lin-sys): b~ = b - mean(b) in float64 (eq. neutrality), Phi with
+ * A Phi = b~ and 1^T Phi = 0 by an in-LDS FFT, element field E_e = -(Phi_{e+1}-Phi_e)/h,
+ * projected curvature g_e (lumped L2 projection of E onto P1, differentiated),
+ * W = (1/2) sum h E_e^2.  One workgroup per instance. */
+vp_status vp_poisson(vp_handle* h);
+
+/* Exact sub-flows of the splitting with the current field (eq. sw-evolution):
+ * kick:  P += kick * E[i],  q* += kick * p* * g[i]   (Q, p* frozen),
+ * drift: Q += drift * P (periodic wrap into [0, L)),  p* -= drift * q*   (P, q* frozen).
+ * Requires |drift * P| < L. */
+vp_status vp_gather_push(vp_handle* h, double kick, double drift);
+
+/* ---------------------------------------------------------------- fused stepping */
+
+/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused particle pass
+ * per step (pending half-kick, diagnostics at the integer step, half-kick, drift, deposit),
+ * whose last workgroup per instance performs that instance's Poisson solve; optionally
+ * replayed from captured HIP graphs.  Equals the primitive composition up to rounding.
+ * Leaves a pending half-kick (P, q* at t + dt/2); every state read-back must go through
+ * vp_sync_state, vp_retire or vp_diagnostics (which accounts for it). */
+vp_status vp_step(vp_handle* h, int32_t nsteps);
+
+/* Apply the pending half-kick of every occupied slot (P, q* back to integer time). */
+vp_status vp_sync_state(vp_handle* h);
+
+/* Chunked stable counting sort of one slot's particles by cell index (element
+ * i = min(floor(Q * Ng / L), Ng - 1), computed in float64), chunks of cfg.sort_chunk
+ * particles, ties kept in original order.  Permutes all five arrays in place.  If
+ * dev_perm is non-NULL, writes the permutation (dev_perm[k] = source index of slot k,
+ * int32, n entries).  slot < 0 sorts every occupied slot (dev_perm must then be NULL). */
+vp_status vp_sort(vp_handle* h, int32_t slot, int32_t* dev_perm);
+
+/* Cell index of every particle of one slot into dev_cells (int32, n entries), by the
+ * same float64 formula the kernels use. */
+vp_status vp_cell_index(vp_handle* h, int32_t slot, int32_t* dev_cells);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+/* Synchronises the stream.  Diagnostics of one slot at its current integer step (a
+ * pending half-kick is accounted for without modifying the state).  host_grid, if
+ * non-NULL, receives 4*Ng float64 values: b~, Phi, E, g of the current field.
+ * Returns VP_ERR_NONFINITE (after filling *host_out) if any value is NaN or Inf. */
+vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* host_grid);
+
+/* Synchronises the stream.  Copies the per-step records written by vp_step for steps
+ * first_step .. first_step+count-1 (each record is the state at that integer step,
+ * before the step was taken).  VP_ERR_RANGE if any is outside the stored ring. */
+vp_status vp_history(vp_handle* h, int32_t slot, int64_t first_step, int32_t count,
+                     vp_diag* host_out);
+
+/* ---------------------------------------------------------------- tuning and misc */
+vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t);
+vp_status vp_get_tuning(const vp_handle* h, vp_tuning* t);
+
+/* Time each candidate launch shape on the handle's current slots (the particle arrays
+ * are advanced and then restored from a device copy the caller provides: scratch of
+ * vp_tune_scratch_bytes), keep the fastest and report it. */
+vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out);
+vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_tuning* best_out,
+                  double* best_us_per_step_out);
+
+/* Number of occupied slots and the total particle count over them. */
+vp_status vp_occupancy(const vp_handle* h, int32_t* slots_out, int64_t* particles_out);
+
+const char* vp_status_string(vp_status s);
+const char* vp_last_error(void);
+int32_t vp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VP_H_ */

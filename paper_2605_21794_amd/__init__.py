@@ -1,0 +1,224 @@
+"""MI355X-native decorated-particle (Scovel-Weinstein, k = 2) Vlasov-Poisson hot path.
+
+Thin Python binding over the C ABI of include/vp.h (libvp.so, HIP for gfx950).  PyTorch
+provides device memory and the stream; every step of the method runs in the HIP kernels.
+
+    eng = Engine("fp32c", max_slots=1)
+    eng.admit(0, state, L=..., ng=512, dt=0.05)     # state: dict Q, P, qs, ps, psi
+    eng.step(1000)
+    d = eng.diagnostics(0)                           # K, W, H, charge, momentum, ...
+    st = eng.retire(0)                               # state at the last integer step
+
+There is no CPU fallback: constructing an Engine without the built library or without a
+GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import VPError  # noqa: F401
+
+PRECISIONS = {"fp64": L.VP_FP64, "fp32c": L.VP_FP32_COMP, "fp32": L.VP_FP32}
+FIELDS = ("Q", "P", "qs", "ps", "psi")
+
+
+def load_library():
+    return L.load()
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096):
+    return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
+                       dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
+                       hist_cap=int(hist_cap), reserved=0)
+
+
+def workspace_bytes(cfg) -> int:
+    lib = L.load()
+    b = c_size_t()
+    L.check(lib.vp_workspace_bytes(byref(cfg), byref(b)), "vp_workspace_bytes")
+    return int(b.value)
+
+
+class Engine:
+    """A set of slots, each holding one simulation instance, advanced together."""
+
+    def __init__(self, precision="fp32c", max_slots: int = 1, device=None, stream=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the decorated-particle path runs only on the GPU")
+        self.lib = L.load()
+        self.prec = _prec(precision)
+        self.dtype = torch.float64 if self.prec == L.VP_FP64 else torch.float32
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.max_slots = int(max_slots)
+        h = c_void_p()
+        L.check(self.lib.vp_engine_create(self.prec, self.max_slots,
+                                          c_void_p(self.stream.cuda_stream), byref(h)),
+                "vp_engine_create")
+        self.h = h
+        self.slots = {}
+
+    # ---------------------------------------------------------------- slots
+    def _tensor(self, a):
+        t = self._torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=self.dtype).contiguous().clone()
+        return t.from_numpy(np.ascontiguousarray(a)).to(device=self.device, dtype=self.dtype)
+
+    def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
+              sort_chunk: int = 0, hist_cap: int = 4096):
+        """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`."""
+        t = self._torch
+        tens = {k: self._tensor(state[k]) for k in FIELDS}
+        n = int(tens["Q"].numel())
+        if any(int(v.numel()) != n for v in tens.values()):
+            raise ValueError("state arrays differ in length")
+        cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap)
+        ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
+        if ws.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        parts = L.vp_particles(*(c_void_p(tens[k].data_ptr()) for k in FIELDS))
+        t.cuda.current_stream(self.device).synchronize()
+        L.check(self.lib.vp_admit(self.h, int(slot), byref(cfg), parts, c_void_p(ws.data_ptr())),
+                "vp_admit")
+        self.slots[int(slot)] = {"tensors": tens, "ws": ws, "cfg": cfg}
+        return tens
+
+    def retire(self, slot: int) -> dict:
+        """Remove the instance; returns its tensors holding the state at its last integer step."""
+        L.check(self.lib.vp_retire(self.h, int(slot)), "vp_retire")
+        rec = self.slots.pop(int(slot))
+        return rec["tensors"]
+
+    def free_slot(self):
+        for s in range(self.max_slots):
+            if s not in self.slots:
+                return s
+        return None
+
+    def state(self, slot: int = 0) -> dict:
+        """Device tensors of one slot (P, q* are half a kick ahead until sync_state())."""
+        return self.slots[int(slot)]["tensors"]
+
+    def state_numpy(self, slot: int = 0) -> dict:
+        self.sync_state()
+        self._torch.cuda.synchronize(self.device)
+        return {k: v.detach().cpu().numpy() for k, v in self.state(slot).items()}
+
+    # ---------------------------------------------------------------- steps
+    def step(self, nsteps: int = 1):
+        L.check(self.lib.vp_step(self.h, int(nsteps)), "vp_step")
+
+    def sync_state(self):
+        L.check(self.lib.vp_sync_state(self.h), "vp_sync_state")
+
+    def deposit(self):
+        L.check(self.lib.vp_deposit(self.h), "vp_deposit")
+
+    def poisson(self):
+        L.check(self.lib.vp_poisson(self.h), "vp_poisson")
+
+    def gather_push(self, kick: float, drift: float):
+        L.check(self.lib.vp_gather_push(self.h, float(kick), float(drift)), "vp_gather_push")
+
+    def sort(self, slot: int = 0, want_perm: bool = False):
+        t = self._torch
+        perm = None
+        ptr = None
+        if want_perm:
+            n = int(self.slots[int(slot)]["cfg"].n)
+            perm = t.empty(n, dtype=t.int32, device=self.device)
+            ptr = c_void_p(perm.data_ptr())
+        L.check(self.lib.vp_sort(self.h, int(slot), ptr), "vp_sort")
+        return perm
+
+    def cell_index(self, slot: int = 0):
+        t = self._torch
+        n = int(self.slots[int(slot)]["cfg"].n)
+        cells = t.empty(n, dtype=t.int32, device=self.device)
+        L.check(self.lib.vp_cell_index(self.h, int(slot), c_void_p(cells.data_ptr())),
+                "vp_cell_index")
+        return cells
+
+    # ---------------------------------------------------------------- diagnostics
+    def diagnostics(self, slot: int = 0, grid: bool = False, allow_nonfinite: bool = False):
+        d = L.vp_diag()
+        ng = int(self.slots[int(slot)]["cfg"].ng)
+        buf = np.zeros(4 * ng) if grid else None
+        ptr = buf.ctypes.data_as(c_void_p) if grid else None
+        st = self.lib.vp_diagnostics(self.h, int(slot), byref(d), ptr)
+        if not (allow_nonfinite and st == L.VP_ERR_NONFINITE):
+            L.check(st, "vp_diagnostics")
+        out = d.as_dict()
+        if grid:
+            out.update(bt=buf[:ng], Phi=buf[ng:2 * ng], E=buf[2 * ng:3 * ng], g=buf[3 * ng:])
+        return out
+
+    def history(self, slot: int, first: int, count: int, allow_nonfinite: bool = False):
+        arr = (L.vp_diag * max(1, int(count)))()
+        st = self.lib.vp_history(self.h, int(slot), int(first), int(count), arr)
+        if not (allow_nonfinite and st == L.VP_ERR_NONFINITE):
+            L.check(st, "vp_history")
+        return [arr[i].as_dict() for i in range(int(count))]
+
+    # ---------------------------------------------------------------- tuning
+    def get_tuning(self) -> dict:
+        tu = L.vp_tuning()
+        L.check(self.lib.vp_get_tuning(self.h, byref(tu)), "vp_get_tuning")
+        return tu.as_dict()
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        tu = L.vp_tuning(**cur)
+        L.check(self.lib.vp_set_tuning(self.h, byref(tu)), "vp_set_tuning")
+
+    def tune(self, steps_per_trial: int = 20):
+        """Time every candidate launch shape on the current slots, keep the fastest."""
+        t = self._torch
+        b = c_size_t()
+        L.check(self.lib.vp_tune_scratch_bytes(self.h, byref(b)), "vp_tune_scratch_bytes")
+        scratch = t.empty(max(256, int(b.value)), dtype=t.uint8, device=self.device)
+        best = L.vp_tuning()
+        us = c_double()
+        L.check(self.lib.vp_tune(self.h, c_void_p(scratch.data_ptr()), int(steps_per_trial),
+                                 byref(best), byref(us)), "vp_tune")
+        return best.as_dict(), float(us.value)
+
+    def occupancy(self):
+        s, p = c_int32(), c_int64()
+        L.check(self.lib.vp_occupancy(self.h, byref(s), byref(p)), "vp_occupancy")
+        return int(s.value), int(p.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Simulation(Engine):
+    """One instance: Simulation(state, L, ng, dt, precision)."""
+
+    def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
+                 sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
+                 stream=None):
+        super().__init__(precision, 1, device, stream)
+        self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap)

@@ -1,0 +1,692 @@
+// Host side of the C ABI declared in vp.h: validation, slot and tile tables, launch order,
+// HIP graph capture of the fused step, diagnostics read-back and the launch-shape tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vp.h"
+#include "vp_internal.h"
+
+using vpk::InstDev;
+using vpk::Tile;
+
+namespace {
+
+thread_local std::string g_err;
+
+vp_status fail(vp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define VP_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(VP_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define VP_TRY(expr)              \
+  do {                            \
+    vp_status s_ = (expr);        \
+    if (s_ != VP_OK) return s_;   \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int x) { int m = 0; while ((1 << m) < x) ++m; return m; }
+size_t state_elem_size(int prec) { return prec == VP_FP64 ? sizeof(double) : sizeof(float); }
+int max_sort_chunk(int prec) { return prec == VP_FP64 ? VP_MAX_SORT_CHUNK_F64 : VP_MAX_SORT_CHUNK_F32; }
+
+vp_status validate(const vp_config* c) {
+  if (!c) return fail(VP_ERR_ARG, "config is NULL");
+  if (c->n < 1 || c->n > (int64_t)1 << 40) return fail(VP_ERR_ARG, "n = %lld out of range", (long long)c->n);
+  if (!is_pow2(c->ng) || c->ng < VP_MIN_NG || c->ng > VP_MAX_NG)
+    return fail(VP_ERR_ARG, "ng = %d must be a power of two in [%d, %d]", c->ng, VP_MIN_NG, VP_MAX_NG);
+  if (c->precision < VP_FP64 || c->precision > VP_FP32) return fail(VP_ERR_ARG, "bad precision %d", c->precision);
+  if (!(c->L > 0.0) || !std::isfinite(c->L)) return fail(VP_ERR_ARG, "L must be positive and finite");
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(VP_ERR_ARG, "dt must be positive and finite");
+  if (c->sort_every < 0) return fail(VP_ERR_ARG, "sort_every < 0");
+  if (c->sort_chunk < 0 || c->sort_chunk > max_sort_chunk(c->precision))
+    return fail(VP_ERR_ARG, "sort_chunk = %d exceeds %d", c->sort_chunk, max_sort_chunk(c->precision));
+  if (c->hist_cap < 1) return fail(VP_ERR_ARG, "hist_cap must be >= 1");
+  if (c->reserved != 0) return fail(VP_ERR_ARG, "reserved must be 0");
+  return VP_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+struct Slot {
+  bool used = false;
+  vp_config cfg{};
+  vp_particles parts{};
+  void* ws = nullptr;
+  int tile_begin = 0, ntiles = 0;
+  long long step = 0;   // host mirror of the device step counter
+  bool pending = false; // host mirror of the pending half-kick
+  long long last_sort = -1;
+};
+
+}  // namespace
+
+struct vp_handle {
+  int precision = VP_FP64;
+  int max_slots = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Slot> slots;
+  std::vector<InstDev> h_inst;
+  std::vector<Tile> h_tiles;
+  std::vector<int> h_occ;
+  InstDev* d_inst = nullptr;
+  Tile* d_tiles = nullptr;
+  size_t tiles_cap = 0;
+  int ntiles = 0;
+  int* d_occ = nullptr;
+  int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
+  int max_ng = VP_MIN_NG;
+  vp_tuning tun{4, 8, 1, 32};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_len = 0;
+  bool graph_ok = false;
+};
+
+namespace {
+
+void drop_graph(vp_handle* h) {
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->graph_ok = false;
+  h->graph_len = 0;
+}
+
+// Rebuild the tile list and occupied-slot list from the slots and upload them (with the
+// instance table).  Synchronises the stream (no kernel may still read the old tables).
+vp_status rebuild_tables(vp_handle* h) {
+  VP_HIP(hipStreamSynchronize(h->stream));
+  drop_graph(h);
+  const int tile_n = vpk::kBlock * h->tun.ppt;
+  h->h_tiles.clear();
+  h->h_occ.clear();
+  h->max_ng = VP_MIN_NG;
+  for (int s = 0; s < h->max_slots; ++s) {
+    Slot& sl = h->slots[s];
+    if (!sl.used) continue;
+    h->h_occ.push_back(s);
+    h->max_ng = std::max(h->max_ng, sl.cfg.ng);
+    const long long n = sl.cfg.n;
+    const int nt = (int)((n + tile_n - 1) / tile_n);
+    sl.tile_begin = (int)h->h_tiles.size();
+    sl.ntiles = nt;
+    for (int t = 0; t < nt; ++t) {
+      Tile tl{};
+      tl.inst = s;
+      tl.begin = (long long)t * tile_n;
+      tl.count = (int)std::min<long long>(tile_n, n - tl.begin);
+      tl.local = t;
+      h->h_tiles.push_back(tl);
+    }
+    InstDev& d = h->h_inst[s];
+    d.ntiles = nt;
+    d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
+  }
+  h->ntiles = (int)h->h_tiles.size();
+  if ((size_t)h->ntiles > h->tiles_cap) {
+    if (h->d_tiles) VP_HIP(hipFree(h->d_tiles));
+    h->d_tiles = nullptr;
+    size_t cap = std::max<size_t>(1024, (size_t)h->ntiles * 2);
+    VP_HIP(hipMalloc(&h->d_tiles, cap * sizeof(Tile)));
+    h->tiles_cap = cap;
+  }
+  if (h->ntiles > 0)
+    VP_HIP(hipMemcpyAsync(h->d_tiles, h->h_tiles.data(), h->ntiles * sizeof(Tile),
+                          hipMemcpyHostToDevice, h->stream));
+  if (!h->h_occ.empty())
+    VP_HIP(hipMemcpyAsync(h->d_occ, h->h_occ.data(), h->h_occ.size() * sizeof(int),
+                          hipMemcpyHostToDevice, h->stream));
+  VP_HIP(hipMemcpyAsync(h->d_inst, h->h_inst.data(), h->max_slots * sizeof(InstDev),
+                        hipMemcpyHostToDevice, h->stream));
+  VP_HIP(hipStreamSynchronize(h->stream));
+  return VP_OK;
+}
+
+vp_status check_slot(const vp_handle* h, int slot) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (slot < 0 || slot >= h->max_slots) return fail(VP_ERR_STATE, "slot %d out of range", slot);
+  if (!h->slots[slot].used) return fail(VP_ERR_STATE, "slot %d is empty", slot);
+  return VP_OK;
+}
+
+vp_status launch_steps_direct(vp_handle* h, int nsteps) {
+  for (int i = 0; i < nsteps; ++i)
+    VP_HIP(vpk::launch_fused(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                             h->max_ng, h->stream));
+  return VP_OK;
+}
+
+vp_status ensure_graph(vp_handle* h) {
+  if (h->graph_ok && h->graph_len == h->tun.graph_steps) return VP_OK;
+  drop_graph(h);
+  VP_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < h->tun.graph_steps && le == hipSuccess; ++i)
+    le = vpk::launch_fused(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                           h->max_ng, h->stream);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(h->stream, &g);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(VP_ERR_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
+                hipGetErrorString(ee));
+  }
+  h->graph = g;
+  VP_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  h->graph_len = h->tun.graph_steps;
+  h->graph_ok = true;
+  return VP_OK;
+}
+
+int sort_chunk_of(const vp_config& c) { return c.sort_chunk > 0 ? c.sort_chunk : max_sort_chunk(c.precision); }
+
+void to_diag(const double* r, vp_diag* o) {
+  o->step = (int64_t)r[0];
+  o->t = r[1];
+  o->K = r[2];
+  o->W = r[3];
+  o->H = r[4];
+  o->charge = r[5];
+  o->momentum = r[6];
+  o->e_amp = r[7];
+  o->e1_re = r[8];
+  o->e1_im = r[9];
+}
+
+bool diag_finite(const vp_diag& d) {
+  return std::isfinite(d.K) && std::isfinite(d.W) && std::isfinite(d.H) && std::isfinite(d.charge) &&
+         std::isfinite(d.momentum) && std::isfinite(d.e_amp) && std::isfinite(d.e1_re) &&
+         std::isfinite(d.e1_im);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vp_abi_version(void) { return VP_ABI_VERSION; }
+
+const char* vp_status_string(vp_status s) {
+  switch (s) {
+    case VP_OK: return "ok";
+    case VP_ERR_ARG: return "invalid argument";
+    case VP_ERR_HIP: return "HIP runtime error";
+    case VP_ERR_NONFINITE: return "non-finite diagnostic";
+    case VP_ERR_STATE: return "invalid handle state";
+    case VP_ERR_RANGE: return "history record out of range";
+  }
+  return "unknown status";
+}
+
+const char* vp_last_error(void) { return g_err.c_str(); }
+
+vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out) {
+  VP_TRY(validate(cfg));
+  if (!bytes_out) return fail(VP_ERR_ARG, "bytes_out is NULL");
+  *bytes_out = vpk::workspace_layout(cfg->ng, cfg->hist_cap).total;
+  return VP_OK;
+}
+
+vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream, vp_handle** out) {
+  if (!out) return fail(VP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (precision < VP_FP64 || precision > VP_FP32) return fail(VP_ERR_ARG, "bad precision %d", precision);
+  if (max_slots < 1 || max_slots > 65536) return fail(VP_ERR_ARG, "max_slots = %d out of range", max_slots);
+  vp_handle* h = new vp_handle();
+  h->precision = precision;
+  h->max_slots = max_slots;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->slots.resize(max_slots);
+  h->h_inst.assign(max_slots, InstDev{});
+  std::vector<int> ids(max_slots);
+  for (int i = 0; i < max_slots; ++i) ids[i] = i;
+  hipError_t e = hipMalloc(&h->d_inst, max_slots * sizeof(InstDev));
+  if (e == hipSuccess) e = hipMalloc(&h->d_occ, max_slots * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&h->d_ids, max_slots * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->d_ids, ids.data(), max_slots * sizeof(int), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    vp_destroy(h);
+    return fail(VP_ERR_HIP, "engine allocation: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return VP_OK;
+}
+
+vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particles parts,
+                   void* workspace) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  VP_TRY(validate(cfg));
+  if (slot < 0 || slot >= h->max_slots) return fail(VP_ERR_STATE, "slot %d out of range", slot);
+  if (h->slots[slot].used) return fail(VP_ERR_STATE, "slot %d is in use", slot);
+  if (cfg->precision != h->precision)
+    return fail(VP_ERR_ARG, "precision %d differs from the engine's %d", cfg->precision, h->precision);
+  const size_t es = state_elem_size(cfg->precision);
+  void* arrs[5] = {parts.Q, parts.P, parts.qs, parts.ps, parts.psi};
+  for (int k = 0; k < 5; ++k)
+    if (!arrs[k] || !aligned(arrs[k], es)) return fail(VP_ERR_ARG, "particle array %d NULL or misaligned", k);
+  if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
+
+  const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, cfg->hist_cap);
+  char* ws = static_cast<char*>(workspace);
+  InstDev d{};
+  d.Q = parts.Q; d.P = parts.P; d.qs = parts.qs; d.ps = parts.ps; d.psi = parts.psi;
+  d.n = cfg->n;
+  d.ng = cfg->ng;
+  d.log2ng = ilog2(cfg->ng);
+  d.hist_cap = cfg->hist_cap;
+  d.active = 1;
+  d.L = cfg->L;
+  d.inv_h = (double)cfg->ng / cfg->L;
+  d.h = cfg->L / (double)cfg->ng;
+  d.dt = cfg->dt;
+  d.acc = reinterpret_cast<double*>(ws + w.acc);
+  d.E = reinterpret_cast<double*>(ws + w.E);
+  d.g = reinterpret_cast<double*>(ws + w.g);
+  d.Ef = reinterpret_cast<float*>(ws + w.Ef);
+  d.gf = reinterpret_cast<float*>(ws + w.gf);
+  d.Phi = reinterpret_cast<double*>(ws + w.Phi);
+  d.bt = reinterpret_cast<double*>(ws + w.bt);
+  d.tw = reinterpret_cast<double*>(ws + w.tw);
+  d.inv_lam = reinterpret_cast<double*>(ws + w.inv_lam);
+  d.scal = reinterpret_cast<vpk::InstScal*>(ws + w.scal);
+  d.hist = reinterpret_cast<double*>(ws + w.hist);
+
+  // FFT twiddles and inverse stiffness eigenvalues lambda_m = (2/h)(1 - cos(2 pi m / Ng)).
+  const int ng = cfg->ng;
+  std::vector<double> tw(ng), il(ng);
+  const double two_pi = 6.283185307179586;
+  for (int k = 0; k < ng / 2; ++k) {
+    tw[2 * k] = std::cos(two_pi * k / ng);
+    tw[2 * k + 1] = std::sin(two_pi * k / ng);
+  }
+  il[0] = 0.0;
+  for (int m = 1; m < ng; ++m) il[m] = 1.0 / ((2.0 / d.h) * (1.0 - std::cos(two_pi * m / ng)));
+
+  VP_HIP(hipStreamSynchronize(h->stream));
+  VP_HIP(vpk::launch_fill_zero(ws, w.total, h->stream));
+  VP_HIP(hipMemcpyAsync(d.tw, tw.data(), ng * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  VP_HIP(hipMemcpyAsync(d.inv_lam, il.data(), ng * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  VP_HIP(hipStreamSynchronize(h->stream));
+
+  Slot& sl = h->slots[slot];
+  sl.used = true;
+  sl.cfg = *cfg;
+  sl.parts = parts;
+  sl.ws = workspace;
+  sl.step = 0;
+  sl.pending = false;
+  sl.last_sort = -1;
+  h->h_inst[slot] = d;
+  vp_status st = rebuild_tables(h);
+  if (st != VP_OK) {
+    sl.used = false;
+    return st;
+  }
+  // Field at t = 0 from the initial state.
+  VP_HIP(vpk::launch_deposit(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
+                             h->tun.ppt, h->max_ng, h->stream));
+  VP_HIP(vpk::launch_solve(h->precision, h->d_inst, h->d_ids + slot, 1, h->max_ng, h->stream));
+  return VP_OK;
+}
+
+vp_status vp_create(const vp_config* cfg, vp_particles parts, void* workspace, void* stream,
+                    vp_handle** out) {
+  VP_TRY(validate(cfg));
+  VP_TRY(vp_engine_create(cfg->precision, 1, stream, out));
+  vp_status s = vp_admit(*out, 0, cfg, parts, workspace);
+  if (s != VP_OK) {
+    std::string keep = g_err;
+    vp_destroy(*out);
+    *out = nullptr;
+    g_err = keep;
+  }
+  return s;
+}
+
+vp_status vp_create_batch(int32_t n_inst, const vp_config* cfgs, const vp_particles* parts,
+                          void* const* workspaces, void* stream, vp_handle** out) {
+  if (n_inst < 1 || !cfgs || !parts || !workspaces || !out) return fail(VP_ERR_ARG, "bad batch arguments");
+  VP_TRY(vp_engine_create(cfgs[0].precision, n_inst, stream, out));
+  for (int i = 0; i < n_inst; ++i) {
+    vp_status s = vp_admit(*out, i, &cfgs[i], parts[i], workspaces[i]);
+    if (s != VP_OK) {
+      std::string keep = g_err;
+      vp_destroy(*out);
+      *out = nullptr;
+      g_err = "instance " + std::to_string(i) + ": " + keep;
+      return s;
+    }
+  }
+  return VP_OK;
+}
+
+vp_status vp_retire(vp_handle* h, int32_t slot) {
+  VP_TRY(check_slot(h, slot));
+  Slot& sl = h->slots[slot];
+  if (sl.pending) {
+    VP_HIP(vpk::launch_settle(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
+                              h->tun.ppt, h->max_ng, h->stream));
+    VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearPending, h->stream));
+    sl.pending = false;
+  }
+  VP_HIP(hipStreamSynchronize(h->stream));
+  sl.used = false;
+  h->h_inst[slot] = InstDev{};
+  return rebuild_tables(h);
+}
+
+vp_status vp_destroy(vp_handle* h) {
+  if (!h) return VP_OK;
+  hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  if (h->d_inst) hipFree(h->d_inst);
+  if (h->d_tiles) hipFree(h->d_tiles);
+  if (h->d_occ) hipFree(h->d_occ);
+  if (h->d_ids) hipFree(h->d_ids);
+  delete h;
+  return VP_OK;
+}
+
+vp_status vp_deposit(vp_handle* h) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  VP_HIP(vpk::launch_deposit(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                             h->max_ng, h->stream));
+  return VP_OK;
+}
+
+vp_status vp_poisson(vp_handle* h) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  VP_HIP(vpk::launch_solve(h->precision, h->d_inst, h->d_occ, (int)h->h_occ.size(), h->max_ng,
+                           h->stream));
+  return VP_OK;
+}
+
+vp_status vp_gather_push(vp_handle* h, double kick, double drift) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (!std::isfinite(kick) || !std::isfinite(drift)) return fail(VP_ERR_ARG, "kick and drift must be finite");
+  VP_HIP(vpk::launch_gather_push(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                                 h->max_ng, kick, drift, h->stream));
+  return VP_OK;
+}
+
+vp_status vp_step(vp_handle* h, int32_t nsteps) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (nsteps < 0) return fail(VP_ERR_ARG, "nsteps < 0");
+  if (h->h_occ.empty() || nsteps == 0) return VP_OK;
+  const bool graphs = h->tun.use_graph && h->stream != nullptr;
+  int done = 0;
+  while (done < nsteps) {
+    // sort the slots whose step count is a multiple of their sort interval (once per step)
+    for (int s : h->h_occ) {
+      Slot& sl = h->slots[s];
+      if (sl.cfg.sort_every > 0 && sl.step % sl.cfg.sort_every == 0 && sl.last_sort != sl.step) {
+        VP_HIP(vpk::launch_sort(h->precision, h->d_inst, s, sl.cfg.n, sort_chunk_of(sl.cfg),
+                                nullptr, h->stream));
+        sl.last_sort = sl.step;
+      }
+    }
+    int chunk = nsteps - done;
+    for (int s : h->h_occ) {
+      const Slot& sl = h->slots[s];
+      if (sl.cfg.sort_every <= 0) continue;
+      const long long r = sl.step % sl.cfg.sort_every;
+      chunk = (int)std::min<long long>(chunk, sl.cfg.sort_every - r);
+    }
+    if (graphs && chunk >= h->tun.graph_steps) {
+      VP_TRY(ensure_graph(h));
+      const int reps = chunk / h->tun.graph_steps;
+      for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
+      chunk = reps * h->tun.graph_steps;
+    } else {
+      VP_TRY(launch_steps_direct(h, chunk));
+    }
+    for (int s : h->h_occ) {
+      h->slots[s].step += chunk;
+      h->slots[s].pending = true;
+    }
+    done += chunk;
+  }
+  return VP_OK;
+}
+
+vp_status vp_sync_state(vp_handle* h) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (h->h_occ.empty()) return VP_OK;
+  VP_HIP(vpk::launch_settle(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                            h->max_ng, h->stream));
+  VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalClearPending,
+                                  h->stream));
+  for (int s : h->h_occ) h->slots[s].pending = false;
+  return VP_OK;
+}
+
+vp_status vp_sort(vp_handle* h, int32_t slot, int32_t* dev_perm) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (slot < 0) {
+    if (dev_perm) return fail(VP_ERR_ARG, "dev_perm must be NULL when sorting every slot");
+    for (int s : h->h_occ)
+      VP_HIP(vpk::launch_sort(h->precision, h->d_inst, s, h->slots[s].cfg.n,
+                              sort_chunk_of(h->slots[s].cfg), nullptr, h->stream));
+    return VP_OK;
+  }
+  VP_TRY(check_slot(h, slot));
+  const Slot& sl = h->slots[slot];
+  if (dev_perm && sl.cfg.n > INT32_MAX) return fail(VP_ERR_ARG, "n too large for an int32 permutation");
+  VP_HIP(vpk::launch_sort(h->precision, h->d_inst, slot, sl.cfg.n, sort_chunk_of(sl.cfg), dev_perm,
+                          h->stream));
+  return VP_OK;
+}
+
+vp_status vp_cell_index(vp_handle* h, int32_t slot, int32_t* dev_cells) {
+  VP_TRY(check_slot(h, slot));
+  if (!dev_cells) return fail(VP_ERR_ARG, "dev_cells is NULL");
+  VP_HIP(vpk::launch_cell_index(h->d_inst, slot, h->precision, dev_cells, h->slots[slot].cfg.n,
+                                h->stream));
+  return VP_OK;
+}
+
+vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* host_grid) {
+  VP_TRY(check_slot(h, slot));
+  if (!host_out) return fail(VP_ERR_ARG, "host_out is NULL");
+  const Slot& sl = h->slots[slot];
+  const InstDev& d = h->h_inst[slot];
+  VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearDiag, h->stream));
+  VP_HIP(vpk::launch_diag(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles, h->tun.ppt,
+                          h->max_ng, h->stream));
+  vpk::InstScal sc{};
+  VP_HIP(hipMemcpyAsync(&sc, d.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
+  if (host_grid) {
+    const int ng = sl.cfg.ng;
+    VP_HIP(hipMemcpyAsync(host_grid, d.bt, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + ng, d.Phi, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + 2 * ng, d.E, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + 3 * ng, d.g, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
+  VP_HIP(hipStreamSynchronize(h->stream));
+  host_out->step = sc.step;
+  host_out->t = (double)sc.step * sl.cfg.dt;
+  host_out->K = sc.Kd;
+  host_out->W = sc.W;
+  host_out->H = sc.Kd + sc.W;
+  host_out->charge = sc.chgd;
+  host_out->momentum = sc.momd;
+  host_out->e_amp = std::sqrt(2.0 * sc.W / sl.cfg.L);
+  host_out->e1_re = sc.e1r;
+  host_out->e1_im = sc.e1i;
+  if (!diag_finite(*host_out) || sc.nonfinite)
+    return fail(VP_ERR_NONFINITE, "slot %d: non-finite diagnostics at step %lld", slot, sc.step);
+  return VP_OK;
+}
+
+vp_status vp_history(vp_handle* h, int32_t slot, int64_t first_step, int32_t count,
+                     vp_diag* host_out) {
+  VP_TRY(check_slot(h, slot));
+  if (count < 0 || (count > 0 && !host_out)) return fail(VP_ERR_ARG, "bad count or output");
+  const Slot& sl = h->slots[slot];
+  const InstDev& d = h->h_inst[slot];
+  const long long cap = sl.cfg.hist_cap;
+  const long long lo = std::max(0LL, sl.step - cap);
+  if (first_step < lo || first_step + count > sl.step)
+    return fail(VP_ERR_RANGE, "records %lld..%lld not stored (have %lld..%lld)", (long long)first_step,
+                (long long)(first_step + count - 1), lo, sl.step - 1);
+  std::vector<double> buf((size_t)count * vpk::kHistFields);
+  VP_HIP(hipStreamSynchronize(h->stream));
+  long long k = 0;
+  while (k < count) {
+    const long long st = first_step + k;
+    const long long pos = st % cap;
+    const long long run = std::min<long long>(count - k, cap - pos);
+    VP_HIP(hipMemcpy(buf.data() + k * vpk::kHistFields, d.hist + pos * vpk::kHistFields,
+                     run * vpk::kHistFields * sizeof(double), hipMemcpyDeviceToHost));
+    k += run;
+  }
+  bool finite = true;
+  for (int i = 0; i < count; ++i) {
+    to_diag(buf.data() + (size_t)i * vpk::kHistFields, host_out + i);
+    finite = finite && diag_finite(host_out[i]);
+  }
+  if (!finite) return fail(VP_ERR_NONFINITE, "slot %d: non-finite records in the requested range", slot);
+  return VP_OK;
+}
+
+vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
+  if (!h || !t) return fail(VP_ERR_ARG, "NULL argument");
+  if (!(t->ppt == 1 || t->ppt == 2 || t->ppt == 4 || t->ppt == 8 || t->ppt == 16))
+    return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8 or 16");
+  if (t->acc_copies < 1 || t->acc_copies > VP_MAX_ACC_COPIES) return fail(VP_ERR_ARG, "acc_copies out of range");
+  if (t->graph_steps < 1 || t->graph_steps > 256) return fail(VP_ERR_ARG, "graph_steps out of range");
+  h->tun = *t;
+  h->tun.use_graph = t->use_graph ? 1 : 0;
+  return rebuild_tables(h);
+}
+
+vp_status vp_get_tuning(const vp_handle* h, vp_tuning* t) {
+  if (!h || !t) return fail(VP_ERR_ARG, "NULL argument");
+  *t = h->tun;
+  return VP_OK;
+}
+
+vp_status vp_occupancy(const vp_handle* h, int32_t* slots_out, int64_t* particles_out) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  int64_t p = 0;
+  for (int s : h->h_occ) p += h->slots[s].cfg.n;
+  if (slots_out) *slots_out = (int32_t)h->h_occ.size();
+  if (particles_out) *particles_out = p;
+  return VP_OK;
+}
+
+vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
+  if (!h || !bytes_out) return fail(VP_ERR_ARG, "NULL argument");
+  size_t b = 0;
+  for (int s : h->h_occ) {
+    const Slot& sl = h->slots[s];
+    b += ((size_t)4 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
+    b += vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
+  }
+  *bytes_out = b;
+  return VP_OK;
+}
+
+namespace {
+// Copy the mutable state of every occupied slot (Q, P, q*, p* and the workspace) to or from
+// the tuner scratch buffer.
+vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
+  size_t off = 0;
+  for (int s : h->h_occ) {
+    const Slot& sl = h->slots[s];
+    const size_t es = state_elem_size(h->precision);
+    void* arrs[4] = {sl.parts.Q, sl.parts.P, sl.parts.qs, sl.parts.ps};
+    for (int k = 0; k < 4; ++k) {
+      char* sp = scratch + off + (size_t)k * sl.cfg.n * es;
+      if (save) VP_HIP(hipMemcpyAsync(sp, arrs[k], sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
+      else VP_HIP(hipMemcpyAsync(arrs[k], sp, sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
+    }
+    off += ((size_t)4 * sl.cfg.n * es + 255) & ~size_t(255);
+    const size_t wb = vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
+    if (save) VP_HIP(hipMemcpyAsync(scratch + off, sl.ws, wb, hipMemcpyDeviceToDevice, h->stream));
+    else VP_HIP(hipMemcpyAsync(sl.ws, scratch + off, wb, hipMemcpyDeviceToDevice, h->stream));
+    off += wb;
+  }
+  return VP_OK;
+}
+}  // namespace
+
+vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_tuning* best_out,
+                  double* best_us_per_step_out) {
+  if (!h || !dev_scratch) return fail(VP_ERR_ARG, "NULL argument");
+  if (steps_per_trial < 1) return fail(VP_ERR_ARG, "steps_per_trial < 1");
+  if (h->h_occ.empty()) return fail(VP_ERR_STATE, "no occupied slot to tune on");
+  char* scratch = static_cast<char*>(dev_scratch);
+  std::vector<Slot> saved = h->slots;
+  const vp_tuning orig = h->tun;
+  VP_TRY(tune_copy(h, scratch, true));
+  hipEvent_t e0, e1;
+  VP_HIP(hipEventCreate(&e0));
+  VP_HIP(hipEventCreate(&e1));
+  vp_tuning best = orig;
+  double best_us = 1e300;
+  const int ppts[] = {1, 2, 4, 8, 16};
+  const int accs[] = {1, 4, 16};
+  vp_status st = VP_OK;
+  for (int pi = 0; pi < 5 && st == VP_OK; ++pi) {
+    for (int ai = 0; ai < 3 && st == VP_OK; ++ai) {
+      vp_tuning t = orig;
+      t.ppt = ppts[pi];
+      t.acc_copies = accs[ai];
+      t.use_graph = (h->stream != nullptr) ? 1 : 0;
+      t.graph_steps = std::min(steps_per_trial, 256);
+      st = vp_set_tuning(h, &t);
+      if (st != VP_OK) break;
+      // one untimed graph build + warm-up pass, then the timed steps
+      st = vp_step(h, t.graph_steps);
+      if (st != VP_OK) break;
+      hipEventRecord(e0, h->stream);
+      st = vp_step(h, steps_per_trial);
+      hipEventRecord(e1, h->stream);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / steps_per_trial;
+      if (us < best_us) {
+        best_us = us;
+        best = t;
+      }
+      h->slots = saved;
+      if (st == VP_OK) st = tune_copy(h, scratch, false);
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  h->slots = saved;
+  vp_status s2 = tune_copy(h, scratch, false);
+  vp_status s3 = vp_set_tuning(h, st == VP_OK ? &best : &orig);
+  if (st != VP_OK) return st;
+  if (s2 != VP_OK) return s2;
+  if (s3 != VP_OK) return s3;
+  if (best_out) *best_out = best;
+  if (best_us_per_step_out) *best_us_per_step_out = best_us;
+  return VP_OK;
+}
+
+}  // extern "C"

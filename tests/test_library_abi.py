@@ -1,0 +1,67 @@
+"""CPU checks of the C-ABI library: it builds, loads next to torch's HIP runtime, exports
+every symbol include/vp.h declares, and validates configurations without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "vp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vp_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2605_21794_amd._lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libvp.so is not built (run `python -m paper_2605_21794_amd.build`)")
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_2605_21794_amd._lib as L
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.SIGNATURES, f"{n} has no ctypes signature"
+    assert set(L.SIGNATURES) == set(names)
+
+
+def test_single_hip_runtime(lib):
+    import paper_2605_21794_amd._lib as L
+    assert len(L._hip_runtime_paths()) <= 1
+
+
+def test_workspace_sizing_and_validation(lib):
+    import paper_2605_21794_amd._lib as L
+    b = ctypes.c_size_t()
+    for ng in (8, 64, 1024):
+        c = L.vp_config(n=1000, ng=ng, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
+        assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
+        assert b.value % 256 == 0 and b.value >= (L.VP_MAX_ACC_COPIES + 8) * ng * 4
+    bad = [dict(ng=12), dict(ng=4), dict(ng=2048), dict(n=0), dict(L=-1.0), dict(dt=0.0),
+           dict(precision=7), dict(sort_chunk=5000), dict(hist_cap=0), dict(reserved=1),
+           dict(L=float("nan")), dict(sort_every=-2)]
+    for kw in bad:
+        args = dict(n=1000, ng=64, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
+        args.update(kw)
+        c = L.vp_config(**args)
+        assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_ERR_ARG, kw
+        assert lib.vp_last_error()
+    c = L.vp_config(n=1000, ng=64, precision=L.VP_FP64, L=1.0, dt=0.1, sort_chunk=2049, hist_cap=1)
+    assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_ERR_ARG
+
+
+def test_null_handles_rejected(lib):
+    import paper_2605_21794_amd._lib as L
+    assert lib.vp_step(None, 1) == L.VP_ERR_ARG
+    assert lib.vp_deposit(None) == L.VP_ERR_ARG
+    assert lib.vp_destroy(None) == L.VP_OK
+    assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
+    assert lib.vp_abi_version() == 1
