@@ -40,6 +40,7 @@ extern "C" {
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
 #define VP_MAX_SORT_CHUNK_F64 2048 /* particles per sorted chunk, float64 state */
 #define VP_MAX_ACC_COPIES 32       /* spread copies of the global load accumulator */
+#define VP_MAX_SLOTS 65536
 
 typedef enum vp_status {
   VP_OK = 0,
@@ -52,9 +53,9 @@ typedef enum vp_status {
 
 typedef enum vp_precision {
   VP_FP64 = 0,       /* float64 state; float64 loads accumulated in LDS and globally      */
-  VP_FP32_COMP = 1,  /* float32 state; per-particle arithmetic in float64; loads summed in
-                        LDS as float32 (hi, lo) pairs with two-sum error capture, block
-                        totals added in float64                                           */
+  VP_FP32_COMP = 1,  /* float32 state; per-particle arithmetic in float64; each nodal load
+                        summed in LDS as a float32 (hi, lo) pair updated by a two-sum under a
+                        64-bit compare-and-swap; block totals added in float64            */
   VP_FP32 = 2        /* float32 state, float32 arithmetic and float32 accumulation
                         (naive reference for the precision study)                         */
 } vp_precision;
@@ -70,8 +71,16 @@ typedef struct vp_config {
   int32_t sort_every;  /* vp_step sorts particles by cell every this many steps; 0 = never */
   int32_t sort_chunk;  /* particles per sorted chunk (<= VP_MAX_SORT_CHUNK_*); 0 = max */
   int32_t hist_cap;    /* per-step diagnostic records kept on the device (ring); >= 1 */
-  int32_t reserved;    /* must be 0 */
+  int32_t solver;      /* vp_solver: how vp_poisson / vp_step solve A Phi = b~ */
 } vp_config;
+
+typedef enum vp_solver {
+  VP_SOLVE_SCAN = 0,  /* discrete Gauss law: on the periodic P1 mesh (A Phi)_j = E_j - E_{j-1},
+                         so E is a prefix sum of b~ with sum_e E_e = 0 (periodic Phi), and Phi a
+                         prefix sum of -h E with sum_j Phi_j = 0; exact, O(Ng), one workgroup */
+  VP_SOLVE_FFT = 1    /* diagonalise the circulant A by an in-LDS radix-2 FFT:
+                         Phi_m = b~_m / lambda_m, lambda_m = (2/h)(1 - cos(2 pi m / Ng)), Phi_0 = 0 */
+} vp_solver;
 
 typedef struct vp_particles {
   void* Q;    /* position in [0, L)                    */
@@ -96,7 +105,8 @@ typedef struct vp_diag {
 
 /* Launch shape of the particle kernels; chosen by vp_tune or set by the caller. */
 typedef struct vp_tuning {
-  int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 (256 threads) */
+  int32_t threads;      /* threads per workgroup of the particle kernels: 256, 512 or 1024 */
+  int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 */
   int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..32 */
   int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
   int32_t graph_steps;  /* steps per captured graph, 1..256 */

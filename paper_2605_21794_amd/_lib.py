@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32 = 0, 1, 2
+VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_MIN_NG, VP_MAX_NG = 8, 1024
 VP_MAX_SORT_CHUNK_F32, VP_MAX_SORT_CHUNK_F64 = 4096, 2048
 VP_MAX_ACC_COPIES = 32
@@ -18,7 +19,7 @@ VP_MAX_ACC_COPIES = 32
 class vp_config(Structure):
     _fields_ = [("n", c_int64), ("ng", c_int32), ("precision", c_int32), ("L", c_double),
                 ("dt", c_double), ("sort_every", c_int32), ("sort_chunk", c_int32),
-                ("hist_cap", c_int32), ("reserved", c_int32)]
+                ("hist_cap", c_int32), ("solver", c_int32)]
 
 
 class vp_particles(Structure):
@@ -36,8 +37,8 @@ class vp_diag(Structure):
 
 
 class vp_tuning(Structure):
-    _fields_ = [("ppt", c_int32), ("acc_copies", c_int32), ("use_graph", c_int32),
-                ("graph_steps", c_int32)]
+    _fields_ = [("threads", c_int32), ("ppt", c_int32), ("acc_copies", c_int32),
+                ("use_graph", c_int32), ("graph_steps", c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -60,7 +60,7 @@ vp_status validate(const vp_config* c) {
   if (c->sort_chunk < 0 || c->sort_chunk > max_sort_chunk(c->precision))
     return fail(VP_ERR_ARG, "sort_chunk = %d exceeds %d", c->sort_chunk, max_sort_chunk(c->precision));
   if (c->hist_cap < 1) return fail(VP_ERR_ARG, "hist_cap must be >= 1");
-  if (c->reserved != 0) return fail(VP_ERR_ARG, "reserved must be 0");
+  if (c->solver != VP_SOLVE_SCAN && c->solver != VP_SOLVE_FFT) return fail(VP_ERR_ARG, "bad solver %d", c->solver);
   return VP_OK;
 }
 
@@ -94,7 +94,7 @@ struct vp_handle {
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   int max_ng = VP_MIN_NG;
-  vp_tuning tun{4, 8, 1, 32};
+  vp_tuning tun{1024, 4, 8, 1, 32};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_len = 0;
@@ -117,7 +117,7 @@ void drop_graph(vp_handle* h) {
 vp_status rebuild_tables(vp_handle* h) {
   VP_HIP(hipStreamSynchronize(h->stream));
   drop_graph(h);
-  const int tile_n = vpk::kBlock * h->tun.ppt;
+  const int tile_n = h->tun.threads * h->tun.ppt;
   h->h_tiles.clear();
   h->h_occ.clear();
   h->max_ng = VP_MIN_NG;
@@ -171,7 +171,7 @@ vp_status check_slot(const vp_handle* h, int slot) {
 
 vp_status launch_steps_direct(vp_handle* h, int nsteps) {
   for (int i = 0; i < nsteps; ++i)
-    VP_HIP(vpk::launch_fused(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+    VP_HIP(vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                              h->max_ng, h->stream));
   return VP_OK;
 }
@@ -182,7 +182,7 @@ vp_status ensure_graph(vp_handle* h) {
   VP_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < h->tun.graph_steps && le == hipSuccess; ++i)
-    le = vpk::launch_fused(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+    le = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                            h->max_ng, h->stream);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(h->stream, &g);
@@ -250,7 +250,7 @@ vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream, v
   if (!out) return fail(VP_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (precision < VP_FP64 || precision > VP_FP32) return fail(VP_ERR_ARG, "bad precision %d", precision);
-  if (max_slots < 1 || max_slots > 65536) return fail(VP_ERR_ARG, "max_slots = %d out of range", max_slots);
+  if (max_slots < 1 || max_slots > VP_MAX_SLOTS) return fail(VP_ERR_ARG, "max_slots = %d out of range", max_slots);
   vp_handle* h = new vp_handle();
   h->precision = precision;
   h->max_slots = max_slots;
@@ -295,7 +295,7 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.ng = cfg->ng;
   d.log2ng = ilog2(cfg->ng);
   d.hist_cap = cfg->hist_cap;
-  d.active = 1;
+  d.solver = cfg->solver;
   d.L = cfg->L;
   d.inv_h = (double)cfg->ng / cfg->L;
   d.h = cfg->L / (double)cfg->ng;
@@ -344,7 +344,7 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
     return st;
   }
   // Field at t = 0 from the initial state.
-  VP_HIP(vpk::launch_deposit(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
+  VP_HIP(vpk::launch_deposit(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
                              h->tun.ppt, h->max_ng, h->stream));
   VP_HIP(vpk::launch_solve(h->precision, h->d_inst, h->d_ids + slot, 1, h->max_ng, h->stream));
   return VP_OK;
@@ -385,7 +385,7 @@ vp_status vp_retire(vp_handle* h, int32_t slot) {
   VP_TRY(check_slot(h, slot));
   Slot& sl = h->slots[slot];
   if (sl.pending) {
-    VP_HIP(vpk::launch_settle(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
+    VP_HIP(vpk::launch_settle(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
                               h->tun.ppt, h->max_ng, h->stream));
     VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearPending, h->stream));
     sl.pending = false;
@@ -410,7 +410,7 @@ vp_status vp_destroy(vp_handle* h) {
 
 vp_status vp_deposit(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
-  VP_HIP(vpk::launch_deposit(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+  VP_HIP(vpk::launch_deposit(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                              h->max_ng, h->stream));
   return VP_OK;
 }
@@ -425,7 +425,7 @@ vp_status vp_poisson(vp_handle* h) {
 vp_status vp_gather_push(vp_handle* h, double kick, double drift) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (!std::isfinite(kick) || !std::isfinite(drift)) return fail(VP_ERR_ARG, "kick and drift must be finite");
-  VP_HIP(vpk::launch_gather_push(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+  VP_HIP(vpk::launch_gather_push(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                                  h->max_ng, kick, drift, h->stream));
   return VP_OK;
 }
@@ -473,7 +473,7 @@ vp_status vp_step(vp_handle* h, int32_t nsteps) {
 vp_status vp_sync_state(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (h->h_occ.empty()) return VP_OK;
-  VP_HIP(vpk::launch_settle(h->precision, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+  VP_HIP(vpk::launch_settle(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                             h->max_ng, h->stream));
   VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalClearPending,
                                   h->stream));
@@ -512,7 +512,7 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   const Slot& sl = h->slots[slot];
   const InstDev& d = h->h_inst[slot];
   VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearDiag, h->stream));
-  VP_HIP(vpk::launch_diag(h->precision, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles, h->tun.ppt,
+  VP_HIP(vpk::launch_diag(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles, h->tun.ppt,
                           h->max_ng, h->stream));
   vpk::InstScal sc{};
   VP_HIP(hipMemcpyAsync(&sc, d.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
@@ -572,6 +572,8 @@ vp_status vp_history(vp_handle* h, int32_t slot, int64_t first_step, int32_t cou
 
 vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
   if (!h || !t) return fail(VP_ERR_ARG, "NULL argument");
+  if (!(t->threads == 256 || t->threads == 512 || t->threads == 1024))
+    return fail(VP_ERR_ARG, "threads must be 256, 512 or 1024");
   if (!(t->ppt == 1 || t->ppt == 2 || t->ppt == 4 || t->ppt == 8 || t->ppt == 16))
     return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8 or 16");
   if (t->acc_copies < 1 || t->acc_copies > VP_MAX_ACC_COPIES) return fail(VP_ERR_ARG, "acc_copies out of range");
@@ -601,7 +603,7 @@ vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   size_t b = 0;
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
-    b += ((size_t)4 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
+    b += ((size_t)5 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
     b += vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
   }
   *bytes_out = b;
@@ -609,20 +611,21 @@ vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
 }
 
 namespace {
-// Copy the mutable state of every occupied slot (Q, P, q*, p* and the workspace) to or from
+// Copy the state of every occupied slot (the five particle arrays, which a scheduled sort
+// permutes, and the workspace) to or from
 // the tuner scratch buffer.
 vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
   size_t off = 0;
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
     const size_t es = state_elem_size(h->precision);
-    void* arrs[4] = {sl.parts.Q, sl.parts.P, sl.parts.qs, sl.parts.ps};
-    for (int k = 0; k < 4; ++k) {
+    void* arrs[5] = {sl.parts.Q, sl.parts.P, sl.parts.qs, sl.parts.ps, sl.parts.psi};
+    for (int k = 0; k < 5; ++k) {
       char* sp = scratch + off + (size_t)k * sl.cfg.n * es;
       if (save) VP_HIP(hipMemcpyAsync(sp, arrs[k], sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
       else VP_HIP(hipMemcpyAsync(arrs[k], sp, sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
     }
-    off += ((size_t)4 * sl.cfg.n * es + 255) & ~size_t(255);
+    off += ((size_t)5 * sl.cfg.n * es + 255) & ~size_t(255);
     const size_t wb = vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
     if (save) VP_HIP(hipMemcpyAsync(scratch + off, sl.ws, wb, hipMemcpyDeviceToDevice, h->stream));
     else VP_HIP(hipMemcpyAsync(sl.ws, scratch + off, wb, hipMemcpyDeviceToDevice, h->stream));
@@ -646,14 +649,18 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   VP_HIP(hipEventCreate(&e1));
   vp_tuning best = orig;
   double best_us = 1e300;
-  const int ppts[] = {1, 2, 4, 8, 16};
-  const int accs[] = {1, 4, 16};
+  struct Cand { int threads, ppt, acc; };
+  std::vector<Cand> cands;
+  for (int th : {256, 1024})
+    for (int pp : {1, 2, 4, 8})
+      for (int ac : {1, 8, 32}) cands.push_back({th, pp, ac});
   vp_status st = VP_OK;
-  for (int pi = 0; pi < 5 && st == VP_OK; ++pi) {
-    for (int ai = 0; ai < 3 && st == VP_OK; ++ai) {
+  for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
+    {
       vp_tuning t = orig;
-      t.ppt = ppts[pi];
-      t.acc_copies = accs[ai];
+      t.threads = cands[ci].threads;
+      t.ppt = cands[ci].ppt;
+      t.acc_copies = cands[ci].acc;
       t.use_graph = (h->stream != nullptr) ? 1 : 0;
       t.graph_steps = std::min(steps_per_trial, 256);
       st = vp_set_tuning(h, &t);

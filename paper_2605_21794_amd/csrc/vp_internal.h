@@ -35,7 +35,7 @@ struct InstDev {
   long long n;
   int ng, log2ng;
   int ntiles, acc_copies;
-  int hist_cap, active;
+  int hist_cap, solver;
   double L, inv_h, h, dt;
   double* acc;      // acc_copies * ng global load accumulators (float for kFP32)
   double* E;        // element field, ng
@@ -67,16 +67,16 @@ WsLayout workspace_layout(int ng, int hist_cap);
 
 size_t particle_lds_bytes(int mode, int max_ng);
 
-hipError_t launch_fused(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, hipStream_t s);
-hipError_t launch_deposit(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, hipStream_t s);
-hipError_t launch_gather_push(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                              int ntiles, int ppt, int max_ng, double kick, double drift,
+hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,
+                              int tile0, int ntiles, int ppt, int max_ng, double kick, double drift,
                               hipStream_t s);
-hipError_t launch_settle(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_settle(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                          int ntiles, int ppt, int max_ng, hipStream_t s);
-hipError_t launch_diag(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                        int ntiles, int ppt, int max_ng, hipStream_t s);
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
                         int max_ng, hipStream_t s);

@@ -3,12 +3,14 @@
 // the zero-mean gauge (eq. lin-sys), gather of E = -phi_h' and of the projected phi_h'',
 // and the kick / drift sub-flows of eq. sw-evolution.
 //
-// Layout: particles are five structure-of-arrays streams; one workgroup of 256 threads
-// owns one tile of consecutive particles of one instance, so every load and store is
-// coalesced.  The instance's field (E, g) is staged in LDS and the load vector is
-// accumulated into an LDS-private copy of the grid, which the workgroup adds into the
-// instance's global accumulator once (Ng float64 atomics per tile).  The fused step's
-// last workgroup of an instance (ticket counter) runs that instance's solve in LDS.
+// Layout: particles are five structure-of-arrays streams; one workgroup owns one tile of
+// consecutive particles of one instance, so every load and store is coalesced.  The
+// instance's field (E, g) is staged in LDS; the load vector is accumulated into an
+// LDS-private copy of the grid (float64 LDS atomics, or float32 (hi, lo) two-sum pairs
+// under a 64-bit compare-and-swap, or float32 atomics in the naive mode), and each tile
+// adds its grid into one of the instance's spread global accumulator copies.  In the fused
+// step the last workgroup to finish an instance (ticket counter) runs that instance's
+// solve in LDS, so one kernel per step advances every instance.
 //
 // Rounding: every kernel is compiled without floating-point contraction, and the float64
 // particle arithmetic follows the same operation order as the plain CPU definition, so the
@@ -51,85 +53,142 @@ __device__ __forceinline__ float frac01_f(float x, int i) {
   return s;
 }
 
-// Deterministic workgroup sum (fixed shuffle tree, then the four wave totals in order).
+// Deterministic workgroup sum: fixed shuffle tree per wave, then the wave totals in order.
+// `red` holds at least TPB/64 doubles.  Every thread of the workgroup must call it.
+template <int TPB>
 __device__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return ((red[0] + red[1]) + red[2]) + red[3];
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < TPB / 64; ++w) r += red[w];
+  return r;
 }
 
-// ------------------------------------------------------------------ LDS staging
-// Field region: 2*Ng doubles (E then g; float copies for kFP32).  Accumulator region:
-// Ng*8 bytes (Ng doubles; Ng (hi, lo) float pairs for kFP32Comp; Ng floats for kFP32).
-template <int MODE>
+// In-place inclusive prefix sum of x[0..n) (n <= 4 * TPB) by the whole workgroup; `red`
+// holds at least TPB/64 doubles.  Deterministic.
+template <int TPB>
+__device__ void block_scan(double* x, int n, double* red) {
+  const int tid = threadIdx.x;
+  const int per = (n + TPB - 1) / TPB;  // <= 4
+  const int j0 = tid * per;
+  double loc[4];
+  double run = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < per) {
+      const int j = j0 + k;
+      run += (j < n) ? x[j] : 0.0;
+      loc[k] = run;
+    }
+  }
+  double incl = run;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_up(incl, off, 64);
+    if ((tid & 63) >= off) incl += y;
+  }
+  __syncthreads();
+  if ((tid & 63) == 63) red[tid >> 6] = incl;
+  __syncthreads();
+  double before = 0.0;
+  for (int w = 0; w < (tid >> 6); ++w) before += red[w];
+  const double excl = before + incl - run;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < per) {
+      const int j = j0 + k;
+      if (j < n) x[j] = excl + loc[k];
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ LDS layout
+// [0, 2*Ng) doubles: field E then g (float copies for kFP32); [2*Ng, 3*Ng): accumulator
+// (Ng doubles / Ng packed float (hi, lo) pairs / Ng floats).  The solve reuses [0, 4*Ng).
+__host__ __device__ constexpr size_t lds_doubles_per_node() { return 4; }
+
+template <int MODE, int TPB>
 __device__ void stage(const InstDev& d, double* fld, double* sacc, bool need_field,
                       bool need_acc) {
   const int ng = d.ng;
   if (need_field) {
     if constexpr (MODE == kFP32) {
       float* f = reinterpret_cast<float*>(fld);
-      for (int j = threadIdx.x; j < ng; j += kBlock) {
+      for (int j = threadIdx.x; j < ng; j += TPB) {
         f[j] = d.Ef[j];
         f[ng + j] = d.gf[j];
       }
     } else {
-      for (int j = threadIdx.x; j < ng; j += kBlock) {
+      for (int j = threadIdx.x; j < ng; j += TPB) {
         fld[j] = d.E[j];
         fld[ng + j] = d.g[j];
       }
     }
   }
   if (need_acc)
-    for (int j = threadIdx.x; j < ng; j += kBlock) sacc[j] = 0.0;
+    for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
   __syncthreads();
 }
 
-// Add one nodal contribution c into the LDS grid.
+// Add the nodal contribution c into the LDS grid.
 template <int MODE>
-__device__ __forceinline__ void lds_add(double* sacc, int ng, int j, double c) {
+__device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
   if constexpr (MODE == kFP64) {
     atomicAdd(sacc + j, c);
   } else {
-    // float (hi, lo): c is split exactly into ch + cl; ch is added with a returning atomic,
-    // and the rounding error of that very addition (two-sum of the returned old value and
-    // ch) is added, with cl, into lo.
-    float* hi = reinterpret_cast<float*>(sacc);
-    float* lo = hi + ng;
+    // float32 (hi, lo) pair packed in one 64-bit word: c = ch + cl exactly (to float64
+    // precision); (hi, lo) <- (fl(hi + ch), lo + (e + cl)) with e the exact rounding error of
+    // hi + ch (two-sum), committed with a 64-bit compare-and-swap so the pair stays
+    // consistent.  A lane retries only when another lane changed the word in between.
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(sacc) + j;
     const float ch = (float)c;
     const float cl = (float)(c - (double)ch);
-    const float old = atomicAdd(hi + j, ch);
-    const float s = old + ch;
-    const float bp = s - old;
-    const float err = (old - (s - bp)) + (ch - bp);
-    atomicAdd(lo + j, err + cl);
+    unsigned long long old = *reinterpret_cast<volatile unsigned long long*>(w);
+    while (true) {
+      const float hi = __uint_as_float((unsigned)(old & 0xffffffffull));
+      const float lo = __uint_as_float((unsigned)(old >> 32));
+      const float s = hi + ch;
+      const float bp = s - hi;
+      const float err = (hi - (s - bp)) + (ch - bp);
+      const float nlo = lo + (err + cl);
+      const unsigned long long nw =
+          (unsigned long long)__float_as_uint(s) | ((unsigned long long)__float_as_uint(nlo) << 32);
+      const unsigned long long prev = atomicCAS(w, old, nw);
+      if (prev == old) break;
+      old = prev;
+    }
   }
 }
 
-// Add the LDS grid into the global accumulator copy `copy` of the instance.
-template <int MODE>
+// Add the LDS grid into the global accumulator copy `copy` of the instance (device-scope
+// atomics; only non-zero nodes).
+template <int MODE, int TPB>
 __device__ void flush(const InstDev& d, const double* sacc, int copy) {
   const int ng = d.ng;
   if constexpr (MODE == kFP32) {
     const float* a = reinterpret_cast<const float*>(sacc);
     float* gacc = reinterpret_cast<float*>(d.acc) + (size_t)copy * ng;
-    for (int j = threadIdx.x; j < ng; j += kBlock) {
+    for (int j = threadIdx.x; j < ng; j += TPB) {
       const float v = a[j];
       if (v != 0.0f) unsafeAtomicAdd(gacc + j, v);
     }
   } else if constexpr (MODE == kFP32Comp) {
-    const float* hi = reinterpret_cast<const float*>(sacc);
-    const float* lo = hi + ng;
+    const unsigned long long* wv = reinterpret_cast<const unsigned long long*>(sacc);
     double* gacc = d.acc + (size_t)copy * ng;
-    for (int j = threadIdx.x; j < ng; j += kBlock) {
-      const double v = (double)hi[j] + (double)lo[j];
+    for (int j = threadIdx.x; j < ng; j += TPB) {
+      const unsigned long long w = wv[j];
+      const double v = (double)__uint_as_float((unsigned)(w & 0xffffffffull)) +
+                       (double)__uint_as_float((unsigned)(w >> 32));
       if (v != 0.0) unsafeAtomicAdd(gacc + j, v);
     }
   } else {
     double* gacc = d.acc + (size_t)copy * ng;
-    for (int j = threadIdx.x; j < ng; j += kBlock) {
+    for (int j = threadIdx.x; j < ng; j += TPB) {
       const double v = sacc[j];
       if (v != 0.0) unsafeAtomicAdd(gacc + j, v);
     }
@@ -137,27 +196,38 @@ __device__ void flush(const InstDev& d, const double* sacc, int copy) {
 }
 
 // Count this workgroup's tile as done; true in the workgroup that completes the instance.
+// Every wave first waits until its own device-scope atomics (load flush and kinetic sums)
+// have been performed; the ticket is then taken by one thread.  The completing workgroup
+// reads those sums with device-scope loads.  No cache write-back is needed because all
+// cross-workgroup data of the pass travels through device-scope atomics.
 __device__ bool arrive(const InstDev& d, int* sflag) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(&d.scal->ticket, 1u, __ATOMIC_ACQ_REL,
+    const unsigned prev = __hip_atomic_fetch_add(&d.scal->ticket, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     *sflag = (prev + 1u == (unsigned)d.ntiles) ? 1 : 0;
   }
   __syncthreads();
-  const bool last = *sflag != 0;
-  if (last) __threadfence();
-  return last;
+  return *sflag != 0;
+}
+
+__device__ __forceinline__ double ld_agent(double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ Poisson solve
-// Radix-2 FFT on (re, im) held in bit-reversed order; tw holds cos/sin of 2 pi k / Ng.
+// Radix-2 FFT on (re, im) in LDS, input in bit-reversed order; tw in LDS holds
+// cos/sin(2 pi k / Ng) for k < Ng/2.
+template <int TPB>
 __device__ void fft_lds(double* re, double* im, int ng, int m, const double* tw, bool inverse) {
   for (int s = 1; s <= m; ++s) {
     const int half = 1 << (s - 1);
     const int tstride = ng >> s;
-    for (int b = threadIdx.x; b < (ng >> 1); b += kBlock) {
+    for (int b = threadIdx.x; b < (ng >> 1); b += TPB) {
       const int pos = b & (half - 1);
       const int i0 = ((b >> (s - 1)) << s) + pos;
       const int i1 = i0 + half;
@@ -177,8 +247,9 @@ __device__ void fft_lds(double* re, double* im, int ng, int m, const double* tw,
   }
 }
 
+template <int TPB>
 __device__ void bit_reverse_lds(double* re, double* im, int ng, int m) {
-  for (int j = threadIdx.x; j < ng; j += kBlock) {
+  for (int j = threadIdx.x; j < ng; j += TPB) {
     const int r = (int)(__brev((unsigned)j) >> (32 - m));
     if (j < r) {
       double t = re[j];
@@ -192,17 +263,25 @@ __device__ void bit_reverse_lds(double* re, double* im, int ng, int m) {
   __syncthreads();
 }
 
-// Solve for one instance with one workgroup: gather and clear the global load, subtract its
-// mean (float64), Phi = A^+ b~ by FFT, E, g, W and the mode-1 amplitude.  With `record`,
-// first write the diagnostic record of the step that just ran its particle pass (kinetic
-// sums of this pass + the field summary from the previous solve) and advance the counter.
-template <int MODE>
-__device__ void solve_instance(const InstDev& d, double* re, double* im, double* red,
-                               bool record) {
-  const int ng = d.ng, m = d.log2ng, mask = ng - 1;
+// Solve for one instance with one workgroup, in LDS (4*Ng doubles at `sm`):
+//   b_j   = sum of the accumulator copies (then cleared);
+//   b~_j  = b_j - mean(b)                                  (float64, eq. neutrality);
+//   E, Phi from A Phi = b~, 1^T Phi = 0                     (scan or FFT);
+//   g_e   = -(b~_e + b~_{e+1}) / (2h)   (lumped projection of E onto P1, differentiated;
+//           equal to -(E_{e+1} - E_{e-1}) / (2h) by (A Phi)_j = E_j - E_{j-1});
+//   W     = (1/2) h sum_e E_e^2;  E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng).
+// With `record`, first write the record of the integer step whose particle pass just ran
+// (kinetic sums of the pass + the field summary of the previous solve) and advance.
+template <int MODE, int TPB>
+__device__ void solve_instance(const InstDev& d, double* sm, double* red, bool record) {
+  const int ng = d.ng, mask = ng - 1;
   const int tid = threadIdx.x;
+  double* bt = sm;            // b~ (kept)
+  double* E = sm + ng;        // E
+  double* ph = sm + 2 * ng;   // scratch: prefix sums / FFT re
+  double* aux = sm + 3 * ng;  // scratch: FFT im
 
-  for (int j = tid; j < ng; j += kBlock) {
+  for (int j = tid; j < ng; j += TPB) {
     double b = 0.0;
     for (int c = 0; c < d.acc_copies; ++c) {
       if constexpr (MODE == kFP32) {
@@ -211,77 +290,103 @@ __device__ void solve_instance(const InstDev& d, double* re, double* im, double*
         __hip_atomic_store(a, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         double* a = d.acc + (size_t)c * ng + j;
-        b += __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b += ld_agent(a);
+        st_agent(a, 0.0);
       }
     }
-    re[j] = b;
+    bt[j] = b;
   }
   __syncthreads();
   double part = 0.0;
-  for (int j = tid; j < ng; j += kBlock) part += re[j];
-  const double mean = block_sum(part, red) / (double)ng;
-  for (int j = tid; j < ng; j += kBlock) {
-    const double bt = re[j] - mean;
-    re[j] = bt;
-    im[j] = 0.0;
-    d.bt[j] = bt;
+  for (int j = tid; j < ng; j += TPB) part += bt[j];
+  const double mean = block_sum<TPB>(part, red) / (double)ng;
+  for (int j = tid; j < ng; j += TPB) {
+    const double v = bt[j] - mean;
+    bt[j] = v;
+    d.bt[j] = v;
   }
   __syncthreads();
 
-  bit_reverse_lds(re, im, ng, m);
-  fft_lds(re, im, ng, m, d.tw, false);
-  for (int k = tid; k < ng; k += kBlock) {
-    const double il = d.inv_lam[k];
-    re[k] = re[k] * il;
-    im[k] = im[k] * il;
+  const double h = d.h, inv_h = d.inv_h;
+  if (d.solver == VP_SOLVE_FFT) {
+    // Phi = IFFT(FFT(b~) / lambda); E_e = -(Phi_{e+1} - Phi_e) / h.  The twiddles and the
+    // inverse eigenvalues are staged in LDS (E and the field region serve as buffers).
+    const int m = d.log2ng;
+    double* re = ph;
+    double* im = aux;
+    double* tw = E;  // Ng doubles: Ng/2 (cos, sin) pairs
+    for (int j = tid; j < ng; j += TPB) {
+      re[j] = bt[j];
+      im[j] = 0.0;
+      tw[j] = d.tw[j];
+    }
+    __syncthreads();
+    bit_reverse_lds<TPB>(re, im, ng, m);
+    fft_lds<TPB>(re, im, ng, m, tw, false);
+    for (int k = tid; k < ng; k += TPB) {
+      const double il = d.inv_lam[k];
+      re[k] = re[k] * il;
+      im[k] = im[k] * il;
+    }
+    __syncthreads();
+    bit_reverse_lds<TPB>(re, im, ng, m);
+    fft_lds<TPB>(re, im, ng, m, tw, true);
+    const double inv_ng = 1.0 / (double)ng;
+    for (int j = tid; j < ng; j += TPB) {
+      const double phi = re[j] * inv_ng;
+      re[j] = phi;
+      d.Phi[j] = phi;
+    }
+    __syncthreads();
+    for (int e = tid; e < ng; e += TPB) E[e] = -(re[(e + 1) & mask] - re[e]) * inv_h;
+    __syncthreads();
+  } else {
+    // Gauss law: E_e = C + sum_{j=1..e} b~_j with sum_e E_e = 0.
+    for (int j = tid; j < ng; j += TPB) ph[j] = (j == 0) ? 0.0 : bt[j];
+    __syncthreads();
+    block_scan<TPB>(ph, ng, red);
+    double tp = 0.0;
+    for (int j = tid; j < ng; j += TPB) tp += ph[j];
+    const double C = -block_sum<TPB>(tp, red) / (double)ng;
+    for (int e = tid; e < ng; e += TPB) E[e] = C + ph[e];
+    __syncthreads();
+    // Phi_e = Phi_0 - h sum_{k<e} E_k with sum_j Phi_j = 0.
+    for (int j = tid; j < ng; j += TPB) ph[j] = (j == 0) ? 0.0 : E[j - 1];
+    __syncthreads();
+    block_scan<TPB>(ph, ng, red);
+    double up = 0.0;
+    for (int j = tid; j < ng; j += TPB) up += ph[j];
+    const double U = block_sum<TPB>(up, red) / (double)ng;
+    for (int j = tid; j < ng; j += TPB) d.Phi[j] = -h * (ph[j] - U);
   }
-  __syncthreads();
-  bit_reverse_lds(re, im, ng, m);
-  fft_lds(re, im, ng, m, d.tw, true);
-  const double inv_ng = 1.0 / (double)ng;
-  for (int j = tid; j < ng; j += kBlock) {
-    const double phi = re[j] * inv_ng;
-    re[j] = phi;
-    d.Phi[j] = phi;
-  }
-  __syncthreads();
-  const double inv_h = d.inv_h;
-  for (int e = tid; e < ng; e += kBlock) {
-    const double E = -(re[(e + 1) & mask] - re[e]) * inv_h;
-    im[e] = E;
-    d.E[e] = E;
-    d.Ef[e] = (float)E;
-  }
-  __syncthreads();
+
   double wpart = 0.0, e1r = 0.0, e1i = 0.0;
-  const int halfn = ng >> 1;
-  for (int e = tid; e < ng; e += kBlock) {
-    const double Em = im[(e - 1) & mask], E0 = im[e], Ep = im[(e + 1) & mask];
-    const double En_a = 0.5 * (Em + E0);
-    const double En_b = 0.5 * (E0 + Ep);
-    const double g = -(En_b - En_a) * inv_h;
+  for (int e = tid; e < ng; e += TPB) {
+    const double Ee = E[e];
+    d.E[e] = Ee;
+    d.Ef[e] = (float)Ee;
+    const double g = -(bt[e] + bt[(e + 1) & mask]) * (0.5 * inv_h);
     d.g[e] = g;
     d.gf[e] = (float)g;
-    wpart += E0 * E0;
-    const int k = e & (halfn - 1);
-    const double sg = (e < halfn) ? 1.0 : -1.0;  // cos/sin of theta + pi flip sign
-    e1r += E0 * (sg * d.tw[2 * k]);
-    e1i -= E0 * (sg * d.tw[2 * k + 1]);
+    wpart += Ee * Ee;
+    double sn, cs;
+    sincospi(2.0 * (double)e / (double)ng, &sn, &cs);
+    e1r += Ee * cs;
+    e1i -= Ee * sn;
   }
-  const double Wsum = block_sum(wpart, red);
-  const double E1r = block_sum(e1r, red) * inv_ng;
-  const double E1i = block_sum(e1i, red) * inv_ng;
-  const double Wn = 0.5 * d.h * Wsum;
+  const double Wsum = block_sum<TPB>(wpart, red);
+  const double E1r = block_sum<TPB>(e1r, red) / (double)ng;
+  const double E1i = block_sum<TPB>(e1i, red) / (double)ng;
+  const double Wn = 0.5 * h * Wsum;
 
   if (tid == 0) {
     InstScal* sc = d.scal;
     if (record) {
       const long long st = sc->step;
       double* r = d.hist + (size_t)(st % d.hist_cap) * kHistFields;
-      const double K = __hip_atomic_load(&sc->K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double mom = __hip_atomic_load(&sc->mom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double chg = __hip_atomic_load(&sc->chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double K = ld_agent(&sc->K);
+      const double mom = ld_agent(&sc->mom);
+      const double chg = ld_agent(&sc->chg);
       const double W = sc->W;
       r[0] = (double)st;
       r[1] = (double)st * d.dt;
@@ -294,9 +399,9 @@ __device__ void solve_instance(const InstDev& d, double* re, double* im, double*
       r[8] = sc->e1r;
       r[9] = sc->e1i;
       if (!isfinite(K) || !isfinite(W)) sc->nonfinite = 1;
-      __hip_atomic_store(&sc->K, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&sc->mom, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&sc->chg, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_agent(&sc->K, 0.0);
+      st_agent(&sc->mom, 0.0);
+      st_agent(&sc->chg, 0.0);
       sc->step = st + 1;
       sc->pending = 1;
     }
@@ -310,13 +415,13 @@ __device__ void solve_instance(const InstDev& d, double* re, double* im, double*
 
 // ------------------------------------------------------------------ particle passes
 // Loop shape shared by the particle kernels: thread t of the workgroup handles particles
-// tile.begin + k * 256 + t for k < ppt, four at a time with all loads issued first.
+// tile.begin + k * TPB + t for k < ppt, four at a time with all loads issued first.
 #define VP_TILE_LOOP_BEGIN                                                        \
   for (int k0 = 0; k0 < ppt; k0 += 4) {                                           \
     bool v[4];                                                                    \
     long long idx[4];                                                             \
     _Pragma("unroll") for (int u = 0; u < 4; ++u) {                              \
-      const int loc = (k0 + u) * kBlock + (int)threadIdx.x;                       \
+      const int loc = (k0 + u) * TPB + (int)threadIdx.x;                          \
       v[u] = (k0 + u < ppt) && (loc < tl.count);                                  \
       idx[u] = tl.begin + loc;                                                    \
     }
@@ -325,12 +430,12 @@ __device__ void solve_instance(const InstDev& d, double* re, double* im, double*
 
 // One fused step for every tile: [pending half-kick] -> kinetic sums at the integer step
 // -> half-kick -> drift -> deposit of the drifted state -> (last workgroup) solve.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_fused(const InstDev* __restrict__ insts,
-                                                  const Tile* __restrict__ tiles, int tile0,
-                                                  int ppt) {
+template <int MODE, int TPB>
+__global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
+                                               const Tile* __restrict__ tiles, int tile0,
+                                               int ppt) {
   extern __shared__ double smem[];
-  __shared__ double red[4];
+  __shared__ double red[TPB / 64];
   __shared__ int sflag;
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
@@ -338,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(const InstDev* __restrict__ in
   const int ng = d.ng;
   double* fld = smem;
   double* sacc = smem + 2 * ng;
-  stage<MODE>(d, fld, sacc, true, true);
+  stage<MODE, TPB>(d, fld, sacc, true, true);
   const int pend = d.scal->pending;
   T* __restrict__ Qp = static_cast<T*>(d.Q);
   T* __restrict__ Pp = static_cast<T*>(d.P);
@@ -350,6 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(const InstDev* __restrict__ in
   if constexpr (MODE == kFP32) {
     const float* fE = reinterpret_cast<const float*>(fld);
     const float* fG = fE + ng;
+    float* fa = reinterpret_cast<float*>(sacc);
     const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
     VP_TILE_LOOP_BEGIN
     float q[4], p[4], a[4], b[4], w[4];
@@ -381,7 +487,6 @@ __global__ __launch_bounds__(kBlock) void k_fused(const InstDev* __restrict__ in
       const float x = Qn * ihf;
       const int j = cell_of_f(x, ng);
       const float s = frac01_f(x, j);
-      float* fa = reinterpret_cast<float*>(sacc);
       atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
       atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
     }
@@ -419,37 +524,37 @@ __global__ __launch_bounds__(kBlock) void k_fused(const InstDev* __restrict__ in
       const double x = Qd * inv_h;
       const int j = cell_of(x, ng);
       const double s = frac01(x, j);
-      lds_add<MODE>(sacc, ng, j, psi * (1.0 - s) + psd * inv_h);
-      lds_add<MODE>(sacc, ng, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
     }
     VP_TILE_LOOP_END
   }
 
-  const double Kb = block_sum(Ks, red);
-  const double Mb = block_sum(Ms, red);
-  const double Cb = block_sum(Cs, red);
+  const double Kb = block_sum<TPB>(Ks, red);
+  const double Mb = block_sum<TPB>(Ms, red);
+  const double Cb = block_sum<TPB>(Cs, red);
   if (threadIdx.x == 0) {
     unsafeAtomicAdd(&d.scal->K, Kb);
     unsafeAtomicAdd(&d.scal->mom, Mb);
     unsafeAtomicAdd(&d.scal->chg, Cb);
   }
   __syncthreads();
-  flush<MODE>(d, sacc, tl.local % d.acc_copies);
-  if (arrive(d, &sflag)) solve_instance<MODE>(d, fld, fld + ng, red, true);
+  flush<MODE, TPB>(d, sacc, tl.local % d.acc_copies);
+  if (arrive(d, &sflag)) solve_instance<MODE, TPB>(d, smem, red, true);
 }
 
 // Deposit of the current state only (eq. rhs-assembly), added to the global accumulator.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_deposit(const InstDev* __restrict__ insts,
-                                                    const Tile* __restrict__ tiles, int tile0,
-                                                    int ppt) {
+template <int MODE, int TPB>
+__global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ insts,
+                                                 const Tile* __restrict__ tiles, int tile0,
+                                                 int ppt) {
   extern __shared__ double smem[];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
   const InstDev& d = insts[tl.inst];
   const int ng = d.ng;
   double* sacc = smem + 2 * ng;
-  stage<MODE>(d, smem, sacc, false, true);
+  stage<MODE, TPB>(d, smem, sacc, false, true);
   const T* __restrict__ Qp = static_cast<const T*>(d.Q);
   const T* __restrict__ psp = static_cast<const T*>(d.ps);
   const T* __restrict__ psip = static_cast<const T*>(d.psi);
@@ -485,22 +590,22 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const InstDev* __restrict__ 
       const double x = (double)q[u] * inv_h;
       const int j = cell_of(x, ng);
       const double s = frac01(x, j);
-      lds_add<MODE>(sacc, ng, j, psi * (1.0 - s) + psd * inv_h);
-      lds_add<MODE>(sacc, ng, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
     }
     VP_TILE_LOOP_END
   }
   __syncthreads();
-  flush<MODE>(d, sacc, tl.local % d.acc_copies);
+  flush<MODE, TPB>(d, sacc, tl.local % d.acc_copies);
 }
 
 // Kick by `kick` then drift by `drift` with the current field.  With use_pending, the kick of
 // each instance is dt/2 when its half-kick is pending and 0 otherwise, and drift is 0.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_gather_push(const InstDev* __restrict__ insts,
-                                                        const Tile* __restrict__ tiles,
-                                                        int tile0, int ppt, double kick_in,
-                                                        double drift_in, int use_pending) {
+template <int MODE, int TPB>
+__global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__ insts,
+                                                     const Tile* __restrict__ tiles, int tile0,
+                                                     int ppt, double kick_in, double drift_in,
+                                                     int use_pending) {
   extern __shared__ double smem[];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
@@ -512,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(const InstDev* __restric
     drift = 0.0;
   }
   if (kick == 0.0 && drift == 0.0) return;  // uniform per workgroup: no barrier skipped
-  stage<MODE>(d, smem, nullptr, true, false);
+  stage<MODE, TPB>(d, smem, nullptr, true, false);
   T* __restrict__ Qp = static_cast<T*>(d.Q);
   T* __restrict__ Pp = static_cast<T*>(d.P);
   T* __restrict__ qsp = static_cast<T*>(d.qs);
@@ -570,17 +675,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(const InstDev* __restric
 
 // Kinetic diagnostics at the integer step without touching the state: a pending half-kick
 // is applied to local copies only.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_diag(const InstDev* __restrict__ insts,
-                                                 const Tile* __restrict__ tiles, int tile0,
-                                                 int ppt) {
+template <int MODE, int TPB>
+__global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
+                                              const Tile* __restrict__ tiles, int tile0,
+                                              int ppt) {
   extern __shared__ double smem[];
-  __shared__ double red[4];
+  __shared__ double red[TPB / 64];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
   const InstDev& d = insts[tl.inst];
   const int ng = d.ng;
-  stage<MODE>(d, smem, nullptr, true, false);
+  stage<MODE, TPB>(d, smem, nullptr, true, false);
   const T* __restrict__ Qp = static_cast<const T*>(d.Q);
   const T* __restrict__ Pp = static_cast<const T*>(d.P);
   const T* __restrict__ qsp = static_cast<const T*>(d.qs);
@@ -628,9 +733,9 @@ __global__ __launch_bounds__(kBlock) void k_diag(const InstDev* __restrict__ ins
     }
     VP_TILE_LOOP_END
   }
-  const double Kb = block_sum(Ks, red);
-  const double Mb = block_sum(Ms, red);
-  const double Cb = block_sum(Cs, red);
+  const double Kb = block_sum<TPB>(Ks, red);
+  const double Mb = block_sum<TPB>(Ms, red);
+  const double Cb = block_sum<TPB>(Cs, red);
   if (threadIdx.x == 0) {
     unsafeAtomicAdd(&d.scal->Kd, Kb);
     unsafeAtomicAdd(&d.scal->momd, Mb);
@@ -640,13 +745,12 @@ __global__ __launch_bounds__(kBlock) void k_diag(const InstDev* __restrict__ ins
 
 // One workgroup per listed slot: solve and refresh the field summary (no record).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_solve(const InstDev* __restrict__ insts,
-                                                  const int* __restrict__ slots) {
+__global__ __launch_bounds__(256) void k_solve(const InstDev* __restrict__ insts,
+                                               const int* __restrict__ slots) {
   extern __shared__ double smem[];
   __shared__ double red[4];
   const InstDev& d = insts[slots[blockIdx.x]];
-  __threadfence();
-  solve_instance<MODE>(d, smem, smem + d.ng, red, false);
+  solve_instance<MODE, 256>(d, smem, red, false);
 }
 
 __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __restrict__ slots,
@@ -786,52 +890,64 @@ WsLayout workspace_layout(int ng, int hist_cap) {
   return w;
 }
 
-size_t particle_lds_bytes(int /*mode*/, int max_ng) { return (size_t)3 * max_ng * sizeof(double); }
+size_t particle_lds_bytes(int /*mode*/, int max_ng) {
+  return lds_doubles_per_node() * (size_t)max_ng * sizeof(double);
+}
 
-#define VP_DISPATCH(mode, KERNEL, ...)                                                     \
-  do {                                                                                     \
-    if ((mode) == kFP64) hipLaunchKernelGGL(KERNEL<kFP64>, __VA_ARGS__);                   \
-    else if ((mode) == kFP32Comp) hipLaunchKernelGGL(KERNEL<kFP32Comp>, __VA_ARGS__);      \
-    else hipLaunchKernelGGL(KERNEL<kFP32>, __VA_ARGS__);                                   \
+#define VP_DISPATCH(mode, tpb, KERNEL, ...)                                                  \
+  do {                                                                                       \
+    if ((mode) == kFP64) {                                                                   \
+      if ((tpb) == 1024) hipLaunchKernelGGL((KERNEL<kFP64, 1024>), __VA_ARGS__);             \
+      else if ((tpb) == 512) hipLaunchKernelGGL((KERNEL<kFP64, 512>), __VA_ARGS__);          \
+      else hipLaunchKernelGGL((KERNEL<kFP64, 256>), __VA_ARGS__);                            \
+    } else if ((mode) == kFP32Comp) {                                                        \
+      if ((tpb) == 1024) hipLaunchKernelGGL((KERNEL<kFP32Comp, 1024>), __VA_ARGS__);         \
+      else if ((tpb) == 512) hipLaunchKernelGGL((KERNEL<kFP32Comp, 512>), __VA_ARGS__);      \
+      else hipLaunchKernelGGL((KERNEL<kFP32Comp, 256>), __VA_ARGS__);                        \
+    } else {                                                                                 \
+      if ((tpb) == 1024) hipLaunchKernelGGL((KERNEL<kFP32, 1024>), __VA_ARGS__);             \
+      else if ((tpb) == 512) hipLaunchKernelGGL((KERNEL<kFP32, 512>), __VA_ARGS__);          \
+      else hipLaunchKernelGGL((KERNEL<kFP32, 256>), __VA_ARGS__);                            \
+    }                                                                                        \
   } while (0)
 
-hipError_t launch_fused(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_fused, dim3(ntiles), dim3(kBlock), particle_lds_bytes(mode, max_ng), s,
+  VP_DISPATCH(mode, tpb, k_fused, dim3(ntiles), dim3(tpb), particle_lds_bytes(mode, max_ng), s,
               d_inst, d_tiles, tile0, ppt);
   return hipGetLastError();
 }
 
-hipError_t launch_deposit(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_deposit, dim3(ntiles), dim3(kBlock), particle_lds_bytes(mode, max_ng), s,
+  VP_DISPATCH(mode, tpb, k_deposit, dim3(ntiles), dim3(tpb), particle_lds_bytes(mode, max_ng), s,
               d_inst, d_tiles, tile0, ppt);
   return hipGetLastError();
 }
 
-hipError_t launch_gather_push(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                              int ntiles, int ppt, int max_ng, double kick, double drift,
+hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,
+                              int tile0, int ntiles, int ppt, int max_ng, double kick, double drift,
                               hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_gather_push, dim3(ntiles), dim3(kBlock),
+  VP_DISPATCH(mode, tpb, k_gather_push, dim3(ntiles), dim3(tpb),
               (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, kick, drift, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_settle(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_settle(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                          int ntiles, int ppt, int max_ng, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_gather_push, dim3(ntiles), dim3(kBlock),
+  VP_DISPATCH(mode, tpb, k_gather_push, dim3(ntiles), dim3(tpb),
               (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, 0.0, 0.0, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_diag(int mode, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                        int ntiles, int ppt, int max_ng, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_diag, dim3(ntiles), dim3(kBlock), (size_t)2 * max_ng * sizeof(double), s,
+  VP_DISPATCH(mode, tpb, k_diag, dim3(ntiles), dim3(tpb), (size_t)2 * max_ng * sizeof(double), s,
               d_inst, d_tiles, tile0, ppt);
   return hipGetLastError();
 }
@@ -839,8 +955,13 @@ hipError_t launch_diag(int mode, const InstDev* d_inst, const Tile* d_tiles, int
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
                         int max_ng, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
-  VP_DISPATCH(mode, k_solve, dim3(nslots), dim3(kBlock), (size_t)2 * max_ng * sizeof(double), s,
-              d_inst, d_slots);
+  const size_t lds = lds_doubles_per_node() * (size_t)max_ng * sizeof(double);
+  if (mode == kFP64)
+    hipLaunchKernelGGL(k_solve<kFP64>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
+  else if (mode == kFP32Comp)
+    hipLaunchKernelGGL(k_solve<kFP32Comp>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
+  else
+    hipLaunchKernelGGL(k_solve<kFP32>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ def test_workspace_sizing_and_validation(lib):
         assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
         assert b.value % 256 == 0 and b.value >= (L.VP_MAX_ACC_COPIES + 8) * ng * 4
     bad = [dict(ng=12), dict(ng=4), dict(ng=2048), dict(n=0), dict(L=-1.0), dict(dt=0.0),
-           dict(precision=7), dict(sort_chunk=5000), dict(hist_cap=0), dict(reserved=1),
+           dict(precision=7), dict(sort_chunk=5000), dict(hist_cap=0), dict(solver=2),
            dict(L=float("nan")), dict(sort_every=-2)]
     for kw in bad:
         args = dict(n=1000, ng=64, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
