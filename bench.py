@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 METRIC = "decorated-particle updates/s (1 GPU, % HBM roofline); served p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle per fused step: read Q, P, q*, p*, psi*; write Q, P, q*, p*
-FUSED_BYTES = {"fp64": 72, "fp32c": 36, "fp32": 36}
+FUSED_BYTES = {"fp64": 72, "fp32c": 36, "fp32": 36, "fp32ts": 36}
 
 
 def log(*a):
@@ -118,7 +118,8 @@ def main():
     log(f"initial state built in {time.perf_counter() - t0:.1f} s")
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()          # a non-null stream, so steps can be graph-captured
+    torch.cuda.set_stream(stream)
     sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8))
     tuning_us = None
     if not args.no_tune:

@@ -16,7 +16,7 @@
  *     particle arrays and workspaces are borrowed from vp_create / vp_admit until
  *     vp_destroy / vp_retire and must stay allocated and untouched by other work until then.
  *   - Particle arrays are five separate contiguous arrays (structure of arrays) of n
- *     elements each, float64 for VP_FP64 and float32 for VP_FP32_COMP and VP_FP32.
+ *     elements each, float64 for VP_FP64 and float32 for the three float32 modes.
  *     Positions must lie in [0, L) on entry; psi* is never written.
  *   - Work is enqueued asynchronously on the stream given at creation (a hipStream_t
  *     passed as void*, NULL for the null stream) unless a function says it synchronises.
@@ -39,7 +39,7 @@ extern "C" {
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
 #define VP_MAX_SORT_CHUNK_F64 2048 /* particles per sorted chunk, float64 state */
-#define VP_MAX_ACC_COPIES 32       /* spread copies of the global load accumulator */
+#define VP_MAX_ACC_COPIES 8        /* spread copies of the global load accumulator */
 #define VP_MAX_SLOTS 65536
 
 typedef enum vp_status {
@@ -52,12 +52,17 @@ typedef enum vp_status {
 } vp_status;
 
 typedef enum vp_precision {
-  VP_FP64 = 0,       /* float64 state; float64 loads accumulated in LDS and globally      */
-  VP_FP32_COMP = 1,  /* float32 state; per-particle arithmetic in float64; each nodal load
-                        summed in LDS as a float32 (hi, lo) pair updated by a two-sum under a
-                        64-bit compare-and-swap; block totals added in float64            */
-  VP_FP32 = 2        /* float32 state, float32 arithmetic and float32 accumulation
-                        (naive reference for the precision study)                         */
+  VP_FP64 = 0,         /* float64 state; float64 loads accumulated in LDS and globally     */
+  VP_FP32_COMP = 1,    /* float32 state; per-particle arithmetic in float64; nodal loads
+                          accumulated in float64 (LDS atomics, then global atomics), so the
+                          sum carries the low-order bits a float32 two-sum would keep in its
+                          error word (float64 LDS atomics are the fast ones on gfx950)    */
+  VP_FP32 = 2,         /* float32 state, float32 arithmetic and float32 accumulation
+                          (naive reference for the precision study)                        */
+  VP_FP32_TWOSUM = 3   /* float32 state; per-particle arithmetic in float64; each nodal load
+                          kept in LDS as a float32 (hi, lo) pair updated by a two-sum under a
+                          64-bit compare-and-swap; block totals added in float64.  Slower
+                          when many lanes of a wavefront hit one node (retries serialise). */
 } vp_precision;
 /* In every mode the neutralising mean subtraction, the Poisson solve and all
  * diagnostics (K, W, H, charge, momentum) are computed in float64 on the GPU. */
@@ -107,7 +112,7 @@ typedef struct vp_diag {
 typedef struct vp_tuning {
   int32_t threads;      /* threads per workgroup of the particle kernels: 256, 512 or 1024 */
   int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 */
-  int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..32 */
+  int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..8 */
   int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
   int32_t graph_steps;  /* steps per captured graph, 1..256 */
 } vp_tuning;

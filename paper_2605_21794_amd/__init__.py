@@ -22,7 +22,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import VPError  # noqa: F401
 
-PRECISIONS = {"fp64": L.VP_FP64, "fp32c": L.VP_FP32_COMP, "fp32": L.VP_FP32}
+PRECISIONS = {"fp64": L.VP_FP64, "fp32c": L.VP_FP32_COMP, "fp32": L.VP_FP32,
+              "fp32ts": L.VP_FP32_TWOSUM}
 FIELDS = ("Q", "P", "qs", "ps", "psi")
 
 

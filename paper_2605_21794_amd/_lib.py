@@ -9,11 +9,11 @@ from ctypes import (POINTER, Structure, c_char_p, c_double, c_int32, c_int64, c_
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
-VP_FP64, VP_FP32_COMP, VP_FP32 = 0, 1, 2
+VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_MIN_NG, VP_MAX_NG = 8, 1024
 VP_MAX_SORT_CHUNK_F32, VP_MAX_SORT_CHUNK_F64 = 4096, 2048
-VP_MAX_ACC_COPIES = 32
+VP_MAX_ACC_COPIES = 8
 
 
 class vp_config(Structure):

@@ -53,7 +53,7 @@ vp_status validate(const vp_config* c) {
   if (c->n < 1 || c->n > (int64_t)1 << 40) return fail(VP_ERR_ARG, "n = %lld out of range", (long long)c->n);
   if (!is_pow2(c->ng) || c->ng < VP_MIN_NG || c->ng > VP_MAX_NG)
     return fail(VP_ERR_ARG, "ng = %d must be a power of two in [%d, %d]", c->ng, VP_MIN_NG, VP_MAX_NG);
-  if (c->precision < VP_FP64 || c->precision > VP_FP32) return fail(VP_ERR_ARG, "bad precision %d", c->precision);
+  if (c->precision < VP_FP64 || c->precision > VP_FP32_TWOSUM) return fail(VP_ERR_ARG, "bad precision %d", c->precision);
   if (!(c->L > 0.0) || !std::isfinite(c->L)) return fail(VP_ERR_ARG, "L must be positive and finite");
   if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(VP_ERR_ARG, "dt must be positive and finite");
   if (c->sort_every < 0) return fail(VP_ERR_ARG, "sort_every < 0");
@@ -94,7 +94,7 @@ struct vp_handle {
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   int max_ng = VP_MIN_NG;
-  vp_tuning tun{1024, 4, 8, 1, 32};
+  vp_tuning tun{1024, 4, 4, 1, 32};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_len = 0;
@@ -249,7 +249,7 @@ vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out) {
 vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream, vp_handle** out) {
   if (!out) return fail(VP_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (precision < VP_FP64 || precision > VP_FP32) return fail(VP_ERR_ARG, "bad precision %d", precision);
+  if (precision < VP_FP64 || precision > VP_FP32_TWOSUM) return fail(VP_ERR_ARG, "bad precision %d", precision);
   if (max_slots < 1 || max_slots > VP_MAX_SLOTS) return fail(VP_ERR_ARG, "max_slots = %d out of range", max_slots);
   vp_handle* h = new vp_handle();
   h->precision = precision;
@@ -653,7 +653,7 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   std::vector<Cand> cands;
   for (int th : {256, 1024})
     for (int pp : {1, 2, 4, 8})
-      for (int ac : {1, 8, 32}) cands.push_back({th, pp, ac});
+      for (int ac : {1, 4, 8}) cands.push_back({th, pp, ac});
   vp_status st = VP_OK;
   for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
     {

@@ -11,7 +11,7 @@ namespace vpk {
 constexpr int kBlock = 256;      // threads per workgroup for every particle kernel
 constexpr int kHistFields = 10;  // doubles per diagnostic record (layout of vp_diag)
 
-enum Mode { kFP64 = 0, kFP32Comp = 1, kFP32 = 2 };
+enum Mode { kFP64 = 0, kFP32Comp = 1, kFP32 = 2, kFP32TwoSum = 3 };
 
 // Per-instance scalars living in the instance workspace.
 struct InstScal {

@@ -25,6 +25,35 @@ namespace vpk {
 template <int MODE> struct StateType { using T = double; };
 template <> struct StateType<kFP32Comp> { using T = float; };
 template <> struct StateType<kFP32> { using T = float; };
+template <> struct StateType<kFP32TwoSum> { using T = float; };
+
+// Global-memory pointers are spelled in address space 1: pointers read out of the instance
+// table would otherwise be generic, and generic (flat) accesses count against the LDS wait
+// counter too, so every LDS wait would also drain the in-flight particle traffic.
+#define VPG __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ VPG T* gp(void* p) { return (VPG T*)p; }
+template <typename T>
+__device__ __forceinline__ VPG T* gp(T* p) { return (VPG T*)p; }
+// device-scope (all XCDs) atomics and coherent loads / stores
+__device__ __forceinline__ void gadd(VPG double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd(VPG float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double gld(VPG double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float gld(VPG float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst(VPG double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst(VPG float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Element index of x = Q * Ng / L: floor, clamped to [0, Ng-1] (NaN maps to 0), so an LDS
 // index is always in range whatever the state holds.
@@ -68,45 +97,6 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// In-place inclusive prefix sum of x[0..n) (n <= 4 * TPB) by the whole workgroup; `red`
-// holds at least TPB/64 doubles.  Deterministic.
-template <int TPB>
-__device__ void block_scan(double* x, int n, double* red) {
-  const int tid = threadIdx.x;
-  const int per = (n + TPB - 1) / TPB;  // <= 4
-  const int j0 = tid * per;
-  double loc[4];
-  double run = 0.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k < per) {
-      const int j = j0 + k;
-      run += (j < n) ? x[j] : 0.0;
-      loc[k] = run;
-    }
-  }
-  double incl = run;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double y = __shfl_up(incl, off, 64);
-    if ((tid & 63) >= off) incl += y;
-  }
-  __syncthreads();
-  if ((tid & 63) == 63) red[tid >> 6] = incl;
-  __syncthreads();
-  double before = 0.0;
-  for (int w = 0; w < (tid >> 6); ++w) before += red[w];
-  const double excl = before + incl - run;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k < per) {
-      const int j = j0 + k;
-      if (j < n) x[j] = excl + loc[k];
-    }
-  }
-  __syncthreads();
-}
-
 // ------------------------------------------------------------------ LDS layout
 // [0, 2*Ng) doubles: field E then g (float copies for kFP32); [2*Ng, 3*Ng): accumulator
 // (Ng doubles / Ng packed float (hi, lo) pairs / Ng floats).  The solve reuses [0, 4*Ng).
@@ -119,14 +109,18 @@ __device__ void stage(const InstDev& d, double* fld, double* sacc, bool need_fie
   if (need_field) {
     if constexpr (MODE == kFP32) {
       float* f = reinterpret_cast<float*>(fld);
+      const VPG float* Ef = gp(d.Ef);
+      const VPG float* gf = gp(d.gf);
       for (int j = threadIdx.x; j < ng; j += TPB) {
-        f[j] = d.Ef[j];
-        f[ng + j] = d.gf[j];
+        f[j] = Ef[j];
+        f[ng + j] = gf[j];
       }
     } else {
+      const VPG double* E = gp(d.E);
+      const VPG double* g = gp(d.g);
       for (int j = threadIdx.x; j < ng; j += TPB) {
-        fld[j] = d.E[j];
-        fld[ng + j] = d.g[j];
+        fld[j] = E[j];
+        fld[ng + j] = g[j];
       }
     }
   }
@@ -138,7 +132,7 @@ __device__ void stage(const InstDev& d, double* fld, double* sacc, bool need_fie
 // Add the nodal contribution c into the LDS grid.
 template <int MODE>
 __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
-  if constexpr (MODE == kFP64) {
+  if constexpr (MODE == kFP64 || MODE == kFP32Comp) {
     atomicAdd(sacc + j, c);
   } else {
     // float32 (hi, lo) pair packed in one 64-bit word: c = ch + cl exactly (to float64
@@ -148,7 +142,7 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
     unsigned long long* w = reinterpret_cast<unsigned long long*>(sacc) + j;
     const float ch = (float)c;
     const float cl = (float)(c - (double)ch);
-    unsigned long long old = *reinterpret_cast<volatile unsigned long long*>(w);
+    unsigned long long old = *w;  // first guess; the compare-and-swap validates it
     while (true) {
       const float hi = __uint_as_float((unsigned)(old & 0xffffffffull));
       const float lo = __uint_as_float((unsigned)(old >> 32));
@@ -172,25 +166,25 @@ __device__ void flush(const InstDev& d, const double* sacc, int copy) {
   const int ng = d.ng;
   if constexpr (MODE == kFP32) {
     const float* a = reinterpret_cast<const float*>(sacc);
-    float* gacc = reinterpret_cast<float*>(d.acc) + (size_t)copy * ng;
+    VPG float* gacc = gp<float>(d.acc) + (size_t)copy * ng;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const float v = a[j];
-      if (v != 0.0f) unsafeAtomicAdd(gacc + j, v);
+      if (v != 0.0f) gadd(gacc + j, v);
     }
-  } else if constexpr (MODE == kFP32Comp) {
+  } else if constexpr (MODE == kFP32TwoSum) {
     const unsigned long long* wv = reinterpret_cast<const unsigned long long*>(sacc);
-    double* gacc = d.acc + (size_t)copy * ng;
+    VPG double* gacc = gp(d.acc) + (size_t)copy * ng;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const unsigned long long w = wv[j];
       const double v = (double)__uint_as_float((unsigned)(w & 0xffffffffull)) +
                        (double)__uint_as_float((unsigned)(w >> 32));
-      if (v != 0.0) unsafeAtomicAdd(gacc + j, v);
+      if (v != 0.0) gadd(gacc + j, v);
     }
   } else {
-    double* gacc = d.acc + (size_t)copy * ng;
+    VPG double* gacc = gp(d.acc) + (size_t)copy * ng;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const double v = sacc[j];
-      if (v != 0.0) unsafeAtomicAdd(gacc + j, v);
+      if (v != 0.0) gadd(gacc + j, v);
     }
   }
 }
@@ -204,7 +198,8 @@ __device__ bool arrive(const InstDev& d, int* sflag) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(&d.scal->ticket, 1u, __ATOMIC_RELAXED,
+    VPG InstScal* sc = gp(d.scal);
+    const unsigned prev = __hip_atomic_fetch_add(&sc->ticket, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     *sflag = (prev + 1u == (unsigned)d.ntiles) ? 1 : 0;
   }
@@ -212,22 +207,56 @@ __device__ bool arrive(const InstDev& d, int* sflag) {
   return *sflag != 0;
 }
 
-__device__ __forceinline__ double ld_agent(double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ------------------------------------------------------------------ Poisson solve
-// Radix-2 FFT on (re, im) in LDS, input in bit-reversed order; tw in LDS holds
-// cos/sin(2 pi k / Ng) for k < Ng/2.
-template <int TPB>
-__device__ void fft_lds(double* re, double* im, int ng, int m, const double* tw, bool inverse) {
+// The solve runs on ONE wavefront (64 lanes) so that it needs no workgroup barrier: lane l
+// owns the contiguous nodes [l*per, (l+1)*per), per = ceil(Ng / 64), and cross-lane sums and
+// scans go through shuffles.  LDS traffic between lanes stays inside the wavefront, whose
+// LDS operations execute in issue order.
+
+// Wavefront collectives built from DPP row moves (VALU, no LDS round trip): a 64-lane
+// inclusive scan is row_shr 1, 2, 4, 8 inside each 16-lane row, then row_bcast 15 and 31
+// carry the row totals upward.  Out-of-row sources read as zero.  Every lane must be
+// active.  The order of additions is fixed, so results do not depend on timing.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_incl_scan(double x) {
+  x += dpp_move<0x111, 0xf, true>(x);   // row_shr:1
+  x += dpp_move<0x112, 0xf, true>(x);   // row_shr:2
+  x += dpp_move<0x114, 0xf, true>(x);   // row_shr:4
+  x += dpp_move<0x118, 0xf, true>(x);   // row_shr:8
+  x += dpp_move<0x142, 0xa, false>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_move<0x143, 0xc, false>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ double wave_bcast63(double x) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes; every lane gets the same total.
+__device__ __forceinline__ double wave_sum(double v) { return wave_bcast63(wave_incl_scan(v)); }
+
+// Exclusive prefix over lanes of one value per lane.
+__device__ __forceinline__ double wave_excl_scan(double v, int /*lane*/) {
+  return wave_incl_scan(v) - v;
+}
+
+// Radix-2 FFT by one wavefront on (re, im) in LDS, input in bit-reversed order; tw holds
+// cos/sin(2 pi k / Ng) for k < Ng/2 (LDS).
+__device__ void fft_wave(double* re, double* im, int ng, int m, const double* tw, bool inverse,
+                         int lane) {
   for (int s = 1; s <= m; ++s) {
     const int half = 1 << (s - 1);
     const int tstride = ng >> s;
-    for (int b = threadIdx.x; b < (ng >> 1); b += TPB) {
+    for (int b = lane; b < (ng >> 1); b += 64) {
       const int pos = b & (half - 1);
       const int i0 = ((b >> (s - 1)) << s) + pos;
       const int i1 = i0 + half;
@@ -243,13 +272,12 @@ __device__ void fft_lds(double* re, double* im, int ng, int m, const double* tw,
       re[i1] = ur - tr;
       im[i1] = ui - ti;
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-template <int TPB>
-__device__ void bit_reverse_lds(double* re, double* im, int ng, int m) {
-  for (int j = threadIdx.x; j < ng; j += TPB) {
+__device__ void bit_reverse_wave(double* re, double* im, int ng, int m, int lane) {
+  for (int j = lane; j < ng; j += 64) {
     const int r = (int)(__brev((unsigned)j) >> (32 - m));
     if (j < r) {
       double t = re[j];
@@ -260,10 +288,11 @@ __device__ void bit_reverse_lds(double* re, double* im, int ng, int m) {
       im[r] = t;
     }
   }
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Solve for one instance with one workgroup, in LDS (4*Ng doubles at `sm`):
+// Solve for one instance by one workgroup, LDS scratch of 4*Ng doubles at `sm` plus
+// kSolveScal doubles at `ss`:
 //   b_j   = sum of the accumulator copies (then cleared);
 //   b~_j  = b_j - mean(b)                                  (float64, eq. neutrality);
 //   E, Phi from A Phi = b~, 1^T Phi = 0                     (scan or FFT);
@@ -272,144 +301,222 @@ __device__ void bit_reverse_lds(double* re, double* im, int ng, int m) {
 //   W     = (1/2) h sum_e E_e^2;  E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng).
 // With `record`, first write the record of the integer step whose particle pass just ran
 // (kinetic sums of the pass + the field summary of the previous solve) and advance.
-template <int MODE, int TPB>
-__device__ void solve_instance(const InstDev& d, double* sm, double* red, bool record) {
-  const int ng = d.ng, mask = ng - 1;
-  const int tid = threadIdx.x;
-  double* bt = sm;            // b~ (kept)
-  double* E = sm + ng;        // E
-  double* ph = sm + 2 * ng;   // scratch: prefix sums / FFT re
-  double* aux = sm + 3 * ng;  // scratch: FFT im
+// Three phases: every thread loads (one memory round trip), wavefront 0 computes in LDS
+// without workgroup barriers, every thread stores.  All threads of the workgroup call it.
+constexpr int kSolveScal = 9;
 
-  for (int j = tid; j < ng; j += TPB) {
-    double b = 0.0;
-    for (int c = 0; c < d.acc_copies; ++c) {
-      if constexpr (MODE == kFP32) {
-        float* a = reinterpret_cast<float*>(d.acc) + (size_t)c * ng + j;
-        b += (double)__hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        double* a = d.acc + (size_t)c * ng + j;
-        b += ld_agent(a);
-        st_agent(a, 0.0);
+template <int MODE, int TPB>
+__device__ __forceinline__ void solve_block(const InstDev& d, double* sm, double* ss, bool record) {
+  const int ng = d.ng, mask = ng - 1, halfn = ng >> 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  double* bt = sm;            // b, then b~
+  double* tw = sm + ng;       // cos / sin (2 pi t / Ng), t < Ng/2, interleaved
+  double* re = sm + 2 * ng;   // prefix sums / FFT real part, then Phi
+  double* im = sm + 3 * ng;   // FFT imaginary part, then E
+  double* E = im;
+  const int copies = d.acc_copies;
+  VPG InstScal* sc = gp(d.scal);
+
+  // ---- phase 1: loads (and clearing of the accumulators)
+  {
+    const VPG double* tw_g = gp(d.tw);
+    for (int j = tid; j < ng; j += TPB) {
+      double t[VP_MAX_ACC_COPIES];
+#pragma unroll
+      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) {
+        t[c] = 0.0;
+        if (c < copies) {
+          if constexpr (MODE == kFP32)
+            t[c] = (double)gld(gp<float>(d.acc) + (size_t)c * ng + j);
+          else
+            t[c] = gld(gp(d.acc) + (size_t)c * ng + j);
+        }
+      }
+      double b = 0.0;
+#pragma unroll
+      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) b += t[c];
+      bt[j] = b;
+      tw[j] = tw_g[j];
+      for (int c = 0; c < copies; ++c) {
+        if constexpr (MODE == kFP32)
+          gst(gp<float>(d.acc) + (size_t)c * ng + j, 0.0f);
+        else
+          gst(gp(d.acc) + (size_t)c * ng + j, 0.0);
       }
     }
-    bt[j] = b;
+    if (record && tid == 0) {
+      ss[0] = gld(&sc->K);
+      ss[1] = gld(&sc->mom);
+      ss[2] = gld(&sc->chg);
+      ss[3] = sc->W;
+      ss[4] = sc->e1r;
+      ss[5] = sc->e1i;
+    }
   }
   __syncthreads();
-  double part = 0.0;
-  for (int j = tid; j < ng; j += TPB) part += bt[j];
-  const double mean = block_sum<TPB>(part, red) / (double)ng;
-  for (int j = tid; j < ng; j += TPB) {
-    const double v = bt[j] - mean;
-    bt[j] = v;
-    d.bt[j] = v;
+
+  // ---- phase 2: wavefront 0 solves (lane l owns nodes [l*per, l*per + cnt), in registers)
+  if (tid < 64) {
+    constexpr int kMaxPer = VP_MAX_NG / 64;
+    const int per = (ng + 63) / 64;
+    const int j0 = lane * per;
+    const int cnt = (j0 < ng) ? min(per, ng - j0) : 0;
+    const double h = d.h, inv_h = d.inv_h;
+    double x[kMaxPer], Ev[kMaxPer];
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+      x[k] = (k < cnt) ? bt[j0 + k] : 0.0;
+      part += x[k];
+    }
+    const double mean = wave_sum(part) / (double)ng;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k)
+      if (k < cnt) {
+        x[k] = x[k] - mean;
+        bt[j0 + k] = x[k];
+      }
+    if (d.solver == VP_SOLVE_FFT) {
+      __builtin_amdgcn_wave_barrier();
+      const int m = d.log2ng;
+      for (int j = lane; j < ng; j += 64) {
+        re[j] = bt[j];
+        im[j] = 0.0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      bit_reverse_wave(re, im, ng, m, lane);
+      fft_wave(re, im, ng, m, tw, false, lane);
+      const VPG double* il_g = gp(d.inv_lam);
+      for (int k = lane; k < ng; k += 64) {
+        const double il = il_g[k];
+        re[k] = re[k] * il;
+        im[k] = im[k] * il;
+      }
+      __builtin_amdgcn_wave_barrier();
+      bit_reverse_wave(re, im, ng, m, lane);
+      fft_wave(re, im, ng, m, tw, true, lane);
+      const double inv_ng = 1.0 / (double)ng;
+      for (int j = lane; j < ng; j += 64) re[j] = re[j] * inv_ng;  // Phi
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) {
+          const int e = j0 + k;
+          Ev[k] = -(re[(e + 1) & mask] - re[e]) * inv_h;
+        }
+    } else {
+      // Gauss law: E_e = C + sum_{j=1..e} b~_j with C such that sum_e E_e = 0; then
+      // Phi_e = Phi_0 - h sum_{k<e} E_k with sum_j Phi_j = 0.
+      double run = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) {
+          run += (j0 + k == 0) ? 0.0 : x[k];
+          Ev[k] = run;
+        }
+      const double off = wave_excl_scan(run, lane);
+      double tp = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) {
+          Ev[k] = Ev[k] + off;
+          tp += Ev[k];
+        }
+      const double C = -wave_sum(tp) / (double)ng;
+      double run2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) {
+          Ev[k] = Ev[k] + C;
+          x[k] = run2;  // exclusive prefix of E within the lane
+          run2 += Ev[k];
+        }
+      const double off2 = wave_excl_scan(run2, lane);
+      double up = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) {
+          x[k] = x[k] + off2;
+          up += x[k];
+        }
+      const double Um = wave_sum(up) / (double)ng;
+#pragma unroll
+      for (int k = 0; k < kMaxPer; ++k)
+        if (k < cnt) re[j0 + k] = -h * (x[k] - Um);  // Phi
+    }
+    double wpart = 0.0, e1r = 0.0, e1i = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k)
+      if (k < cnt) {
+        const int e = j0 + k;
+        const double Ee = Ev[k];
+        E[e] = Ee;
+        wpart += Ee * Ee;
+        const int t = e & (halfn - 1);
+        const double sg = (e < halfn) ? 1.0 : -1.0;  // cos/sin of theta + pi
+        e1r += Ee * (sg * tw[2 * t]);
+        e1i -= Ee * (sg * tw[2 * t + 1]);
+      }
+    const double Wn = 0.5 * h * wave_sum(wpart);
+    const double E1r = wave_sum(e1r) / (double)ng;
+    const double E1i = wave_sum(e1i) / (double)ng;
+    if (lane == 0) {
+      ss[6] = Wn;
+      ss[7] = E1r;
+      ss[8] = E1i;
+    }
   }
   __syncthreads();
 
-  const double h = d.h, inv_h = d.inv_h;
-  if (d.solver == VP_SOLVE_FFT) {
-    // Phi = IFFT(FFT(b~) / lambda); E_e = -(Phi_{e+1} - Phi_e) / h.  The twiddles and the
-    // inverse eigenvalues are staged in LDS (E and the field region serve as buffers).
-    const int m = d.log2ng;
-    double* re = ph;
-    double* im = aux;
-    double* tw = E;  // Ng doubles: Ng/2 (cos, sin) pairs
-    for (int j = tid; j < ng; j += TPB) {
-      re[j] = bt[j];
-      im[j] = 0.0;
-      tw[j] = d.tw[j];
+  // ---- phase 3: stores
+  {
+    VPG double* bt_g = gp(d.bt);
+    VPG double* E_g = gp(d.E);
+    VPG double* g_g = gp(d.g);
+    VPG double* Phi_g = gp(d.Phi);
+    VPG float* Ef_g = gp(d.Ef);
+    VPG float* gf_g = gp(d.gf);
+    const double half_inv_h = 0.5 * d.inv_h;
+    for (int e = tid; e < ng; e += TPB) {
+      const double Ee = E[e];
+      const double b0 = bt[e];
+      const double g = -(b0 + bt[(e + 1) & mask]) * half_inv_h;
+      bt_g[e] = b0;
+      E_g[e] = Ee;
+      Ef_g[e] = (float)Ee;
+      g_g[e] = g;
+      gf_g[e] = (float)g;
+      Phi_g[e] = re[e];
     }
-    __syncthreads();
-    bit_reverse_lds<TPB>(re, im, ng, m);
-    fft_lds<TPB>(re, im, ng, m, tw, false);
-    for (int k = tid; k < ng; k += TPB) {
-      const double il = d.inv_lam[k];
-      re[k] = re[k] * il;
-      im[k] = im[k] * il;
+    if (tid == 0) {
+      const double Wn = ss[6];
+      if (record) {
+        const long long step = sc->step;
+        const double K = ss[0], mom = ss[1], chg = ss[2], Wold = ss[3];
+        VPG double* r = gp(d.hist) + (size_t)(step % d.hist_cap) * kHistFields;
+        r[0] = (double)step;
+        r[1] = (double)step * d.dt;
+        r[2] = K;
+        r[3] = Wold;
+        r[4] = K + Wold;
+        r[5] = chg;
+        r[6] = mom;
+        r[7] = sqrt(2.0 * Wold / d.L);
+        r[8] = ss[4];
+        r[9] = ss[5];
+        if (!isfinite(K) || !isfinite(Wold)) sc->nonfinite = 1;
+        gst(&sc->K, 0.0);
+        gst(&sc->mom, 0.0);
+        gst(&sc->chg, 0.0);
+        sc->step = step + 1;
+        sc->pending = 1;
+      }
+      sc->W = Wn;
+      sc->e1r = ss[7];
+      sc->e1i = ss[8];
+      if (!isfinite(Wn)) sc->nonfinite = 1;
+      __hip_atomic_store(&sc->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    bit_reverse_lds<TPB>(re, im, ng, m);
-    fft_lds<TPB>(re, im, ng, m, tw, true);
-    const double inv_ng = 1.0 / (double)ng;
-    for (int j = tid; j < ng; j += TPB) {
-      const double phi = re[j] * inv_ng;
-      re[j] = phi;
-      d.Phi[j] = phi;
-    }
-    __syncthreads();
-    for (int e = tid; e < ng; e += TPB) E[e] = -(re[(e + 1) & mask] - re[e]) * inv_h;
-    __syncthreads();
-  } else {
-    // Gauss law: E_e = C + sum_{j=1..e} b~_j with sum_e E_e = 0.
-    for (int j = tid; j < ng; j += TPB) ph[j] = (j == 0) ? 0.0 : bt[j];
-    __syncthreads();
-    block_scan<TPB>(ph, ng, red);
-    double tp = 0.0;
-    for (int j = tid; j < ng; j += TPB) tp += ph[j];
-    const double C = -block_sum<TPB>(tp, red) / (double)ng;
-    for (int e = tid; e < ng; e += TPB) E[e] = C + ph[e];
-    __syncthreads();
-    // Phi_e = Phi_0 - h sum_{k<e} E_k with sum_j Phi_j = 0.
-    for (int j = tid; j < ng; j += TPB) ph[j] = (j == 0) ? 0.0 : E[j - 1];
-    __syncthreads();
-    block_scan<TPB>(ph, ng, red);
-    double up = 0.0;
-    for (int j = tid; j < ng; j += TPB) up += ph[j];
-    const double U = block_sum<TPB>(up, red) / (double)ng;
-    for (int j = tid; j < ng; j += TPB) d.Phi[j] = -h * (ph[j] - U);
-  }
-
-  double wpart = 0.0, e1r = 0.0, e1i = 0.0;
-  for (int e = tid; e < ng; e += TPB) {
-    const double Ee = E[e];
-    d.E[e] = Ee;
-    d.Ef[e] = (float)Ee;
-    const double g = -(bt[e] + bt[(e + 1) & mask]) * (0.5 * inv_h);
-    d.g[e] = g;
-    d.gf[e] = (float)g;
-    wpart += Ee * Ee;
-    double sn, cs;
-    sincospi(2.0 * (double)e / (double)ng, &sn, &cs);
-    e1r += Ee * cs;
-    e1i -= Ee * sn;
-  }
-  const double Wsum = block_sum<TPB>(wpart, red);
-  const double E1r = block_sum<TPB>(e1r, red) / (double)ng;
-  const double E1i = block_sum<TPB>(e1i, red) / (double)ng;
-  const double Wn = 0.5 * h * Wsum;
-
-  if (tid == 0) {
-    InstScal* sc = d.scal;
-    if (record) {
-      const long long st = sc->step;
-      double* r = d.hist + (size_t)(st % d.hist_cap) * kHistFields;
-      const double K = ld_agent(&sc->K);
-      const double mom = ld_agent(&sc->mom);
-      const double chg = ld_agent(&sc->chg);
-      const double W = sc->W;
-      r[0] = (double)st;
-      r[1] = (double)st * d.dt;
-      r[2] = K;
-      r[3] = W;
-      r[4] = K + W;
-      r[5] = chg;
-      r[6] = mom;
-      r[7] = sqrt(2.0 * W / d.L);
-      r[8] = sc->e1r;
-      r[9] = sc->e1i;
-      if (!isfinite(K) || !isfinite(W)) sc->nonfinite = 1;
-      st_agent(&sc->K, 0.0);
-      st_agent(&sc->mom, 0.0);
-      st_agent(&sc->chg, 0.0);
-      sc->step = st + 1;
-      sc->pending = 1;
-    }
-    sc->W = Wn;
-    sc->e1r = E1r;
-    sc->e1i = E1i;
-    if (!isfinite(Wn)) sc->nonfinite = 1;
-    __hip_atomic_store(&sc->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -430,117 +537,136 @@ __device__ void solve_instance(const InstDev& d, double* sm, double* red, bool r
 
 // One fused step for every tile: [pending half-kick] -> kinetic sums at the integer step
 // -> half-kick -> drift -> deposit of the drifted state -> (last workgroup) solve.
+// Thread t handles particles tile.begin + k * TPB + t, k < ppt, kGroup at a time with all
+// loads of a group issued before any use; the first group is in flight while the field is
+// staged in LDS.
+constexpr int kGroup = 4;
+
 template <int MODE, int TPB>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
                                                int ppt) {
   extern __shared__ double smem[];
-  __shared__ double red[TPB / 64];
+  __shared__ double red[3 * (TPB / 64)];
+  __shared__ double ss[kSolveScal];
   __shared__ int sflag;
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
   const InstDev& d = insts[tl.inst];
   const int ng = d.ng;
+  VPG T* __restrict__ Qp = gp<T>(d.Q);
+  VPG T* __restrict__ Pp = gp<T>(d.P);
+  VPG T* __restrict__ qsp = gp<T>(d.qs);
+  VPG T* __restrict__ psp = gp<T>(d.ps);
+  const VPG T* __restrict__ psip = gp<T>(d.psi);
   double* fld = smem;
   double* sacc = smem + 2 * ng;
-  stage<MODE, TPB>(d, fld, sacc, true, true);
-  const int pend = d.scal->pending;
-  T* __restrict__ Qp = static_cast<T*>(d.Q);
-  T* __restrict__ Pp = static_cast<T*>(d.P);
-  T* __restrict__ qsp = static_cast<T*>(d.qs);
-  T* __restrict__ psp = static_cast<T*>(d.ps);
-  const T* __restrict__ psip = static_cast<const T*>(d.psi);
   double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+  int pend = 0;
 
-  if constexpr (MODE == kFP32) {
-    const float* fE = reinterpret_cast<const float*>(fld);
-    const float* fG = fE + ng;
-    float* fa = reinterpret_cast<float*>(sacc);
-    const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
-    VP_TILE_LOOP_BEGIN
-    float q[4], p[4], a[4], b[4], w[4];
+  for (int k0 = 0; k0 < ppt; k0 += kGroup) {
+    T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
+    long long idx[kGroup];
+    bool v[kGroup];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kGroup; ++u) {
+      const int loc = (k0 + u) * TPB + (int)threadIdx.x;
+      v[u] = (k0 + u < ppt) && (loc < tl.count);
+      idx[u] = tl.begin + loc;
       if (v[u]) {
         q[u] = Qp[idx[u]]; p[u] = Pp[idx[u]]; a[u] = qsp[idx[u]]; b[u] = psp[idx[u]];
         w[u] = psip[idx[u]];
       }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!v[u]) continue;
-      float Q = q[u], P = p[u], qs = a[u], ps = b[u];
-      const float psi = w[u];
-      const int i = cell_of_f(Q * ihf, ng);
-      const float Ei = fE[i], gi = fG[i];
-      if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
-      const double Pd = P, qd = qs, wd = psi;
-      Ks += 0.5 * wd * Pd * Pd + qd * Pd;
-      Ms += wd * Pd + qd;
-      Cs += wd;
-      P = P + hf * Ei;
-      qs = qs + hf * ps * gi;
-      float Qn = Q + dtf * P;
-      if (Qn < 0.0f) Qn += Lf;
-      if (Qn >= Lf) Qn -= Lf;
-      ps = ps - dtf * qs;
-      Qp[idx[u]] = Qn; Pp[idx[u]] = P; qsp[idx[u]] = qs; psp[idx[u]] = ps;
-      const float x = Qn * ihf;
-      const int j = cell_of_f(x, ng);
-      const float s = frac01_f(x, j);
-      atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
-      atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
     }
-    VP_TILE_LOOP_END
-  } else {
-    const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
-    VP_TILE_LOOP_BEGIN
-    T q[4], p[4], a[4], b[4], w[4];
+    if (k0 == 0) {  // the field is staged while the first group's loads are in flight
+      stage<MODE, TPB>(d, fld, sacc, true, true);
+      pend = gp(d.scal)->pending;
+    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (v[u]) {
-        q[u] = Qp[idx[u]]; p[u] = Pp[idx[u]]; a[u] = qsp[idx[u]]; b[u] = psp[idx[u]];
-        w[u] = psip[idx[u]];
+    for (int u = 0; u < kGroup; ++u) {
+      if (!v[u]) continue;
+      if constexpr (MODE == kFP32) {
+        const float* fE = reinterpret_cast<const float*>(fld);
+        const float* fG = fE + ng;
+        float* fa = reinterpret_cast<float*>(sacc);
+        const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
+        float Q = q[u], P = p[u], qs = a[u], ps = b[u];
+        const float psi = w[u];
+        const int i = cell_of_f(Q * ihf, ng);
+        const float Ei = fE[i], gi = fG[i];
+        if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
+        const double Pd = P, qd = qs, wd = psi;
+        Ks += 0.5 * wd * Pd * Pd + qd * Pd;
+        Ms += wd * Pd + qd;
+        Cs += wd;
+        P = P + hf * Ei;
+        qs = qs + hf * ps * gi;
+        float Qn = Q + dtf * P;
+        if (Qn < 0.0f) Qn += Lf;
+        if (Qn >= Lf) Qn -= Lf;
+        ps = ps - dtf * qs;
+        Qp[idx[u]] = Qn; Pp[idx[u]] = P; qsp[idx[u]] = qs; psp[idx[u]] = ps;
+        const float x = Qn * ihf;
+        const int j = cell_of_f(x, ng);
+        const float s = frac01_f(x, j);
+        atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
+        atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
+      } else {
+        const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
+        const double Q = q[u], psi = w[u];
+        double P = p[u], qs = a[u], ps = b[u];
+        const int i = cell_of(Q * inv_h, ng);
+        const double Ei = fld[i], gi = fld[ng + i];
+        if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
+        Ks += 0.5 * psi * P * P + qs * P;
+        Ms += psi * P + qs;
+        Cs += psi;
+        P = P + half * Ei;
+        qs = qs + half * ps * gi;
+        double Qn = Q + dt * P;
+        if (Qn < 0.0) Qn += L;
+        if (Qn >= L) Qn -= L;
+        const double psn = ps - dt * qs;
+        const T Qs = (T)Qn, pss = (T)psn;
+        Qp[idx[u]] = Qs; Pp[idx[u]] = (T)P; qsp[idx[u]] = (T)qs; psp[idx[u]] = pss;
+        const double Qd = Qs, psd = pss;
+        const double x = Qd * inv_h;
+        const int j = cell_of(x, ng);
+        const double s = frac01(x, j);
+        lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
       }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (!v[u]) continue;
-      const double Q = q[u], psi = w[u];
-      double P = p[u], qs = a[u], ps = b[u];
-      const int i = cell_of(Q * inv_h, ng);
-      const double Ei = fld[i], gi = fld[ng + i];
-      if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
-      Ks += 0.5 * psi * P * P + qs * P;
-      Ms += psi * P + qs;
-      Cs += psi;
-      P = P + half * Ei;
-      qs = qs + half * ps * gi;
-      double Qn = Q + dt * P;
-      if (Qn < 0.0) Qn += L;
-      if (Qn >= L) Qn -= L;
-      const double psn = ps - dt * qs;
-      const T Qs = (T)Qn, pss = (T)psn;
-      Qp[idx[u]] = Qs; Pp[idx[u]] = (T)P; qsp[idx[u]] = (T)qs; psp[idx[u]] = pss;
-      const double Qd = Qs, psd = pss;
-      const double x = Qd * inv_h;
-      const int j = cell_of(x, ng);
-      const double s = frac01(x, j);
-      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
     }
-    VP_TILE_LOOP_END
+  }
+  if (ppt <= 0) {  // no particle work: still stage (zero the LDS grid) before the flush
+    stage<MODE, TPB>(d, fld, sacc, false, true);
   }
 
-  const double Kb = block_sum<TPB>(Ks, red);
-  const double Mb = block_sum<TPB>(Ms, red);
-  const double Cb = block_sum<TPB>(Cs, red);
+  // kinetic sums: wave butterflies, one barrier, one thread adds the workgroup totals
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  Ks = wave_sum(Ks);
+  Ms = wave_sum(Ms);
+  Cs = wave_sum(Cs);
+  if (lane == 0) {
+    red[3 * wid] = Ks;
+    red[3 * wid + 1] = Ms;
+    red[3 * wid + 2] = Cs;
+  }
+  __syncthreads();  // also completes every LDS deposit of the workgroup
   if (threadIdx.x == 0) {
-    unsafeAtomicAdd(&d.scal->K, Kb);
-    unsafeAtomicAdd(&d.scal->mom, Mb);
-    unsafeAtomicAdd(&d.scal->chg, Cb);
+    double kb = 0.0, mb = 0.0, cbs = 0.0;
+    for (int w = 0; w < TPB / 64; ++w) {
+      kb += red[3 * w];
+      mb += red[3 * w + 1];
+      cbs += red[3 * w + 2];
+    }
+    VPG InstScal* sc = gp(d.scal);
+    gadd(&sc->K, kb);
+    gadd(&sc->mom, mb);
+    gadd(&sc->chg, cbs);
   }
-  __syncthreads();
   flush<MODE, TPB>(d, sacc, tl.local % d.acc_copies);
-  if (arrive(d, &sflag)) solve_instance<MODE, TPB>(d, smem, red, true);
+  if (arrive(d, &sflag)) solve_block<MODE, TPB>(d, smem, ss, true);
 }
 
 // Deposit of the current state only (eq. rhs-assembly), added to the global accumulator.
@@ -555,9 +681,9 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
   const int ng = d.ng;
   double* sacc = smem + 2 * ng;
   stage<MODE, TPB>(d, smem, sacc, false, true);
-  const T* __restrict__ Qp = static_cast<const T*>(d.Q);
-  const T* __restrict__ psp = static_cast<const T*>(d.ps);
-  const T* __restrict__ psip = static_cast<const T*>(d.psi);
+  const VPG T* __restrict__ Qp = gp<T>(d.Q);
+  const VPG T* __restrict__ psp = gp<T>(d.ps);
+  const VPG T* __restrict__ psip = gp<T>(d.psi);
   if constexpr (MODE == kFP32) {
     const float ihf = (float)d.inv_h;
     float* fa = reinterpret_cast<float*>(sacc);
@@ -613,15 +739,15 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
   const int ng = d.ng;
   double kick = kick_in, drift = drift_in;
   if (use_pending) {
-    kick = d.scal->pending ? 0.5 * d.dt : 0.0;
+    kick = gp(d.scal)->pending ? 0.5 * d.dt : 0.0;
     drift = 0.0;
   }
   if (kick == 0.0 && drift == 0.0) return;  // uniform per workgroup: no barrier skipped
   stage<MODE, TPB>(d, smem, nullptr, true, false);
-  T* __restrict__ Qp = static_cast<T*>(d.Q);
-  T* __restrict__ Pp = static_cast<T*>(d.P);
-  T* __restrict__ qsp = static_cast<T*>(d.qs);
-  T* __restrict__ psp = static_cast<T*>(d.ps);
+  VPG T* __restrict__ Qp = gp<T>(d.Q);
+  VPG T* __restrict__ Pp = gp<T>(d.P);
+  VPG T* __restrict__ qsp = gp<T>(d.qs);
+  VPG T* __restrict__ psp = gp<T>(d.ps);
   const bool do_kick = kick != 0.0, do_drift = drift != 0.0;
   if constexpr (MODE == kFP32) {
     const float* fE = reinterpret_cast<const float*>(smem);
@@ -686,12 +812,12 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   const InstDev& d = insts[tl.inst];
   const int ng = d.ng;
   stage<MODE, TPB>(d, smem, nullptr, true, false);
-  const T* __restrict__ Qp = static_cast<const T*>(d.Q);
-  const T* __restrict__ Pp = static_cast<const T*>(d.P);
-  const T* __restrict__ qsp = static_cast<const T*>(d.qs);
-  const T* __restrict__ psp = static_cast<const T*>(d.ps);
-  const T* __restrict__ psip = static_cast<const T*>(d.psi);
-  const int pend = d.scal->pending;
+  const VPG T* __restrict__ Qp = gp<T>(d.Q);
+  const VPG T* __restrict__ Pp = gp<T>(d.P);
+  const VPG T* __restrict__ qsp = gp<T>(d.qs);
+  const VPG T* __restrict__ psp = gp<T>(d.ps);
+  const VPG T* __restrict__ psip = gp<T>(d.psi);
+  const int pend = gp(d.scal)->pending;
   double Ks = 0.0, Ms = 0.0, Cs = 0.0;
   if constexpr (MODE == kFP32) {
     const float* fE = reinterpret_cast<const float*>(smem);
@@ -737,9 +863,10 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   const double Mb = block_sum<TPB>(Ms, red);
   const double Cb = block_sum<TPB>(Cs, red);
   if (threadIdx.x == 0) {
-    unsafeAtomicAdd(&d.scal->Kd, Kb);
-    unsafeAtomicAdd(&d.scal->momd, Mb);
-    unsafeAtomicAdd(&d.scal->chgd, Cb);
+    VPG InstScal* sc = gp(d.scal);
+    gadd(&sc->Kd, Kb);
+    gadd(&sc->momd, Mb);
+    gadd(&sc->chgd, Cb);
   }
 }
 
@@ -748,16 +875,16 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_solve(const InstDev* __restrict__ insts,
                                                const int* __restrict__ slots) {
   extern __shared__ double smem[];
-  __shared__ double red[4];
+  __shared__ double ss[kSolveScal];
   const InstDev& d = insts[slots[blockIdx.x]];
-  solve_instance<MODE, 256>(d, smem, red, false);
+  solve_block<MODE, 256>(d, smem, ss, false);
 }
 
 __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __restrict__ slots,
                                int nslots, int op) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslots) return;
-  InstScal* sc = insts[slots[t]].scal;
+  VPG InstScal* sc = gp(insts[slots[t]].scal);
   if (op == kScalClearDiag) {
     sc->Kd = 0.0; sc->momd = 0.0; sc->chgd = 0.0;
   } else if (op == kScalClearPending) {
@@ -782,7 +909,7 @@ template <typename T>
 __global__ void k_cell_index(const InstDev* __restrict__ insts, int slot, int* __restrict__ cells,
                              long long n) {
   const InstDev& d = insts[slot];
-  const T* Qp = static_cast<const T*>(d.Q);
+  const VPG T* Qp = gp<T>(d.Q);
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
     cells[k] = cell_of((double)Qp[k] * d.inv_h, d.ng);
@@ -793,7 +920,7 @@ __global__ void k_cell_index(const InstDev* __restrict__ insts, int slot, int* _
 // formula) with two stable 5-bit counting passes in LDS, then permutes the five arrays
 // in place through an LDS staging buffer.
 template <typename T>
-__device__ void permute_array(T* __restrict__ X, long long c0, int m, const unsigned short* order,
+__device__ void permute_array(VPG T* __restrict__ X, long long c0, int m, const unsigned short* order,
                               T* stagebuf) {
   for (int k = threadIdx.x; k < m; k += kBlock) stagebuf[k] = X[c0 + order[k]];
   __syncthreads();
@@ -817,7 +944,7 @@ __global__ __launch_bounds__(kBlock) void k_sort(const InstDev* __restrict__ ins
   unsigned short* iB = iA + chunk;
   int* cnt = reinterpret_cast<int*>(iB + chunk);                              // 32 x 256
   const int tid = threadIdx.x;
-  const T* Qp = static_cast<const T*>(d.Q);
+  const VPG T* Qp = gp<T>(d.Q);
   for (int k = tid; k < m; k += kBlock) {
     kA[k] = (unsigned short)cell_of((double)Qp[c0 + k] * d.inv_h, d.ng);
     iA[k] = (unsigned short)k;
@@ -862,11 +989,11 @@ __global__ __launch_bounds__(kBlock) void k_sort(const InstDev* __restrict__ ins
   }
   if (perm)
     for (int k = tid; k < m; k += kBlock) perm[c0 + k] = (int)(c0 + iA[k]);
-  permute_array<T>(static_cast<T*>(d.Q), c0, m, iA, stagebuf);
-  permute_array<T>(static_cast<T*>(d.P), c0, m, iA, stagebuf);
-  permute_array<T>(static_cast<T*>(d.qs), c0, m, iA, stagebuf);
-  permute_array<T>(static_cast<T*>(d.ps), c0, m, iA, stagebuf);
-  permute_array<T>(static_cast<T*>(d.psi), c0, m, iA, stagebuf);
+  permute_array<T>(gp<T>(d.Q), c0, m, iA, stagebuf);
+  permute_array<T>(gp<T>(d.P), c0, m, iA, stagebuf);
+  permute_array<T>(gp<T>(d.qs), c0, m, iA, stagebuf);
+  permute_array<T>(gp<T>(d.ps), c0, m, iA, stagebuf);
+  permute_array<T>(gp<T>(d.psi), c0, m, iA, stagebuf);
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -896,7 +1023,11 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
 
 #define VP_DISPATCH(mode, tpb, KERNEL, ...)                                                  \
   do {                                                                                       \
-    if ((mode) == kFP64) {                                                                   \
+    if ((mode) == kFP32TwoSum) {                                                             \
+      if ((tpb) == 1024) hipLaunchKernelGGL((KERNEL<kFP32TwoSum, 1024>), __VA_ARGS__);       \
+      else if ((tpb) == 512) hipLaunchKernelGGL((KERNEL<kFP32TwoSum, 512>), __VA_ARGS__);    \
+      else hipLaunchKernelGGL((KERNEL<kFP32TwoSum, 256>), __VA_ARGS__);                      \
+    } else if ((mode) == kFP64) {                                                            \
       if ((tpb) == 1024) hipLaunchKernelGGL((KERNEL<kFP64, 1024>), __VA_ARGS__);             \
       else if ((tpb) == 512) hipLaunchKernelGGL((KERNEL<kFP64, 512>), __VA_ARGS__);          \
       else hipLaunchKernelGGL((KERNEL<kFP64, 256>), __VA_ARGS__);                            \
@@ -956,7 +1087,7 @@ hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int
                         int max_ng, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   const size_t lds = lds_doubles_per_node() * (size_t)max_ng * sizeof(double);
-  if (mode == kFP64)
+  if (mode == kFP64 || mode == kFP32TwoSum)
     hipLaunchKernelGGL(k_solve<kFP64>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
   else if (mode == kFP32Comp)
     hipLaunchKernelGGL(k_solve<kFP32Comp>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
