@@ -2,6 +2,9 @@
 """Throughput of the decorated-particle step on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload two_stream|probe|landau_nonlinear]
+    python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
+    python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
+    python bench.py --pmc-summary FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR --workload W
 
 One step = one pass of the whole hot path over the batch of particles: pending half-kick,
 kinetic diagnostics, half-kick, drift, deposit, and the Poisson solve (run by the last
@@ -9,9 +12,9 @@ workgroup of the fused kernel).  Default workload: the two-stream instability, N
 decorated particles, Ng = 512, dt = 0.05, FP32 state with compensated deposition.
 
 Prints ONE JSON line on stdout.  `value` = N * K / wall time of the K timed steps
-(particle state resident in HBM, graph-replayed steps).  `roofline` times the fused kernel
-alone with HIP events around each launch (direct launches on the library's stream, right
-after the timed region) and divides its algorithmic bytes by that duration.
+(particle state resident in HBM, graph-replayed steps).  `roofline` divides the fused
+kernel's algorithmic bytes by its average launch duration, taken with HIP events on the
+library's stream around the timed region (one fused launch per step).
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -54,6 +57,79 @@ def load_traffic(workload: str, n: int):
     return rec.get("traffic_bytes_per_launch")
 
 
+def _counter_rows(d: str):
+    """Rows of every rocprofv3 counter_collection.csv under directory d."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _per_dispatch(rows, counter: str, kernel_sub: str):
+    """Mean over dispatches of kernels whose name contains kernel_sub of the counter (KiB)."""
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or kernel_sub not in r["Kernel_Name"]:
+            continue
+        key = r["Dispatch_Id"]
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise SystemExit(f"no {counter} rows for kernels matching {kernel_sub!r}")
+    vals = sorted(per.values())
+    return sum(vals) / len(vals), len(vals)
+
+
+COPY_BYTES = 1 << 30          # --copy-calibration copies this many bytes (reads and writes each)
+
+
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    n = COPY_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {COPY_BYTES} bytes 3 times")
+
+
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
+    """Write profiles/pmc_k_fused_<workload>.json: FETCH_SIZE + WRITE_SIZE per fused launch,
+    each scaled by the ratio of known bytes to what the same counter reads for a copy."""
+    fetch_kib, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "k_fused")
+    write_kib, nw = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", "k_fused")
+    # the copy kernel is the largest dispatch in its run (torch launches a few small ones too)
+    cf_rows = _counter_rows(cfetch_dir)
+    cw_rows = _counter_rows(cwrite_dir)
+    cf_kib = max(float(r["Counter_Value"]) for r in cf_rows if r["Counter_Name"] == "FETCH_SIZE")
+    cw_kib = max(float(r["Counter_Value"]) for r in cw_rows if r["Counter_Name"] == "WRITE_SIZE")
+    f_scale = COPY_BYTES / (cf_kib * 1024.0)
+    w_scale = COPY_BYTES / (cw_kib * 1024.0)
+    fetch_b = fetch_kib * 1024.0 * f_scale
+    write_b = write_kib * 1024.0 * w_scale
+    w, _ = make_workload(workload)
+    rec = {"kernel": "k_fused", "workload": workload, "n": w.n,
+           "kernel_src_sha": kernel_src_sha(),
+           "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
+           "dispatches": [nf, nw],
+           "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+           "traffic_bytes_per_launch": fetch_b + write_b,
+           "traffic_bytes_per_particle": (fetch_b + write_b) / w.n}
+    out = os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "two_stream":
@@ -93,12 +169,25 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="two_stream")
-    ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--kernel-steps", type=int, default=0,
+                    help="after the timed region, also time this many direct (non-graph) "
+                         "launches one by one with events (reported as direct_launch_us)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default=None)
+    ap.add_argument("--launch", default=None,
+                    help="threads,ppt,acc_copies for the fused kernel (use with --no-tune)")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"))
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.workload)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
               "supported (instance sharding across GPUs is described in DESIGN.md)",
@@ -122,6 +211,9 @@ def main():
     torch.cuda.set_stream(stream)
     sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8))
     tuning_us = None
+    if args.launch:
+        t_, p_, a_ = (int(x) for x in args.launch.split(","))
+        sim.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
     if not args.no_tune:
         best, tuning_us = sim.tune(steps_per_trial=32)
         log(f"tuned launch shape {best} ({tuning_us:.2f} us/step)")
@@ -130,27 +222,35 @@ def main():
     sim.step(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
+    # HIP events on the library's stream bracket the timed region; every step is one launch
+    # of the fused kernel, replayed back to back from a graph, so elapsed / steps is the
+    # fused kernel's average launch duration
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
+    ev0.record(stream)
     sim.step(args.steps)
+    ev1.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    log(f"timed {args.steps} steps in {elapsed * 1e3:.2f} ms")
+    kern_avg_s = ev0.elapsed_time(ev1) * 1e-3 / args.steps
+    log(f"timed {args.steps} steps in {elapsed * 1e3:.2f} ms; fused kernel "
+        f"{kern_avg_s * 1e6:.2f} us per launch (events)")
 
-    # per-launch timing of the fused kernel with HIP events on the library's stream
-    sim.set_tuning(use_graph=0)
-    ks = max(1, args.kernel_steps)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(ks)]
-    for a, b in evs:
-        a.record(stream)
-        sim.step(1)
-        b.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = [a.elapsed_time(b) for a, b in evs]
-    kern_avg_s = float(np.mean(kern_ms)) * 1e-3
-    log(f"fused kernel: mean {kern_avg_s * 1e6:.2f} us over {ks} launches "
-        f"(min {min(kern_ms) * 1e3:.2f} us)")
-    sim.set_tuning(use_graph=tun["use_graph"])
+    direct_us = None
+    if args.kernel_steps > 0:
+        sim.set_tuning(use_graph=0)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.kernel_steps)]
+        for a, b in evs:
+            a.record(stream)
+            sim.step(1)
+            b.record(stream)
+        torch.cuda.synchronize()
+        direct_us = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e3
+        log(f"direct launches: {direct_us:.2f} us each between events")
+        sim.set_tuning(use_graph=tun["use_graph"])
 
     diag = sim.diagnostics(0, allow_nonfinite=True)
     finite = bool(np.isfinite(diag["H"]))
@@ -181,7 +281,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_fused", "bytes_per_launch": bytes_per_launch,
-            "kernel_us": kern_avg_s * 1e6,
+            "kernel_us": kern_avg_s * 1e6, "direct_launch_us": direct_us,
         },
     }
     if not args.no_cpu:
