@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 1
+#define VP_ABI_VERSION 2
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -114,7 +114,7 @@ typedef struct vp_tuning {
   int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 */
   int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..8 */
   int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
-  int32_t graph_steps;  /* steps per captured graph, 1..256 */
+  int32_t graph_steps;  /* steps per captured graph, 1..256 (rounded up to a multiple of 3) */
 } vp_tuning;
 
 typedef struct vp_handle vp_handle;
@@ -162,30 +162,36 @@ vp_status vp_destroy(vp_handle* h);
  * Each acts on every occupied slot and leaves the step counter alone. */
 
 /* Load vector b_j = sum_a [psi*_a phi_j(Q_a) - p*_a phi_j'(Q_a)] (eq. rhs-assembly) of the
- * current positions and dipoles, added into each instance's accumulator (which
- * vp_poisson consumes and clears). */
+ * current positions and dipoles.  Replaces each instance's load vector (the one vp_poisson
+ * and the next vp_step solve from). */
 vp_status vp_deposit(vp_handle* h);
 
-/* Poisson solve (eq. lin-sys): b~ = b - mean(b) in float64 (eq. neutrality), Phi with
- * A Phi = b~ and 1^T Phi = 0 by an in-LDS FFT, element field E_e = -(Phi_{e+1}-Phi_e)/h,
- * projected curvature g_e (lumped L2 projection of E onto P1, differentiated),
- * W = (1/2) sum h E_e^2.  One workgroup per instance. */
+/* Poisson solve (eq. lin-sys) of the current load vector: b~ = b - mean(b) in float64
+ * (eq. neutrality), A Phi = b~ with 1^T Phi = 0 (the Gauss-law scan E_e - E_{e-1} = b~_e,
+ * sum_e E_e = 0, or an in-LDS FFT, per cfg.solver), element field
+ * E_e = -(Phi_{e+1} - Phi_e)/h, projected curvature g_e (lumped L2 projection of E onto
+ * P1, differentiated), W = (1/2) sum h E_e^2.  Writes the field arrays that
+ * vp_gather_push and vp_diagnostics read.  One workgroup per instance. */
 vp_status vp_poisson(vp_handle* h);
 
 /* Exact sub-flows of the splitting with the current field (eq. sw-evolution):
  * kick:  P += kick * E[i],  q* += kick * p* * g[i]   (Q, p* frozen),
  * drift: Q += drift * P (periodic wrap into [0, L)),  p* -= drift * q*   (P, q* frozen).
- * Requires |drift * P| < L. */
+ * Requires |drift * P| < L.  After vp_step it first writes the field of the current
+ * positions (as vp_poisson); a drift makes the load vector stale until vp_deposit (which
+ * vp_step then runs by itself). */
 vp_status vp_gather_push(vp_handle* h, double kick, double drift);
 
 /* ---------------------------------------------------------------- fused stepping */
 
-/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused particle pass
- * per step (pending half-kick, diagnostics at the integer step, half-kick, drift, deposit),
- * whose last workgroup per instance performs that instance's Poisson solve; optionally
- * replayed from captured HIP graphs.  Equals the primitive composition up to rounding.
- * Leaves a pending half-kick (P, q* at t + dt/2); every state read-back must go through
- * vp_sync_state, vp_retire or vp_diagnostics (which accounts for it). */
+/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused kernel per step:
+ * every workgroup solves the field of the current positions from the load vector the
+ * previous step deposited, then runs its particles through the pending half-kick, the
+ * diagnostics at the integer step, the half-kick, the drift and the deposit of the new
+ * load vector; optionally replayed from captured HIP graphs.  Equals the primitive
+ * composition up to rounding.  Leaves a pending half-kick (P, q* at t + dt/2); every state
+ * read-back must go through vp_sync_state, vp_retire or vp_diagnostics (which accounts for
+ * it). */
 vp_status vp_step(vp_handle* h, int32_t nsteps);
 
 /* Apply the pending half-kick of every occupied slot (P, q* back to integer time). */

@@ -94,18 +94,23 @@ struct vp_handle {
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   int max_ng = VP_MIN_NG;
-  vp_tuning tun{1024, 4, 4, 1, 32};
+  bool any_fft = false;     // some slot uses the FFT solver (fused launches need more LDS)
+  vp_tuning tun{1024, 4, 4, 1, 33};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int graph_len = 0;
+  int graph_len = 0;        // fused launches per graph (a multiple of the ring period)
+  int graph_phase = 0;      // ring phase the graph was captured at
   bool graph_ok = false;
+  int phase = 0;            // ring phase of the next fused launch (step count mod kRing)
+  bool field_stale = false; // fused steps ran since the field arrays were last written
+  bool acc_stale = false;   // a drift ran since the ring entry of `phase` was deposited
 };
 
 namespace {
 
 void drop_graph(vp_handle* h) {
-  if (h->gexec) hipGraphExecDestroy(h->gexec);
-  if (h->graph) hipGraphDestroy(h->graph);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
   h->gexec = nullptr;
   h->graph = nullptr;
   h->graph_ok = false;
@@ -139,10 +144,13 @@ vp_status rebuild_tables(vp_handle* h) {
       h->h_tiles.push_back(tl);
     }
     InstDev& d = h->h_inst[s];
+    if (nt > d.kin_cap) return fail(VP_ERR_STATE, "slot %d: %d tiles exceed the kinetic-sum ring (%d)", s, nt, d.kin_cap);
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
   }
   h->ntiles = (int)h->h_tiles.size();
+  h->any_fft = false;
+  for (int s : h->h_occ) h->any_fft = h->any_fft || h->slots[s].cfg.solver == VP_SOLVE_FFT;
   if ((size_t)h->ntiles > h->tiles_cap) {
     if (h->d_tiles) VP_HIP(hipFree(h->d_tiles));
     h->d_tiles = nullptr;
@@ -158,6 +166,9 @@ vp_status rebuild_tables(vp_handle* h) {
                           hipMemcpyHostToDevice, h->stream));
   VP_HIP(hipMemcpyAsync(h->d_inst, h->h_inst.data(), h->max_slots * sizeof(InstDev),
                         hipMemcpyHostToDevice, h->stream));
+  // the number of accumulator copies may have changed: fold the live ring entry into copy 0
+  VP_HIP(vpk::launch_ring(h->precision, h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kRingFold,
+                          h->phase, h->stream));
   VP_HIP(hipStreamSynchronize(h->stream));
   return VP_OK;
 }
@@ -169,32 +180,88 @@ vp_status check_slot(const vp_handle* h, int slot) {
   return VP_OK;
 }
 
+int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
+
 vp_status launch_steps_direct(vp_handle* h, int nsteps) {
-  for (int i = 0; i < nsteps; ++i)
+  for (int i = 0; i < nsteps; ++i) {
     VP_HIP(vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                             h->max_ng, h->stream));
+                             h->max_ng, h->any_fft, h->phase, h->stream));
+    h->phase = next_phase(h->phase);
+  }
   return VP_OK;
 }
 
+// Fused launches per graph: graph_steps rounded up to a multiple of the ring period, so a
+// replay leaves the phase where it found it.
+int graph_len_of(const vp_handle* h) {
+  return (h->tun.graph_steps + vpk::kRing - 1) / vpk::kRing * vpk::kRing;
+}
+
 vp_status ensure_graph(vp_handle* h) {
-  if (h->graph_ok && h->graph_len == h->tun.graph_steps) return VP_OK;
+  if (h->graph_ok && h->graph_len == graph_len_of(h)) return VP_OK;
   drop_graph(h);
+  const int len = graph_len_of(h);
   VP_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
-  for (int i = 0; i < h->tun.graph_steps && le == hipSuccess; ++i)
+  int ph = h->phase;
+  for (int i = 0; i < len && le == hipSuccess; ++i) {
     le = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                           h->max_ng, h->stream);
+                           h->max_ng, h->any_fft, ph, h->stream);
+    ph = next_phase(ph);
+  }
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(h->stream, &g);
   if (le != hipSuccess || ee != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return fail(VP_ERR_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
                 hipGetErrorString(ee));
   }
   h->graph = g;
   VP_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-  h->graph_len = h->tun.graph_steps;
+  h->graph_len = len;
+  h->graph_phase = h->phase;
   h->graph_ok = true;
+  return VP_OK;
+}
+
+// Run k fused steps of every slot: graph replays where whole graphs fit (after at most
+// kRing-1 direct launches that bring the phase to the graph's), direct launches otherwise.
+vp_status advance(vp_handle* h, int k) {
+  const bool graphs = h->tun.use_graph && h->stream != nullptr;
+  if (graphs && k >= graph_len_of(h) + vpk::kRing - 1) {
+    VP_TRY(ensure_graph(h));
+    while (h->phase != h->graph_phase) {
+      VP_TRY(launch_steps_direct(h, 1));
+      --k;
+    }
+    const int reps = k / h->graph_len;
+    for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
+    k -= reps * h->graph_len;
+  }
+  return launch_steps_direct(h, k);
+}
+
+// Solve the listed slots from the live ring entry and write their field arrays (and the
+// record a fused step still owes).
+vp_status materialise(vp_handle* h, const int* d_slots, int nslots) {
+  VP_HIP(vpk::launch_solve(h->precision, h->d_inst, d_slots, nslots, h->max_ng, h->any_fft, h->phase,
+                           h->stream));
+  return VP_OK;
+}
+
+vp_status materialise_all(vp_handle* h) {
+  VP_TRY(materialise(h, h->d_occ, (int)h->h_occ.size()));
+  h->field_stale = false;
+  return VP_OK;
+}
+
+// Deposit the current positions of every slot into the live ring entry (cleared first).
+vp_status deposit_all(vp_handle* h) {
+  VP_HIP(vpk::launch_ring(h->precision, h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kRingClear,
+                          h->phase, h->stream));
+  VP_HIP(vpk::launch_deposit(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
+                             h->max_ng, h->phase, h->stream));
+  h->acc_stale = false;
   return VP_OK;
 }
 
@@ -242,7 +309,7 @@ const char* vp_last_error(void) { return g_err.c_str(); }
 vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out) {
   VP_TRY(validate(cfg));
   if (!bytes_out) return fail(VP_ERR_ARG, "bytes_out is NULL");
-  *bytes_out = vpk::workspace_layout(cfg->ng, cfg->hist_cap).total;
+  *bytes_out = vpk::workspace_layout(cfg->ng, cfg->hist_cap, cfg->n).total;
   return VP_OK;
 }
 
@@ -287,7 +354,7 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
     if (!arrs[k] || !aligned(arrs[k], es)) return fail(VP_ERR_ARG, "particle array %d NULL or misaligned", k);
   if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
 
-  const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, cfg->hist_cap);
+  const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, cfg->hist_cap, cfg->n);
   char* ws = static_cast<char*>(workspace);
   InstDev d{};
   d.Q = parts.Q; d.P = parts.P; d.qs = parts.qs; d.ps = parts.ps; d.psi = parts.psi;
@@ -311,6 +378,8 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.inv_lam = reinterpret_cast<double*>(ws + w.inv_lam);
   d.scal = reinterpret_cast<vpk::InstScal*>(ws + w.scal);
   d.hist = reinterpret_cast<double*>(ws + w.hist);
+  d.kin = reinterpret_cast<double*>(ws + w.kin);
+  d.kin_cap = vpk::kin_capacity(cfg->n);
 
   // FFT twiddles and inverse stiffness eigenvalues lambda_m = (2/h)(1 - cos(2 pi m / Ng)).
   const int ng = cfg->ng;
@@ -343,10 +412,10 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
     sl.used = false;
     return st;
   }
-  // Field at t = 0 from the initial state.
+  // Load vector and field at t = 0 from the initial state (the ring entries start cleared).
   VP_HIP(vpk::launch_deposit(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
-                             h->tun.ppt, h->max_ng, h->stream));
-  VP_HIP(vpk::launch_solve(h->precision, h->d_inst, h->d_ids + slot, 1, h->max_ng, h->stream));
+                             h->tun.ppt, h->max_ng, h->phase, h->stream));
+  VP_TRY(materialise(h, h->d_ids + slot, 1));
   return VP_OK;
 }
 
@@ -385,9 +454,11 @@ vp_status vp_retire(vp_handle* h, int32_t slot) {
   VP_TRY(check_slot(h, slot));
   Slot& sl = h->slots[slot];
   if (sl.pending) {
+    VP_TRY(materialise(h, h->d_ids + slot, 1));
     VP_HIP(vpk::launch_settle(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles,
-                              h->tun.ppt, h->max_ng, h->stream));
-    VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearPending, h->stream));
+                              h->tun.ppt, h->max_ng, h->phase, h->stream));
+    VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearPending, h->phase,
+                                    h->stream));
     sl.pending = false;
   }
   VP_HIP(hipStreamSynchronize(h->stream));
@@ -398,35 +469,36 @@ vp_status vp_retire(vp_handle* h, int32_t slot) {
 
 vp_status vp_destroy(vp_handle* h) {
   if (!h) return VP_OK;
-  hipStreamSynchronize(h->stream);
+  (void)hipStreamSynchronize(h->stream);
   drop_graph(h);
-  if (h->d_inst) hipFree(h->d_inst);
-  if (h->d_tiles) hipFree(h->d_tiles);
-  if (h->d_occ) hipFree(h->d_occ);
-  if (h->d_ids) hipFree(h->d_ids);
+  if (h->d_inst) (void)hipFree(h->d_inst);
+  if (h->d_tiles) (void)hipFree(h->d_tiles);
+  if (h->d_occ) (void)hipFree(h->d_occ);
+  if (h->d_ids) (void)hipFree(h->d_ids);
   delete h;
   return VP_OK;
 }
 
 vp_status vp_deposit(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
-  VP_HIP(vpk::launch_deposit(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                             h->max_ng, h->stream));
-  return VP_OK;
+  if (h->h_occ.empty()) return VP_OK;
+  return deposit_all(h);
 }
 
 vp_status vp_poisson(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
-  VP_HIP(vpk::launch_solve(h->precision, h->d_inst, h->d_occ, (int)h->h_occ.size(), h->max_ng,
-                           h->stream));
-  return VP_OK;
+  if (h->h_occ.empty()) return VP_OK;
+  return materialise_all(h);
 }
 
 vp_status vp_gather_push(vp_handle* h, double kick, double drift) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (!std::isfinite(kick) || !std::isfinite(drift)) return fail(VP_ERR_ARG, "kick and drift must be finite");
+  if (h->h_occ.empty()) return VP_OK;
+  if (h->field_stale) VP_TRY(materialise_all(h));
   VP_HIP(vpk::launch_gather_push(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
                                  h->max_ng, kick, drift, h->stream));
+  if (drift != 0.0) h->acc_stale = true;
   return VP_OK;
 }
 
@@ -434,7 +506,7 @@ vp_status vp_step(vp_handle* h, int32_t nsteps) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (nsteps < 0) return fail(VP_ERR_ARG, "nsteps < 0");
   if (h->h_occ.empty() || nsteps == 0) return VP_OK;
-  const bool graphs = h->tun.use_graph && h->stream != nullptr;
+  if (h->acc_stale) VP_TRY(deposit_all(h));
   int done = 0;
   while (done < nsteps) {
     // sort the slots whose step count is a multiple of their sort interval (once per step)
@@ -453,14 +525,8 @@ vp_status vp_step(vp_handle* h, int32_t nsteps) {
       const long long r = sl.step % sl.cfg.sort_every;
       chunk = (int)std::min<long long>(chunk, sl.cfg.sort_every - r);
     }
-    if (graphs && chunk >= h->tun.graph_steps) {
-      VP_TRY(ensure_graph(h));
-      const int reps = chunk / h->tun.graph_steps;
-      for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
-      chunk = reps * h->tun.graph_steps;
-    } else {
-      VP_TRY(launch_steps_direct(h, chunk));
-    }
+    VP_TRY(advance(h, chunk));
+    h->field_stale = true;
     for (int s : h->h_occ) {
       h->slots[s].step += chunk;
       h->slots[s].pending = true;
@@ -473,10 +539,11 @@ vp_status vp_step(vp_handle* h, int32_t nsteps) {
 vp_status vp_sync_state(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (h->h_occ.empty()) return VP_OK;
+  VP_TRY(materialise_all(h));
   VP_HIP(vpk::launch_settle(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                            h->max_ng, h->stream));
+                            h->max_ng, h->phase, h->stream));
   VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalClearPending,
-                                  h->stream));
+                                  h->phase, h->stream));
   for (int s : h->h_occ) h->slots[s].pending = false;
   return VP_OK;
 }
@@ -511,9 +578,10 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   if (!host_out) return fail(VP_ERR_ARG, "host_out is NULL");
   const Slot& sl = h->slots[slot];
   const InstDev& d = h->h_inst[slot];
-  VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearDiag, h->stream));
+  VP_TRY(materialise(h, h->d_ids + slot, 1));
+  VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_ids + slot, 1, vpk::kScalClearDiag, h->phase, h->stream));
   VP_HIP(vpk::launch_diag(h->precision, h->tun.threads, h->d_inst, h->d_tiles, sl.tile_begin, sl.ntiles, h->tun.ppt,
-                          h->max_ng, h->stream));
+                          h->max_ng, h->phase, h->stream));
   vpk::InstScal sc{};
   VP_HIP(hipMemcpyAsync(&sc, d.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
   if (host_grid) {
@@ -526,14 +594,15 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   VP_HIP(hipStreamSynchronize(h->stream));
   host_out->step = sc.step;
   host_out->t = (double)sc.step * sl.cfg.dt;
+  const int p = h->phase;
   host_out->K = sc.Kd;
-  host_out->W = sc.W;
-  host_out->H = sc.Kd + sc.W;
+  host_out->W = sc.W[p];
+  host_out->H = sc.Kd + sc.W[p];
   host_out->charge = sc.chgd;
   host_out->momentum = sc.momd;
-  host_out->e_amp = std::sqrt(2.0 * sc.W / sl.cfg.L);
-  host_out->e1_re = sc.e1r;
-  host_out->e1_im = sc.e1i;
+  host_out->e_amp = std::sqrt(2.0 * sc.W[p] / sl.cfg.L);
+  host_out->e1_re = sc.e1r[p];
+  host_out->e1_im = sc.e1i[p];
   if (!diag_finite(*host_out) || sc.nonfinite)
     return fail(VP_ERR_NONFINITE, "slot %d: non-finite diagnostics at step %lld", slot, sc.step);
   return VP_OK;
@@ -551,6 +620,7 @@ vp_status vp_history(vp_handle* h, int32_t slot, int64_t first_step, int32_t cou
     return fail(VP_ERR_RANGE, "records %lld..%lld not stored (have %lld..%lld)", (long long)first_step,
                 (long long)(first_step + count - 1), lo, sl.step - 1);
   std::vector<double> buf((size_t)count * vpk::kHistFields);
+  if (sl.pending) VP_TRY(materialise(h, h->d_ids + slot, 1));  // the last step's record
   VP_HIP(hipStreamSynchronize(h->stream));
   long long k = 0;
   while (k < count) {
@@ -604,7 +674,7 @@ vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
     b += ((size_t)5 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
-    b += vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
+    b += vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap, sl.cfg.n).total;
   }
   *bytes_out = b;
   return VP_OK;
@@ -626,7 +696,7 @@ vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
       else VP_HIP(hipMemcpyAsync(arrs[k], sp, sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
     }
     off += ((size_t)5 * sl.cfg.n * es + 255) & ~size_t(255);
-    const size_t wb = vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap).total;
+    const size_t wb = vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap, sl.cfg.n).total;
     if (save) VP_HIP(hipMemcpyAsync(scratch + off, sl.ws, wb, hipMemcpyDeviceToDevice, h->stream));
     else VP_HIP(hipMemcpyAsync(sl.ws, scratch + off, wb, hipMemcpyDeviceToDevice, h->stream));
     off += wb;
@@ -643,6 +713,8 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   char* scratch = static_cast<char*>(dev_scratch);
   std::vector<Slot> saved = h->slots;
   const vp_tuning orig = h->tun;
+  const int saved_phase = h->phase;
+  const bool saved_fs = h->field_stale, saved_as = h->acc_stale;
   VP_TRY(tune_copy(h, scratch, true));
   hipEvent_t e0, e1;
   VP_HIP(hipEventCreate(&e0));
@@ -651,9 +723,9 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   double best_us = 1e300;
   struct Cand { int threads, ppt, acc; };
   std::vector<Cand> cands;
-  for (int th : {256, 1024})
+  for (int th : {512, 1024})
     for (int pp : {1, 2, 4, 8})
-      for (int ac : {1, 4, 8}) cands.push_back({th, pp, ac});
+      for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac});
   vp_status st = VP_OK;
   for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
     {
@@ -668,24 +740,33 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
       // one untimed graph build + warm-up pass, then the timed steps
       st = vp_step(h, t.graph_steps);
       if (st != VP_OK) break;
-      hipEventRecord(e0, h->stream);
+      if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(VP_ERR_HIP, "event record"); break; }
       st = vp_step(h, steps_per_trial);
-      hipEventRecord(e1, h->stream);
-      hipEventSynchronize(e1);
+      if (st != VP_OK) break;
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(VP_ERR_HIP, "event timing");
+        break;
+      }
       const double us = 1000.0 * ms / steps_per_trial;
       if (us < best_us) {
         best_us = us;
         best = t;
       }
       h->slots = saved;
+      h->phase = saved_phase;
+      h->field_stale = saved_fs;
+      h->acc_stale = saved_as;
       if (st == VP_OK) st = tune_copy(h, scratch, false);
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   h->slots = saved;
+  h->phase = saved_phase;
+  h->field_stale = saved_fs;
+  h->acc_stale = saved_as;
   vp_status s2 = tune_copy(h, scratch, false);
   vp_status s3 = vp_set_tuning(h, st == VP_OK ? &best : &orig);
   if (st != VP_OK) return st;

@@ -10,19 +10,24 @@ namespace vpk {
 
 constexpr int kBlock = 256;      // threads per workgroup for every particle kernel
 constexpr int kHistFields = 10;  // doubles per diagnostic record (layout of vp_diag)
+constexpr int kKinFields = 4;    // per-tile kinetic sums: K, momentum, charge, (unused)
+constexpr int kMinTile = 256;    // fewest particles per tile (256 threads x 1 particle)
 
 enum Mode { kFP64 = 0, kFP32Comp = 1, kFP32 = 2, kFP32TwoSum = 3 };
 
+// The fused step runs in one of three phases r = (engine step count) mod 3.  A pass in phase
+// r solves the field from accumulator ring entry r (deposited by the previous pass), adds the
+// new deposit into entry r+1 and clears entry r+2 (read by the pass before it); the kinetic
+// sums and the field summary live in rings of the same period.
+constexpr int kRing = 3;
+
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
-  double K, mom, chg;      // fused-pass partial sums, cleared by the solving workgroup
-  double Kd, momd, chgd;   // partial sums of the diagnostic kernel
-  double W, e1r, e1i;      // summary of the current field
-  long long step;          // steps taken by the fused path
-  int pending;             // 1 when P, q* sit half a kick behind Q, p*
-  unsigned ticket;         // workgroups of this instance done in the current pass
-  int nonfinite;           // set when a diagnostic came out NaN or Inf
-  int pad;
+  double W[kRing], e1r[kRing], e1i[kRing];  // summary of the field solved from ring entry r
+  double Kd, momd, chgd;                    // partial sums of the diagnostic kernel
+  long long step;                           // integer step of the state (fused path)
+  int pend[kRing];                          // 1 when P, q* owe the half-kick with the field of entry r
+  int nonfinite;                            // set when a diagnostic came out NaN or Inf
 };
 
 // Device descriptor of one instance (one slot of an engine).
@@ -37,7 +42,7 @@ struct InstDev {
   int ntiles, acc_copies;
   int hist_cap, solver;
   double L, inv_h, h, dt;
-  double* acc;      // acc_copies * ng global load accumulators (float for kFP32)
+  double* acc;      // kRing x VP_MAX_ACC_COPIES x ng load accumulators (float for kFP32)
   double* E;        // element field, ng
   double* g;        // projected curvature phi_h'', ng
   float* Ef;        // float copies for the kFP32 gather
@@ -48,6 +53,9 @@ struct InstDev {
   double* inv_lam;  // 1 / eigenvalue of the stiffness matrix per Fourier mode (0 for m = 0)
   InstScal* scal;
   double* hist;     // hist_cap records of kHistFields doubles
+  double* kin;      // kRing x kin_cap x kKinFields per-tile kinetic sums of phase r's pass
+  int kin_cap;      // tiles the kinetic-sum ring can hold (ceil(n / 256))
+  int pad_;
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.
@@ -61,27 +69,33 @@ struct Tile {
 
 // Byte offsets of the workspace regions of one instance (all 256-byte aligned).
 struct WsLayout {
-  size_t acc, E, g, Ef, gf, Phi, bt, tw, inv_lam, scal, hist, total;
+  size_t acc, E, g, Ef, gf, Phi, bt, tw, inv_lam, scal, hist, kin, total;
 };
-WsLayout workspace_layout(int ng, int hist_cap);
+WsLayout workspace_layout(int ng, int hist_cap, long long n);
+int kin_capacity(long long n);
 
 size_t particle_lds_bytes(int mode, int max_ng);
 
+// `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS).
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                        int ntiles, int ppt, int max_ng, hipStream_t s);
+                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                          int ntiles, int ppt, int max_ng, hipStream_t s);
+                          int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,
                               int tile0, int ntiles, int ppt, int max_ng, double kick, double drift,
                               hipStream_t s);
 hipError_t launch_settle(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                         int ntiles, int ppt, int max_ng, hipStream_t s);
+                         int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                       int ntiles, int ppt, int max_ng, hipStream_t s);
+                       int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
+// Solve the listed slots from ring entry `phase` and write the field arrays (materialise).
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
-                        int max_ng, hipStream_t s);
+                        int max_ng, bool lds_fft, int phase, hipStream_t s);
+// Ring maintenance for the listed slots (RingOp).
+hipError_t launch_ring(int mode, const InstDev* d_inst, const int* d_slots, int nslots, int op,
+                       int phase, hipStream_t s);
 hipError_t launch_slot_scalars(const InstDev* d_inst, const int* d_slots, int nslots, int op,
-                               hipStream_t s);
+                               int phase, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_cell_index(const InstDev* d_inst, int slot, int mode, int* cells, long long n,
                              hipStream_t s);
@@ -89,6 +103,9 @@ hipError_t launch_sort(int mode, const InstDev* d_inst, int slot, long long n, i
                        int* perm, hipStream_t s);
 
 // ops for launch_slot_scalars
-enum ScalOp { kScalClearDiag = 0, kScalClearPending = 1, kScalReset = 2 };
+enum ScalOp { kScalClearDiag = 0, kScalClearPending = 1 };
+// ops for launch_ring: fold entry `phase` into its copy 0 and clear the two other entries
+// (after the number of accumulator copies changed); or clear entry `phase` (before a deposit)
+enum RingOp { kRingFold = 0, kRingClear = 1 };
 
 }  // namespace vpk

@@ -4,13 +4,14 @@
 // and the kick / drift sub-flows of eq. sw-evolution.
 //
 // Layout: particles are five structure-of-arrays streams; one workgroup owns one tile of
-// consecutive particles of one instance, so every load and store is coalesced.  The
-// instance's field (E, g) is staged in LDS; the load vector is accumulated into an
-// LDS-private copy of the grid (float64 LDS atomics, or float32 (hi, lo) two-sum pairs
-// under a 64-bit compare-and-swap, or float32 atomics in the naive mode), and each tile
-// adds its grid into one of the instance's spread global accumulator copies.  In the fused
-// step the last workgroup to finish an instance (ticket counter) runs that instance's
-// solve in LDS, so one kernel per step advances every instance.
+// consecutive particles of one instance, so every load and store is coalesced.  The load
+// vector is accumulated into an LDS-private copy of the grid (float64 LDS atomics, or float32
+// (hi, lo) two-sum pairs under a 64-bit compare-and-swap, or float32 atomics in the naive
+// mode), and each tile adds its grid into one of the instance's spread global accumulator
+// copies.  The fused step needs no grid-wide wait: the accumulators form a ring of three
+// entries, and every workgroup of the next launch solves the field of the entry the previous
+// launch filled (a few microseconds of LDS work that overlap its first particle loads), so
+// one kernel per step advances every instance and the kernel boundary is the only barrier.
 //
 // Rounding: every kernel is compiled without floating-point contraction, and the float64
 // particle arithmetic follows the same operation order as the plain CPU definition, so the
@@ -54,6 +55,13 @@ __device__ __forceinline__ void gst(VPG double* p, double v) {
 __device__ __forceinline__ void gst(VPG float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Streaming access to the particle arrays: every element is read and written once per step,
+// so the loads and stores are marked non-temporal (they do not displace cached grid data).
+template <typename T>
+__device__ __forceinline__ T ntld(const VPG T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void ntst(VPG T* p, T v) { __builtin_nontemporal_store(v, p); }
 
 // Element index of x = Q * Ng / L: floor, clamped to [0, Ng-1] (NaN maps to 0), so an LDS
 // index is always in range whatever the state holds.
@@ -159,21 +167,22 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
   }
 }
 
-// Add the LDS grid into the global accumulator copy `copy` of the instance (device-scope
+// Add the LDS grid into accumulator copy `copy` of ring entry r of the instance (device-scope
 // atomics; only non-zero nodes).
 template <int MODE, int TPB>
-__device__ void flush(const InstDev& d, const double* sacc, int copy) {
+__device__ void flush(const InstDev& d, const double* sacc, int r, int copy) {
   const int ng = d.ng;
+  const size_t off = ((size_t)r * VP_MAX_ACC_COPIES + (size_t)copy) * (size_t)ng;
   if constexpr (MODE == kFP32) {
     const float* a = reinterpret_cast<const float*>(sacc);
-    VPG float* gacc = gp<float>(d.acc) + (size_t)copy * ng;
+    VPG float* gacc = gp<float>(d.acc) + off;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const float v = a[j];
       if (v != 0.0f) gadd(gacc + j, v);
     }
   } else if constexpr (MODE == kFP32TwoSum) {
     const unsigned long long* wv = reinterpret_cast<const unsigned long long*>(sacc);
-    VPG double* gacc = gp(d.acc) + (size_t)copy * ng;
+    VPG double* gacc = gp(d.acc) + off;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const unsigned long long w = wv[j];
       const double v = (double)__uint_as_float((unsigned)(w & 0xffffffffull)) +
@@ -181,38 +190,13 @@ __device__ void flush(const InstDev& d, const double* sacc, int copy) {
       if (v != 0.0) gadd(gacc + j, v);
     }
   } else {
-    VPG double* gacc = gp(d.acc) + (size_t)copy * ng;
+    VPG double* gacc = gp(d.acc) + off;
     for (int j = threadIdx.x; j < ng; j += TPB) {
       const double v = sacc[j];
       if (v != 0.0) gadd(gacc + j, v);
     }
   }
 }
-
-// Count this workgroup's tile as done; true in the workgroup that completes the instance.
-// Every wave first waits until its own device-scope atomics (load flush and kinetic sums)
-// have been performed; the ticket is then taken by one thread.  The completing workgroup
-// reads those sums with device-scope loads.  No cache write-back is needed because all
-// cross-workgroup data of the pass travels through device-scope atomics.
-__device__ bool arrive(const InstDev& d, int* sflag) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    VPG InstScal* sc = gp(d.scal);
-    const unsigned prev = __hip_atomic_fetch_add(&sc->ticket, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    *sflag = (prev + 1u == (unsigned)d.ntiles) ? 1 : 0;
-  }
-  __syncthreads();
-  return *sflag != 0;
-}
-
-
-// ------------------------------------------------------------------ Poisson solve
-// The solve runs on ONE wavefront (64 lanes) so that it needs no workgroup barrier: lane l
-// owns the contiguous nodes [l*per, (l+1)*per), per = ceil(Ng / 64), and cross-lane sums and
-// scans go through shuffles.  LDS traffic between lanes stays inside the wavefront, whose
-// LDS operations execute in issue order.
 
 // Wavefront collectives built from DPP row moves (VALU, no LDS round trip): a 64-lane
 // inclusive scan is row_shr 1, 2, 4, 8 inside each 16-lane row, then row_bcast 15 and 31
@@ -291,93 +275,228 @@ __device__ void bit_reverse_wave(double* re, double* im, int ng, int m, int lane
   __builtin_amdgcn_wave_barrier();
 }
 
-// Solve for one instance by one workgroup, LDS scratch of 4*Ng doubles at `sm` plus
-// kSolveScal doubles at `ss`:
-//   b_j   = sum of the accumulator copies (then cleared);
-//   b~_j  = b_j - mean(b)                                  (float64, eq. neutrality);
-//   E, Phi from A Phi = b~, 1^T Phi = 0                     (scan or FFT);
-//   g_e   = -(b~_e + b~_{e+1}) / (2h)   (lumped projection of E onto P1, differentiated;
-//           equal to -(E_{e+1} - E_{e-1}) / (2h) by (A Phi)_j = E_j - E_{j-1});
-//   W     = (1/2) h sum_e E_e^2;  E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng).
-// With `record`, first write the record of the integer step whose particle pass just ran
-// (kinetic sums of the pass + the field summary of the previous solve) and advance.
-// Three phases: every thread loads (one memory round trip), wavefront 0 computes in LDS
-// without workgroup barriers, every thread stores.  All threads of the workgroup call it.
-constexpr int kSolveScal = 9;
+// ------------------------------------------------------------------ Poisson solve
+// Every solve (the prologue of each fused workgroup and the materialising kernel) runs on
+// the first kSolveThreads threads with the same node split, so the arithmetic, and hence the
+// field, is bitwise the same whatever the workgroup size: thread t owns the contiguous nodes
+// [t*per, (t+1)*per), per = max(1, Ng / kSolveThreads).  Sums go through fixed DPP wave
+// trees and the four wave totals in order.
+constexpr int kSolveThreads = 256;
+constexpr int kSolveWaves = kSolveThreads / 64;
+constexpr int kSolvePer = VP_MAX_NG / kSolveThreads;
+// LDS doubles for the solve's wave totals: mean | scan carries | gauge sums | W | Re E1 |
+// Im E1 | K | momentum | charge
+constexpr int kSolveRed = 9 * kSolveWaves;
 
-template <int MODE, int TPB>
-__device__ __forceinline__ void solve_block(const InstDev& d, double* sm, double* ss, bool record) {
-  const int ng = d.ng, mask = ng - 1, halfn = ng >> 1;
-  const int tid = threadIdx.x, lane = tid & 63;
-  double* bt = sm;            // b, then b~
-  double* tw = sm + ng;       // cos / sin (2 pi t / Ng), t < Ng/2, interleaved
-  double* re = sm + 2 * ng;   // prefix sums / FFT real part, then Phi
-  double* im = sm + 3 * ng;   // FFT imaginary part, then E
-  double* E = im;
-  const int copies = d.acc_copies;
-  VPG InstScal* sc = gp(d.scal);
+__device__ __forceinline__ int ring_next(int r) { return r == kRing - 1 ? 0 : r + 1; }
+__device__ __forceinline__ int ring_prev(int r) { return r == 0 ? kRing - 1 : r - 1; }
 
-  // ---- phase 1: loads (and clearing of the accumulators)
-  {
-    const VPG double* tw_g = gp(d.tw);
-    for (int j = tid; j < ng; j += TPB) {
-      double t[VP_MAX_ACC_COPIES];
+// Element offset of accumulator copy c of ring entry r (in doubles, or in floats for kFP32).
+__device__ __forceinline__ size_t acc_off(const InstDev& d, int r, int c) {
+  return ((size_t)r * VP_MAX_ACC_COPIES + (size_t)c) * (size_t)d.ng;
+}
+
+__device__ __forceinline__ int solve_per(int ng) {
+  return ng >= kSolveThreads ? ng / kSolveThreads : 1;
+}
+
+// What a solving thread loads up front: its nodes' load-vector values and, when the field
+// summary is wanted, the Fourier weights cos / sin(2 pi e / Ng) of those nodes.
+struct SolveIn {
+  double b[kSolvePer];
+  double c[kSolvePer];
+  double s[kSolvePer];
+  double kin[3];  // this thread's share of the previous pass's per-tile kinetic sums
+};
+
+// Sum over tiles t = tid, tid + kSolveThreads, ... (in that order) of the per-tile kinetic
+// sums of ring entry r, eight loads in flight at a time.
+__device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[3]) {
+  kin[0] = kin[1] = kin[2] = 0.0;
+  const VPG double* base = gp(d.kin) + (size_t)r * d.kin_cap * kKinFields;
+  for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += 8 * kSolveThreads) {
+    double v[8][3];
 #pragma unroll
-      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) {
-        t[c] = 0.0;
-        if (c < copies) {
-          if constexpr (MODE == kFP32)
-            t[c] = (double)gld(gp<float>(d.acc) + (size_t)c * ng + j);
-          else
-            t[c] = gld(gp(d.acc) + (size_t)c * ng + j);
-        }
-      }
-      double b = 0.0;
-#pragma unroll
-      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) b += t[c];
-      bt[j] = b;
-      tw[j] = tw_g[j];
-      for (int c = 0; c < copies; ++c) {
-        if constexpr (MODE == kFP32)
-          gst(gp<float>(d.acc) + (size_t)c * ng + j, 0.0f);
-        else
-          gst(gp(d.acc) + (size_t)c * ng + j, 0.0);
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * kSolveThreads;
+      v[u][0] = v[u][1] = v[u][2] = 0.0;
+      if (t < d.ntiles) {
+        v[u][0] = base[(size_t)t * kKinFields];
+        v[u][1] = base[(size_t)t * kKinFields + 1];
+        v[u][2] = base[(size_t)t * kKinFields + 2];
       }
     }
-    if (record && tid == 0) {
-      ss[0] = gld(&sc->K);
-      ss[1] = gld(&sc->mom);
-      ss[2] = gld(&sc->chg);
-      ss[3] = sc->W;
-      ss[4] = sc->e1r;
-      ss[5] = sc->e1i;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      kin[0] += v[u][0];
+      kin[1] += v[u][1];
+      kin[2] += v[u][2];
     }
   }
-  __syncthreads();
+}
 
-  // ---- phase 2: wavefront 0 solves (lane l owns nodes [l*per, l*per + cnt), in registers)
-  if (tid < 64) {
-    constexpr int kMaxPer = VP_MAX_NG / 64;
-    const int per = (ng + 63) / 64;
-    const int j0 = lane * per;
-    const int cnt = (j0 < ng) ? min(per, ng - j0) : 0;
-    const double h = d.h, inv_h = d.inv_h;
-    double x[kMaxPer], Ev[kMaxPer];
-    double part = 0.0;
+template <int MODE, int COPIES>
+__device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0, int per,
+                                            double (&b)[kSolvePer]) {
+  double t[COPIES][kSolvePer];
 #pragma unroll
-    for (int k = 0; k < kMaxPer; ++k) {
-      x[k] = (k < cnt) ? bt[j0 + k] : 0.0;
-      part += x[k];
-    }
-    const double mean = wave_sum(part) / (double)ng;
+  for (int c = 0; c < COPIES; ++c)
 #pragma unroll
-    for (int k = 0; k < kMaxPer; ++k)
-      if (k < cnt) {
-        x[k] = x[k] - mean;
-        bt[j0 + k] = x[k];
+    for (int k = 0; k < kSolvePer; ++k) {
+      t[c][k] = 0.0;
+      if (k < per) {
+        if constexpr (MODE == kFP32)
+          t[c][k] = (double)gp<float>(d.acc)[acc_off(d, r, c) + j0 + k];
+        else
+          t[c][k] = gp(d.acc)[acc_off(d, r, c) + j0 + k];
       }
-    if (d.solver == VP_SOLVE_FFT) {
-      __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+  for (int k = 0; k < kSolvePer; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < COPIES; ++c) v += t[c][k];  // copy order
+    b[k] = v;
+  }
+}
+
+// Issue the solve's loads (load vector of ring entry r; with want_sum also the Fourier
+// weights and the kinetic sums of the previous pass, ring entry r-1): all of them before
+// any use, so they overlap other work of the caller.
+template <int MODE>
+__device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_sum, SolveIn& in) {
+  const int ng = d.ng, tid = threadIdx.x;
+  const int per = solve_per(ng), j0 = tid * per;
+#pragma unroll
+  for (int k = 0; k < kSolvePer; ++k) in.b[k] = in.c[k] = in.s[k] = 0.0;
+  in.kin[0] = in.kin[1] = in.kin[2] = 0.0;
+  if (tid >= kSolveThreads) return;
+  if (want_sum) load_kin(d, ring_prev(r), in.kin);
+  if (j0 >= ng) return;
+  switch (d.acc_copies) {
+    case 1: load_copies<MODE, 1>(d, r, j0, per, in.b); break;
+    case 2: load_copies<MODE, 2>(d, r, j0, per, in.b); break;
+    case 3: load_copies<MODE, 3>(d, r, j0, per, in.b); break;
+    case 4: load_copies<MODE, 4>(d, r, j0, per, in.b); break;
+    default: load_copies<MODE, VP_MAX_ACC_COPIES>(d, r, j0, per, in.b); break;
+  }
+  if (want_sum) {
+    const VPG double* tw = gp(d.tw);
+    const int halfn = ng >> 1;
+#pragma unroll
+    for (int k = 0; k < kSolvePer; ++k)
+      if (k < per) {
+        const int e = j0 + k, t = e & (halfn - 1);
+        const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
+        in.c[k] = sg * tw[2 * t];
+        in.s[k] = sg * tw[2 * t + 1];
+      }
+  }
+}
+
+// Sum of one value per solving thread (fixed DPP tree, then the wave totals in order),
+// published through red[slot*kSolveWaves ..] at the caller's next barrier.
+__device__ __forceinline__ void solve_wave_total(double v, double* red, int slot) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[slot * kSolveWaves + (threadIdx.x >> 6)] = v;
+}
+__device__ __forceinline__ double solve_total(const double* red, int slot) {
+  return red[slot * kSolveWaves] + red[slot * kSolveWaves + 1] + red[slot * kSolveWaves + 2] +
+         red[slot * kSolveWaves + 3];
+}
+
+// From the loaded values, compute into LDS:
+//   bt_j = b~_j = b_j - mean(b)                          (float64, eq. neutrality);
+//   E_e  from A Phi = b~, 1^T Phi = 0: E_e - E_{e-1} = b~_e (row j of A Phi = b~ written with
+//        E_e = (Phi_e - Phi_{e+1}) / h) and sum_e E_e = 0, so E_e = S_e + C with
+//        S_e = sum_{j=1..e} b~_j and C = -(1/Ng) sum_{j>=1} (Ng - j) b~_j;  or by FFT;
+//   g_e  = -(b~_e + b~_{e+1}) / (2h): the lumped L2 projection of E onto P1, differentiated;
+//   phi  (only when `phi` is given): nodal potential, zero mean;
+// and, with want_sum, sum[0..2] = W = (1/2) h sum_e E_e^2 and
+// E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng), sum[3..5] = K, momentum, charge of the previous
+// pass (its per-tile sums in tile order), in every thread.
+// `fft` is LDS scratch of 3 Ng doubles (FFT solver only).  All threads of the workgroup call
+// it (it holds workgroup barriers; want_sum must be uniform); on return bt, E, g (and phi)
+// are visible to all threads.
+template <int TPB>
+__device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum, double* bt,
+                              double* E, double* g, double* red, double* fft, double* phi,
+                              double* sum) {
+  const int ng = d.ng, mask = ng - 1, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int per = solve_per(ng), j0 = tid * per;
+  const bool solver_thread = tid < kSolveThreads;           // whole waves
+  const bool act = solver_thread && j0 < ng;
+  const bool use_fft = d.solver == VP_SOLVE_FFT;
+
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSolvePer; ++k)
+    if (act && k < per) part += in.b[k];
+  if (solver_thread) {
+    solve_wave_total(part, red, 0);
+    if (want_sum) {
+      solve_wave_total(in.kin[0], red, 6);
+      solve_wave_total(in.kin[1], red, 7);
+      solve_wave_total(in.kin[2], red, 8);
+    }
+  }
+  if (use_fft) {  // twiddles for the wavefront FFT
+    const VPG double* tw_g = gp(d.tw);
+    for (int j = tid; j < ng; j += TPB) fft[2 * ng + j] = tw_g[j];
+  }
+  __syncthreads();
+  const double mean = solve_total(red, 0) / (double)ng;
+
+  double S[kSolvePer];
+  double tot = 0.0, wsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSolvePer; ++k) {
+    S[k] = 0.0;
+    if (act && k < per) {
+      const int j = j0 + k;
+      const double x = in.b[k] - mean;
+      bt[j] = x;
+      if (j > 0) {
+        tot += x;
+        wsum += (double)(ng - j) * x;
+      }
+      S[k] = tot;
+    }
+  }
+  double wp = 0.0, er = 0.0, ei = 0.0;  // field-summary partials of this thread's nodes
+  if (!use_fft) {
+    double off = 0.0;
+    if (solver_thread) {
+      const double incl = wave_incl_scan(tot);
+      off = incl - tot;
+      if (lane == 63) red[kSolveWaves + wid] = incl;
+      solve_wave_total(wsum, red, 2);
+    }
+    __syncthreads();
+    if (act) {
+      for (int w = 0; w < wid; ++w) off += red[kSolveWaves + w];
+      const double C = -solve_total(red, 2) / (double)ng;
+#pragma unroll
+      for (int k = 0; k < kSolvePer; ++k)
+        if (k < per) {
+          const double Ee = (S[k] + off) + C;
+          E[j0 + k] = Ee;
+          wp += Ee * Ee;
+          er += Ee * in.c[k];
+          ei -= Ee * in.s[k];
+        }
+    }
+    if (want_sum && solver_thread) {
+      solve_wave_total(wp, red, 3);
+      solve_wave_total(er, red, 4);
+      solve_wave_total(ei, red, 5);
+    }
+  } else {
+    __syncthreads();  // b~ and the twiddles in LDS
+    if (tid < 64) {
+      double* re = fft;
+      double* im = fft + ng;
+      const double* tw = fft + 2 * ng;
       const int m = d.log2ng;
       for (int j = lane; j < ng; j += 64) {
         re[j] = bt[j];
@@ -398,126 +517,91 @@ __device__ __forceinline__ void solve_block(const InstDev& d, double* sm, double
       const double inv_ng = 1.0 / (double)ng;
       for (int j = lane; j < ng; j += 64) re[j] = re[j] * inv_ng;  // Phi
       __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) {
-          const int e = j0 + k;
-          Ev[k] = -(re[(e + 1) & mask] - re[e]) * inv_h;
-        }
-    } else {
-      // Gauss law: E_e = C + sum_{j=1..e} b~_j with C such that sum_e E_e = 0; then
-      // Phi_e = Phi_0 - h sum_{k<e} E_k with sum_j Phi_j = 0.
-      double run = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) {
-          run += (j0 + k == 0) ? 0.0 : x[k];
-          Ev[k] = run;
-        }
-      const double off = wave_excl_scan(run, lane);
-      double tp = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) {
-          Ev[k] = Ev[k] + off;
-          tp += Ev[k];
-        }
-      const double C = -wave_sum(tp) / (double)ng;
-      double run2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) {
-          Ev[k] = Ev[k] + C;
-          x[k] = run2;  // exclusive prefix of E within the lane
-          run2 += Ev[k];
-        }
-      const double off2 = wave_excl_scan(run2, lane);
-      double up = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) {
-          x[k] = x[k] + off2;
-          up += x[k];
-        }
-      const double Um = wave_sum(up) / (double)ng;
-#pragma unroll
-      for (int k = 0; k < kMaxPer; ++k)
-        if (k < cnt) re[j0 + k] = -h * (x[k] - Um);  // Phi
-    }
-    double wpart = 0.0, e1r = 0.0, e1i = 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxPer; ++k)
-      if (k < cnt) {
-        const int e = j0 + k;
-        const double Ee = Ev[k];
-        E[e] = Ee;
-        wpart += Ee * Ee;
-        const int t = e & (halfn - 1);
-        const double sg = (e < halfn) ? 1.0 : -1.0;  // cos/sin of theta + pi
-        e1r += Ee * (sg * tw[2 * t]);
-        e1i -= Ee * (sg * tw[2 * t + 1]);
+      const double inv_h = d.inv_h;
+      for (int e = lane; e < ng; e += 64) {
+        E[e] = -(re[(e + 1) & mask] - re[e]) * inv_h;
+        if (phi) phi[e] = re[e];
       }
-    const double Wn = 0.5 * h * wave_sum(wpart);
-    const double E1r = wave_sum(e1r) / (double)ng;
-    const double E1i = wave_sum(e1i) / (double)ng;
-    if (lane == 0) {
-      ss[6] = Wn;
-      ss[7] = E1r;
-      ss[8] = E1i;
+    }
+    if (want_sum) {
+      __syncthreads();  // E complete
+      if (act)
+#pragma unroll
+        for (int k = 0; k < kSolvePer; ++k)
+          if (k < per) {
+            const double Ee = E[j0 + k];
+            wp += Ee * Ee;
+            er += Ee * in.c[k];
+            ei -= Ee * in.s[k];
+          }
+      if (solver_thread) {
+        solve_wave_total(wp, red, 3);
+        solve_wave_total(er, red, 4);
+        solve_wave_total(ei, red, 5);
+      }
+    }
+  }
+  __syncthreads();  // bt, E and the summary totals complete
+  if (want_sum) {
+    sum[0] = 0.5 * d.h * solve_total(red, 3);
+    sum[1] = solve_total(red, 4) / (double)ng;
+    sum[2] = solve_total(red, 5) / (double)ng;
+    sum[3] = solve_total(red, 6);
+    sum[4] = solve_total(red, 7);
+    sum[5] = solve_total(red, 8);
+  }
+  const double half_inv_h = 0.5 * d.inv_h;
+  for (int e = tid; e < ng; e += TPB) g[e] = -(bt[e] + bt[(e + 1) & mask]) * half_inv_h;
+  if (phi && !use_fft) {
+    // Phi_e = -h (P_e - mean(P)), P_e = sum_{k<e} E_k; sum_e P_e = sum_k (Ng-1-k) E_k
+    double P[kSolvePer];
+    double ptot = 0.0, pw = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSolvePer; ++k) {
+      P[k] = 0.0;
+      if (act && k < per) {
+        const int j = j0 + k;
+        P[k] = ptot;
+        const double Ej = E[j];
+        ptot += Ej;
+        pw += (double)(ng - 1 - j) * Ej;
+      }
+    }
+    double poff = 0.0;
+    if (solver_thread) {
+      const double incl = wave_incl_scan(ptot);
+      poff = incl - ptot;
+      if (lane == 63) red[kSolveWaves + wid] = incl;
+      solve_wave_total(pw, red, 2);
+    }
+    __syncthreads();
+    if (act) {
+      for (int w = 0; w < wid; ++w) poff += red[kSolveWaves + w];
+      const double Pm = solve_total(red, 2) / (double)ng;
+#pragma unroll
+      for (int k = 0; k < kSolvePer; ++k)
+        if (k < per) phi[j0 + k] = -d.h * ((P[k] + poff) - Pm);
     }
   }
   __syncthreads();
+}
 
-  // ---- phase 3: stores
-  {
-    VPG double* bt_g = gp(d.bt);
-    VPG double* E_g = gp(d.E);
-    VPG double* g_g = gp(d.g);
-    VPG double* Phi_g = gp(d.Phi);
-    VPG float* Ef_g = gp(d.Ef);
-    VPG float* gf_g = gp(d.gf);
-    const double half_inv_h = 0.5 * d.inv_h;
-    for (int e = tid; e < ng; e += TPB) {
-      const double Ee = E[e];
-      const double b0 = bt[e];
-      const double g = -(b0 + bt[(e + 1) & mask]) * half_inv_h;
-      bt_g[e] = b0;
-      E_g[e] = Ee;
-      Ef_g[e] = (float)Ee;
-      g_g[e] = g;
-      gf_g[e] = (float)g;
-      Phi_g[e] = re[e];
-    }
-    if (tid == 0) {
-      const double Wn = ss[6];
-      if (record) {
-        const long long step = sc->step;
-        const double K = ss[0], mom = ss[1], chg = ss[2], Wold = ss[3];
-        VPG double* r = gp(d.hist) + (size_t)(step % d.hist_cap) * kHistFields;
-        r[0] = (double)step;
-        r[1] = (double)step * d.dt;
-        r[2] = K;
-        r[3] = Wold;
-        r[4] = K + Wold;
-        r[5] = chg;
-        r[6] = mom;
-        r[7] = sqrt(2.0 * Wold / d.L);
-        r[8] = ss[4];
-        r[9] = ss[5];
-        if (!isfinite(K) || !isfinite(Wold)) sc->nonfinite = 1;
-        gst(&sc->K, 0.0);
-        gst(&sc->mom, 0.0);
-        gst(&sc->chg, 0.0);
-        sc->step = step + 1;
-        sc->pending = 1;
-      }
-      sc->W = Wn;
-      sc->e1r = ss[7];
-      sc->e1i = ss[8];
-      if (!isfinite(Wn)) sc->nonfinite = 1;
-      __hip_atomic_store(&sc->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+// Record of integer step `step` (kinetic sums of that step's pass, field summary of its
+// field) into the history ring; flags non-finite values.  One thread.
+__device__ void write_record(const InstDev& d, long long step, double K, double mom, double chg,
+                             double W, double e1r, double e1i) {
+  VPG double* r = gp(d.hist) + (size_t)(step % d.hist_cap) * kHistFields;
+  r[0] = (double)step;
+  r[1] = (double)step * d.dt;
+  r[2] = K;
+  r[3] = W;
+  r[4] = K + W;
+  r[5] = chg;
+  r[6] = mom;
+  r[7] = sqrt(2.0 * W / d.L);
+  r[8] = e1r;
+  r[9] = e1i;
+  if (!isfinite(K) || !isfinite(W)) gp(d.scal)->nonfinite = 1;
 }
 
 // ------------------------------------------------------------------ particle passes
@@ -535,36 +619,68 @@ __device__ __forceinline__ void solve_block(const InstDev& d, double* sm, double
 
 #define VP_TILE_LOOP_END }
 
-// One fused step for every tile: [pending half-kick] -> kinetic sums at the integer step
-// -> half-kick -> drift -> deposit of the drifted state -> (last workgroup) solve.
-// Thread t handles particles tile.begin + k * TPB + t, k < ppt, kGroup at a time with all
-// loads of a group issued before any use; the first group is in flight while the field is
-// staged in LDS.
-constexpr int kGroup = 4;
+// LDS of the fused kernel, in doubles: E [0, Ng), g [Ng, 2Ng), deposit grid [2Ng, 3Ng),
+// b~ [3Ng, 4Ng), FFT scratch [4Ng, 7Ng) (FFT solver only).
+__host__ __device__ constexpr size_t fused_lds_doubles(bool fft) { return fft ? 7 : 4; }
+
+// One fused step of every tile, in phase r:
+//   solve the field of the current positions from ring entry r (every workgroup, redundantly,
+//   while its first particle loads are in flight) ->
+//   [pending half-kick] -> kinetic sums at the integer step -> half-kick -> drift ->
+//   deposit of the drifted state into ring entry r+1.
+// The first tile of each instance also records the previous integer step (its kinetic sums
+// and field summary are complete once the previous launch ended), stores this step's field
+// summary, clears ring entry r+2 and advances the step counter.  No workgroup waits for
+// another: the next launch reads what this one deposited.
+// Particles per thread whose loads are in flight together (float64 state at 1024 threads
+// per workgroup holds two, to stay within 128 registers without spilling).
+template <int MODE, int TPB>
+__host__ __device__ constexpr int group_of() { return (MODE == kFP64 && TPB == 1024) ? 2 : 4; }
 
 template <int MODE, int TPB>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
-                                               int ppt) {
+                                               int ppt, int phase) {
   extern __shared__ double smem[];
   __shared__ double red[3 * (TPB / 64)];
-  __shared__ double ss[kSolveScal];
-  __shared__ int sflag;
+  __shared__ double sred[kSolveRed];
   using T = typename StateType<MODE>::T;
+  constexpr int kGroup = group_of<MODE, TPB>();
   const Tile tl = tiles[tile0 + blockIdx.x];
   const InstDev& d = insts[tl.inst];
   const int ng = d.ng;
+  const int r0 = phase, r1 = ring_next(phase), r2 = ring_prev(phase);
   VPG T* __restrict__ Qp = gp<T>(d.Q);
   VPG T* __restrict__ Pp = gp<T>(d.P);
   VPG T* __restrict__ qsp = gp<T>(d.qs);
   VPG T* __restrict__ psp = gp<T>(d.ps);
   const VPG T* __restrict__ psip = gp<T>(d.psi);
-  double* fld = smem;
+  double* fE = smem;
+  double* fG = smem + ng;
   double* sacc = smem + 2 * ng;
-  double Ks = 0.0, Ms = 0.0, Cs = 0.0;
-  int pend = 0;
+  double* bt = smem + 3 * ng;
+  double* fft = smem + 4 * ng;
+  VPG InstScal* sc = gp(d.scal);
+  const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
 
-  for (int k0 = 0; k0 < ppt; k0 += kGroup) {
+  SolveIn sin_;
+  solve_load<MODE>(d, r0, first, sin_);
+  for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
+  const int pend = sc->pend[r0];
+  // the first tile records the previous step (if it was a fused step of this instance):
+  // its inputs are read now and written after the solve
+  long long step = 0;
+  double rec[3] = {0.0, 0.0, 0.0};
+  if (first) {
+    step = sc->step;
+    rec[0] = sc->W[r2];
+    rec[1] = sc->e1r[r2];
+    rec[2] = sc->e1i[r2];
+  }
+  double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+
+  const int nloop = ppt > 0 ? ppt : 1;  // the solve below runs in the first iteration
+  for (int k0 = 0; k0 < nloop; k0 += kGroup) {
     T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
     long long idx[kGroup];
     bool v[kGroup];
@@ -574,26 +690,44 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       v[u] = (k0 + u < ppt) && (loc < tl.count);
       idx[u] = tl.begin + loc;
       if (v[u]) {
-        q[u] = Qp[idx[u]]; p[u] = Pp[idx[u]]; a[u] = qsp[idx[u]]; b[u] = psp[idx[u]];
-        w[u] = psip[idx[u]];
+        q[u] = ntld(Qp + idx[u]); p[u] = ntld(Pp + idx[u]); a[u] = ntld(qsp + idx[u]);
+        b[u] = ntld(psp + idx[u]); w[u] = ntld(psip + idx[u]);
       }
     }
-    if (k0 == 0) {  // the field is staged while the first group's loads are in flight
-      stage<MODE, TPB>(d, fld, sacc, true, true);
-      pend = gp(d.scal)->pending;
+    if (k0 == 0) {  // uniform: every thread runs the first group
+      double sum[6];
+      solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+      if (first) {
+        const int copies = d.acc_copies;
+        for (int c = 0; c < copies; ++c)
+          for (int j = threadIdx.x; j < ng; j += TPB) {
+            if constexpr (MODE == kFP32)
+              gp<float>(d.acc)[acc_off(d, r2, c) + j] = 0.0f;
+            else
+              gp(d.acc)[acc_off(d, r2, c) + j] = 0.0;
+          }
+        if (threadIdx.x == 0) {
+          if (pend && step >= 1)
+            write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
+          sc->W[r0] = sum[0];
+          sc->e1r[r0] = sum[1];
+          sc->e1i[r0] = sum[2];
+          if (!isfinite(sum[0])) sc->nonfinite = 1;
+          sc->pend[r1] = 1;
+          sc->step = step + 1;
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       if (!v[u]) continue;
       if constexpr (MODE == kFP32) {
-        const float* fE = reinterpret_cast<const float*>(fld);
-        const float* fG = fE + ng;
         float* fa = reinterpret_cast<float*>(sacc);
         const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
         float Q = q[u], P = p[u], qs = a[u], ps = b[u];
         const float psi = w[u];
         const int i = cell_of_f(Q * ihf, ng);
-        const float Ei = fE[i], gi = fG[i];
+        const float Ei = (float)fE[i], gi = (float)fG[i];
         if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
         const double Pd = P, qd = qs, wd = psi;
         Ks += 0.5 * wd * Pd * Pd + qd * Pd;
@@ -605,7 +739,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         if (Qn < 0.0f) Qn += Lf;
         if (Qn >= Lf) Qn -= Lf;
         ps = ps - dtf * qs;
-        Qp[idx[u]] = Qn; Pp[idx[u]] = P; qsp[idx[u]] = qs; psp[idx[u]] = ps;
+        ntst(Qp + idx[u], Qn); ntst(Pp + idx[u], P); ntst(qsp + idx[u], qs); ntst(psp + idx[u], ps);
         const float x = Qn * ihf;
         const int j = cell_of_f(x, ng);
         const float s = frac01_f(x, j);
@@ -616,7 +750,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         const double Q = q[u], psi = w[u];
         double P = p[u], qs = a[u], ps = b[u];
         const int i = cell_of(Q * inv_h, ng);
-        const double Ei = fld[i], gi = fld[ng + i];
+        const double Ei = fE[i], gi = fG[i];
         if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
         Ks += 0.5 * psi * P * P + qs * P;
         Ms += psi * P + qs;
@@ -628,7 +762,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         if (Qn >= L) Qn -= L;
         const double psn = ps - dt * qs;
         const T Qs = (T)Qn, pss = (T)psn;
-        Qp[idx[u]] = Qs; Pp[idx[u]] = (T)P; qsp[idx[u]] = (T)qs; psp[idx[u]] = pss;
+        ntst(Qp + idx[u], Qs); ntst(Pp + idx[u], (T)P); ntst(qsp + idx[u], (T)qs); ntst(psp + idx[u], pss);
         const double Qd = Qs, psd = pss;
         const double x = Qd * inv_h;
         const int j = cell_of(x, ng);
@@ -638,11 +772,9 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       }
     }
   }
-  if (ppt <= 0) {  // no particle work: still stage (zero the LDS grid) before the flush
-    stage<MODE, TPB>(d, fld, sacc, false, true);
-  }
 
-  // kinetic sums: wave butterflies, one barrier, one thread adds the workgroup totals
+  // kinetic sums: wave trees, one barrier, one thread stores the workgroup totals in this
+  // tile's slot (the next pass's first tile adds the slots in tile order)
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   Ks = wave_sum(Ks);
   Ms = wave_sum(Ms);
@@ -660,20 +792,19 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       mb += red[3 * w + 1];
       cbs += red[3 * w + 2];
     }
-    VPG InstScal* sc = gp(d.scal);
-    gadd(&sc->K, kb);
-    gadd(&sc->mom, mb);
-    gadd(&sc->chg, cbs);
+    VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
+    slot[0] = kb;
+    slot[1] = mb;
+    slot[2] = cbs;
   }
-  flush<MODE, TPB>(d, sacc, tl.local % d.acc_copies);
-  if (arrive(d, &sflag)) solve_block<MODE, TPB>(d, smem, ss, true);
+  flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
 }
 
-// Deposit of the current state only (eq. rhs-assembly), added to the global accumulator.
+// Deposit of the current state only (eq. rhs-assembly), added into ring entry `phase`.
 template <int MODE, int TPB>
 __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ insts,
                                                  const Tile* __restrict__ tiles, int tile0,
-                                                 int ppt) {
+                                                 int ppt, int phase) {
   extern __shared__ double smem[];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
@@ -722,16 +853,17 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
     VP_TILE_LOOP_END
   }
   __syncthreads();
-  flush<MODE, TPB>(d, sacc, tl.local % d.acc_copies);
+  flush<MODE, TPB>(d, sacc, phase, tl.local % d.acc_copies);
 }
 
-// Kick by `kick` then drift by `drift` with the current field.  With use_pending, the kick of
-// each instance is dt/2 when its half-kick is pending and 0 otherwise, and drift is 0.
+// Kick by `kick` then drift by `drift` with the field arrays.  With use_pending, the kick of
+// each instance is dt/2 when its half-kick is pending in phase `phase` and 0 otherwise, and
+// drift is 0.
 template <int MODE, int TPB>
 __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__ insts,
                                                      const Tile* __restrict__ tiles, int tile0,
                                                      int ppt, double kick_in, double drift_in,
-                                                     int use_pending) {
+                                                     int use_pending, int phase) {
   extern __shared__ double smem[];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[tile0 + blockIdx.x];
@@ -739,7 +871,7 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
   const int ng = d.ng;
   double kick = kick_in, drift = drift_in;
   if (use_pending) {
-    kick = gp(d.scal)->pending ? 0.5 * d.dt : 0.0;
+    kick = gp(d.scal)->pend[phase] ? 0.5 * d.dt : 0.0;
     drift = 0.0;
   }
   if (kick == 0.0 && drift == 0.0) return;  // uniform per workgroup: no barrier skipped
@@ -804,7 +936,7 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
 template <int MODE, int TPB>
 __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
                                               const Tile* __restrict__ tiles, int tile0,
-                                              int ppt) {
+                                              int ppt, int phase) {
   extern __shared__ double smem[];
   __shared__ double red[TPB / 64];
   using T = typename StateType<MODE>::T;
@@ -817,7 +949,7 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   const VPG T* __restrict__ qsp = gp<T>(d.qs);
   const VPG T* __restrict__ psp = gp<T>(d.ps);
   const VPG T* __restrict__ psip = gp<T>(d.psi);
-  const int pend = gp(d.scal)->pending;
+  const int pend = gp(d.scal)->pend[phase];
   double Ks = 0.0, Ms = 0.0, Cs = 0.0;
   if constexpr (MODE == kFP32) {
     const float* fE = reinterpret_cast<const float*>(smem);
@@ -870,33 +1002,107 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   }
 }
 
-// One workgroup per listed slot: solve and refresh the field summary (no record).
+// One workgroup per listed slot: solve the field of ring entry `phase` and write the field
+// arrays and the field summary (materialise); when the instance's last pass was a fused
+// step, also write that step's record (the next fused pass would write the same record).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_solve(const InstDev* __restrict__ insts,
-                                               const int* __restrict__ slots) {
+__global__ __launch_bounds__(kSolveThreads) void k_solve(const InstDev* __restrict__ insts,
+                                                         const int* __restrict__ slots,
+                                                         int phase) {
   extern __shared__ double smem[];
-  __shared__ double ss[kSolveScal];
+  __shared__ double sred[kSolveRed];
   const InstDev& d = insts[slots[blockIdx.x]];
-  solve_block<MODE, 256>(d, smem, ss, false);
+  const int ng = d.ng;
+  double* fE = smem;
+  double* fG = smem + ng;
+  double* phi = smem + 2 * ng;
+  double* bt = smem + 3 * ng;
+  double* fft = smem + 4 * ng;
+  SolveIn sin_;
+  solve_load<MODE>(d, phase, true, sin_);
+  double sum[6];
+  solve_compute<kSolveThreads>(d, sin_, true, bt, fE, fG, sred, fft, phi, sum);
+  VPG double* bt_g = gp(d.bt);
+  VPG double* E_g = gp(d.E);
+  VPG double* g_g = gp(d.g);
+  VPG double* Phi_g = gp(d.Phi);
+  VPG float* Ef_g = gp(d.Ef);
+  VPG float* gf_g = gp(d.gf);
+  for (int e = threadIdx.x; e < ng; e += kSolveThreads) {
+    const double Ee = fE[e], ge = fG[e];
+    bt_g[e] = bt[e];
+    E_g[e] = Ee;
+    Ef_g[e] = (float)Ee;
+    g_g[e] = ge;
+    gf_g[e] = (float)ge;
+    Phi_g[e] = phi[e];
+  }
+  if (threadIdx.x == 0) {
+    VPG InstScal* sc = gp(d.scal);
+    const int r2 = ring_prev(phase);
+    if (sc->pend[phase] && sc->step >= 1)
+      write_record(d, sc->step - 1, sum[3], sum[4], sum[5], sc->W[r2], sc->e1r[r2], sc->e1i[r2]);
+    sc->W[phase] = sum[0];
+    sc->e1r[phase] = sum[1];
+    sc->e1i[phase] = sum[2];
+    if (!isfinite(sum[0])) sc->nonfinite = 1;
+  }
+}
+
+// Ring maintenance, one workgroup per listed slot (see RingOp).
+template <typename A>
+__global__ __launch_bounds__(256) void k_ring(const InstDev* __restrict__ insts,
+                                              const int* __restrict__ slots, int op, int phase) {
+  const InstDev& d = insts[slots[blockIdx.x]];
+  const int ng = d.ng;
+  VPG A* acc = gp<A>(reinterpret_cast<A*>(d.acc));
+  for (int j = threadIdx.x; j < ng; j += 256) {
+    if (op == kRingFold) {
+      double s = 0.0;
+      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) s += (double)acc[acc_off(d, phase, c) + j];
+      acc[acc_off(d, phase, 0) + j] = (A)s;
+      for (int c = 1; c < VP_MAX_ACC_COPIES; ++c) acc[acc_off(d, phase, c) + j] = (A)0;
+      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) {
+        acc[acc_off(d, ring_next(phase), c) + j] = (A)0;
+        acc[acc_off(d, ring_prev(phase), c) + j] = (A)0;
+      }
+    } else {
+      for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) acc[acc_off(d, phase, c) + j] = (A)0;
+    }
+  }
+  if (op == kRingFold) {
+    // per-tile kinetic sums: the tile count may change, so each entry's sum moves to tile 0
+    // (one thread per entry and field, in tile order) and the other tiles are cleared
+    VPG double* kin = gp(d.kin);
+    __syncthreads();
+    if (threadIdx.x < kRing * 3) {
+      const int r = threadIdx.x / 3, f = threadIdx.x % 3;
+      VPG double* base = kin + (size_t)r * d.kin_cap * kKinFields + f;
+      double s = 0.0;
+      for (int t0 = 0; t0 < d.kin_cap; t0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (t0 + u < d.kin_cap) ? base[(size_t)(t0 + u) * kKinFields] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+      }
+      base[0] = s;
+      for (int t = 1; t < d.kin_cap; ++t) base[(size_t)t * kKinFields] = 0.0;
+    }
+  }
 }
 
 __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __restrict__ slots,
-                               int nslots, int op) {
+                               int nslots, int op, int phase) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslots) return;
   VPG InstScal* sc = gp(insts[slots[t]].scal);
   if (op == kScalClearDiag) {
-    sc->Kd = 0.0; sc->momd = 0.0; sc->chgd = 0.0;
+    sc->Kd = 0.0;
+    sc->momd = 0.0;
+    sc->chgd = 0.0;
   } else if (op == kScalClearPending) {
-    sc->pending = 0;
-  } else {
-    sc->K = sc->mom = sc->chg = 0.0;
-    sc->Kd = sc->momd = sc->chgd = 0.0;
-    sc->W = sc->e1r = sc->e1i = 0.0;
-    sc->step = 0;
-    sc->pending = 0;
-    sc->ticket = 0u;
-    sc->nonfinite = 0;
+    sc->pend[phase] = 0;
   }
 }
 
@@ -999,10 +1205,10 @@ __global__ __launch_bounds__(kBlock) void k_sort(const InstDev* __restrict__ ins
 // ------------------------------------------------------------------ host launchers
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-WsLayout workspace_layout(int ng, int hist_cap) {
+WsLayout workspace_layout(int ng, int hist_cap, long long n) {
   WsLayout w{};
   size_t o = 0;
-  w.acc = o;     o = align256(o + (size_t)VP_MAX_ACC_COPIES * ng * sizeof(double));
+  w.acc = o;     o = align256(o + (size_t)kRing * VP_MAX_ACC_COPIES * ng * sizeof(double));
   w.E = o;       o = align256(o + (size_t)ng * sizeof(double));
   w.g = o;       o = align256(o + (size_t)ng * sizeof(double));
   w.Ef = o;      o = align256(o + (size_t)ng * sizeof(float));
@@ -1013,9 +1219,12 @@ WsLayout workspace_layout(int ng, int hist_cap) {
   w.inv_lam = o; o = align256(o + (size_t)ng * sizeof(double));
   w.scal = o;    o = align256(o + sizeof(InstScal));
   w.hist = o;    o = align256(o + (size_t)hist_cap * kHistFields * sizeof(double));
+  w.kin = o;     o = align256(o + (size_t)kRing * kin_capacity(n) * kKinFields * sizeof(double));
   w.total = o;
   return w;
 }
+
+int kin_capacity(long long n) { return (int)((n + kMinTile - 1) / kMinTile); }
 
 size_t particle_lds_bytes(int /*mode*/, int max_ng) {
   return lds_doubles_per_node() * (size_t)max_ng * sizeof(double);
@@ -1043,18 +1252,19 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
   } while (0)
 
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                        int ntiles, int ppt, int max_ng, hipStream_t s) {
+                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  VP_DISPATCH(mode, tpb, k_fused, dim3(ntiles), dim3(tpb), particle_lds_bytes(mode, max_ng), s,
-              d_inst, d_tiles, tile0, ppt);
+  const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
+  VP_DISPATCH(mode, tpb, k_fused, dim3(ntiles), dim3(tpb), lds, s, d_inst, d_tiles, tile0, ppt,
+              phase);
   return hipGetLastError();
 }
 
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                          int ntiles, int ppt, int max_ng, hipStream_t s) {
+                          int ntiles, int ppt, int max_ng, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   VP_DISPATCH(mode, tpb, k_deposit, dim3(ntiles), dim3(tpb), particle_lds_bytes(mode, max_ng), s,
-              d_inst, d_tiles, tile0, ppt);
+              d_inst, d_tiles, tile0, ppt, phase);
   return hipGetLastError();
 }
 
@@ -1063,44 +1273,59 @@ hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Ti
                               hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   VP_DISPATCH(mode, tpb, k_gather_push, dim3(ntiles), dim3(tpb),
-              (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, kick, drift, 0);
+              (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, kick, drift, 0,
+              0);
   return hipGetLastError();
 }
 
 hipError_t launch_settle(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                         int ntiles, int ppt, int max_ng, hipStream_t s) {
+                         int ntiles, int ppt, int max_ng, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   VP_DISPATCH(mode, tpb, k_gather_push, dim3(ntiles), dim3(tpb),
-              (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, 0.0, 0.0, 1);
+              (size_t)2 * max_ng * sizeof(double), s, d_inst, d_tiles, tile0, ppt, 0.0, 0.0, 1,
+              phase);
   return hipGetLastError();
 }
 
 hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                       int ntiles, int ppt, int max_ng, hipStream_t s) {
+                       int ntiles, int ppt, int max_ng, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   VP_DISPATCH(mode, tpb, k_diag, dim3(ntiles), dim3(tpb), (size_t)2 * max_ng * sizeof(double), s,
-              d_inst, d_tiles, tile0, ppt);
+              d_inst, d_tiles, tile0, ppt, phase);
   return hipGetLastError();
 }
 
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
-                        int max_ng, hipStream_t s) {
+                        int max_ng, bool lds_fft, int phase, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
-  const size_t lds = lds_doubles_per_node() * (size_t)max_ng * sizeof(double);
+  const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
   if (mode == kFP64 || mode == kFP32TwoSum)
-    hipLaunchKernelGGL(k_solve<kFP64>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
+    hipLaunchKernelGGL(k_solve<kFP64>, dim3(nslots), dim3(kSolveThreads), lds, s, d_inst, d_slots,
+                       phase);
   else if (mode == kFP32Comp)
-    hipLaunchKernelGGL(k_solve<kFP32Comp>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
+    hipLaunchKernelGGL(k_solve<kFP32Comp>, dim3(nslots), dim3(kSolveThreads), lds, s, d_inst,
+                       d_slots, phase);
   else
-    hipLaunchKernelGGL(k_solve<kFP32>, dim3(nslots), dim3(256), lds, s, d_inst, d_slots);
+    hipLaunchKernelGGL(k_solve<kFP32>, dim3(nslots), dim3(kSolveThreads), lds, s, d_inst, d_slots,
+                       phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring(int mode, const InstDev* d_inst, const int* d_slots, int nslots, int op,
+                       int phase, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  if (mode == kFP32)
+    hipLaunchKernelGGL(k_ring<float>, dim3(nslots), dim3(256), 0, s, d_inst, d_slots, op, phase);
+  else
+    hipLaunchKernelGGL(k_ring<double>, dim3(nslots), dim3(256), 0, s, d_inst, d_slots, op, phase);
   return hipGetLastError();
 }
 
 hipError_t launch_slot_scalars(const InstDev* d_inst, const int* d_slots, int nslots, int op,
-                               hipStream_t s) {
+                               int phase, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slot_scalars, dim3((nslots + 63) / 64), dim3(64), 0, s, d_inst, d_slots,
-                     nslots, op);
+                     nslots, op, phase);
   return hipGetLastError();
 }
 
