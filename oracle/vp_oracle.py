@@ -16,8 +16,8 @@ Readings taken where the paper is silent (each is also listed in the design doc):
   * a particle sitting exactly on a node belongs to the element on its right;
   * the second derivative phi_h'' needed by the dipole equation (eq. sw-evolution) is
     taken from the lumped-mass L2 projection of the element-constant field E_h onto
-    P1, then differentiated on each element ("auxiliary projection step");
-  * "leapfrog as in standard PIC" is read as the kick-drift-kick Strang splitting of
+    P1, then differentiated on each element (the paper's projection step for phi_h'');
+  * the paper's leapfrog (the standard PIC one) is read as the kick-drift-kick Strang splitting of
     H_h = H_kin + H_field, each sub-flow solved exactly (derived from the 1D bracket,
     eq. lp1d): the kick freezes (Q, p*) and moves (P, q*), the drift freezes (P, q*)
     and moves (Q, p*).

@@ -399,3 +399,20 @@ def test_two_stream_root_value():
     with a purely growing root."""
     om = PH.two_stream_root(0.2, 2.4)
     assert abs(om.real) < 1e-8 and 0.2 < om.imag < 0.25
+
+
+def test_two_stream_growth_matches_dispersion_root():
+    """T-L2 on a small lattice: the two-stream configuration (k = 0.2, alpha = 1e-3, beams
+    +-2.4, T = 1, Ng = 64, 128 x 128 decorated particles, dt = 0.05) grows its mode-1 field
+    at the rate of the unstable root (gamma = 0.2258): a least-squares line through
+    log |E1| over t in [12, 26], after the stable beam modes have faded and before
+    saturation, within 3%.  A wrong sign in the kick or in the deposit's dipole term
+    turns the instability off."""
+    om = PH.two_stream_root(0.2, 2.4)
+    w = W.two_stream(nx=128, nv=128, ng=64)
+    st = w.state()
+    _, _, hist = O.run(st["Q"], st["P"], st["qs"], st["ps"], st["psi"], w.L, w.ng, w.dt, 540)
+    t = np.arange(len(hist)) * w.dt
+    a = np.array([abs(complex(h["e1_re"], h["e1_im"])) for h in hist])
+    g = PH.fit_growth(t, a, 12.0, 26.0)
+    assert abs(g - om.imag) < 0.03 * om.imag, (g, om.imag)
