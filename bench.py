@@ -143,6 +143,97 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_sweep(args):
+    """The uneven batched sweep (256 Landau instances): one fused launch per step for all
+    instances (batched) against one launch per instance per step (plain), same kernels,
+    same stream.  Prints one JSON line; `value` is the batched aggregate throughput."""
+    import numpy as np
+    import torch
+    import paper_2605_21794_amd as vp
+    import workloads as W
+    prec = args.precision or "fp32c"
+    ws = W.landau_sweep(n_inst=args.instances)
+    dt_np = np.float64 if prec == "fp64" else np.float32
+    sts = [w.state(dt_np) for w in ws]
+    ntot = sum(w.n for w in ws)
+    log(f"landau_sweep: {len(ws)} instances, sum N = {ntot}, precision {prec}")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    steps = args.steps
+
+    # batched: one engine, one fused launch per step for every instance
+    eng = vp.Engine(prec, max_slots=len(ws), stream=stream)
+    for s, (w, st) in enumerate(zip(ws, sts)):
+        eng.admit(s, st, w.L, w.ng, w.dt, hist_cap=max(64, steps + args.warmup + 8))
+    if args.launch:
+        t_, p_, a_ = (int(x) for x in args.launch.split(","))
+        eng.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
+    if not args.no_tune:
+        best, us = eng.tune(steps_per_trial=33)
+        log(f"batched: tuned launch shape {best} ({us:.2f} us/step)")
+    tun = eng.get_tuning()
+    eng.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    eng.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    kern_avg_s = ev0.elapsed_time(ev1) * 1e-3 / steps
+    log(f"batched: {steps} steps in {el_b * 1e3:.2f} ms ({kern_avg_s * 1e6:.2f} us per launch)")
+    wb = [eng.diagnostics(s, allow_nonfinite=True)["W"] for s in range(len(ws))]
+    eng.close()
+
+    # plain: one engine per instance, one launch per instance per step (graph-replayed)
+    sims = []
+    for w, st in zip(ws, sts):
+        sim = vp.Simulation(st, w.L, w.ng, w.dt, prec, stream=stream,
+                            hist_cap=max(64, steps + args.warmup + 8))
+        sim.set_tuning(threads=tun["threads"], ppt=tun["ppt"], acc_copies=tun["acc_copies"],
+                       graph_steps=tun["graph_steps"])
+        sims.append(sim)
+    for sim in sims:
+        sim.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    chunk = tun["graph_steps"]
+    while done < steps:
+        c = min(chunk, steps - done)
+        for sim in sims:
+            sim.step(c)
+        done += c
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    log(f"plain: {steps} steps in {el_p * 1e3:.2f} ms")
+    wp = [sim.diagnostics(0, allow_nonfinite=True)["W"] for sim in sims]
+    rel = max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(wb, wp))
+    for sim in sims:
+        sim.close()
+
+    value = ntot * steps / el_b
+    bytes_per_launch = FUSED_BYTES[prec] * ntot
+    achieved = bytes_per_launch / kern_avg_s / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "decorated-particle updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": el_b * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": "landau_sweep", "instances": len(ws), "n_total": ntot,
+                   "precision": prec, "launch": tun,
+                   "plain_value": ntot * steps / el_p, "batched_over_plain": el_p / el_b,
+                   "max_rel_W_difference_batched_vs_plain": rel},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fused", "bytes_per_launch": bytes_per_launch,
+                     "kernel_us": kern_avg_s * 1e6},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(state, w, budget_s: float, max_steps: int):
     """FP64 oracle steps on the same initial state until the time budget is spent."""
     import numpy as np
@@ -176,6 +267,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default=None)
+    ap.add_argument("--instances", type=int, default=256, help="landau_sweep instances")
     ap.add_argument("--launch", default=None,
                     help="threads,ppt,acc_copies for the fused kernel (use with --no-tune)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -189,10 +281,14 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (instance sharding across GPUs is described in DESIGN.md)",
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(whole instances would shard across GPUs with no exchange, and one large "
+              "instance would all-reduce its Ng-long load vector once per step)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "landau_sweep":
+        run_sweep(args)
+        return
 
     import numpy as np
     import torch

@@ -10,7 +10,7 @@ Decorated Particle Method for the Vlasov-Poisson System"), Section 5 "Discretiza
 space and time", in the normalised 1D1V setting e = m = eps0 = 1 on the periodic
 domain [0, L).
 
-Readings taken where the paper is silent (each is also listed in the design doc):
+Readings taken where the paper is silent:
   * finite elements are P1 (degree k = 1) on a uniform periodic mesh of Ng elements,
     h = L / Ng, element e = [e h, (e+1) h), nodes q_j = j h, node Ng == node 0;
   * a particle sitting exactly on a node belongs to the element on its right;
