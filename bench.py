@@ -170,7 +170,7 @@ def run_sweep(args):
         t_, p_, a_ = (int(x) for x in args.launch.split(","))
         eng.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
     if not args.no_tune:
-        best, us = eng.tune(steps_per_trial=33)
+        best, us = eng.tune(steps_per_trial=99)
         log(f"batched: tuned launch shape {best} ({us:.2f} us/step)")
     tun = eng.get_tuning()
     eng.step(args.warmup)
@@ -258,7 +258,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=198,
+                    help="untimed steps before the timed region (they also build the step "
+                         "graph, so keep at least two graphs' worth)")
     ap.add_argument("--workload", default="two_stream")
     ap.add_argument("--kernel-steps", type=int, default=0,
                     help="after the timed region, also time this many direct (non-graph) "
@@ -311,7 +313,7 @@ def main():
         t_, p_, a_ = (int(x) for x in args.launch.split(","))
         sim.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
     if not args.no_tune:
-        best, tuning_us = sim.tune(steps_per_trial=32)
+        best, tuning_us = sim.tune(steps_per_trial=99)
         log(f"tuned launch shape {best} ({tuning_us:.2f} us/step)")
     tun = sim.get_tuning()
 

@@ -228,15 +228,16 @@ vp_status ensure_graph(vp_handle* h) {
 // kRing-1 direct launches that bring the phase to the graph's), direct launches otherwise.
 vp_status advance(vp_handle* h, int k) {
   const bool graphs = h->tun.use_graph && h->stream != nullptr;
-  if (graphs && k >= graph_len_of(h) + vpk::kRing - 1) {
-    VP_TRY(ensure_graph(h));
-    while (h->phase != h->graph_phase) {
-      VP_TRY(launch_steps_direct(h, 1));
-      --k;
+  if (graphs && k >= graph_len_of(h)) {
+    VP_TRY(ensure_graph(h));  // captured at the current phase if there was none
+    const int lead = (h->graph_phase - h->phase + vpk::kRing) % vpk::kRing;
+    if (k - lead >= h->graph_len) {
+      VP_TRY(launch_steps_direct(h, lead));
+      k -= lead;
+      const int reps = k / h->graph_len;
+      for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
+      k -= reps * h->graph_len;
     }
-    const int reps = k / h->graph_len;
-    for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
-    k -= reps * h->graph_len;
   }
   return launch_steps_direct(h, k);
 }

@@ -17,6 +17,9 @@ that builds the initial decorated-particle arrays from `workloads.lattice`.
   served_stream      Poisson arrivals of mixed Landau / two-stream / bump-on-tail jobs with
                      N log-uniform in [2^12, 2^20], Ng in {64 .. 1024}, horizons 100-2000.
 
+Particles are stored in a seeded random order (like the arbitrary cluster order of a
+k-means initialisation); `order="lattice"` keeps the v-major lattice order.
+
 Every preset jitters the central particle in x only (jx = 1, jv = 0).  Velocity jitter
 makes q* = -(P - v_mean) psi* non-zero, and under free streaming the dipole offset p*/psi*
 then grows like (P - v_mean) t; once it exceeds the mesh size the first-order (k = 2)
@@ -52,6 +55,7 @@ class Workload:
     jx: float = 1.0
     jv: float = 0.0                # centre velocity at the cell midpoint (see module doc)
     rng_seedseq: object = None     # optional SeedSequence overriding `seed`
+    order: str = "random"          # particle order in memory: "random" or "lattice"
 
     @property
     def n(self) -> int:
@@ -72,7 +76,7 @@ class Workload:
         if self.rng_seedseq is not None:
             rng = np.random.default_rng(self.rng_seedseq)
         st = make_lattice(self.L, self.nx, self.nv, self.vmin, self.vmax, self.profile(),
-                          seed=self.seed, jx=self.jx, jv=self.jv, rng=rng)
+                          seed=self.seed, jx=self.jx, jv=self.jv, rng=rng, order=self.order)
         return cast_state(st, dtype)
 
 

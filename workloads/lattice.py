@@ -17,9 +17,11 @@ k-means cluster S_a):
         q*   = -int_C f0(x, v) (P - v);
   * integrals use 8-point Gauss-Legendre rules in x and in v; f0 is separable,
     f0(x, v) = X(x) V(v), for every workload here.
-Particle order is v-major: index a = iv * nx + ix, so neighbouring particles sit in
-neighbouring x cells.  RNG: NumPy PCG64 seeded from SeedSequence(seed); xi is drawn first
-as an (nv, nx) array, then eta.
+Particle order: by default a seeded random permutation of the cells (drawn after xi and
+eta), like the arbitrary cluster order of a k-means initialisation, so that particles that
+are neighbours in memory are not neighbours in phase space; order="lattice" keeps the
+v-major order a = iv * nx + ix.  RNG: NumPy PCG64 seeded from SeedSequence(seed); xi is
+drawn first as an (nv, nx) array, then eta, then the permutation.
 """
 from __future__ import annotations
 
@@ -65,7 +67,8 @@ def bump_on_tail_profile(alpha: float = 0.04, k: float = 0.3):
 
 
 def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
-                 seed: int = 0, jx: float = 1.0, jv: float = 1.0, rng=None):
+                 seed: int = 0, jx: float = 1.0, jv: float = 1.0, rng=None,
+                 order: str = "random"):
     """Return dict(Q, P, qs, ps, psi) of float64 arrays with nx*nv decorated particles."""
     X, V = profile
     dx = float(L) / nx
@@ -74,6 +77,9 @@ def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
         rng = np.random.default_rng(np.random.SeedSequence(seed))
     xi = rng.uniform(-0.5, 0.5, size=(nv, nx))
     eta = rng.uniform(-0.5, 0.5, size=(nv, nx))
+    if order not in ("random", "lattice"):
+        raise ValueError(f"unknown particle order {order!r}")
+    perm = rng.permutation(nx * nv) if order == "random" else None
 
     x0 = np.arange(nx, dtype=np.float64) * dx
     v0 = float(vmin) + np.arange(nv, dtype=np.float64) * dv
@@ -103,13 +109,10 @@ def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
         dvp = P[r0:r1, :, None] - vn[r0:r1, None, :]
         qs[r0:r1] = -Ix0[None, :] * np.sum(Vw[r0:r1, None, :] * dvp, axis=2)
 
-    return {
-        "Q": Q.reshape(-1).copy(),
-        "P": P.reshape(-1).copy(),
-        "qs": qs.reshape(-1).copy(),
-        "ps": ps.reshape(-1).copy(),
-        "psi": psi.reshape(-1).copy(),
-    }
+    out = {"Q": Q, "P": P, "qs": qs, "ps": ps, "psi": psi}
+    if perm is None:
+        return {k: v.reshape(-1).copy() for k, v in out.items()}
+    return {k: v.reshape(-1)[perm].copy() for k, v in out.items()}
 
 
 def cast_state(state: dict, dtype):
