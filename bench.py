@@ -2,6 +2,8 @@
 """Throughput of the decorated-particle step on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload two_stream|probe|landau_nonlinear]
+    python bench.py --workload landau_sweep      batched (256 uneven instances) vs plain
+    python bench.py --workload served            continuous batching of a job stream
     python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
     python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
     python bench.py --pmc-summary FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR --workload W
@@ -234,6 +236,48 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_served(args):
+    """Served request stream: seeded Poisson arrivals of mixed Landau / two-stream /
+    bump-on-tail jobs, continuously batched over the slots of one engine.  Prints one JSON
+    line with aggregate updates/s and p50/p99 step and job latency."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2605_21794_amd.serve import Job, Server
+    prec = args.precision or "fp32c"
+    dt_np = np.float64 if prec == "fp64" else np.float32
+    stream_jobs = W.served_jobs(seed=0, n_jobs=args.jobs, rate=args.rate)
+    t0 = time.perf_counter()
+    jobs = [Job(state=w.state(dt_np), L=w.L, ng=w.ng, dt=w.dt, horizon=w.nsteps, arrival=t,
+                name=w.name) for t, w in stream_jobs]
+    log(f"served: {len(jobs)} jobs built in {time.perf_counter() - t0:.1f} s; rate "
+        f"{args.rate} jobs/s, sum N*horizon = {sum(j.n * j.horizon for j in jobs):.3g}")
+    torch.cuda.set_device(0)
+    budget = int(args.budget_gib * (1 << 30)) if args.budget_gib else None
+    srv = Server(precision=prec, max_slots=args.slots, budget_bytes=budget, chunk=args.chunk)
+    # warm the kernels and the graph path once on a throwaway job
+    w0 = stream_jobs[0][1]
+    srv.run([Job(state=w0.state(dt_np), L=w0.L, ng=w0.ng, dt=w0.dt, horizon=66, name="warm")])
+    rep = srv.run(jobs)
+    d = rep.as_dict()
+    log(f"served: wall {rep.wall_s:.2f} s, {rep.updates_per_s:.3g} updates/s, step latency "
+        f"p50 {d['step_latency_us']['p50']:.1f} us p99 {d['step_latency_us']['p99']:.1f} us, "
+        f"job latency p50 {d['job_latency_s']['p50']:.3f} s p99 {d['job_latency_s']['p99']:.3f} s")
+    out = {
+        "metric": METRIC, "value": rep.updates_per_s, "unit": "decorated-particle updates/s",
+        "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": args.rate,
+                   "slots": args.slots, "budget_bytes": srv.budget, "chunk": args.chunk,
+                   "precision": prec},
+        "served": {"step_latency_us": d["step_latency_us"], "job_latency_s": d["job_latency_s"],
+                   "admission_wait_s": d["admission_wait_s"], "wall_s": rep.wall_s,
+                   "updates": rep.updates},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(state, w, budget_s: float, max_steps: int):
     """FP64 oracle steps on the same initial state until the time budget is spent."""
     import numpy as np
@@ -270,6 +314,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--instances", type=int, default=256, help="landau_sweep instances")
+    ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
+    ap.add_argument("--rate", type=float, default=150.0, help="served: arrivals per second")
+    ap.add_argument("--slots", type=int, default=64, help="served: engine slots")
+    ap.add_argument("--chunk", type=int, default=33, help="served: steps between decisions")
+    ap.add_argument("--budget-gib", type=float, default=None, help="served: device bytes cap")
     ap.add_argument("--launch", default=None,
                     help="threads,ppt,acc_copies for the fused kernel (use with --no-tune)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -290,6 +339,9 @@ def main():
         sys.exit(2)
     if args.workload == "landau_sweep":
         run_sweep(args)
+        return
+    if args.workload == "served":
+        run_served(args)
         return
 
     import numpy as np

@@ -1,0 +1,58 @@
+"""Serving loop on the GPU: jobs that arrive while others run are admitted as slots and
+memory free up, run batched with the others, and end with the same result as alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("Q", "P", "qs", "ps", "psi")
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def small_jobs(dtype):
+    from paper_2605_21794_amd.serve import Job
+    ws = W.landau_sweep(seed=21, n_inst=5)
+    horizons = [37, 12, 50, 25, 8]
+    arrivals = [0.0, 0.0, 0.002, 0.004, 0.004]
+    jobs = []
+    for i, w in enumerate(ws):
+        st = w.state(dtype)
+        jobs.append(Job(state=st, L=w.L, ng=w.ng, dt=w.dt, horizon=horizons[i],
+                        arrival=arrivals[i], solver="fft" if i == 3 else "scan",
+                        name=f"job{i}"))
+    return ws, jobs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_each_job_same_alone_and_in_the_mix(vp, prec):
+    from paper_2605_21794_amd.serve import Server
+    dtype = np.float64 if prec == "fp64" else np.float32
+    ws, jobs = small_jobs(dtype)
+    # three slots for five jobs, and a budget that holds about two of them: jobs queue
+    srv = Server(precision=prec, max_slots=3, chunk=9, keep_state=True)
+    budget = sorted(srv.backend.job_bytes(j) for j in jobs)
+    srv.budget = budget[-1] + budget[-2]
+    rep = srv.run(jobs)
+    assert rep.updates == sum(j.n * j.horizon for j in jobs)
+    assert rep.step_latency_us["p50"] > 0 and rep.step_latency_us["p99"] >= rep.step_latency_us["p50"]
+    for j in jobs:
+        assert j.steps_done == j.horizon and j.result["step"] == j.horizon
+        alone = vp.Simulation(j.state, j.L, j.ng, j.dt, prec, solver=j.solver)
+        alone.step(j.horizon)
+        ref = alone.state_numpy(0)
+        got = {k: v.detach().cpu().numpy() for k, v in j.final_state.items()}
+        for k in FIELDS:
+            if prec == "fp64":
+                assert np.allclose(got[k], ref[k], rtol=0, atol=1e-12), (j.name, k)
+            else:
+                assert rel_l2(got[k], ref[k]) < 1e-5, (j.name, k)
+        da = alone.diagnostics(0)
+        assert abs(j.result["W"] - da["W"]) <= (1e-10 if prec == "fp64" else 1e-5) * abs(da["W"])
+        alone.close()

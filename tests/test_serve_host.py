@@ -1,0 +1,120 @@
+"""Host logic of the serving loop, with a fake backend and a fake clock (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_2605_21794_amd.serve import Job, Server, _weighted_pcts
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeBackend:
+    """Each step of k costs 1e-5 * k * (resident particles / 1000) seconds of fake time."""
+
+    def __init__(self, clock, max_slots=3):
+        self.clock = clock
+        self.max_slots = max_slots
+        self.resident = {}
+        self.log = []
+        self.peak_bytes = 0
+
+    def default_budget(self):
+        return 10 ** 9
+
+    def job_bytes(self, job):
+        return 100 * job.n
+
+    def admit(self, slot, job):
+        assert slot not in self.resident, "slot double-booked"
+        self.resident[slot] = job
+        self.log.append(("admit", job.name, slot, self.clock()))
+        self.peak_bytes = max(self.peak_bytes, sum(self.job_bytes(j) for j in self.resident.values()))
+
+    def step(self, k):
+        assert self.resident
+        dt = 1e-5 * k * sum(j.n for j in self.resident.values()) / 1000.0
+        self.clock.t += dt
+        return dt
+
+    def diagnostics(self, slot):
+        return {"step": self.resident[slot].steps_done}
+
+    def retire(self, slot):
+        job = self.resident.pop(slot)
+        self.log.append(("retire", job.name, slot, self.clock()))
+        return {"Q": np.zeros(job.n)}
+
+
+def make_jobs(spec):
+    return [Job(state={"Q": np.zeros(n)}, L=1.0, ng=16, dt=0.1, horizon=h, arrival=a, name=nm)
+            for nm, n, h, a in spec]
+
+
+def test_every_job_runs_exactly_its_horizon_fifo():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=2)
+    jobs = make_jobs([("a", 1000, 50, 0.0), ("b", 2000, 7, 0.0), ("c", 500, 40, 0.0),
+                      ("d", 800, 3, 0.0005)])
+    rep = Server(backend=be, chunk=10, clock=clk).run(jobs, sleep=clk.sleep)
+    for j in jobs:
+        assert j.steps_done == j.horizon and j.result["step"] == j.horizon
+        assert j.finished_at >= j.admitted_at >= j.arrival
+    admits = [e[1] for e in be.log if e[0] == "admit"]
+    assert admits == ["a", "b", "c", "d"]          # first come, first served
+    assert rep.updates == sum(j.n * j.horizon for j in jobs)
+    assert len(be.resident) == 0
+
+
+def test_budget_and_slots_are_respected():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=4)
+    jobs = make_jobs([(f"j{i}", 1000 + 100 * i, 20 + i, 0.0001 * i) for i in range(9)])
+    budget = 100 * 2500                             # at most two of these jobs at once
+    Server(backend=be, budget_bytes=budget, chunk=8, clock=clk).run(jobs, sleep=clk.sleep)
+    assert be.peak_bytes <= budget
+    assert all(j.steps_done == j.horizon for j in jobs)
+
+
+def test_head_of_line_job_blocks_later_ones_until_it_fits():
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=4)
+    jobs = make_jobs([("big0", 2000, 30, 0.0), ("big1", 2000, 5, 0.0), ("small", 10, 5, 0.0)])
+    Server(backend=be, budget_bytes=100 * 2100, chunk=8, clock=clk).run(jobs, sleep=clk.sleep)
+    order = [e[1] for e in be.log if e[0] == "admit"]
+    assert order == ["big0", "big1", "small"]
+    t_admit = {e[1]: e[3] for e in be.log if e[0] == "admit"}
+    t_retire = {e[1]: e[3] for e in be.log if e[0] == "retire"}
+    assert t_admit["big1"] >= t_retire["big0"]       # waited for the budget
+    assert t_admit["small"] >= t_admit["big1"]       # no overtaking
+
+
+def test_idle_server_waits_for_the_next_arrival():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    jobs = make_jobs([("late", 100, 4, 2.5)])
+    rep = Server(backend=be, clock=clk).run(jobs, sleep=clk.sleep)
+    assert jobs[0].admitted_at >= 2.5 and rep.wall_s >= 2.5
+
+
+def test_rejects_oversized_job_and_empty_horizon():
+    clk = FakeClock()
+    with pytest.raises(ValueError):
+        Server(backend=FakeBackend(clk), budget_bytes=1000, clock=clk).run(
+            make_jobs([("huge", 1000, 5, 0.0)]), sleep=clk.sleep)
+    with pytest.raises(ValueError):
+        Server(backend=FakeBackend(clk), clock=clk).run(make_jobs([("zero", 10, 0, 0.0)]),
+                                                        sleep=clk.sleep)
+
+
+def test_weighted_percentiles():
+    r = _weighted_pcts([3.0, 1.0, 2.0], [1, 98, 1])
+    assert r["p50"] == 1.0 and r["max"] == 3.0
+    assert _weighted_pcts([5.0, 7.0], [1, 1])["p99"] == 7.0
