@@ -278,6 +278,71 @@ def run_served(args):
     print(json.dumps(out), flush=True)
 
 
+GOLDEN_LN = os.path.join(ROOT, "tests", "golden", "landau_nonlinear_oracle.npz")
+
+
+def run_precision_study(args):
+    """Nonlinear Landau damping (alpha = 0.5, k = 0.5, Ng = 256, N = 2^22, dt = 0.05) in every
+    precision mode from the same FP32 input bits, against the stored FP64 oracle history
+    (written by tests/golden/make_landau_nonlinear_history.py).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2605_21794_amd as vp
+    import workloads as W
+    ref = np.load(GOLDEN_LN, allow_pickle=False)
+    keys = [str(k) for k in ref["keys"]]
+    H = ref["hist"]
+    steps = min(args.steps, int(ref["steps"]))
+    w = W.landau_nonlinear()
+    st32 = w.state(np.float32)
+    col = {k: H[:steps + 1, keys.index(k)] for k in keys}
+    t = col["t"]
+    windows = [("t<=10", t <= 10.0), ("10<t<=50", (t > 10.0) & (t <= 50.0)),
+               ("50<t<=100", (t > 50.0) & (t <= 100.0))]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    modes = {}
+    for prec in ("fp64", "fp32c", "fp32ts", "fp32"):
+        st = {k: (v.astype(np.float64) if prec == "fp64" else v) for k, v in st32.items()}
+        sim = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=steps + 8, stream=stream)
+        if args.launch:
+            t_, p_, a_ = (int(x) for x in args.launch.split(","))
+            sim.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) * 1e-3
+        hist = sim.history(0, 0, steps, allow_nonfinite=True) + [sim.diagnostics(0, grid=True, allow_nonfinite=True)]
+        g = {k: np.array([h[k] for h in hist]) for k in ("W", "K", "H", "charge", "momentum")}
+        grid_bt_sum = float(np.sum(hist[-1]["bt"]))
+        rec = {"updates_per_s": w.n * steps / sec, "ms": sec * 1e3,
+               "finite": bool(np.all(np.isfinite(g["W"])))}
+        for name, m in windows:
+            if m.any():
+                rec[f"W_rel_l2[{name}]"] = float(np.linalg.norm(g["W"][m] - col["W"][m]) /
+                                                 np.linalg.norm(col["W"][m]))
+        rec["H_drift_max_rel"] = float(np.max(np.abs(g["H"] - g["H"][0])) / abs(g["H"][0]))
+        rec["charge_drift_max"] = float(np.max(np.abs(g["charge"] - g["charge"][0])))
+        rec["momentum_drift_max"] = float(np.max(np.abs(g["momentum"] - g["momentum"][0])))
+        rec["sum_bt_over_charge"] = grid_bt_sum / float(g["charge"][0])
+        modes[prec] = rec
+        log(f"{prec}: {json.dumps(rec)}")
+        sim.close()
+    oracle = {"H_drift_max_rel": float(np.max(np.abs(col["H"] - col["H"][0])) / abs(col["H"][0])),
+              "momentum_drift_max": float(np.max(np.abs(col["momentum"] - col["momentum"][0])))}
+    out = {"metric": METRIC, "value": modes["fp32c"]["updates_per_s"],
+           "unit": "decorated-particle updates/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+           "ms_per_step": modes["fp32c"]["ms"] / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "landau_nonlinear", "n": w.n, "ng": w.ng, "dt": w.dt,
+                      "study": "precision"},
+           "precision_study": modes, "oracle": oracle}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(state, w, budget_s: float, max_steps: int):
     """FP64 oracle steps on the same initial state until the time budget is spent."""
     import numpy as np
@@ -314,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--instances", type=int, default=256, help="landau_sweep instances")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="landau_nonlinear in every precision mode against the stored oracle")
     ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
     ap.add_argument("--rate", type=float, default=150.0, help="served: arrivals per second")
     ap.add_argument("--slots", type=int, default=64, help="served: engine slots")
@@ -342,6 +409,9 @@ def main():
         return
     if args.workload == "served":
         run_served(args)
+        return
+    if args.precision_study:
+        run_precision_study(args)
         return
 
     import numpy as np

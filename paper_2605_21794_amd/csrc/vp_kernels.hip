@@ -335,28 +335,50 @@ __device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[
   }
 }
 
-template <int MODE, int COPIES>
-__device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0, int per,
+template <int MODE, int COPIES, int PER>
+__device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0,
                                             double (&b)[kSolvePer]) {
-  double t[COPIES][kSolvePer];
+  double t[COPIES][PER];
 #pragma unroll
   for (int c = 0; c < COPIES; ++c)
 #pragma unroll
-    for (int k = 0; k < kSolvePer; ++k) {
-      t[c][k] = 0.0;
-      if (k < per) {
-        if constexpr (MODE == kFP32)
-          t[c][k] = (double)gp<float>(d.acc)[acc_off(d, r, c) + j0 + k];
-        else
-          t[c][k] = gp(d.acc)[acc_off(d, r, c) + j0 + k];
-      }
+    for (int k = 0; k < PER; ++k) {
+      if constexpr (MODE == kFP32)
+        t[c][k] = (double)gp<float>(d.acc)[acc_off(d, r, c) + j0 + k];
+      else
+        t[c][k] = gp(d.acc)[acc_off(d, r, c) + j0 + k];
     }
 #pragma unroll
-  for (int k = 0; k < kSolvePer; ++k) {
+  for (int k = 0; k < PER; ++k) {
     double v = 0.0;
 #pragma unroll
     for (int c = 0; c < COPIES; ++c) v += t[c][k];  // copy order
     b[k] = v;
+  }
+}
+
+// The node count per thread and the copy count are template parameters, so every load is
+// unconditional and all of them are in flight before the first use.
+template <int MODE, int PER>
+__device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, bool want_sum,
+                                               SolveIn& in) {
+  switch (d.acc_copies) {
+    case 1: load_copies<MODE, 1, PER>(d, r, j0, in.b); break;
+    case 2: load_copies<MODE, 2, PER>(d, r, j0, in.b); break;
+    case 3: load_copies<MODE, 3, PER>(d, r, j0, in.b); break;
+    case 4: load_copies<MODE, 4, PER>(d, r, j0, in.b); break;
+    default: load_copies<MODE, VP_MAX_ACC_COPIES, PER>(d, r, j0, in.b); break;
+  }
+  if (want_sum) {
+    const VPG double* tw = gp(d.tw);
+    const int halfn = d.ng >> 1;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = j0 + k, t = e & (halfn - 1);
+      const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
+      in.c[k] = sg * tw[2 * t];
+      in.s[k] = sg * tw[2 * t + 1];
+    }
   }
 }
 
@@ -371,27 +393,12 @@ __device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_su
   for (int k = 0; k < kSolvePer; ++k) in.b[k] = in.c[k] = in.s[k] = 0.0;
   in.kin[0] = in.kin[1] = in.kin[2] = 0.0;
   if (tid >= kSolveThreads) return;
-  if (want_sum) load_kin(d, ring_prev(r), in.kin);
-  if (j0 >= ng) return;
-  switch (d.acc_copies) {
-    case 1: load_copies<MODE, 1>(d, r, j0, per, in.b); break;
-    case 2: load_copies<MODE, 2>(d, r, j0, per, in.b); break;
-    case 3: load_copies<MODE, 3>(d, r, j0, per, in.b); break;
-    case 4: load_copies<MODE, 4>(d, r, j0, per, in.b); break;
-    default: load_copies<MODE, VP_MAX_ACC_COPIES>(d, r, j0, per, in.b); break;
+  if (j0 < ng) {
+    if (per == 1) solve_load_per<MODE, 1>(d, r, j0, want_sum, in);
+    else if (per == 2) solve_load_per<MODE, 2>(d, r, j0, want_sum, in);
+    else solve_load_per<MODE, kSolvePer>(d, r, j0, want_sum, in);
   }
-  if (want_sum) {
-    const VPG double* tw = gp(d.tw);
-    const int halfn = ng >> 1;
-#pragma unroll
-    for (int k = 0; k < kSolvePer; ++k)
-      if (k < per) {
-        const int e = j0 + k, t = e & (halfn - 1);
-        const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
-        in.c[k] = sg * tw[2 * t];
-        in.s[k] = sg * tw[2 * t + 1];
-      }
-  }
+  if (want_sum) load_kin(d, ring_prev(r), in.kin);  // after the grid loads: waits overlap
 }
 
 // Sum of one value per solving thread (fixed DPP tree, then the wave totals in order),
@@ -663,6 +670,29 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   VPG InstScal* sc = gp(d.scal);
   const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
 
+  // one group of particles per thread: thread t takes tile.begin + k * TPB + t, k0 <= k < k0 + kGroup
+  struct Group {
+    T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
+    long long idx[kGroup];
+    bool v[kGroup];
+  };
+  auto load_group = [&](int k0, Group& g) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int loc = (k0 + u) * TPB + (int)threadIdx.x;
+      g.v[u] = (k0 + u < ppt) && (loc < tl.count);
+      g.idx[u] = tl.begin + loc;
+      if (g.v[u]) {
+        g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.a[u] = ntld(qsp + g.idx[u]);
+        g.b[u] = ntld(psp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
+      }
+    }
+  };
+
+  // The first group's loads go out first: the solve's own loads queue behind them, so both
+  // latencies overlap instead of adding up.
+  Group g;
+  load_group(0, g);
   SolveIn sin_;
   solve_load<MODE>(d, r0, first, sin_);
   for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
@@ -678,54 +708,40 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     rec[2] = sc->e1i[r2];
   }
   double Ks = 0.0, Ms = 0.0, Cs = 0.0;
-
-  const int nloop = ppt > 0 ? ppt : 1;  // the solve below runs in the first iteration
-  for (int k0 = 0; k0 < nloop; k0 += kGroup) {
-    T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
-    long long idx[kGroup];
-    bool v[kGroup];
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      const int loc = (k0 + u) * TPB + (int)threadIdx.x;
-      v[u] = (k0 + u < ppt) && (loc < tl.count);
-      idx[u] = tl.begin + loc;
-      if (v[u]) {
-        q[u] = ntld(Qp + idx[u]); p[u] = ntld(Pp + idx[u]); a[u] = ntld(qsp + idx[u]);
-        b[u] = ntld(psp + idx[u]); w[u] = ntld(psip + idx[u]);
-      }
-    }
-    if (k0 == 0) {  // uniform: every thread runs the first group
-      double sum[6];
-      solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
-      if (first) {
-        const int copies = d.acc_copies;
-        for (int c = 0; c < copies; ++c)
-          for (int j = threadIdx.x; j < ng; j += TPB) {
-            if constexpr (MODE == kFP32)
-              gp<float>(d.acc)[acc_off(d, r2, c) + j] = 0.0f;
-            else
-              gp(d.acc)[acc_off(d, r2, c) + j] = 0.0;
-          }
-        if (threadIdx.x == 0) {
-          if (pend && step >= 1)
-            write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
-          sc->W[r0] = sum[0];
-          sc->e1r[r0] = sum[1];
-          sc->e1i[r0] = sum[2];
-          if (!isfinite(sum[0])) sc->nonfinite = 1;
-          sc->pend[r1] = 1;
-          sc->step = step + 1;
+  {
+    double sum[6];
+    solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+    if (first) {
+      const int copies = d.acc_copies;
+      for (int c = 0; c < copies; ++c)
+        for (int j = threadIdx.x; j < ng; j += TPB) {
+          if constexpr (MODE == kFP32)
+            gp<float>(d.acc)[acc_off(d, r2, c) + j] = 0.0f;
+          else
+            gp(d.acc)[acc_off(d, r2, c) + j] = 0.0;
         }
+      if (threadIdx.x == 0) {
+        if (pend && step >= 1)
+          write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
+        sc->W[r0] = sum[0];
+        sc->e1r[r0] = sum[1];
+        sc->e1i[r0] = sum[2];
+        if (!isfinite(sum[0])) sc->nonfinite = 1;
+        sc->pend[r1] = 1;
+        sc->step = step + 1;
       }
     }
-#pragma unroll
+  }
+
+  auto run_group = [&](Group& g) {
+  #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
-      if (!v[u]) continue;
+      if (!g.v[u]) continue;
       if constexpr (MODE == kFP32) {
         float* fa = reinterpret_cast<float*>(sacc);
         const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
-        float Q = q[u], P = p[u], qs = a[u], ps = b[u];
-        const float psi = w[u];
+        float Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
+        const float psi = g.w[u];
         const int i = cell_of_f(Q * ihf, ng);
         const float Ei = (float)fE[i], gi = (float)fG[i];
         if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
@@ -739,7 +755,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         if (Qn < 0.0f) Qn += Lf;
         if (Qn >= Lf) Qn -= Lf;
         ps = ps - dtf * qs;
-        ntst(Qp + idx[u], Qn); ntst(Pp + idx[u], P); ntst(qsp + idx[u], qs); ntst(psp + idx[u], ps);
+        ntst(Qp + g.idx[u], Qn); ntst(Pp + g.idx[u], P); ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps);
         const float x = Qn * ihf;
         const int j = cell_of_f(x, ng);
         const float s = frac01_f(x, j);
@@ -747,8 +763,8 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
       } else {
         const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
-        const double Q = q[u], psi = w[u];
-        double P = p[u], qs = a[u], ps = b[u];
+        const double Q = g.q[u], psi = g.w[u];
+        double P = g.p[u], qs = g.a[u], ps = g.b[u];
         const int i = cell_of(Q * inv_h, ng);
         const double Ei = fE[i], gi = fG[i];
         if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
@@ -762,7 +778,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         if (Qn >= L) Qn -= L;
         const double psn = ps - dt * qs;
         const T Qs = (T)Qn, pss = (T)psn;
-        ntst(Qp + idx[u], Qs); ntst(Pp + idx[u], (T)P); ntst(qsp + idx[u], (T)qs); ntst(psp + idx[u], pss);
+        ntst(Qp + g.idx[u], Qs); ntst(Pp + g.idx[u], (T)P); ntst(qsp + g.idx[u], (T)qs); ntst(psp + g.idx[u], pss);
         const double Qd = Qs, psd = pss;
         const double x = Qd * inv_h;
         const int j = cell_of(x, ng);
@@ -771,6 +787,12 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
       }
     }
+  };
+
+  run_group(g);
+  for (int k0 = kGroup; k0 < ppt; k0 += kGroup) {
+    load_group(k0, g);
+    run_group(g);
   }
 
   // kinetic sums: wave trees, one barrier, one thread stores the workgroup totals in this
