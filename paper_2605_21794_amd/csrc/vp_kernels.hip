@@ -1094,22 +1094,25 @@ __global__ __launch_bounds__(256) void k_ring(const InstDev* __restrict__ insts,
   }
   if (op == kRingFold) {
     // per-tile kinetic sums: the tile count may change, so each entry's sum moves to tile 0
-    // (one thread per entry and field, in tile order) and the other tiles are cleared
+    // and the other tiles are cleared.  Thread t adds tiles t, t + 256, ... in order, then
+    // thread 0 adds the 256 partial sums in thread order (fixed order, deterministic).
+    __shared__ double part[256];
     VPG double* kin = gp(d.kin);
-    __syncthreads();
-    if (threadIdx.x < kRing * 3) {
-      const int r = threadIdx.x / 3, f = threadIdx.x % 3;
+    for (int rf = 0; rf < kRing * 3; ++rf) {
+      const int r = rf / 3, f = rf % 3;
       VPG double* base = kin + (size_t)r * d.kin_cap * kKinFields + f;
-      double s = 0.0;
-      for (int t0 = 0; t0 < d.kin_cap; t0 += 16) {
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = (t0 + u < d.kin_cap) ? base[(size_t)(t0 + u) * kKinFields] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) s += v[u];
+      double acc_t = 0.0;
+      for (int t = threadIdx.x; t < d.kin_cap; t += 256) acc_t += base[(size_t)t * kKinFields];
+      __syncthreads();
+      part[threadIdx.x] = acc_t;
+      __syncthreads();
+      for (int t = threadIdx.x; t < d.kin_cap; t += 256) base[(size_t)t * kKinFields] = 0.0;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int t = 0; t < 256; ++t) s += part[t];
+        base[0] = s;
       }
-      base[0] = s;
-      for (int t = 1; t < d.kin_cap; ++t) base[(size_t)t * kKinFields] = 0.0;
     }
   }
 }
