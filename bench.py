@@ -137,7 +137,9 @@ def make_workload(name: str):
     if name == "two_stream":
         return W.two_stream(), "fp32c"
     if name == "probe":
-        return W.two_stream(nx=8192, nv=8192), "fp32c"
+        w = W.two_stream(nx=8192, nv=8192)
+        w.name = "two_stream_probe"
+        return w, "fp32c"
     if name == "landau_nonlinear":
         return W.landau_nonlinear(), "fp32c"
     if name == "landau_linear":
