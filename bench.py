@@ -381,6 +381,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--instances", type=int, default=256, help="landau_sweep instances")
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="sort particles by cell every this many steps (0: never)")
+    ap.add_argument("--sort-chunk", type=int, default=0, help="particles per sorted chunk")
     ap.add_argument("--precision-study", action="store_true",
                     help="landau_nonlinear in every precision mode against the stored oracle")
     ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
@@ -431,7 +434,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()          # a non-null stream, so steps can be graph-captured
     torch.cuda.set_stream(stream)
-    sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8))
+    sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8),
+                        sort_every=args.sort_every, sort_chunk=args.sort_chunk)
     tuning_us = None
     if args.launch:
         t_, p_, a_ = (int(x) for x in args.launch.split(","))
@@ -497,6 +501,7 @@ def main():
         "config": {
             "workload": w.name, "n": n, "ng": w.ng, "L": w.L, "dt": w.dt,
             "precision": prec, "instances": 1, "launch": tun,
+            "sort_every": args.sort_every, "sort_chunk": args.sort_chunk,
             "state_finite_after_run": finite, "t_end": diag["t"],
         },
         "roofline": {
