@@ -188,7 +188,13 @@ def run_sweep(args):
     el_b = time.perf_counter() - t0
     kern_avg_s = ev0.elapsed_time(ev1) * 1e-3 / steps
     log(f"batched: {steps} steps in {el_b * 1e3:.2f} ms ({kern_avg_s * 1e6:.2f} us per launch)")
-    wb = [eng.diagnostics(s, allow_nonfinite=True)["W"] for s in range(len(ws))]
+    db = [eng.diagnostics(s, allow_nonfinite=True) for s in range(len(ws))]
+    wb = [d["W"] for d in db]
+    nonfinite = sum(1 for d in db if not (np.isfinite(d["W"]) and np.isfinite(d["K"])))
+    # updates actually performed: an instance whose state went non-finite is frozen by the
+    # engine, so it counts only the steps it took inside the timed region
+    live = [min(steps, max(0, int(d["step"]) - args.warmup)) for d in db]
+    upd_b = sum(w.n * k for w, k in zip(ws, live))
     eng.close()
 
     # plain: one engine per instance, one launch per instance per step (graph-replayed)
@@ -213,12 +219,15 @@ def run_sweep(args):
     torch.cuda.synchronize()
     el_p = time.perf_counter() - t0
     log(f"plain: {steps} steps in {el_p * 1e3:.2f} ms")
-    wp = [sim.diagnostics(0, allow_nonfinite=True)["W"] for sim in sims]
-    rel = max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(wb, wp))
+    dp = [sim.diagnostics(0, allow_nonfinite=True) for sim in sims]
+    wp = [d["W"] for d in dp]
+    upd_p = sum(w.n * min(steps, max(0, int(d["step"]) - args.warmup)) for w, d in zip(ws, dp))
+    rel = max((abs(a - b) / max(abs(b), 1e-300) for a, b in zip(wb, wp)
+               if np.isfinite(a) and np.isfinite(b)), default=0.0)
     for sim in sims:
         sim.close()
 
-    value = ntot * steps / el_b
+    value = upd_b / el_b
     bytes_per_launch = FUSED_BYTES[prec] * ntot
     achieved = bytes_per_launch / kern_avg_s / 1e9
     out = {
@@ -228,8 +237,10 @@ def run_sweep(args):
         "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": "landau_sweep", "instances": len(ws), "n_total": ntot,
                    "precision": prec, "launch": tun,
-                   "plain_value": ntot * steps / el_p, "batched_over_plain": el_p / el_b,
-                   "max_rel_W_difference_batched_vs_plain": rel},
+                   "plain_value": upd_p / el_p,
+                   "batched_over_plain": (upd_b / el_b) / max(upd_p / el_p, 1e-300),
+                   "max_rel_W_difference_batched_vs_plain": rel,
+                   "nonfinite_instances": nonfinite},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_fused", "bytes_per_launch": bytes_per_launch,

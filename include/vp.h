@@ -193,6 +193,9 @@ vp_status vp_gather_push(vp_handle* h, double kick, double drift);
  * read-back must go through vp_sync_state, vp_retire or vp_diagnostics (which accounts for
  * it). */
 vp_status vp_step(vp_handle* h, int32_t nsteps);
+/* (vp_step) An instance whose diagnostics come out NaN or Inf is frozen from the next step
+ * on: its state, step counter and history stop where they are, vp_diagnostics and
+ * vp_history report VP_ERR_NONFINITE, and the other instances are unaffected. */
 
 /* Apply the pending half-kick of every occupied slot (P, q* back to integer time). */
 vp_status vp_sync_state(vp_handle* h);

@@ -616,13 +616,17 @@ vp_status vp_history(vp_handle* h, int32_t slot, int64_t first_step, int32_t cou
   const Slot& sl = h->slots[slot];
   const InstDev& d = h->h_inst[slot];
   const long long cap = sl.cfg.hist_cap;
-  const long long lo = std::max(0LL, sl.step - cap);
-  if (first_step < lo || first_step + count > sl.step)
-    return fail(VP_ERR_RANGE, "records %lld..%lld not stored (have %lld..%lld)", (long long)first_step,
-                (long long)(first_step + count - 1), lo, sl.step - 1);
-  std::vector<double> buf((size_t)count * vpk::kHistFields);
   if (sl.pending) VP_TRY(materialise(h, h->d_ids + slot, 1));  // the last step's record
+  // the device step counter is authoritative: a frozen (non-finite) instance stops counting
+  vpk::InstScal sc{};
+  VP_HIP(hipMemcpyAsync(&sc, d.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
   VP_HIP(hipStreamSynchronize(h->stream));
+  const long long have = std::min<long long>(sc.step, sl.step);
+  const long long lo = std::max(0LL, have - cap);
+  if (first_step < lo || first_step + count > have)
+    return fail(VP_ERR_RANGE, "records %lld..%lld not stored (have %lld..%lld)", (long long)first_step,
+                (long long)(first_step + count - 1), lo, have - 1);
+  std::vector<double> buf((size_t)count * vpk::kHistFields);
   long long k = 0;
   while (k < count) {
     const long long st = first_step + k;

@@ -668,6 +668,9 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   double* bt = smem + 3 * ng;
   double* fft = smem + 4 * ng;
   VPG InstScal* sc = gp(d.scal);
+  // An instance whose diagnostics went NaN / Inf is frozen: its state is no longer a
+  // solution, and its particles would all land in element 0.  (Uniform per workgroup.)
+  if (sc->nonfinite) return;
   const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
 
   // one group of particles per thread: thread t takes tile.begin + k * TPB + t, k0 <= k < k0 + kGroup

@@ -114,3 +114,27 @@ def test_retire_returns_integer_time_state(vp):
     ref_state, _, _ = oracle_run(st, w, 5)
     for k, r in zip(FIELDS, ref_state):
         assert np.allclose(got[k], r, rtol=0, atol=1e-11), k
+
+
+def test_nonfinite_instance_is_frozen_and_others_continue(vp):
+    """A NaN in one instance freezes that instance (its step counter stops, diagnostics
+    report non-finite) and leaves the others exactly on their oracle trajectories."""
+    ws = sweep(3, seed=13)
+    sts = [w.state() for w in ws]
+    bad = {k: v.copy() for k, v in sts[1].items()}
+    bad["P"][5] = np.nan
+    eng = vp.Engine("fp64", max_slots=3)
+    eng.admit(0, sts[0], ws[0].L, ws[0].ng, ws[0].dt)
+    eng.admit(1, bad, ws[1].L, ws[1].ng, ws[1].dt)
+    eng.admit(2, sts[2], ws[2].L, ws[2].ng, ws[2].dt)
+    eng.step(8)
+    with pytest.raises(vp.VPError) as e:
+        eng.diagnostics(1)
+    assert e.value.status == vp._lib.VP_ERR_NONFINITE
+    assert eng.diagnostics(1, allow_nonfinite=True)["step"] < 8
+    for s in (0, 2):
+        got = eng.state_numpy(s)
+        ref_state, _, _ = oracle_run(sts[s], ws[s], 8)
+        for k, r in zip(FIELDS, ref_state):
+            assert np.allclose(got[k], r, rtol=0, atol=1e-11), (s, k)
+        assert eng.diagnostics(s)["step"] == 8
