@@ -190,7 +190,7 @@ def run_sweep(args):
     log(f"batched: {steps} steps in {el_b * 1e3:.2f} ms ({kern_avg_s * 1e6:.2f} us per launch)")
     db = [eng.diagnostics(s, allow_nonfinite=True) for s in range(len(ws))]
     wb = [d["W"] for d in db]
-    nonfinite = sum(1 for d in db if not (np.isfinite(d["W"]) and np.isfinite(d["K"])))
+    nonfinite = sum(1 for d in db if not d["finite"])
     # updates actually performed: an instance whose state went non-finite is frozen by the
     # engine, so it counts only the steps it took inside the timed region
     live = [min(steps, max(0, int(d["step"]) - args.warmup)) for d in db]
@@ -222,8 +222,8 @@ def run_sweep(args):
     dp = [sim.diagnostics(0, allow_nonfinite=True) for sim in sims]
     wp = [d["W"] for d in dp]
     upd_p = sum(w.n * min(steps, max(0, int(d["step"]) - args.warmup)) for w, d in zip(ws, dp))
-    rel = max((abs(a - b) / max(abs(b), 1e-300) for a, b in zip(wb, wp)
-               if np.isfinite(a) and np.isfinite(b)), default=0.0)
+    rel = max((abs(a["W"] - b["W"]) / max(abs(b["W"]), 1e-300) for a, b in zip(db, dp)
+               if a["finite"] and b["finite"]), default=0.0)
     for sim in sims:
         sim.close()
 
@@ -284,7 +284,8 @@ def run_served(args):
         "config": {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": args.rate,
                    "slots": args.slots, "budget_bytes": srv.budget, "chunk": args.chunk,
                    "precision": prec},
-        "served": {"step_latency_us": d["step_latency_us"], "job_latency_s": d["job_latency_s"],
+        "served": {"nonfinite_jobs": d["nonfinite_jobs"],
+                   "step_latency_us": d["step_latency_us"], "job_latency_s": d["job_latency_s"],
                    "admission_wait_s": d["admission_wait_s"], "wall_s": rep.wall_s,
                    "updates": rep.updates},
     }

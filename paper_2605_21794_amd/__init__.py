@@ -168,6 +168,7 @@ class Engine:
         if not (allow_nonfinite and st == L.VP_ERR_NONFINITE):
             L.check(st, "vp_diagnostics")
         out = d.as_dict()
+        out["finite"] = st == L.VP_OK   # False once the instance went NaN / Inf (and froze)
         if grid:
             out.update(bt=buf[:ng], Phi=buf[ng:2 * ng], E=buf[2 * ng:3 * ng], g=buf[3 * ng:])
         return out

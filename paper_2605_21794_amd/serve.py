@@ -57,13 +57,15 @@ class Report:
     step_latency_us: dict = field(default_factory=dict)
     job_latency_s: dict = field(default_factory=dict)
     admission_wait_s: dict = field(default_factory=dict)
+    nonfinite_jobs: int = 0
 
     @property
     def updates_per_s(self) -> float:
         return self.updates / self.wall_s if self.wall_s > 0 else 0.0
 
     def as_dict(self) -> dict:
-        return {"jobs": len(self.jobs), "wall_s": self.wall_s, "updates": self.updates,
+        return {"jobs": len(self.jobs), "nonfinite_jobs": self.nonfinite_jobs,
+                "wall_s": self.wall_s, "updates": self.updates,
                 "updates_per_s": self.updates_per_s, "step_latency_us": self.step_latency_us,
                 "job_latency_s": self.job_latency_s, "admission_wait_s": self.admission_wait_s}
 
@@ -115,7 +117,6 @@ class Server:
         queue = []                       # arrived, not yet admitted (FIFO)
         resident = {}                    # slot -> job
         used_bytes = 0
-        updates = 0
         step_samples = []                # (seconds per step, weight = job-steps)
         t0 = self.clock()
         nxt = 0
@@ -149,8 +150,6 @@ class Server:
                 continue
             k = min(self.chunk, min(j.horizon - j.steps_done for j in resident.values()))
             dev_s = self.backend.step(k)
-            n_res = sum(j.n for j in resident.values())
-            updates += n_res * k
             step_samples.append((dev_s / k, k * len(resident)))
             for j in resident.values():
                 j.steps_done += k
@@ -163,7 +162,12 @@ class Server:
                 job.finished_at = self.clock() - t0
                 used_bytes -= self.backend.job_bytes(job)
         wall = self.clock() - t0
+        # updates actually performed: an instance whose state turned non-finite is frozen by
+        # the engine and stops at the step its diagnostics report
+        updates = sum(j.n * min(j.horizon, int(j.result.get("step", j.horizon)))
+                      for j in pending)
         rep = Report(jobs=list(pending), wall_s=wall, updates=updates)
+        rep.nonfinite_jobs = sum(1 for j in pending if not j.result.get("finite", True))
         rep.step_latency_us = _weighted_pcts([1e6 * v for v, _ in step_samples],
                                              [w for _, w in step_samples])
         rep.job_latency_s = _pcts([j.finished_at - j.arrival for j in pending])
