@@ -132,6 +132,15 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
     print(json.dumps(rec))
 
 
+def parse_launch(text: str) -> dict:
+    """threads,ppt,acc_copies[,persistent] -> tuning fields."""
+    v = [int(x) for x in text.split(",")]
+    out = {"threads": v[0], "ppt": v[1], "acc_copies": v[2]}
+    if len(v) > 3:
+        out["persistent"] = v[3]
+    return out
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "two_stream":
@@ -171,8 +180,7 @@ def run_sweep(args):
     for s, (w, st) in enumerate(zip(ws, sts)):
         eng.admit(s, st, w.L, w.ng, w.dt, hist_cap=max(64, steps + args.warmup + 8))
     if args.launch:
-        t_, p_, a_ = (int(x) for x in args.launch.split(","))
-        eng.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
+        eng.set_tuning(**parse_launch(args.launch))
     if not args.no_tune:
         best, us = eng.tune(steps_per_trial=99)
         log(f"batched: tuned launch shape {best} ({us:.2f} us/step)")
@@ -321,8 +329,7 @@ def run_precision_study(args):
         st = {k: (v.astype(np.float64) if prec == "fp64" else v) for k, v in st32.items()}
         sim = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=steps + 8, stream=stream)
         if args.launch:
-            t_, p_, a_ = (int(x) for x in args.launch.split(","))
-            sim.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
+            sim.set_tuning(**parse_launch(args.launch))
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         sim.step(steps)
@@ -404,7 +411,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=33, help="served: steps between decisions")
     ap.add_argument("--budget-gib", type=float, default=None, help="served: device bytes cap")
     ap.add_argument("--launch", default=None,
-                    help="threads,ppt,acc_copies for the fused kernel (use with --no-tune)")
+                    help="threads,ppt,acc_copies[,persistent] of the fused step (with --no-tune)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--pmc-summary", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"))
@@ -450,8 +457,7 @@ def main():
                         sort_every=args.sort_every, sort_chunk=args.sort_chunk)
     tuning_us = None
     if args.launch:
-        t_, p_, a_ = (int(x) for x in args.launch.split(","))
-        sim.set_tuning(threads=t_, ppt=p_, acc_copies=a_)
+        sim.set_tuning(**parse_launch(args.launch))
     if not args.no_tune:
         best, tuning_us = sim.tune(steps_per_trial=99)
         log(f"tuned launch shape {best} ({tuning_us:.2f} us/step)")

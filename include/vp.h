@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 2
+#define VP_ABI_VERSION 3
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -115,6 +115,10 @@ typedef struct vp_tuning {
   int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..8 */
   int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
   int32_t graph_steps;  /* steps per captured graph, 1..256 (rounded up to a multiple of 3) */
+  int32_t persistent;   /* 1: vp_step runs many steps per cooperative launch with every tile's
+                         * particles held in registers between steps (threads 512 or 1024,
+                         * ppt 2, 4 or 8; every tile must be resident at once, else
+                         * vp_set_tuning returns VP_ERR_ARG); 0: one launch per step */
 } vp_tuning;
 
 typedef struct vp_handle vp_handle;

@@ -38,7 +38,7 @@ class vp_diag(Structure):
 
 class vp_tuning(Structure):
     _fields_ = [("threads", c_int32), ("ppt", c_int32), ("acc_copies", c_int32),
-                ("use_graph", c_int32), ("graph_steps", c_int32)]
+                ("use_graph", c_int32), ("graph_steps", c_int32), ("persistent", c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

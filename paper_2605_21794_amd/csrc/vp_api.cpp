@@ -95,7 +95,7 @@ struct vp_handle {
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   int max_ng = VP_MIN_NG;
   bool any_fft = false;     // some slot uses the FFT solver (fused launches need more LDS)
-  vp_tuning tun{1024, 4, 4, 1, 33};
+  vp_tuning tun{1024, 4, 4, 1, 33, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_len = 0;        // fused launches per graph (a multiple of the ring period)
@@ -224,9 +224,26 @@ vp_status ensure_graph(vp_handle* h) {
   return VP_OK;
 }
 
+constexpr int kMaxPersistSteps = 1024;  // steps per cooperative launch (bounds its duration)
+
+// k steps as cooperative persistent launches (particles in registers between steps).
+vp_status advance_persistent(vp_handle* h, int k) {
+  while (k > 0) {
+    const int c = std::min(k, kMaxPersistSteps);
+    VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalPersistStart,
+                                    h->phase, h->stream));
+    VP_HIP(vpk::launch_persist(h->precision, h->tun.threads, h->tun.ppt, h->d_inst, h->d_tiles, h->ntiles,
+                               h->max_ng, h->any_fft, h->phase, c, h->stream));
+    h->phase = (h->phase + c) % vpk::kRing;
+    k -= c;
+  }
+  return VP_OK;
+}
+
 // Run k fused steps of every slot: graph replays where whole graphs fit (after at most
 // kRing-1 direct launches that bring the phase to the graph's), direct launches otherwise.
 vp_status advance(vp_handle* h, int k) {
+  if (h->tun.persistent) return advance_persistent(h, k);
   const bool graphs = h->tun.use_graph && h->stream != nullptr;
   if (graphs && k >= graph_len_of(h)) {
     VP_TRY(ensure_graph(h));  // captured at the current phase if there was none
@@ -604,6 +621,7 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   host_out->e_amp = std::sqrt(2.0 * sc.W[p] / sl.cfg.L);
   host_out->e1_re = sc.e1r[p];
   host_out->e1_im = sc.e1i[p];
+  if (sc.timeout) return fail(VP_ERR_HIP, "slot %d: a persistent step's wait for its tiles timed out", slot);
   if (!diag_finite(*host_out) || sc.nonfinite)
     return fail(VP_ERR_NONFINITE, "slot %d: non-finite diagnostics at step %lld", slot, sc.step);
   return VP_OK;
@@ -653,9 +671,26 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
     return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8 or 16");
   if (t->acc_copies < 1 || t->acc_copies > VP_MAX_ACC_COPIES) return fail(VP_ERR_ARG, "acc_copies out of range");
   if (t->graph_steps < 1 || t->graph_steps > 256) return fail(VP_ERR_ARG, "graph_steps out of range");
+  if (t->persistent) {
+    if (!(t->threads == 512 || t->threads == 1024) || !(t->ppt == 2 || t->ppt == 4 || t->ppt == 8))
+      return fail(VP_ERR_ARG, "persistent steps need threads 512 or 1024 and ppt 2, 4 or 8");
+  }
+  const vp_tuning old = h->tun;
   h->tun = *t;
   h->tun.use_graph = t->use_graph ? 1 : 0;
-  return rebuild_tables(h);
+  h->tun.persistent = t->persistent ? 1 : 0;
+  VP_TRY(rebuild_tables(h));
+  if (h->tun.persistent) {
+    const int cap = vpk::persist_capacity(h->precision, h->tun.threads, h->tun.ppt, h->max_ng, h->any_fft);
+    if (h->ntiles > cap) {
+      const int need = h->ntiles;
+      h->tun = old;
+      VP_TRY(rebuild_tables(h));
+      return fail(VP_ERR_ARG, "persistent steps need all %d workgroups resident; the device holds %d",
+                  need, cap);
+    }
+  }
+  return VP_OK;
 }
 
 vp_status vp_get_tuning(const vp_handle* h, vp_tuning* t) {
@@ -726,11 +761,22 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   VP_HIP(hipEventCreate(&e1));
   vp_tuning best = orig;
   double best_us = 1e300;
-  struct Cand { int threads, ppt, acc; };
+  struct Cand { int threads, ppt, acc, persistent; };
   std::vector<Cand> cands;
   for (int th : {512, 1024})
     for (int pp : {1, 2, 4, 8})
-      for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac});
+      for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 0});
+  // persistent shapes that keep every tile resident
+  for (int th : {512, 1024})
+      for (int pp : {2, 4, 8}) {
+        const long long tiles_needed = [&] {
+          long long t = 0;
+          for (int s : h->h_occ) t += (h->slots[s].cfg.n + (long long)th * pp - 1) / ((long long)th * pp);
+          return t;
+        }();
+        if (tiles_needed <= vpk::persist_capacity(h->precision, th, pp, h->max_ng, h->any_fft))
+          for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 1});
+      }
   vp_status st = VP_OK;
   for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
     {
@@ -738,9 +784,14 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
       t.threads = cands[ci].threads;
       t.ppt = cands[ci].ppt;
       t.acc_copies = cands[ci].acc;
+      t.persistent = cands[ci].persistent;
       t.use_graph = (h->stream != nullptr) ? 1 : 0;
       t.graph_steps = std::min(steps_per_trial, 256);
       st = vp_set_tuning(h, &t);
+      if (st == VP_ERR_ARG && t.persistent) {  // this shape cannot keep every tile resident
+        st = VP_OK;
+        continue;
+      }
       if (st != VP_OK) break;
       // one untimed graph build + warm-up pass, then the timed steps
       st = vp_step(h, t.graph_steps);

@@ -28,6 +28,9 @@ struct InstScal {
   long long step;                           // integer step of the state (fused path)
   int pend[kRing];                          // 1 when P, q* owe the half-kick with the field of entry r
   int nonfinite;                            // set when a diagnostic came out NaN or Inf
+  int frozen;                               // nonfinite as of the start of a persistent launch
+  unsigned arrive;                          // workgroup arrivals in a persistent launch
+  int timeout;                              // a persistent launch's wait gave up (error)
 };
 
 // Device descriptor of one instance (one slot of an engine).
@@ -88,6 +91,13 @@ hipError_t launch_settle(int mode, int tpb, const InstDev* d_inst, const Tile* d
                          int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                        int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
+// Persistent form of the fused step: nsteps steps in one cooperative launch, the particles
+// of each tile held in registers between steps (ppt per thread, 2, 4 or 8).  Every tile of
+// the launch must be resident at once: persist_capacity gives how many workgroups can be.
+hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
+                          int ntiles, int max_ng, bool lds_fft, int phase, int nsteps,
+                          hipStream_t s);
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft);
 // Solve the listed slots from ring entry `phase` and write the field arrays (materialise).
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
                         int max_ng, bool lds_fft, int phase, hipStream_t s);
@@ -103,7 +113,7 @@ hipError_t launch_sort(int mode, const InstDev* d_inst, int slot, long long n, i
                        int* perm, hipStream_t s);
 
 // ops for launch_slot_scalars
-enum ScalOp { kScalClearDiag = 0, kScalClearPending = 1 };
+enum ScalOp { kScalClearDiag = 0, kScalClearPending = 1, kScalPersistStart = 2 };
 // ops for launch_ring: fold entry `phase` into its copy 0 and clear the two other entries
 // (after the number of accumulator copies changed); or clear entry `phase` (before a deposit)
 enum RingOp { kRingFold = 0, kRingClear = 1 };

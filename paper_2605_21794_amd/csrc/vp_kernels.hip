@@ -56,6 +56,19 @@ __device__ __forceinline__ void gst(VPG float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Loads of data that other workgroups of the same launch wrote (DEV = true: the persistent
+// step) go through device-scope atomic loads, which no stale cache line can answer.
+template <bool DEV, typename T>
+__device__ __forceinline__ T ldx(VPG T* p) {
+  if constexpr (DEV) return gld(p);
+  else return *p;
+}
+template <bool DEV, typename T>
+__device__ __forceinline__ void stx(VPG T* p, T v) {
+  if constexpr (DEV) gst(p, v);
+  else *p = v;
+}
+
 // Streaming access to the particle arrays: every element is read and written once per step,
 // so the loads and stores are marked non-temporal (they do not displace cached grid data).
 template <typename T>
@@ -310,24 +323,25 @@ struct SolveIn {
 };
 
 // Sum over tiles t = tid, tid + kSolveThreads, ... (in that order) of the per-tile kinetic
-// sums of ring entry r, eight loads in flight at a time.
+// sums of ring entry r, four tiles' loads in flight at a time.
+template <bool DEV>
 __device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[3]) {
   kin[0] = kin[1] = kin[2] = 0.0;
-  const VPG double* base = gp(d.kin) + (size_t)r * d.kin_cap * kKinFields;
-  for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += 8 * kSolveThreads) {
-    double v[8][3];
+  VPG double* base = gp(d.kin) + (size_t)r * d.kin_cap * kKinFields;
+  for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += 4 * kSolveThreads) {
+    double v[4][3];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const int t = t0 + u * kSolveThreads;
       v[u][0] = v[u][1] = v[u][2] = 0.0;
       if (t < d.ntiles) {
-        v[u][0] = base[(size_t)t * kKinFields];
-        v[u][1] = base[(size_t)t * kKinFields + 1];
-        v[u][2] = base[(size_t)t * kKinFields + 2];
+        v[u][0] = ldx<DEV>(base + (size_t)t * kKinFields);
+        v[u][1] = ldx<DEV>(base + (size_t)t * kKinFields + 1);
+        v[u][2] = ldx<DEV>(base + (size_t)t * kKinFields + 2);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4; ++u) {
       kin[0] += v[u][0];
       kin[1] += v[u][1];
       kin[2] += v[u][2];
@@ -335,39 +349,44 @@ __device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[
   }
 }
 
-template <int MODE, int COPIES, int PER>
+// Copies are loaded in batches of at most eight values in flight per thread (bounded
+// registers), and added in copy order.
+template <int MODE, int COPIES, int PER, bool DEV>
 __device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0,
                                             double (&b)[kSolvePer]) {
-  double t[COPIES][PER];
+  constexpr int kBatch = (8 / PER) < COPIES ? (8 / PER) : COPIES;
 #pragma unroll
-  for (int c = 0; c < COPIES; ++c)
+  for (int k = 0; k < PER; ++k) b[k] = 0.0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if constexpr (MODE == kFP32)
-        t[c][k] = (double)gp<float>(d.acc)[acc_off(d, r, c) + j0 + k];
-      else
-        t[c][k] = gp(d.acc)[acc_off(d, r, c) + j0 + k];
-    }
+  for (int c0 = 0; c0 < COPIES; c0 += kBatch) {
+    double t[kBatch][PER];
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    double v = 0.0;
+    for (int c = 0; c < kBatch; ++c)
 #pragma unroll
-    for (int c = 0; c < COPIES; ++c) v += t[c][k];  // copy order
-    b[k] = v;
+      for (int k = 0; k < PER; ++k) {
+        if constexpr (MODE == kFP32)
+          t[c][k] = (double)ldx<DEV>(gp<float>(d.acc) + acc_off(d, r, c0 + c) + j0 + k);
+        else
+          t[c][k] = ldx<DEV>(gp(d.acc) + acc_off(d, r, c0 + c) + j0 + k);
+      }
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+#pragma unroll
+      for (int c = 0; c < kBatch; ++c) b[k] += t[c][k];  // copy order
   }
 }
 
 // The node count per thread and the copy count are template parameters, so every load is
 // unconditional and all of them are in flight before the first use.
-template <int MODE, int PER>
+template <int MODE, int PER, bool DEV>
 __device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, bool want_sum,
                                                SolveIn& in) {
   switch (d.acc_copies) {
-    case 1: load_copies<MODE, 1, PER>(d, r, j0, in.b); break;
-    case 2: load_copies<MODE, 2, PER>(d, r, j0, in.b); break;
-    case 3: load_copies<MODE, 3, PER>(d, r, j0, in.b); break;
-    case 4: load_copies<MODE, 4, PER>(d, r, j0, in.b); break;
-    default: load_copies<MODE, VP_MAX_ACC_COPIES, PER>(d, r, j0, in.b); break;
+    case 1: load_copies<MODE, 1, PER, DEV>(d, r, j0, in.b); break;
+    case 2: load_copies<MODE, 2, PER, DEV>(d, r, j0, in.b); break;
+    case 3: load_copies<MODE, 3, PER, DEV>(d, r, j0, in.b); break;
+    case 4: load_copies<MODE, 4, PER, DEV>(d, r, j0, in.b); break;
+    default: load_copies<MODE, VP_MAX_ACC_COPIES, PER, DEV>(d, r, j0, in.b); break;
   }
   if (want_sum) {
     const VPG double* tw = gp(d.tw);
@@ -385,7 +404,7 @@ __device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, 
 // Issue the solve's loads (load vector of ring entry r; with want_sum also the Fourier
 // weights and the kinetic sums of the previous pass, ring entry r-1): all of them before
 // any use, so they overlap other work of the caller.
-template <int MODE>
+template <int MODE, bool DEV = false>
 __device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_sum, SolveIn& in) {
   const int ng = d.ng, tid = threadIdx.x;
   const int per = solve_per(ng), j0 = tid * per;
@@ -394,11 +413,11 @@ __device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_su
   in.kin[0] = in.kin[1] = in.kin[2] = 0.0;
   if (tid >= kSolveThreads) return;
   if (j0 < ng) {
-    if (per == 1) solve_load_per<MODE, 1>(d, r, j0, want_sum, in);
-    else if (per == 2) solve_load_per<MODE, 2>(d, r, j0, want_sum, in);
-    else solve_load_per<MODE, kSolvePer>(d, r, j0, want_sum, in);
+    if (per == 1) solve_load_per<MODE, 1, DEV>(d, r, j0, want_sum, in);
+    else if (per == 2) solve_load_per<MODE, 2, DEV>(d, r, j0, want_sum, in);
+    else solve_load_per<MODE, kSolvePer, DEV>(d, r, j0, want_sum, in);
   }
-  if (want_sum) load_kin(d, ring_prev(r), in.kin);  // after the grid loads: waits overlap
+  if (want_sum) load_kin<DEV>(d, ring_prev(r), in.kin);  // after the grid loads: waits overlap
 }
 
 // Sum of one value per solving thread (fixed DPP tree, then the wave totals in order),
@@ -626,6 +645,68 @@ __device__ void write_record(const InstDev& d, long long step, double K, double 
 
 #define VP_TILE_LOOP_END }
 
+// One particle through one step (eq. sw-evolution as a kick-drift-kick splitting): the
+// half-kick still owed from the previous step (pend), the kinetic terms at the integer step,
+// this step's half-kick, the drift, and the deposit of the drifted particle into the LDS
+// grid (eq. rhs-assembly).  (Q, P, q*, p*) are updated in place in storage precision.  The
+// float64 modes compute in float64 from the stored values in the oracle's operation order.
+template <int MODE, typename T>
+__device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
+                                              double* sacc, int pend, T& Qr, T& Pr, T& qsr,
+                                              T& psr, const T psir, double& Ks, double& Ms,
+                                              double& Cs) {
+  const int ng = d.ng;
+  if constexpr (MODE == kFP32) {
+    float* fa = reinterpret_cast<float*>(sacc);
+    const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
+    float Q = Qr, P = Pr, qs = qsr, ps = psr;
+    const float psi = psir;
+    const int i = cell_of_f(Q * ihf, ng);
+    const float Ei = (float)fE[i], gi = (float)fG[i];
+    if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
+    const double Pd = P, qd = qs, wd = psi;
+    Ks += 0.5 * wd * Pd * Pd + qd * Pd;
+    Ms += wd * Pd + qd;
+    Cs += wd;
+    P = P + hf * Ei;
+    qs = qs + hf * ps * gi;
+    float Qn = Q + dtf * P;
+    if (Qn < 0.0f) Qn += Lf;
+    if (Qn >= Lf) Qn -= Lf;
+    ps = ps - dtf * qs;
+    const float x = Qn * ihf;
+    const int j = cell_of_f(x, ng);
+    const float s = frac01_f(x, j);
+    atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
+    atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
+    Qr = Qn; Pr = P; qsr = qs; psr = ps;
+  } else {
+    const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
+    const double Q = Qr, psi = psir;
+    double P = Pr, qs = qsr, ps = psr;
+    const int i = cell_of(Q * inv_h, ng);
+    const double Ei = fE[i], gi = fG[i];
+    if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
+    Ks += 0.5 * psi * P * P + qs * P;
+    Ms += psi * P + qs;
+    Cs += psi;
+    P = P + half * Ei;
+    qs = qs + half * ps * gi;
+    double Qn = Q + dt * P;
+    if (Qn < 0.0) Qn += L;
+    if (Qn >= L) Qn -= L;
+    const double psn = ps - dt * qs;
+    const T Qs = (T)Qn, pss = (T)psn;
+    const double Qd = Qs, psd = pss;
+    const double x = Qd * inv_h;
+    const int j = cell_of(x, ng);
+    const double s = frac01(x, j);
+    lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+    Qr = Qs; Pr = (T)P; qsr = (T)qs; psr = pss;
+  }
+}
+
 // LDS of the fused kernel, in doubles: E [0, Ng), g [Ng, 2Ng), deposit grid [2Ng, 3Ng),
 // b~ [3Ng, 4Ng), FFT scratch [4Ng, 7Ng) (FFT solver only).
 __host__ __device__ constexpr size_t fused_lds_doubles(bool fft) { return fft ? 7 : 4; }
@@ -737,58 +818,12 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   }
 
   auto run_group = [&](Group& g) {
-  #pragma unroll
+#pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       if (!g.v[u]) continue;
-      if constexpr (MODE == kFP32) {
-        float* fa = reinterpret_cast<float*>(sacc);
-        const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
-        float Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
-        const float psi = g.w[u];
-        const int i = cell_of_f(Q * ihf, ng);
-        const float Ei = (float)fE[i], gi = (float)fG[i];
-        if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
-        const double Pd = P, qd = qs, wd = psi;
-        Ks += 0.5 * wd * Pd * Pd + qd * Pd;
-        Ms += wd * Pd + qd;
-        Cs += wd;
-        P = P + hf * Ei;
-        qs = qs + hf * ps * gi;
-        float Qn = Q + dtf * P;
-        if (Qn < 0.0f) Qn += Lf;
-        if (Qn >= Lf) Qn -= Lf;
-        ps = ps - dtf * qs;
-        ntst(Qp + g.idx[u], Qn); ntst(Pp + g.idx[u], P); ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps);
-        const float x = Qn * ihf;
-        const int j = cell_of_f(x, ng);
-        const float s = frac01_f(x, j);
-        atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
-        atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
-      } else {
-        const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
-        const double Q = g.q[u], psi = g.w[u];
-        double P = g.p[u], qs = g.a[u], ps = g.b[u];
-        const int i = cell_of(Q * inv_h, ng);
-        const double Ei = fE[i], gi = fG[i];
-        if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
-        Ks += 0.5 * psi * P * P + qs * P;
-        Ms += psi * P + qs;
-        Cs += psi;
-        P = P + half * Ei;
-        qs = qs + half * ps * gi;
-        double Qn = Q + dt * P;
-        if (Qn < 0.0) Qn += L;
-        if (Qn >= L) Qn -= L;
-        const double psn = ps - dt * qs;
-        const T Qs = (T)Qn, pss = (T)psn;
-        ntst(Qp + g.idx[u], Qs); ntst(Pp + g.idx[u], (T)P); ntst(qsp + g.idx[u], (T)qs); ntst(psp + g.idx[u], pss);
-        const double Qd = Qs, psd = pss;
-        const double x = Qd * inv_h;
-        const int j = cell_of(x, ng);
-        const double s = frac01(x, j);
-        lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
-      }
+      T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
+      push_particle<MODE>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs);
+      ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P); ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps);
     }
   };
 
@@ -823,6 +858,162 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     slot[2] = cbs;
   }
   flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
+}
+
+
+// ------------------------------------------------------------------ persistent step
+// nsteps fused steps in one cooperative launch (every workgroup resident at once).  The
+// particles of each tile stay in registers from the first step to the last.  Between steps
+// every workgroup of an instance waits until all of the instance's tiles have flushed the
+// previous step: an arrival counter, polled by one thread with a bounded spin (after
+// kSpinLimit polls the instance is flagged and the wait ends, so every wave finishes).  Data
+// other workgroups of the launch wrote (the load vector, the per-tile kinetic sums, the
+// cleared ring entry) is read and written at device scope; the ring protocol, the records
+// and the arithmetic are those of k_fused, so nsteps persistent steps equal nsteps fused
+// launches.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+template <int MODE, int TPB, int PPT>
+__global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ insts,
+                                                 const Tile* __restrict__ tiles, int phase0,
+                                                 int nsteps) {
+  extern __shared__ double smem[];
+  __shared__ double red[3 * (TPB / 64)];
+  __shared__ double sred[kSolveRed];
+  using T = typename StateType<MODE>::T;
+  const Tile tl = tiles[blockIdx.x];
+  const InstDev& d = insts[tl.inst];
+  const int ng = d.ng;
+  VPG T* __restrict__ Qp = gp<T>(d.Q);
+  VPG T* __restrict__ Pp = gp<T>(d.P);
+  VPG T* __restrict__ qsp = gp<T>(d.qs);
+  VPG T* __restrict__ psp = gp<T>(d.ps);
+  const VPG T* __restrict__ psip = gp<T>(d.psi);
+  double* fE = smem;
+  double* fG = smem + ng;
+  double* sacc = smem + 2 * ng;
+  double* bt = smem + 3 * ng;
+  double* fft = smem + 4 * ng;
+  VPG InstScal* sc = gp(d.scal);
+  if (sc->frozen) return;  // fixed for the launch: all tiles of the instance leave together
+  const bool first = tl.local == 0;
+
+  T q[PPT], p[PPT], a[PPT], b[PPT], w[PPT];
+  bool v[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int loc = u * TPB + (int)threadIdx.x;
+    v[u] = loc < tl.count;
+    if (v[u]) {
+      const long long i = tl.begin + loc;
+      q[u] = ntld(Qp + i); p[u] = ntld(Pp + i); a[u] = ntld(qsp + i);
+      b[u] = ntld(psp + i); w[u] = ntld(psip + i);
+    }
+  }
+  int pend = sc->pend[phase0];
+  long long step = 0;
+  double rec[3] = {0.0, 0.0, 0.0};  // field summary of the previous step (first tile)
+  if (first) {
+    step = sc->step;
+    rec[0] = sc->W[ring_prev(phase0)];
+    rec[1] = sc->e1r[ring_prev(phase0)];
+    rec[2] = sc->e1i[ring_prev(phase0)];
+  }
+  VPG unsigned* arrive = &sc->arrive;
+
+  int r0 = phase0;
+  for (int st = 0; st < nsteps; ++st) {
+    // nothing is hoisted out of the step loop: keeps the step's registers per step
+    __asm__ __volatile__("" ::: "memory");
+    const int r1 = ring_next(r0), r2 = ring_prev(r0);
+    if (st > 0) {  // wait for every tile of the instance to finish the previous step
+      if (threadIdx.x == 0) {
+        const unsigned target = (unsigned)st * (unsigned)d.ntiles;
+        unsigned it = 0;
+        while (__hip_atomic_load(arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++it > kSpinLimit) {
+            __hip_atomic_store(&sc->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    SolveIn sin_;
+    solve_load<MODE, true>(d, r0, first, sin_);
+    for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
+    double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+    {
+      double sum[6];
+      solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+      if (first) {
+        const int copies = d.acc_copies;
+        for (int c = 0; c < copies; ++c)
+          for (int j = threadIdx.x; j < ng; j += TPB) {
+            if constexpr (MODE == kFP32)
+              gst(gp<float>(d.acc) + acc_off(d, r2, c) + j, 0.0f);
+            else
+              gst(gp(d.acc) + acc_off(d, r2, c) + j, 0.0);
+          }
+        if (threadIdx.x == 0) {
+          if (pend && step >= 1)
+            write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
+          sc->W[r0] = sum[0];
+          sc->e1r[r0] = sum[1];
+          sc->e1i[r0] = sum[2];
+          if (!isfinite(sum[0])) sc->nonfinite = 1;
+          sc->pend[r1] = 1;
+          sc->step = step + 1;
+        }
+        step += 1;
+        rec[0] = sum[0];
+        rec[1] = sum[1];
+        rec[2] = sum[2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+      if (v[u]) push_particle<MODE>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u], w[u], Ks, Ms, Cs);
+    pend = 1;
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Ks = wave_sum(Ks);
+    Ms = wave_sum(Ms);
+    Cs = wave_sum(Cs);
+    if (lane == 0) {
+      red[3 * wid] = Ks;
+      red[3 * wid + 1] = Ms;
+      red[3 * wid + 2] = Cs;
+    }
+    __syncthreads();  // also completes every LDS deposit of the workgroup
+    if (threadIdx.x == 0) {
+      double kb = 0.0, mb = 0.0, cbs = 0.0;
+      for (int ww = 0; ww < TPB / 64; ++ww) {
+        kb += red[3 * ww];
+        mb += red[3 * ww + 1];
+        cbs += red[3 * ww + 2];
+      }
+      VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
+      gst(slot, kb);
+      gst(slot + 1, mb);
+      gst(slot + 2, cbs);
+    }
+    flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
+    if (st + 1 < nsteps) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's flush, slot and clear are performed
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    r0 = r1;
+  }
+#pragma unroll
+  for (int u = 0; u < PPT; ++u)
+    if (v[u]) {
+      const long long i = tl.begin + u * TPB + (int)threadIdx.x;
+      ntst(Qp + i, q[u]); ntst(Pp + i, p[u]); ntst(qsp + i, a[u]); ntst(psp + i, b[u]);
+    }
 }
 
 // Deposit of the current state only (eq. rhs-assembly), added into ring entry `phase`.
@@ -1131,6 +1322,9 @@ __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __r
     sc->chgd = 0.0;
   } else if (op == kScalClearPending) {
     sc->pend[phase] = 0;
+  } else if (op == kScalPersistStart) {
+    sc->frozen = sc->nonfinite;
+    sc->arrive = 0u;
   }
 }
 
@@ -1286,6 +1480,48 @@ hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_
   VP_DISPATCH(mode, tpb, k_fused, dim3(ntiles), dim3(tpb), lds, s, d_inst, d_tiles, tile0, ppt,
               phase);
   return hipGetLastError();
+}
+
+
+#define VP_PERSIST_CASE(M, TB, PP)                                                          \
+  if (mode == M && tpb == TB && ppt == PP) {                                                \
+    fn = reinterpret_cast<const void*>(&k_persist<M, TB, PP>);                              \
+  }
+
+static const void* persist_fn(int mode, int tpb, int ppt) {
+  const void* fn = nullptr;
+#define VP_PERSIST_MODE(M)                                                                  \
+  VP_PERSIST_CASE(M, 512, 2) VP_PERSIST_CASE(M, 512, 4) VP_PERSIST_CASE(M, 512, 8)          \
+  VP_PERSIST_CASE(M, 1024, 2) VP_PERSIST_CASE(M, 1024, 4) VP_PERSIST_CASE(M, 1024, 8)
+  VP_PERSIST_MODE(kFP64)
+  VP_PERSIST_MODE(kFP32Comp)
+  VP_PERSIST_MODE(kFP32)
+  VP_PERSIST_MODE(kFP32TwoSum)
+#undef VP_PERSIST_MODE
+  return fn;
+}
+#undef VP_PERSIST_CASE
+
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft) {
+  const void* fn = persist_fn(mode, tpb, ppt);
+  if (!fn) return 0;
+  const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tpb, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
+                          int ntiles, int max_ng, bool lds_fft, int phase, int nsteps,
+                          hipStream_t s) {
+  if (ntiles <= 0 || nsteps <= 0) return hipSuccess;
+  const void* fn = persist_fn(mode, tpb, ppt);
+  if (!fn) return hipErrorInvalidValue;
+  const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
+  void* args[] = {(void*)&d_inst, (void*)&d_tiles, (void*)&phase, (void*)&nsteps};
+  return hipLaunchCooperativeKernel(fn, dim3(ntiles), dim3(tpb), args, (unsigned)lds, s);
 }
 
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,

@@ -1,0 +1,111 @@
+"""Persistent steps (many steps per cooperative launch, particles in registers between steps)
+against one fused launch per step and against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("Q", "P", "qs", "ps", "psi")
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def oracle_run(st, w, nsteps):
+    return O.run(*(np.asarray(st[k], dtype=np.float64) for k in FIELDS), w.L, w.ng, w.dt, nsteps)
+
+
+@pytest.mark.parametrize("threads,ppt,copies", [(1024, 4, 4), (512, 2, 1), (512, 8, 8)])
+def test_persistent_fp64_matches_oracle(vp, threads, ppt, copies):
+    w = W.landau_linear(seed=4, nx=96, nv=80, ng=64)   # 7680 particles, several tiles
+    w.params["alpha"] = 0.2
+    st = w.state()
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=64)
+    sim.set_tuning(threads=threads, ppt=ppt, acc_copies=copies, persistent=1)
+    nsteps = 23
+    sim.step(nsteps)
+    got = sim.state_numpy(0)
+    hist = sim.history(0, 0, nsteps) + [sim.diagnostics(0)]
+    ref_state, _, ref_hist = oracle_run(st, w, nsteps)
+    for k, r in zip(FIELDS, ref_state):
+        assert np.allclose(got[k], r, rtol=0, atol=1e-11), k
+    for key in ("W", "K", "H"):
+        assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
+    assert [h["step"] for h in hist] == list(range(nsteps + 1))
+    sim.close()
+
+
+def test_persistent_fp32c_matches_fused_and_continues_across_modes(vp):
+    w = W.two_stream(nx=256, nv=128, ng=128)
+    st = w.state(np.float32)
+    a = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=64)
+    b = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=64)
+    a.set_tuning(threads=1024, ppt=4, acc_copies=2, persistent=1)
+    b.set_tuning(threads=1024, ppt=4, acc_copies=2, persistent=0)
+    a.step(10)
+    b.step(10)
+    # switch modes in the middle: persistent -> fused and fused -> persistent
+    a.set_tuning(persistent=0)
+    b.set_tuning(persistent=1)
+    a.step(11)
+    b.step(11)
+    sa, sb = a.state_numpy(0), b.state_numpy(0)
+    for k in FIELDS:
+        assert rel_l2(sa[k], sb[k]) < 1e-5, k
+    ha, hb = a.history(0, 0, 21), b.history(0, 0, 21)
+    assert rel_l2([h["W"] for h in ha], [h["W"] for h in hb]) < 1e-5
+    assert a.diagnostics(0)["step"] == b.diagnostics(0)["step"] == 21
+    a.close()
+    b.close()
+
+
+def test_persistent_batch_and_mid_run_admission(vp):
+    ws = W.landau_sweep(seed=17, n_inst=4)
+    sts = [w.state() for w in ws]
+    eng = vp.Engine("fp64", max_slots=3)
+    for s in range(3):
+        eng.admit(s, sts[s], ws[s].L, ws[s].ng, ws[s].dt, solver="fft" if s == 1 else "scan")
+    eng.set_tuning(threads=512, ppt=4, acc_copies=2, persistent=1)
+    eng.step(8)
+    eng.retire(2)
+    eng.admit(2, sts[3], ws[3].L, ws[3].ng, ws[3].dt)
+    eng.step(6)
+    for s, (st, w, n) in enumerate(((sts[0], ws[0], 14), (sts[1], ws[1], 14), (sts[3], ws[3], 6))):
+        got = eng.state_numpy(s)
+        ref_state, _, _ = oracle_run(st, w, n)
+        for k, r in zip(FIELDS, ref_state):
+            assert np.allclose(got[k], r, rtol=0, atol=1e-11), (s, k)
+        assert eng.diagnostics(s)["step"] == n
+
+
+def test_persistent_with_sorting_matches_unsorted(vp):
+    w = W.landau_linear(seed=2, nx=128, nv=64, ng=128)
+    st = w.state()
+    a = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", sort_every=4, sort_chunk=1024)
+    b = vp.Simulation(st, w.L, w.ng, w.dt, "fp64")
+    a.set_tuning(threads=512, ppt=4, persistent=1)
+    a.step(13)
+    b.step(13)
+    da, db = a.diagnostics(0), b.diagnostics(0)
+    for k in ("K", "W", "H", "momentum", "charge"):
+        assert abs(da[k] - db[k]) <= 1e-10 * max(1.0, abs(db[k])), k
+
+
+def test_persistent_rejects_shapes_that_do_not_fit(vp):
+    w = W.two_stream(nx=512, nv=512, ng=64)
+    sim = vp.Simulation(w.state(np.float32), w.L, w.ng, w.dt, "fp32c")
+    with pytest.raises(vp.VPError) as e:
+        sim.set_tuning(threads=512, ppt=2, persistent=1, acc_copies=1)  # 256 tiles: fits
+        big = vp.Simulation(W.two_stream(nx=4096, nv=1024, ng=64).state(np.float32), w.L, 64,
+                            w.dt, "fp32c")
+        big.set_tuning(threads=512, ppt=2, persistent=1)         # 4096 tiles: cannot all be resident
+    assert e.value.status == vp._lib.VP_ERR_ARG
+    assert sim.get_tuning()["persistent"] == 1
+    sim.step(3)
+    assert sim.diagnostics(0)["step"] == 3
