@@ -251,7 +251,8 @@ def run_sweep(args):
                    "nonfinite_instances": nonfinite},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fused", "bytes_per_launch": bytes_per_launch,
+                     "kernel": "k_persist" if tun.get("persistent") else "k_fused",
+                     "bytes_per_launch": bytes_per_launch,
                      "kernel_us": kern_avg_s * 1e6},
     }
     print(json.dumps(out), flush=True)
@@ -364,6 +365,56 @@ def run_precision_study(args):
     print(json.dumps(out), flush=True)
 
 
+# algorithmic bytes per particle of the unfused kernels (FP32 state; FP64 doubles them)
+DEPOSIT_BYTES = 12      # read Q, p*, psi*
+GATHER_PUSH_BYTES = 32  # read Q, P, q*, p*; write Q, P, q*, p* (kick and drift)
+
+
+def run_primitives(args):
+    """The unfused kernels on their own: vp_deposit (load vector of the current state) and
+    vp_gather_push (kick + drift), each timed with HIP events over many back-to-back calls.
+    Prints one JSON line with each kernel's achieved GB/s against the HBM peak."""
+    import numpy as np
+    import torch
+    import paper_2605_21794_amd as vp
+    w, prec = make_workload(args.workload)
+    if args.precision:
+        prec = args.precision
+    scale = 2 if prec == "fp64" else 1
+    state = w.state(np.float64 if prec == "fp64" else np.float32)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    sim = vp.Simulation(state, w.L, w.ng, w.dt, prec)
+    reps = max(1, args.steps // 10)
+    res = {}
+    # each kernel at its own launch shape (unless --launch fixes one for both): the deposit
+    # reads 12 B per particle and pays a per-tile grid clear and flush, so it wants big tiles;
+    # the push streams 32 B per particle and wants many small ones
+    shapes = {"k_deposit": args.launch or "1024,16,4", "k_gather_push": args.launch or "1024,4,1"}
+    for name, fn, nbytes in (("k_deposit", sim.deposit, DEPOSIT_BYTES * scale),
+                             ("k_gather_push",
+                              lambda: sim.gather_push(0.5 * w.dt, w.dt), GATHER_PUSH_BYTES * scale)):
+        sim.set_tuning(**parse_launch(shapes[name]))
+        for _ in range(3):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        gbs = nbytes * w.n / (us * 1e-6) / 1e9
+        res[name] = {"us_per_launch": us, "bytes_per_particle": nbytes, "achieved_GBs": gbs,
+                     "frac": gbs / HBM_PEAK_GBS, "launch": shapes[name]}
+        log(f"{name}: {us:.2f} us per launch, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.2f} of peak)")
+    sim.close()
+    print(json.dumps({"metric": METRIC, "config": {"workload": w.name, "n": w.n, "ng": w.ng,
+                                                   "precision": prec, "launches": reps},
+                      "primitives": res}), flush=True)
+
+
 def cpu_baseline(state, w, budget_s: float, max_steps: int):
     """FP64 oracle steps on the same initial state until the time budget is spent."""
     import numpy as np
@@ -403,6 +454,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="sort particles by cell every this many steps (0: never)")
     ap.add_argument("--sort-chunk", type=int, default=0, help="particles per sorted chunk")
+    ap.add_argument("--primitives", action="store_true",
+                    help="time vp_deposit and vp_gather_push on their own")
     ap.add_argument("--precision-study", action="store_true",
                     help="landau_nonlinear in every precision mode against the stored oracle")
     ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
@@ -436,6 +489,9 @@ def main():
         return
     if args.precision_study:
         run_precision_study(args)
+        return
+    if args.primitives:
+        run_primitives(args)
         return
 
     import numpy as np

@@ -111,7 +111,7 @@ typedef struct vp_diag {
 /* Launch shape of the particle kernels; chosen by vp_tune or set by the caller. */
 typedef struct vp_tuning {
   int32_t threads;      /* threads per workgroup of the particle kernels: 256, 512 or 1024 */
-  int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8 or 16 */
+  int32_t ppt;          /* particles per thread per tile: 1, 2, 4, 8, 16, 32 or 64 */
   int32_t acc_copies;   /* copies of each instance's global load accumulator, 1..8 */
   int32_t use_graph;    /* 1: vp_step replays captured HIP graphs; 0: direct launches */
   int32_t graph_steps;  /* steps per captured graph, 1..256 (rounded up to a multiple of 3) */

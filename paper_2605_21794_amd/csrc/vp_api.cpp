@@ -667,8 +667,9 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
   if (!h || !t) return fail(VP_ERR_ARG, "NULL argument");
   if (!(t->threads == 256 || t->threads == 512 || t->threads == 1024))
     return fail(VP_ERR_ARG, "threads must be 256, 512 or 1024");
-  if (!(t->ppt == 1 || t->ppt == 2 || t->ppt == 4 || t->ppt == 8 || t->ppt == 16))
-    return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8 or 16");
+  if (!(t->ppt == 1 || t->ppt == 2 || t->ppt == 4 || t->ppt == 8 || t->ppt == 16 || t->ppt == 32 ||
+        t->ppt == 64))
+    return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8, 16, 32 or 64");
   if (t->acc_copies < 1 || t->acc_copies > VP_MAX_ACC_COPIES) return fail(VP_ERR_ARG, "acc_copies out of range");
   if (t->graph_steps < 1 || t->graph_steps > 256) return fail(VP_ERR_ARG, "graph_steps out of range");
   if (t->persistent) {
@@ -763,9 +764,12 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
   double best_us = 1e300;
   struct Cand { int threads, ppt, acc, persistent; };
   std::vector<Cand> cands;
+  long long nmax = 0;
+  for (int s : h->h_occ) nmax = std::max<long long>(nmax, h->slots[s].cfg.n);
   for (int th : {512, 1024})
-    for (int pp : {1, 2, 4, 8})
-      for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 0});
+    for (int pp : {1, 2, 4, 8, 16, 32})
+      if (pp <= 8 || (long long)th * pp * 512 <= nmax)  // big tiles only for big instances
+        for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 0});
   // persistent shapes that keep every tile resident
   for (int th : {512, 1024})
       for (int pp : {2, 4, 8}) {
