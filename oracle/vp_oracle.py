@@ -16,7 +16,11 @@ Readings taken where the paper is silent:
   * a particle sitting exactly on a node belongs to the element on its right;
   * the second derivative phi_h'' needed by the dipole equation (eq. sw-evolution) is
     taken from the lumped-mass L2 projection of the element-constant field E_h onto
-    P1, then differentiated on each element (the paper's projection step for phi_h'');
+    P1, then differentiated on each element (the paper's projection step for phi_h'').
+    Two other readings of that step are available behind the `projection` argument:
+    the L2 projection onto P1 of phi_h'' itself, taken in the weak sense
+    ((phi_h'', phi_j) = -(phi_h', phi_j') = -b~_j), with the lumped ("nodal") or the
+    consistent ("consistent") mass matrix, evaluated at Q by P1 interpolation;
   * the paper's leapfrog (the standard PIC one) is read as the kick-drift-kick Strang splitting of
     H_h = H_kin + H_field, each sub-flow solved exactly (derived from the 1D bracket,
     eq. lp1d): the kick freezes (Q, p*) and moves (P, q*), the drift freezes (P, q*)
@@ -29,15 +33,19 @@ Functions and the passages they follow:
   poisson_solve       -- eq. lin-sys with the gauge 1^T Phi = 0
   element_field       -- E_e = -phi_h' on each element (field read from the basis)
   projected_curvature -- phi_h'' via the lumped L2 projection (reading above)
-  kick, drift         -- exact sub-flows of eq. sw-evolution split as above
+  mass_eigenvalues,
+  nodal_curvature     -- the two other projections of phi_h'' (readings above)
+  curvature_at        -- phi_h''(Q_a) from any of the three projections
+  kick_values, kick,
+  drift               -- exact sub-flows of eq. sw-evolution split as above
   diagnostics         -- eq. Hh (discrete Hamiltonian), eq. Eamp, charge, momentum
   sort_perm           -- chunked stable counting sort by cell (a layout step of the
                          GPU path; its meaning is fixed here, not by the paper)
   run                 -- the whole cycle, one field solve per step
 
-parity unpinned: the choice of projection for phi_h'' (no printed value in the paper
-discriminates between projections); every other function is pinned by the tests in
-tests/test_oracle_pins.py.
+parity unpinned: the choice among the three projections for phi_h'' (no printed value in
+the paper discriminates between them); each projection itself, and every other function, is
+pinned by the tests in tests/test_oracle_pins.py.
 """
 from __future__ import annotations
 
@@ -45,9 +53,14 @@ import numpy as np
 
 __all__ = [
     "inv_h", "cell_index", "deposit", "neutralize", "poisson_eigenvalues",
-    "poisson_solve", "element_field", "projected_curvature", "solve_field",
-    "kick", "drift", "wrap", "diagnostics", "sort_perm", "step", "run",
+    "poisson_solve", "element_field", "projected_curvature", "mass_eigenvalues",
+    "nodal_curvature", "curvature_at", "solve_field", "kick_values", "kick", "drift", "wrap",
+    "diagnostics", "sort_perm", "step", "run", "PROJECTIONS",
 ]
+
+# Readings of the projection step for phi_h'': element-constant from the lumped projection
+# of E (the default), or a P1 function from the lumped / consistent projection of phi_h''.
+PROJECTIONS = ("elem", "nodal", "consistent")
 
 
 def inv_h(L: float, ng: int) -> float:
@@ -146,31 +159,82 @@ def projected_curvature(E, L: float):
     return -(np.roll(En, -1) - En) * inv_h(L, ng)
 
 
-def solve_field(Q, ps, psi, L: float, ng: int):
-    """Deposit, neutralise, solve; returns dict with b, bt, Phi, E, g, W."""
+def mass_eigenvalues(L: float, ng: int):
+    """Eigenvalues of the periodic P1 mass matrix M_ij = integral(phi_i phi_j).
+
+    On a uniform periodic mesh M = (h/6) circ(1, 4, 1), circulant, so
+    mu_m = (h/3) (2 + cos(2 pi m / Ng)), all positive.
+    """
+    h = float(L) / ng
+    m = np.arange(ng)
+    return (h / 3.0) * (2.0 + np.cos(2.0 * np.pi * m / ng))
+
+
+def nodal_curvature(bt, L: float, projection: str):
+    """phi_h'' as a P1 function g = sum_j g_j phi_j: the L2 projection of the weak second
+    derivative of phi_h, (phi_h'', phi_j) = -(phi_h', phi_j') = -(A Phi)_j = -b~_j.
+
+    projection "nodal": lumped mass (M replaced by its row sums, h on the diagonal), so
+    h g_j = -b~_j; "consistent": M g = -b~ with the full mass matrix, solved in the Fourier
+    basis of the circulant M.
+    """
+    bt = np.asarray(bt, dtype=np.float64)
+    ng = bt.shape[0]
+    if projection == "nodal":
+        return -bt * inv_h(L, ng)
+    if projection == "consistent":
+        return np.fft.ifft(-np.fft.fft(bt) / mass_eigenvalues(L, ng)).real
+    raise ValueError(f"not a nodal projection: {projection!r}")
+
+
+def curvature_at(Q, g, L: float, projection: str):
+    """phi_h''(Q_a): the element value g[i] for the element-constant projection; the P1
+    interpolant (1 - s) g_i + s g_{i+1} for the nodal and consistent ones."""
+    g = np.asarray(g, dtype=np.float64)
+    ng = g.shape[0]
+    i, s = cell_index(Q, L, ng)
+    if projection == "elem":
+        return g[i]
+    if projection in ("nodal", "consistent"):
+        return (1.0 - s) * g[i] + s * g[(i + 1) % ng]
+    raise ValueError(f"unknown projection {projection!r}")
+
+
+def solve_field(Q, ps, psi, L: float, ng: int, projection: str = "elem"):
+    """Deposit, neutralise, solve; returns dict with b, bt, Phi, E, g, W, projection."""
     b = deposit(Q, ps, psi, L, ng)
     bt = neutralize(b)
     Phi = poisson_solve(bt, L)
     E = element_field(Phi, L)
-    g = projected_curvature(E, L)
+    if projection == "elem":
+        g = projected_curvature(E, L)
+    else:
+        g = nodal_curvature(bt, L, projection)
     h = float(L) / ng
     W = 0.5 * h * np.sum(E * E)
-    return {"b": b, "bt": bt, "Phi": Phi, "E": E, "g": g, "W": W}
+    return {"b": b, "bt": bt, "Phi": Phi, "E": E, "g": g, "W": W, "projection": projection}
 
 
-def kick(Q, P, qs, ps, E, g, L: float, tau: float):
-    """Exact flow of H_field = (1/2) Phi^T A Phi for time tau.
-
-    Q and p* (hence b, Phi, E, g) are frozen, so
-        P  <- P  + tau * E[i]            (dP/dt  = -phi_h'(Q)),
-        q* <- q* + tau * p* * g[i]       (dq*/dt =  p* phi_h''(Q)),
-    with the products evaluated left to right.
+def kick_values(P, qs, ps, Ea, ga, tau: float):
+    """Exact flow of the field part of the Hamiltonian for time tau, given each particle's
+    field value Ea = -phi'(Q_a) and curvature ga = phi''(Q_a).  Q and p* are frozen (so are
+    Ea and ga), hence
+        P  <- P  + tau * Ea              (dP/dt  = -phi'(Q)),
+        q* <- q* + tau * p* * ga         (dq*/dt =  p* phi''(Q)),
+    with the products evaluated left to right (eq. sw-evolution; with a prescribed
+    potential V in place of phi, eq. sw_prescribed_potential).
     """
+    P = np.asarray(P, dtype=np.float64) + tau * np.asarray(Ea, dtype=np.float64)
+    qs = np.asarray(qs, dtype=np.float64) + tau * np.asarray(ps, dtype=np.float64) * ga
+    return P, qs
+
+
+def kick(Q, P, qs, ps, E, g, L: float, tau: float, projection: str = "elem"):
+    """Exact flow of H_field = (1/2) Phi^T A Phi for time tau with the mesh field:
+    Ea = E[i_a] read from the basis, ga = phi_h''(Q_a) from the projection."""
     ng = np.asarray(E).shape[0]
     i, _ = cell_index(Q, L, ng)
-    P = np.asarray(P, dtype=np.float64) + tau * E[i]
-    qs = np.asarray(qs, dtype=np.float64) + tau * np.asarray(ps, dtype=np.float64) * g[i]
-    return P, qs
+    return kick_values(P, qs, ps, np.asarray(E)[i], curvature_at(Q, g, L, projection), tau)
 
 
 def wrap(Qn, L: float):
@@ -233,18 +297,20 @@ def sort_perm(cells, chunk: int):
 def step(state, fld, L: float, ng: int, dt: float):
     """One kick(dt/2) - drift(dt) - [deposit, solve] - kick(dt/2) step."""
     Q, P, qs, ps, psi = state
-    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt)
+    proj = fld.get("projection", "elem")
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj)
     Q, ps = drift(Q, P, qs, ps, L, dt)
-    fld = solve_field(Q, ps, psi, L, ng)
-    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt)
+    fld = solve_field(Q, ps, psi, L, ng, proj)
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj)
     return (Q, P, qs, ps, psi), fld
 
 
-def run(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, record=True):
+def run(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, record=True,
+        projection: str = "elem"):
     """Run nsteps KDK steps from the given state.  Returns (state, field, history),
     where history is a list of diagnostics dicts at t = 0, dt, ..., nsteps dt."""
     state = tuple(np.asarray(a, dtype=np.float64).copy() for a in (Q, P, qs, ps, psi))
-    fld = solve_field(state[0], state[3], state[4], L, ng)
+    fld = solve_field(state[0], state[3], state[4], L, ng, projection)
     hist = [diagnostics(state[1], state[2], state[4], fld, L)] if record else []
     for _ in range(nsteps):
         state, fld = step(state, fld, L, ng, dt)

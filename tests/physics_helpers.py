@@ -38,6 +38,25 @@ def two_stream_root(k, v0, T=1.0, guess=0.3j):
     return newton_complex(D, guess)
 
 
+def maxwellian_sum_root(k, beams, guess):
+    """Root of the Vlasov dispersion relation for a sum of Maxwellians
+    beams = [(density, drift, temperature), ...] (unit total charge):
+    1 + sum_s n_s (1 + z_s Z(z_s)) / (k^2 T_s) = 0, z_s = (omega - k v_s) / (k sqrt(2 T_s))."""
+    def D(om):
+        s = 0.0
+        for n, vb, T in beams:
+            z = (om - k * vb) / (k * math.sqrt(2.0 * T))
+            s += n * (1.0 + z * plasma_z(z)) / (k * k * T)
+        return 1.0 + s
+    return newton_complex(D, guess)
+
+
+def bump_on_tail_root(k, guess=1.0 + 0.2j):
+    """The bump-on-tail profile (0.9 exp(-v^2/2) + 0.2 exp(-2 (v - 4.5)^2)) / sqrt(2 pi) is
+    0.9 N(0, 1) + 0.1 N(4.5, 1/4)."""
+    return maxwellian_sum_root(k, [(0.9, 0.0, 1.0), (0.1, 4.5, 0.25)], guess)
+
+
 def fit_damped_mode(t, z, t0, t1):
     """Least-squares fit of z(t) = exp(gamma t) (a cos wt + b sin wt), complex a, b, over
     t0 <= t <= t1; returns (gamma, omega)."""

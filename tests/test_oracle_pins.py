@@ -416,3 +416,239 @@ def test_two_stream_growth_matches_dispersion_root():
     a = np.array([abs(complex(h["e1_re"], h["e1_im"])) for h in hist])
     g = PH.fit_growth(t, a, 12.0, 26.0)
     assert abs(g - om.imag) < 0.03 * om.imag, (g, om.imag)
+
+
+# ---------------------------------------------------------------- projection readings of phi_h''
+def _mass_by_quadrature(L, ng):
+    """M_ij = integral of phi_i phi_j over the periodic domain, by 4-point Gauss-Legendre on
+    every element with the brute-force hats (exact for the quadratic integrands)."""
+    h = L / ng
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    M = np.zeros((ng, ng))
+    for e in range(ng):
+        x = e * h + 0.5 * h * (xg + 1.0)
+        w = 0.5 * h * wg
+        hats = np.array([_hat(x, j, L, ng) for j in range(ng)])
+        M += (hats * w) @ hats.T
+    return M
+
+
+@pytest.mark.parametrize("ng", [8, 32])
+def test_nodal_projections_match_assembled_mass_matrix(ng):
+    """The consistent projection solves M g = -b~ with M assembled from the hats by
+    quadrature; the lumped one uses M's row sums.  Both must match the oracle's
+    (Fourier-diagonalised / scaled) forms."""
+    rng = np.random.default_rng(ng)
+    L = 3.3
+    Q, _, _, ps, psi = _rand_particles(rng, 200, L, ng)
+    f = O.solve_field(Q, ps, psi, L, ng)
+    M = _mass_by_quadrature(L, ng)
+    gc = np.linalg.solve(M, -f["bt"])
+    gl = -f["bt"] / M.sum(axis=1)
+    assert np.allclose(O.nodal_curvature(f["bt"], L, "consistent"), gc, rtol=0,
+                       atol=1e-11 * np.abs(gc).max())
+    assert np.allclose(O.nodal_curvature(f["bt"], L, "nodal"), gl, rtol=0,
+                       atol=1e-12 * np.abs(gl).max())
+    # the weak second derivative of phi_h against each hat is -b~_j: -(phi_h', phi_j')
+    h = L / ng
+    Phi = f["Phi"]
+    slope = -f["E"]                                      # phi_h' per element
+    weak = np.array([-sum(slope[e] * (_hat_slope((e + 0.5) * h, j, L, ng)) * h
+                          for e in range(ng)) for j in range(ng)])
+    assert np.allclose(weak, -f["bt"], rtol=0, atol=1e-11 * np.abs(f["bt"]).max())
+    assert np.allclose(Phi.sum(), 0.0, atol=1e-12 * np.abs(Phi).max())
+
+
+def test_element_projection_is_element_average_of_lumped_nodal():
+    """The default (element-constant) reading equals the average over each element's two
+    nodes of the lumped nodal reading (both are lumped projections; derived identity)."""
+    rng = np.random.default_rng(9)
+    L, ng = 5.0, 64
+    Q, _, _, ps, psi = _rand_particles(rng, 500, L, ng)
+    f = O.solve_field(Q, ps, psi, L, ng)
+    gn = O.nodal_curvature(f["bt"], L, "nodal")
+    assert np.allclose(f["g"], 0.5 * (gn + np.roll(gn, -1)), rtol=0,
+                       atol=1e-12 * np.abs(gn).max())
+
+
+def test_curvature_at_is_p1_interpolant():
+    """For the nodal readings phi_h''(Q) is the P1 function sum_j g_j phi_j(Q) (brute-force
+    hats); for the element reading it is the value of the element holding Q."""
+    rng = np.random.default_rng(2)
+    L, ng = 2.5, 16
+    g = rng.normal(size=ng)
+    Q = rng.uniform(0, L, 300)
+    brute = np.array([sum(g[j] * _hat(q, j, L, ng) for j in range(ng)) for q in Q])
+    for proj in ("nodal", "consistent"):
+        assert np.allclose(O.curvature_at(Q, g, L, proj), brute, rtol=0, atol=1e-13)
+    i = np.floor(Q / (L / ng)).astype(int)
+    assert np.array_equal(O.curvature_at(Q, g, L, "elem"), g[i])
+
+
+@pytest.mark.parametrize("proj", ["elem", "nodal", "consistent"])
+def test_projected_curvature_converges_to_minus_density(proj):
+    """phi'' = -(rho - n0): for rho = 1 + a cos(kx) carried by a fine uniform set of
+    monopoles, every reading of phi_h'' at the mesh points tends to -a cos(kx) at second
+    order in h (element readings at the element midpoints)."""
+    L, a = 2 * np.pi, 0.3
+    errs = []
+    for ng in (16, 32, 64):
+        n = 4096 * 8
+        x = (np.arange(n) + 0.5) * L / n
+        psi = (1.0 + a * np.cos(x)) * L / n
+        f = O.solve_field(x, np.zeros(n), psi, L, ng, proj)
+        h = L / ng
+        pts = (np.arange(ng) + (0.5 if proj == "elem" else 0.0)) * h
+        errs.append(np.abs(f["g"] + a * np.cos(pts)).max())
+    assert errs[0] < 0.05 * a
+    assert errs[1] < errs[0] / 3.5 and errs[2] < errs[1] / 3.5, errs
+
+
+def test_projection_enters_only_through_the_shape_kick():
+    """The curvature multiplies p* in q*'s kick and nothing else: one step from the same
+    state gives bitwise the same positions under every reading (the first half-kick and the
+    drift of Q use E only), and different q*."""
+    w = W.landau_linear(nx=32, nv=32, ng=32)
+    st = w.state()
+    out = {}
+    for proj in O.PROJECTIONS:
+        state, _, _ = O.run(st["Q"], st["P"], st["qs"], st["ps"], st["psi"], w.L, w.ng, w.dt,
+                            1, projection=proj)
+        out[proj] = state
+    for proj in ("nodal", "consistent"):
+        assert np.array_equal(out["elem"][0], out[proj][0])
+        assert not np.array_equal(out["elem"][2], out[proj][2])
+
+
+# ---------------------------------------------------------------- convergence (Theorem 2)
+def _periodic_green(x, Q, L):
+    """Zero-mean periodic solution of -phi'' = delta(x - Q) - 1/L:
+    G(r) = r^2 / (2L) - r/2 + L/12, r = (x - Q) mod L."""
+    r = (x - Q) % L
+    return r * r / (2 * L) - r / 2 + L / 12
+
+
+def _periodic_dipole(x, Q, L):
+    """Zero-mean periodic solution of -phi'' = delta'(x - Q): dG/dr = r/L - 1/2."""
+    r = (x - Q) % L
+    return r / L - 0.5
+
+
+def _l2_error_p1(Phi, exact, Q, L):
+    """|| exact - P1 interpolant of Phi ||_L2 by 6-point Gauss-Legendre on each element,
+    the element holding Q split at Q (the exact solution has a kink or jump there)."""
+    ng = Phi.shape[0]
+    h = L / ng
+    xg, wg = np.polynomial.legendre.leggauss(6)
+    tot = 0.0
+    for e in range(ng):
+        a, b = e * h, (e + 1) * h
+        cuts = [a, Q, b] if a < Q < b else [a, b]
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            x = 0.5 * (hi - lo) * (xg + 1.0) + lo
+            w = 0.5 * (hi - lo) * wg
+            s = (x - a) / h
+            ph = (1 - s) * Phi[e] + s * Phi[(e + 1) % ng]
+            tot += np.sum(w * (exact(x) - ph) ** 2)
+    return math.sqrt(tot)
+
+
+def test_point_source_convergence_rates():
+    """T-S5 (Theorem 2): for one monopole the L2 error of the Galerkin potential falls as
+    h^(3/2), for one dipole as h^(1/2) (the exact potential has a kink, resp. a jump, at
+    the particle).  Q sits at the same relative place in its element on every mesh."""
+    L = 1.0
+    rates = {}
+    for kind in ("monopole", "dipole"):
+        hs, errs = [], []
+        for ng in (16, 32, 64, 128, 256, 512, 1024):
+            h = L / ng
+            Q = L / 4 + 0.3 * h
+            psi, ps = (1.0, 0.0) if kind == "monopole" else (0.0, 1.0)
+            f = O.solve_field(np.array([Q]), np.array([ps]), np.array([psi]), L, ng)
+            exact = (lambda x: _periodic_green(x, Q, L)) if kind == "monopole" else \
+                (lambda x: _periodic_dipole(x, Q, L))
+            hs.append(h)
+            errs.append(_l2_error_p1(f["Phi"], exact, Q, L))
+        rates[kind] = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    assert abs(rates["monopole"] - 1.5) < 0.1, rates
+    assert abs(rates["dipole"] - 0.5) < 0.05, rates
+
+
+# ---------------------------------------------------------------- decorated particle in a potential
+def _pendulum_field(Q, kappa):
+    """V(q) = 1 - cos(kappa q): E = -V'(Q), curvature g = V''(Q)."""
+    return -kappa * np.sin(kappa * Q), kappa * kappa * np.cos(kappa * Q)
+
+
+def _kdk_prescribed(state, kappa, L, dt, n):
+    Q, P, qs, ps, psi = (np.array(a, dtype=np.float64) for a in state)
+    for _ in range(n):
+        P, qs = O.kick_values(P, qs, ps, *_pendulum_field(Q, kappa), 0.5 * dt)
+        Q, ps = O.drift(Q, P, qs, ps, L, dt)
+        P, qs = O.kick_values(P, qs, ps, *_pendulum_field(Q, kappa), 0.5 * dt)
+    return Q, P, qs, ps, psi
+
+
+def test_shape_variables_are_the_tangent_of_the_central_motion():
+    """T-P3 (eq. sw_prescribed_potential): (p*, -q*) evolves as the linearisation of the
+    (Q, P) map along its trajectory, so two central trajectories started eps (p*, -q*)
+    apart separate by eps (p*_n, -q*_n) + O(eps^2).  A wrong sign or factor in the q* kick
+    or in the p* drift breaks it."""
+    L = 10.0
+    kappa = 2 * np.pi / L
+    base = ([2.0, 5.5, 8.0], [0.4, -0.7, 1.1], [0.1, -0.2, 0.05], [0.3, 0.1, -0.25],
+            [1.0, 1.0, 1.0])
+    dt, n = 0.05, 400
+    Q, P, qs, ps, _ = _kdk_prescribed(base, kappa, L, dt, n)
+    res = []
+    for eps in (1e-4, 1e-5):
+        Qe, Pe, _, _, _ = _kdk_prescribed(
+            (np.add(base[0], eps * np.array(base[3])), np.subtract(base[1], eps * np.array(base[2])),
+             base[2], base[3], base[4]), kappa, L, dt, n)
+        dQ = _wrap_dist(Qe, Q, L) / eps
+        dP = (Pe - P) / eps
+        res.append(max(np.abs(dQ - ps).max(), np.abs(dP + qs).max()))
+    assert res[0] < 1e-3 * max(np.abs(ps).max(), np.abs(qs).max()), res
+    assert res[1] < res[0] / 5, res                      # first order in eps
+
+
+def test_test_particle_hamiltonian_is_bounded_at_second_order():
+    """T-P5: three decorated particles in V = 1 - cos(kappa q), L = 10 (the paper's
+    test-particle example, eq. swpic_test_particle): H_SWPIC under the splitting stays
+    within an O(dt^2) band with no secular drift."""
+    L = 10.0
+    kappa = 2 * np.pi / L
+
+    def H(st):
+        Q, P, qs, ps, psi = st
+        return float(np.sum(0.5 * psi * P * P + P * qs + psi * (1 - np.cos(kappa * Q))
+                            - ps * kappa * np.sin(kappa * Q)))
+
+    st0 = ([2.0, 5.0, 8.0], [0.5, -0.3, 1.0], [0.1, -0.05, 0.02], [0.05, 0.1, -0.03],
+           [10.0, 10.0, 10.0])
+    H0 = H(tuple(np.array(a) for a in st0))
+    bands = []
+    for dt in (0.1, 0.05):
+        n = int(round(200.0 / dt))
+        st = tuple(np.array(a, dtype=np.float64) for a in st0)
+        dev = []
+        for _ in range(n // 20):
+            st = _kdk_prescribed(st, kappa, L, dt, 20)
+            dev.append(H(st) - H0)
+        dev = np.abs(np.array(dev))
+        bands.append(dev.max())
+        q = dev.size // 4
+        quarters = [dev[k * q:(k + 1) * q].max() for k in range(4)]
+        assert max(quarters) < 1.3 * min(quarters), quarters      # no secular growth
+    assert bands[0] < 1e-3 * abs(H0)
+    assert 3.6 < bands[0] / bands[1] < 4.4, bands                # second order in dt
+
+
+def test_bump_on_tail_root_value():
+    """The bump-on-tail configuration of the served mix (k = 0.3; the velocity profile is
+    0.9 N(0, 1) + 0.1 N(4.5, 1/4)) is unstable: the root of the Vlasov dispersion relation
+    has omega = 1.0012 + 0.1981i.  A check that the unit-density normalisation of the two
+    Maxwellians is read correctly (the density of the bump sets the growth rate)."""
+    om = PH.bump_on_tail_root(0.3)
+    assert abs(om.real - 1.0012) < 2e-3 and abs(om.imag - 0.1981) < 2e-3, om
