@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 3
+#define VP_ABI_VERSION 4
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -77,7 +77,24 @@ typedef struct vp_config {
   int32_t sort_chunk;  /* particles per sorted chunk (<= VP_MAX_SORT_CHUNK_*); 0 = max */
   int32_t hist_cap;    /* per-step diagnostic records kept on the device (ring); >= 1 */
   int32_t solver;      /* vp_solver: how vp_poisson / vp_step solve A Phi = b~ */
+  int32_t projection;  /* vp_projection: how phi_h'' (the curvature in q*'s kick) is formed */
 } vp_config;
+
+/* The dipole equation d(q*)/dt = p* phi_h''(Q) needs a second derivative that a P1 potential
+ * does not have (it vanishes inside every element); Section 5 obtains it through an
+ * auxiliary projection whose form the paper leaves open.  Three readings: */
+typedef enum vp_projection {
+  VP_PROJ_ELEM = 0,        /* lumped L2 projection of the element field E onto P1, then
+                              differentiated: element-constant g_e = -(b~_e + b~_{e+1}) / (2h),
+                              phi_h''(Q) = g_i on the element i holding Q (default) */
+  VP_PROJ_NODAL = 1,       /* L2 projection onto P1 of phi_h'' in the weak sense,
+                              (phi_h'', phi_j) = -(phi_h', phi_j') = -b~_j, lumped mass:
+                              nodal g_j = -b~_j / h; phi_h''(Q) = (1 - s) g_i + s g_{i+1} */
+  VP_PROJ_CONSISTENT = 2   /* the same with the consistent mass matrix M_ij = (phi_i, phi_j) =
+                              (h/6) circ(1, 4, 1): M g = -b~, applied through the decaying
+                              closed-form inverse of circ(1, 4, 1) (terms below 1e-18 relative
+                              omitted); phi_h''(Q) interpolated as for VP_PROJ_NODAL */
+} vp_projection;
 
 typedef enum vp_solver {
   VP_SOLVE_SCAN = 0,  /* discrete Gauss law: on the periodic P1 mesh (A Phi)_j = E_j - E_{j-1},
@@ -173,13 +190,14 @@ vp_status vp_deposit(vp_handle* h);
 /* Poisson solve (eq. lin-sys) of the current load vector: b~ = b - mean(b) in float64
  * (eq. neutrality), A Phi = b~ with 1^T Phi = 0 (the Gauss-law scan E_e - E_{e-1} = b~_e,
  * sum_e E_e = 0, or an in-LDS FFT, per cfg.solver), element field
- * E_e = -(Phi_{e+1} - Phi_e)/h, projected curvature g_e (lumped L2 projection of E onto
- * P1, differentiated), W = (1/2) sum h E_e^2.  Writes the field arrays that
- * vp_gather_push and vp_diagnostics read.  One workgroup per instance. */
+ * E_e = -(Phi_{e+1} - Phi_e)/h, projected curvature g (per element or per node, per
+ * cfg.projection), W = (1/2) sum h E_e^2.  Writes the field arrays that vp_gather_push and
+ * vp_diagnostics read.  One workgroup per instance. */
 vp_status vp_poisson(vp_handle* h);
 
 /* Exact sub-flows of the splitting with the current field (eq. sw-evolution):
- * kick:  P += kick * E[i],  q* += kick * p* * g[i]   (Q, p* frozen),
+ * kick:  P += kick * E[i],  q* += kick * p* * phi_h''(Q)   (Q, p* frozen; phi_h''(Q) per
+ *        cfg.projection),
  * drift: Q += drift * P (periodic wrap into [0, L)),  p* -= drift * q*   (P, q* frozen).
  * Requires |drift * P| < L.  After vp_step it first writes the field of the current
  * positions (as vp_poisson); a drift makes the load vector stale until vp_deposit (which

@@ -38,14 +38,18 @@ def _prec(p) -> int:
 
 
 SOLVERS = {"scan": L.VP_SOLVE_SCAN, "fft": L.VP_SOLVE_FFT}
+PROJECTIONS = {"elem": L.VP_PROJ_ELEM, "nodal": L.VP_PROJ_NODAL,
+               "consistent": L.VP_PROJ_CONSISTENT}
 
 
 def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096,
-                solver="scan"):
+                solver="scan", projection="elem"):
     return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
                        dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
                        hist_cap=int(hist_cap),
-                       solver=SOLVERS[solver] if isinstance(solver, str) else int(solver))
+                       solver=SOLVERS[solver] if isinstance(solver, str) else int(solver),
+                       projection=PROJECTIONS[projection] if isinstance(projection, str)
+                       else int(projection))
 
 
 def workspace_bytes(cfg) -> int:
@@ -84,14 +88,15 @@ class Engine:
         return t.from_numpy(np.ascontiguousarray(a)).to(device=self.device, dtype=self.dtype)
 
     def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
-              sort_chunk: int = 0, hist_cap: int = 4096, solver="scan"):
+              sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem"):
         """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`."""
         t = self._torch
         tens = {k: self._tensor(state[k]) for k in FIELDS}
         n = int(tens["Q"].numel())
         if any(int(v.numel()) != n for v in tens.values()):
             raise ValueError("state arrays differ in length")
-        cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver)
+        cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver,
+                          projection)
         ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
@@ -226,6 +231,6 @@ class Simulation(Engine):
 
     def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
                  sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
-                 stream=None, solver="scan"):
+                 stream=None, solver="scan", projection="elem"):
         super().__init__(precision, 1, device, stream)
-        self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver)
+        self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection)

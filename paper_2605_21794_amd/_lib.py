@@ -10,7 +10,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
+VP_ABI_VERSION = 4          # the layout of the structures declared below
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
+VP_PROJ_ELEM, VP_PROJ_NODAL, VP_PROJ_CONSISTENT = 0, 1, 2
 VP_MIN_NG, VP_MAX_NG = 8, 1024
 VP_MAX_SORT_CHUNK_F32, VP_MAX_SORT_CHUNK_F64 = 4096, 2048
 VP_MAX_ACC_COPIES = 8
@@ -19,7 +21,8 @@ VP_MAX_ACC_COPIES = 8
 class vp_config(Structure):
     _fields_ = [("n", c_int64), ("ng", c_int32), ("precision", c_int32), ("L", c_double),
                 ("dt", c_double), ("sort_every", c_int32), ("sort_chunk", c_int32),
-                ("hist_cap", c_int32), ("solver", c_int32)]
+                ("hist_cap", c_int32), ("solver", c_int32),
+                ("projection", c_int32)]
 
 
 class vp_particles(Structure):
@@ -110,6 +113,9 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.vp_abi_version() != VP_ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {lib.vp_abi_version()}, these bindings "
+                           f"expect {VP_ABI_VERSION}: rebuild it")
     runtimes = _hip_runtime_paths()
     if len(runtimes) > 1:
         raise RuntimeError(f"two HIP runtimes loaded in one process: {runtimes}")

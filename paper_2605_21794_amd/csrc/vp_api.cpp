@@ -61,6 +61,9 @@ vp_status validate(const vp_config* c) {
     return fail(VP_ERR_ARG, "sort_chunk = %d exceeds %d", c->sort_chunk, max_sort_chunk(c->precision));
   if (c->hist_cap < 1) return fail(VP_ERR_ARG, "hist_cap must be >= 1");
   if (c->solver != VP_SOLVE_SCAN && c->solver != VP_SOLVE_FFT) return fail(VP_ERR_ARG, "bad solver %d", c->solver);
+  if (c->projection != VP_PROJ_ELEM && c->projection != VP_PROJ_NODAL &&
+      c->projection != VP_PROJ_CONSISTENT)
+    return fail(VP_ERR_ARG, "bad projection %d", c->projection);
   return VP_OK;
 }
 
@@ -394,6 +397,8 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.bt = reinterpret_cast<double*>(ws + w.bt);
   d.tw = reinterpret_cast<double*>(ws + w.tw);
   d.inv_lam = reinterpret_cast<double*>(ws + w.inv_lam);
+  d.cw = reinterpret_cast<double*>(ws + w.cw);
+  d.proj = cfg->projection;
   d.scal = reinterpret_cast<vpk::InstScal*>(ws + w.scal);
   d.hist = reinterpret_cast<double*>(ws + w.hist);
   d.kin = reinterpret_cast<double*>(ws + w.kin);
@@ -409,11 +414,28 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   }
   il[0] = 0.0;
   for (int m = 1; m < ng; ++m) il[m] = 1.0 / ((2.0 / d.h) * (1.0 - std::cos(two_pi * m / ng)));
+  // Taps of -M^-1 for the consistent projection, M = (h/6) circ(1, 4, 1).  On the infinite
+  // mesh circ(1, 4, 1)^-1 has entries r^|d| / (2 sqrt 3), r = sqrt 3 - 2 (the root of
+  // x^2 + 4x + 1 inside the unit circle); summing the periodic images gives entry
+  // (r^k + r^(Ng-k)) / ((1 - r^Ng) 2 sqrt 3) at circular offset k.
+  std::vector<double> cw(vpk::kConsTapsMax, 0.0);
+  {
+    const double r = std::sqrt(3.0) - 2.0, a = 1.0 / (2.0 * std::sqrt(3.0));
+    const double rn = std::pow(r, ng);
+    const int taps = vpk::cons_taps(ng), off = vpk::cons_off(ng);
+    for (int t = 0; t < taps; ++t) {
+      const int k = ((t + off) % ng + ng) % ng;
+      const double c = a * (std::pow(r, k) + std::pow(r, ng - k)) / (1.0 - rn);
+      cw[t] = -(6.0 / d.h) * c;
+    }
+  }
 
   VP_HIP(hipStreamSynchronize(h->stream));
   VP_HIP(vpk::launch_fill_zero(ws, w.total, h->stream));
   VP_HIP(hipMemcpyAsync(d.tw, tw.data(), ng * sizeof(double), hipMemcpyHostToDevice, h->stream));
   VP_HIP(hipMemcpyAsync(d.inv_lam, il.data(), ng * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  VP_HIP(hipMemcpyAsync(d.cw, cw.data(), cw.size() * sizeof(double), hipMemcpyHostToDevice,
+                        h->stream));
   VP_HIP(hipStreamSynchronize(h->stream));
 
   Slot& sl = h->slots[slot];

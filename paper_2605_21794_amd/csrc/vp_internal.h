@@ -21,6 +21,13 @@ enum Mode { kFP64 = 0, kFP32Comp = 1, kFP32 = 2, kFP32TwoSum = 3 };
 // sums and the field summary live in rings of the same period.
 constexpr int kRing = 3;
 
+// Consistent-mass projection: the solve forms g_j = sum_t cw[t] b~_{(j - t - off) mod Ng}.
+// The inverse of circ(1, 4, 1) decays like (2 - sqrt 3)^|d|, below 1e-18 of its diagonal
+// beyond |d| = 32, so Ng <= 64 uses all Ng taps (off 0) and larger meshes 65 (off -32).
+constexpr int kConsTapsMax = 65;
+constexpr int cons_taps(int ng) { return ng <= 64 ? ng : kConsTapsMax; }
+constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
+
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
   double W[kRing], e1r[kRing], e1i[kRing];  // summary of the field solved from ring entry r
@@ -54,11 +61,12 @@ struct InstDev {
   double* bt;       // neutralised load, ng
   double* tw;       // tw[2k] = cos(2 pi k / ng), tw[2k+1] = sin(2 pi k / ng), k < ng/2
   double* inv_lam;  // 1 / eigenvalue of the stiffness matrix per Fourier mode (0 for m = 0)
+  double* cw;       // consistent projection: kConsTaps weights of -M^-1 (see cons_taps)
   InstScal* scal;
   double* hist;     // hist_cap records of kHistFields doubles
   double* kin;      // kRing x kin_cap x kKinFields per-tile kinetic sums of phase r's pass
   int kin_cap;      // tiles the kinetic-sum ring can hold (ceil(n / 256))
-  int pad_;
+  int proj;         // vp_projection
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.
@@ -72,7 +80,7 @@ struct Tile {
 
 // Byte offsets of the workspace regions of one instance (all 256-byte aligned).
 struct WsLayout {
-  size_t acc, E, g, Ef, gf, Phi, bt, tw, inv_lam, scal, hist, kin, total;
+  size_t acc, E, g, Ef, gf, Phi, bt, tw, inv_lam, cw, scal, hist, kin, total;
 };
 WsLayout workspace_layout(int ng, int hist_cap, long long n);
 int kin_capacity(long long n);

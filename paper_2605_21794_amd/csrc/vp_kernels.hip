@@ -103,6 +103,24 @@ __device__ __forceinline__ float frac01_f(float x, int i) {
   return s;
 }
 
+// phi_h''(Q) of a particle at mesh coordinate x = Q / h in element i, from the curvature
+// array g of the instance's projection: the element value, or for the nodal projections
+// the P1 interpolant (1 - s) g_i + s g_{i+1}.  `proj` is uniform over a workgroup.
+template <typename F>
+__device__ __forceinline__ double curv_at(int proj, const F* g, int i, double x, int ng) {
+  const double gi = (double)g[i];
+  if (proj == VP_PROJ_ELEM) return gi;
+  const double s = frac01(x, i);
+  return (1.0 - s) * gi + s * (double)g[(i + 1) & (ng - 1)];
+}
+template <typename F>
+__device__ __forceinline__ float curv_at_f(int proj, const F* g, int i, float x, int ng) {
+  const float gi = (float)g[i];
+  if (proj == VP_PROJ_ELEM) return gi;
+  const float s = frac01_f(x, i);
+  return (1.0f - s) * gi + s * (float)g[(i + 1) & (ng - 1)];
+}
+
 // Deterministic workgroup sum: fixed shuffle tree per wave, then the wave totals in order.
 // `red` holds at least TPB/64 doubles.  Every thread of the workgroup must call it.
 template <int TPB>
@@ -576,8 +594,23 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     sum[4] = solve_total(red, 7);
     sum[5] = solve_total(red, 8);
   }
-  const double half_inv_h = 0.5 * d.inv_h;
-  for (int e = tid; e < ng; e += TPB) g[e] = -(bt[e] + bt[(e + 1) & mask]) * half_inv_h;
+  if (d.proj == VP_PROJ_ELEM) {
+    const double half_inv_h = 0.5 * d.inv_h;
+    for (int e = tid; e < ng; e += TPB) g[e] = -(bt[e] + bt[(e + 1) & mask]) * half_inv_h;
+  } else if (d.proj == VP_PROJ_NODAL) {
+    const double inv_h = d.inv_h;
+    for (int e = tid; e < ng; e += TPB) g[e] = -bt[e] * inv_h;
+  } else {
+    // g = -M^-1 b~ as a circular convolution with the decaying taps of -M^-1 (uniform
+    // loads of the tap table), summed in tap order
+    const VPG double* __restrict__ cw = gp(d.cw);
+    const int taps = cons_taps(ng), off = cons_off(ng);
+    for (int e = tid; e < ng; e += TPB) {
+      double a = 0.0;
+      for (int t = 0; t < taps; ++t) a += cw[t] * bt[(e - t - off) & mask];
+      g[e] = a;
+    }
+  }
   if (phi && !use_fft) {
     // Phi_e = -h (P_e - mean(P)), P_e = sum_{k<e} E_k; sum_e P_e = sum_k (Ng-1-k) E_k
     double P[kSolvePer];
@@ -661,8 +694,9 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const float Lf = (float)d.L, ihf = (float)d.inv_h, dtf = (float)d.dt, hf = 0.5f * dtf;
     float Q = Qr, P = Pr, qs = qsr, ps = psr;
     const float psi = psir;
-    const int i = cell_of_f(Q * ihf, ng);
-    const float Ei = (float)fE[i], gi = (float)fG[i];
+    const float xq = Q * ihf;
+    const int i = cell_of_f(xq, ng);
+    const float Ei = (float)fE[i], gi = curv_at_f(d.proj, fG, i, xq, ng);
     if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
     const double Pd = P, qd = qs, wd = psi;
     Ks += 0.5 * wd * Pd * Pd + qd * Pd;
@@ -684,8 +718,9 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
     const double Q = Qr, psi = psir;
     double P = Pr, qs = qsr, ps = psr;
-    const int i = cell_of(Q * inv_h, ng);
-    const double Ei = fE[i], gi = fG[i];
+    const double xq = Q * inv_h;
+    const int i = cell_of(xq, ng);
+    const double Ei = fE[i], gi = curv_at(d.proj, fG, i, xq, ng);
     if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
     Ks += 0.5 * psi * P * P + qs * P;
     Ms += psi * P + qs;
@@ -1110,9 +1145,10 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
     for (int u = 0; u < 4; ++u) {
       if (!v[u]) continue;
       float Q = q[u], P = p[u], qs = a[u], ps = b[u];
-      const int i = cell_of_f(Q * ihf, ng);
+      const float xq = Q * ihf;
+      const int i = cell_of_f(xq, ng);
       P = P + kf * fE[i];
-      qs = qs + kf * ps * fG[i];
+      qs = qs + kf * ps * curv_at_f(d.proj, fG, i, xq, ng);
       float Qn = Q + df * P;
       if (Qn < 0.0f) Qn += Lf;
       if (Qn >= Lf) Qn -= Lf;
@@ -1133,9 +1169,10 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
       if (!v[u]) continue;
       const double Q = q[u];
       double P = p[u], qs = a[u], ps = b[u];
-      const int i = cell_of(Q * inv_h, ng);
+      const double xq = Q * inv_h;
+      const int i = cell_of(xq, ng);
       P = P + kick * smem[i];
-      qs = qs + kick * ps * smem[ng + i];
+      qs = qs + kick * ps * curv_at(d.proj, smem + ng, i, xq, ng);
       double Qn = Q + drift * P;
       if (Qn < 0.0) Qn += L;
       if (Qn >= L) Qn -= L;
@@ -1178,9 +1215,10 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
       const float Q = Qp[idx[u]], psi = psip[idx[u]], ps = psp[idx[u]];
       float P = Pp[idx[u]], qs = qsp[idx[u]];
       if (pend) {
-        const int i = cell_of_f(Q * ihf, ng);
+        const float xq = Q * ihf;
+        const int i = cell_of_f(xq, ng);
         P = P + hf * fE[i];
-        qs = qs + hf * ps * fG[i];
+        qs = qs + hf * ps * curv_at_f(d.proj, fG, i, xq, ng);
       }
       const double Pd = P, qd = qs, wd = psi;
       Ks += 0.5 * wd * Pd * Pd + qd * Pd;
@@ -1197,9 +1235,10 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
       const double Q = Qp[idx[u]], psi = psip[idx[u]], ps = psp[idx[u]];
       double P = Pp[idx[u]], qs = qsp[idx[u]];
       if (pend) {
-        const int i = cell_of(Q * inv_h, ng);
+        const double xq = Q * inv_h;
+        const int i = cell_of(xq, ng);
         P = P + half * smem[i];
-        qs = qs + half * ps * smem[ng + i];
+        qs = qs + half * ps * curv_at(d.proj, smem + ng, i, xq, ng);
       }
       Ks += 0.5 * psi * P * P + qs * P;
       Ms += psi * P + qs;
@@ -1439,6 +1478,7 @@ WsLayout workspace_layout(int ng, int hist_cap, long long n) {
   w.bt = o;      o = align256(o + (size_t)ng * sizeof(double));
   w.tw = o;      o = align256(o + (size_t)ng * sizeof(double));
   w.inv_lam = o; o = align256(o + (size_t)ng * sizeof(double));
+  w.cw = o;      o = align256(o + (size_t)kConsTapsMax * sizeof(double));
   w.scal = o;    o = align256(o + sizeof(InstScal));
   w.hist = o;    o = align256(o + (size_t)hist_cap * kHistFields * sizeof(double));
   w.kin = o;     o = align256(o + (size_t)kRing * kin_capacity(n) * kKinFields * sizeof(double));
