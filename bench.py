@@ -260,43 +260,87 @@ def run_sweep(args):
 
 def run_served(args):
     """Served request stream: seeded Poisson arrivals of mixed Landau / two-stream /
-    bump-on-tail jobs, continuously batched over the slots of one engine.  Prints one JSON
-    line with aggregate updates/s and p50/p99 step and job latency."""
+    bump-on-tail jobs, continuously batched over the slots of one engine.
+
+    The engine's capacity is measured first (every job arriving at t = 0: jobs/s until the
+    last one is done).  The stream is then replayed at arrival rates of the given fractions
+    of that capacity, under a byte cap that forces queueing and under the whole device.
+    Prints one JSON line: value = aggregate updates/s at the middle load on the whole device,
+    with every run's updates/s and p50/p99 step latency, job latency and admission wait.
+    (--rate R instead runs the stream once at R jobs/s.)"""
     import numpy as np
     import torch
     import workloads as W
     from paper_2605_21794_amd.serve import Job, Server
     prec = args.precision or "fp32c"
     dt_np = np.float64 if prec == "fp64" else np.float32
-    stream_jobs = W.served_jobs(seed=0, n_jobs=args.jobs, rate=args.rate)
+    base = W.served_jobs(seed=0, n_jobs=args.jobs, rate=1.0)  # arrival times at 1 job/s
     t0 = time.perf_counter()
-    jobs = [Job(state=w.state(dt_np), L=w.L, ng=w.ng, dt=w.dt, horizon=w.nsteps, arrival=t,
-                name=w.name) for t, w in stream_jobs]
-    log(f"served: {len(jobs)} jobs built in {time.perf_counter() - t0:.1f} s; rate "
-        f"{args.rate} jobs/s, sum N*horizon = {sum(j.n * j.horizon for j in jobs):.3g}")
+    states = [w.state(dt_np) for _, w in base]
+    work = sum(int(st["Q"].size) * w.nsteps for st, (_, w) in zip(states, base))
+    log(f"served: {len(base)} jobs built in {time.perf_counter() - t0:.1f} s; "
+        f"sum N*horizon = {work:.3g}")
+
+    def stream(rate):
+        """The same jobs; arrivals scaled to `rate` jobs/s (None: all at t = 0)."""
+        return [Job(state=st, L=w.L, ng=w.ng, dt=w.dt, horizon=w.nsteps,
+                    arrival=(t / rate if rate else 0.0), name=w.name)
+                for st, (t, w) in zip(states, base)]
+
     torch.cuda.set_device(0)
-    budget = int(args.budget_gib * (1 << 30)) if args.budget_gib else None
-    srv = Server(precision=prec, max_slots=args.slots, budget_bytes=budget, chunk=args.chunk)
-    # warm the kernels and the graph path once on a throwaway job
-    w0 = stream_jobs[0][1]
-    srv.run([Job(state=w0.state(dt_np), L=w0.L, ng=w0.ng, dt=w0.dt, horizon=66, name="warm")])
-    rep = srv.run(jobs)
-    d = rep.as_dict()
-    log(f"served: wall {rep.wall_s:.2f} s, {rep.updates_per_s:.3g} updates/s, step latency "
-        f"p50 {d['step_latency_us']['p50']:.1f} us p99 {d['step_latency_us']['p99']:.1f} us, "
-        f"job latency p50 {d['job_latency_s']['p50']:.3f} s p99 {d['job_latency_s']['p99']:.3f} s")
+    srv = Server(precision=prec, max_slots=args.slots, chunk=args.chunk)
+    full_budget = srv.budget
+    w0 = base[0][1]
+    srv.run([Job(state=states[0], L=w0.L, ng=w0.ng, dt=w0.dt, horizon=66, name="warm")])
+
+    def one(rate, budget, label):
+        srv.budget = budget
+        rep = srv.run(stream(rate))
+        d = rep.as_dict()
+        log(f"served [{label}]: wall {rep.wall_s:.3f} s, {rep.updates_per_s:.3g} updates/s, "
+            f"step p50/p99 {d['step_latency_us']['p50']:.1f}/{d['step_latency_us']['p99']:.1f} us, "
+            f"job p50/p99 {d['job_latency_s']['p50']:.3f}/{d['job_latency_s']['p99']:.3f} s, "
+            f"wait p99 {d['admission_wait_s']['p99']:.3f} s, non-finite {d['nonfinite_jobs']}")
+        return {"rate_jobs_per_s": rate, "budget_bytes": budget,
+                "updates_per_s": rep.updates_per_s, "updates": rep.updates,
+                "wall_s": rep.wall_s, "nonfinite_jobs": d["nonfinite_jobs"],
+                "step_latency_us": d["step_latency_us"], "job_latency_s": d["job_latency_s"],
+                "admission_wait_s": d["admission_wait_s"]}
+
+    runs = []
+    if args.rate:
+        r = one(args.rate, int(args.budget_gib * (1 << 30)) if args.budget_gib else full_budget,
+                f"{args.rate:g} jobs/s")
+        runs.append(r)
+        head, capacity = r, None
+    else:
+        sat = one(None, full_budget, "saturated")
+        capacity = len(base) / sat["wall_s"]
+        log(f"served: capacity {capacity:.1f} jobs/s ({sat['updates_per_s']:.3g} updates/s)")
+        loads = [float(x) for x in args.loads.split(",")]
+        # the largest job holds about 21 MB and a full engine of the mix about 0.3 GB, so a
+        # cap of 128 MiB makes jobs queue for bytes where the whole device never does
+        cap_bytes = int((args.budget_gib or 0.125) * (1 << 30))
+        head = None
+        for budget, tag in ((cap_bytes, f"{cap_bytes / (1 << 30):g} GiB"), (full_budget, "device")):
+            for f in loads:
+                r = one(f * capacity, budget, f"{f:g} x capacity, {tag}")
+                r["load"] = f
+                runs.append(r)
+                if budget == full_budget and head is None and f >= 0.7 - 1e-9:
+                    head = r
+        head = head or runs[-1]
+        runs.insert(0, dict(sat, load="saturated"))
     out = {
-        "metric": METRIC, "value": rep.updates_per_s, "unit": "decorated-particle updates/s",
+        "metric": METRIC, "value": head["updates_per_s"], "unit": "decorated-particle updates/s",
         "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
-        "config": {"workload": "served", "jobs": len(jobs), "rate_jobs_per_s": args.rate,
-                   "slots": args.slots, "budget_bytes": srv.budget, "chunk": args.chunk,
-                   "precision": prec},
-        "served": {"nonfinite_jobs": d["nonfinite_jobs"],
-                   "step_latency_us": d["step_latency_us"], "job_latency_s": d["job_latency_s"],
-                   "admission_wait_s": d["admission_wait_s"], "wall_s": rep.wall_s,
-                   "updates": rep.updates},
+        "config": {"workload": "served", "jobs": len(base), "slots": args.slots,
+                   "chunk": args.chunk, "precision": prec,
+                   "rate_jobs_per_s": head["rate_jobs_per_s"],
+                   "budget_bytes": head["budget_bytes"]},
+        "served": {"capacity_jobs_per_s": capacity, "headline": head, "runs": runs},
     }
     print(json.dumps(out), flush=True)
 
@@ -459,10 +503,15 @@ def main():
     ap.add_argument("--precision-study", action="store_true",
                     help="landau_nonlinear in every precision mode against the stored oracle")
     ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
-    ap.add_argument("--rate", type=float, default=150.0, help="served: arrivals per second")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="served: one run at this many arrivals per second (default: measure "
+                         "capacity, then run at --loads of it)")
+    ap.add_argument("--loads", default="0.5,0.7,0.9",
+                    help="served: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=64, help="served: engine slots")
     ap.add_argument("--chunk", type=int, default=33, help="served: steps between decisions")
-    ap.add_argument("--budget-gib", type=float, default=None, help="served: device bytes cap")
+    ap.add_argument("--budget-gib", type=float, default=None,
+                    help="served: device bytes cap (default: 0.125 GiB for the capped runs)")
     ap.add_argument("--launch", default=None,
                     help="threads,ppt,acc_copies[,persistent] of the fused step (with --no-tune)")
     ap.add_argument("--copy-calibration", action="store_true")

@@ -261,6 +261,17 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
 /* Number of occupied slots and the total particle count over them. */
 vp_status vp_occupancy(const vp_handle* h, int32_t* slots_out, int64_t* particles_out);
 
+/* Synchronises the stream.  For slots 0 .. n-1 of an engine: host_steps[s] = the slot's
+ * device step count (the integer step its state has reached; it stops when the instance
+ * is frozen), or -1 for an empty slot; host_flags[s] = VP_SLOT_OCCUPIED | VP_SLOT_NONFINITE
+ * as they apply.  One small kernel and one copy for all slots, so a serving loop can poll
+ * every resident job between chunks of steps.  Host arrays of n elements, owned by the
+ * caller; n may exceed the engine's slots (the rest read as empty).  Errors: VP_ERR_ARG
+ * for a NULL handle or array or n < 0, VP_ERR_HIP. */
+#define VP_SLOT_OCCUPIED 1
+#define VP_SLOT_NONFINITE 2
+vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* host_flags);
+
 const char* vp_status_string(vp_status s);
 const char* vp_last_error(void);
 int32_t vp_abi_version(void);

@@ -214,6 +214,15 @@ class Engine:
         L.check(self.lib.vp_occupancy(self.h, byref(s), byref(p)), "vp_occupancy")
         return int(s.value), int(p.value)
 
+    def slot_status(self):
+        """{slot: (device step, finite)} for every occupied slot, from one device call."""
+        n = self.max_slots
+        steps = (c_int64 * n)()
+        flags = (c_int32 * n)()
+        L.check(self.lib.vp_slot_status(self.h, n, steps, flags), "vp_slot_status")
+        return {s: (int(steps[s]), not (flags[s] & L.VP_SLOT_NONFINITE))
+                for s in range(n) if flags[s] & L.VP_SLOT_OCCUPIED}
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.vp_destroy(self.h)

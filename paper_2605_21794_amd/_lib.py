@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
 VP_ABI_VERSION = 4          # the layout of the structures declared below
+VP_SLOT_OCCUPIED, VP_SLOT_NONFINITE = 1, 2
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_PROJ_ELEM, VP_PROJ_NODAL, VP_PROJ_CONSISTENT = 0, 1, 2
 VP_MIN_NG, VP_MAX_NG = 8, 1024
@@ -73,6 +74,7 @@ SIGNATURES = {
     "vp_tune_scratch_bytes": (c_int32, [H, POINTER(c_size_t)]),
     "vp_tune": (c_int32, [H, c_void_p, c_int32, POINTER(vp_tuning), POINTER(c_double)]),
     "vp_occupancy": (c_int32, [H, POINTER(c_int32), POINTER(c_int64)]),
+    "vp_slot_status": (c_int32, [H, c_int32, POINTER(c_int64), POINTER(c_int32)]),
     "vp_status_string": (c_char_p, [c_int32]),
     "vp_last_error": (c_char_p, []),
     "vp_abi_version": (c_int32, []),

@@ -96,6 +96,7 @@ struct vp_handle {
   int ntiles = 0;
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
+  long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
   int max_ng = VP_MIN_NG;
   bool any_fft = false;     // some slot uses the FFT solver (fused launches need more LDS)
   vp_tuning tun{1024, 4, 4, 1, 33, 0};
@@ -350,6 +351,7 @@ vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream, v
   hipError_t e = hipMalloc(&h->d_inst, max_slots * sizeof(InstDev));
   if (e == hipSuccess) e = hipMalloc(&h->d_occ, max_slots * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&h->d_ids, max_slots * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&h->d_status, 2 * (size_t)max_slots * sizeof(long long));
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->d_ids, ids.data(), max_slots * sizeof(int), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -515,6 +517,7 @@ vp_status vp_destroy(vp_handle* h) {
   if (h->d_tiles) (void)hipFree(h->d_tiles);
   if (h->d_occ) (void)hipFree(h->d_occ);
   if (h->d_ids) (void)hipFree(h->d_ids);
+  if (h->d_status) (void)hipFree(h->d_status);
   delete h;
   return VP_OK;
 }
@@ -728,6 +731,28 @@ vp_status vp_occupancy(const vp_handle* h, int32_t* slots_out, int64_t* particle
   for (int s : h->h_occ) p += h->slots[s].cfg.n;
   if (slots_out) *slots_out = (int32_t)h->h_occ.size();
   if (particles_out) *particles_out = p;
+  return VP_OK;
+}
+
+vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* host_flags) {
+  if (!h || !host_steps || !host_flags || n < 0) return fail(VP_ERR_ARG, "NULL argument or n < 0");
+  for (int32_t s = 0; s < n; ++s) {
+    host_steps[s] = -1;
+    host_flags[s] = 0;
+  }
+  const int nocc = (int)h->h_occ.size();
+  if (nocc == 0) return VP_OK;
+  std::vector<long long> buf(2 * (size_t)nocc);
+  VP_HIP(vpk::launch_slot_status(h->d_inst, h->d_occ, nocc, h->d_status, h->stream));
+  VP_HIP(hipMemcpyAsync(buf.data(), h->d_status, buf.size() * sizeof(long long),
+                        hipMemcpyDeviceToHost, h->stream));
+  VP_HIP(hipStreamSynchronize(h->stream));
+  for (int t = 0; t < nocc; ++t) {
+    const int s = h->h_occ[t];
+    if (s >= n) continue;
+    host_steps[s] = buf[2 * (size_t)t];
+    host_flags[s] = VP_SLOT_OCCUPIED | (buf[2 * (size_t)t + 1] ? VP_SLOT_NONFINITE : 0);
+  }
   return VP_OK;
 }
 

@@ -114,6 +114,9 @@ hipError_t launch_ring(int mode, const InstDev* d_inst, const int* d_slots, int 
                        int phase, hipStream_t s);
 hipError_t launch_slot_scalars(const InstDev* d_inst, const int* d_slots, int nslots, int op,
                                int phase, hipStream_t s);
+// out[2t] = step, out[2t+1] = nonfinite of instance slots[t], t < nslots.
+hipError_t launch_slot_status(const InstDev* d_inst, const int* d_slots, int nslots,
+                              long long* out, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_cell_index(const InstDev* d_inst, int slot, int mode, int* cells, long long n,
                              hipStream_t s);

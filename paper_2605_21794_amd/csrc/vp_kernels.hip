@@ -1367,6 +1367,15 @@ __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __r
   }
 }
 
+__global__ void k_slot_status(const InstDev* __restrict__ insts, const int* __restrict__ slots,
+                              int nslots, long long* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslots) return;
+  const VPG InstScal* sc = gp(insts[slots[t]].scal);
+  out[2 * t] = sc->step;
+  out[2 * t + 1] = sc->nonfinite;
+}
+
 __global__ void k_fill_zero(unsigned long long* p, size_t n8) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) p[i] = 0ull;
@@ -1630,6 +1639,14 @@ hipError_t launch_slot_scalars(const InstDev* d_inst, const int* d_slots, int ns
   if (nslots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slot_scalars, dim3((nslots + 63) / 64), dim3(64), 0, s, d_inst, d_slots,
                      nslots, op, phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_status(const InstDev* d_inst, const int* d_slots, int nslots,
+                              long long* out, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_status, dim3((nslots + 63) / 64), dim3(64), 0, s, d_inst, d_slots,
+                     nslots, out);
   return hipGetLastError();
 }
 

@@ -6,7 +6,9 @@ resident on the device, and advances all of them with one fused launch per step 
 batched engine of libvp).  A job is admitted as soon as a slot is free and its device bytes
 fit in the budget (first come, first served: a job that does not fit blocks the ones behind
 it, so none waits forever).  It is retired, with its state at its last integer step, exactly
-when it reaches its horizon.
+when it reaches its horizon, or as soon as the engine has frozen it because its state turned
+non-finite (polled for all slots at once after every chunk), which frees its slot and bytes
+for the queue.
 
     srv = Server(precision="fp32c", max_slots=64, budget_bytes=8 << 30)
     report = srv.run(jobs)     # jobs: list of Job, each with its arrival time in seconds
@@ -95,19 +97,23 @@ class Server:
     """Continuous batching over an engine's slots.
 
     backend: an object with the Engine interface used here (max_slots, admit, retire, step,
-    diagnostics, job_bytes, timer); by default a GPU Engine of the given precision.
+    diagnostics, job_bytes, frozen_slots); by default a GPU Engine of the given precision.
     chunk: most steps advanced between scheduling decisions (fewer when a resident job
     reaches its horizon sooner).
+    retire_nonfinite: retire a job the engine has frozen (non-finite state) after the chunk
+    in which it froze, instead of holding its slot until its horizon.
     """
 
     def __init__(self, precision="fp32c", max_slots: int = 64, budget_bytes: int = None,
-                 chunk: int = 33, backend=None, clock=time.perf_counter, keep_state=False):
+                 chunk: int = 33, backend=None, clock=time.perf_counter, keep_state=False,
+                 retire_nonfinite: bool = True):
         self.backend = backend if backend is not None else GpuBackend(precision, max_slots)
         self.max_slots = int(self.backend.max_slots)
         self.budget = budget_bytes if budget_bytes is not None else self.backend.default_budget()
         self.chunk = int(chunk)
         self.clock = clock
         self.keep_state = keep_state
+        self.retire_nonfinite = retire_nonfinite
 
     def run(self, jobs: list, sleep=time.sleep) -> Report:
         for j in jobs:
@@ -154,7 +160,8 @@ class Server:
             for j in resident.values():
                 j.steps_done += k
                 j.step_time_s += dev_s
-            for slot in [s for s, j in resident.items() if j.steps_done >= j.horizon]:
+            frozen = self.backend.frozen_slots() if self.retire_nonfinite else set()
+            for slot in [s for s, j in resident.items() if j.steps_done >= j.horizon or s in frozen]:
                 job = resident.pop(slot)
                 job.result = self.backend.diagnostics(slot)
                 st = self.backend.retire(slot)
@@ -215,6 +222,9 @@ class GpuBackend:
 
     def diagnostics(self, slot: int) -> dict:
         return self.engine.diagnostics(slot, allow_nonfinite=True)
+
+    def frozen_slots(self) -> set:
+        return {s for s, (_, finite) in self.engine.slot_status().items() if not finite}
 
     def retire(self, slot: int) -> dict:
         return self.engine.retire(slot)

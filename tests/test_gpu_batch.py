@@ -131,7 +131,10 @@ def test_nonfinite_instance_is_frozen_and_others_continue(vp):
     with pytest.raises(vp.VPError) as e:
         eng.diagnostics(1)
     assert e.value.status == vp._lib.VP_ERR_NONFINITE
-    assert eng.diagnostics(1, allow_nonfinite=True)["step"] < 8
+    frozen_at = eng.diagnostics(1, allow_nonfinite=True)["step"]
+    assert frozen_at < 8
+    # the one-call status of every slot agrees
+    assert eng.slot_status() == {0: (8, True), 1: (frozen_at, False), 2: (8, True)}
     for s in (0, 2):
         got = eng.state_numpy(s)
         ref_state, _, _ = oracle_run(sts[s], ws[s], 8)

@@ -56,3 +56,30 @@ def test_each_job_same_alone_and_in_the_mix(vp, prec):
         da = alone.diagnostics(0)
         assert abs(j.result["W"] - da["W"]) <= (1e-10 if prec == "fp64" else 1e-5) * abs(da["W"])
         alone.close()
+
+
+def test_frozen_job_leaves_early_and_the_others_are_unchanged(vp):
+    """A job whose state holds a NaN is frozen by the engine; the server sees it in the
+    status poll after its first chunk, retires it (result not finite, far short of its
+    horizon) and gives its slot to the queue.  The other jobs end as they do alone."""
+    from paper_2605_21794_amd.serve import Server
+    ws, jobs = small_jobs(np.float64)
+    bad = jobs[2]
+    bad.state = {k: v.copy() for k, v in bad.state.items()}
+    bad.state["P"][3] = np.nan
+    srv = Server(precision="fp64", max_slots=2, chunk=5, keep_state=True)
+    rep = srv.run(jobs)
+    assert rep.nonfinite_jobs == 1
+    assert bad.result["finite"] is False and bad.result["step"] < 5
+    assert bad.steps_done < bad.horizon
+    for j in jobs:
+        if j is bad:
+            continue
+        assert j.result["finite"] and j.steps_done == j.horizon
+        alone = vp.Simulation(j.state, j.L, j.ng, j.dt, "fp64", solver=j.solver)
+        alone.step(j.horizon)
+        ref = alone.state_numpy(0)
+        got = {k: v.detach().cpu().numpy() for k, v in j.final_state.items()}
+        for k in FIELDS:
+            assert np.allclose(got[k], ref[k], rtol=0, atol=1e-12), (j.name, k)
+        alone.close()

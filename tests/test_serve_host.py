@@ -17,12 +17,16 @@ class FakeClock:
 
 
 class FakeBackend:
-    """Each step of k costs 1e-5 * k * (resident particles / 1000) seconds of fake time."""
+    """Each step of k costs 1e-5 * k * (resident particles / 1000) seconds of fake time.
+    A job named in `freeze_at` stops counting steps there, like an instance the engine has
+    frozen because its state turned non-finite."""
 
-    def __init__(self, clock, max_slots=3):
+    def __init__(self, clock, max_slots=3, freeze_at=None):
         self.clock = clock
         self.max_slots = max_slots
         self.resident = {}
+        self.dev_step = {}
+        self.freeze_at = dict(freeze_at or {})
         self.log = []
         self.peak_bytes = 0
 
@@ -35,6 +39,7 @@ class FakeBackend:
     def admit(self, slot, job):
         assert slot not in self.resident, "slot double-booked"
         self.resident[slot] = job
+        self.dev_step[slot] = 0
         self.log.append(("admit", job.name, slot, self.clock()))
         self.peak_bytes = max(self.peak_bytes, sum(self.job_bytes(j) for j in self.resident.values()))
 
@@ -42,13 +47,22 @@ class FakeBackend:
         assert self.resident
         dt = 1e-5 * k * sum(j.n for j in self.resident.values()) / 1000.0
         self.clock.t += dt
+        for s, j in self.resident.items():
+            self.dev_step[s] = min(self.dev_step[s] + k, self.freeze_at.get(j.name, 1 << 60))
         return dt
 
+    def _frozen(self, slot):
+        return self.dev_step[slot] == self.freeze_at.get(self.resident[slot].name, -1)
+
+    def frozen_slots(self):
+        return {s for s in self.resident if self._frozen(s)}
+
     def diagnostics(self, slot):
-        return {"step": self.resident[slot].steps_done}
+        return {"step": self.dev_step[slot], "finite": not self._frozen(slot)}
 
     def retire(self, slot):
         job = self.resident.pop(slot)
+        self.dev_step.pop(slot)
         self.log.append(("retire", job.name, slot, self.clock()))
         return {"Q": np.zeros(job.n)}
 
@@ -112,6 +126,31 @@ def test_rejects_oversized_job_and_empty_horizon():
     with pytest.raises(ValueError):
         Server(backend=FakeBackend(clk), clock=clk).run(make_jobs([("zero", 10, 0, 0.0)]),
                                                         sleep=clk.sleep)
+
+
+@pytest.mark.parametrize("retire_nonfinite", [True, False])
+def test_frozen_job_is_retired_early_and_frees_its_slot(retire_nonfinite):
+    """A job the engine freezes at step 15 leaves after the chunk in which it froze (not at
+    its horizon of 100), the queued job takes its slot then, and only the updates actually
+    performed are counted."""
+    clk = FakeClock()
+    be = FakeBackend(clk, max_slots=2, freeze_at={"bad": 15})
+    jobs = make_jobs([("bad", 1000, 100, 0.0), ("good", 1000, 60, 0.0), ("queued", 1000, 30, 0.0)])
+    rep = Server(backend=be, chunk=10, clock=clk, retire_nonfinite=retire_nonfinite).run(
+        jobs, sleep=clk.sleep)
+    bad, good, queued = jobs
+    assert bad.result == {"step": 15, "finite": False}
+    assert rep.nonfinite_jobs == 1
+    assert rep.updates == 1000 * (15 + 60 + 30)
+    t_admit = {e[1]: e[3] for e in be.log if e[0] == "admit"}
+    t_retire = {e[1]: e[3] for e in be.log if e[0] == "retire"}
+    if retire_nonfinite:
+        assert bad.steps_done == 20                       # the chunk in which it froze
+        assert t_admit["queued"] == t_retire["bad"] < t_retire["good"]
+    else:
+        assert bad.steps_done == 100
+        assert t_admit["queued"] == t_retire["good"] < t_retire["bad"]
+    assert good.result == {"step": 60, "finite": True}
 
 
 def test_weighted_percentiles():
