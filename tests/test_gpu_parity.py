@@ -119,17 +119,21 @@ def test_primitive_step_matches_oracle(vp, prec):
         assert np.array_equal(s1["P"], P2) and np.array_equal(s1["qs"], qs2)
 
 
-@pytest.mark.parametrize("prec,solver,threads", [("fp64", "scan", 1024), ("fp32c", "scan", 1024),
-                                                 ("fp32", "scan", 1024), ("fp64", "fft", 256),
-                                                 ("fp32c", "fft", 512), ("fp32c", "scan", 256),
-                                                 ("fp32ts", "scan", 1024), ("fp32ts", "fft", 256)])
-def test_fused_step_matches_primitives(vp, prec, solver, threads):
-    """vp_step (fused pass + in-kernel solve, graph-replayed) equals the primitive path."""
-    w = small_workload(nx=200, nv=33, ng=128, seed=5)
+@pytest.mark.parametrize("prec,solver,threads,ppt", [
+    ("fp64", "scan", 1024, 1), ("fp32c", "scan", 1024, 2), ("fp32", "scan", 1024, 2),
+    ("fp64", "fft", 256, 2), ("fp32c", "fft", 512, 2), ("fp32c", "scan", 256, 2),
+    ("fp32ts", "scan", 1024, 2), ("fp32ts", "fft", 256, 2),
+    # several particles per thread, the autotuner's usual shapes
+    ("fp32c", "scan", 512, 4), ("fp32c", "scan", 256, 8), ("fp64", "scan", 512, 4),
+    ("fp64", "scan", 1024, 2), ("fp32", "fft", 512, 4), ("fp32ts", "scan", 512, 8)])
+def test_fused_step_matches_primitives(vp, prec, solver, threads, ppt):
+    """vp_step (fused pass + in-kernel solve, graph-replayed) equals the primitive path.
+    6633 particles: several tiles and a ragged last tile."""
+    w = small_workload(nx=201, nv=33, ng=128, seed=5)
     st = w.state()
     a = vp.Simulation(st, w.L, w.ng, w.dt, prec, solver=solver)
     b = vp.Simulation(st, w.L, w.ng, w.dt, prec, solver=solver)
-    a.set_tuning(threads=threads, ppt=2, graph_steps=4, use_graph=1)
+    a.set_tuning(threads=threads, ppt=ppt, graph_steps=4, use_graph=1)
     nsteps = 9
     a.step(nsteps)
     for _ in range(nsteps):
