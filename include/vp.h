@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 4
+#define VP_ABI_VERSION 5
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -78,6 +78,12 @@ typedef struct vp_config {
   int32_t hist_cap;    /* per-step diagnostic records kept on the device (ring); >= 1 */
   int32_t solver;      /* vp_solver: how vp_poisson / vp_step solve A Phi = b~ */
   int32_t projection;  /* vp_projection: how phi_h'' (the curvature in q*'s kick) is formed */
+  int32_t monopole_only; /* 1: p* = q* = 0 for all time (plain P1 particle-in-cell, the paper's
+                            comparison method and the k = 1 member of the hierarchy).  Admission
+                            fills qs and ps with zeros; the fused step then neither reads nor
+                            writes them (20 bytes of particle traffic per update instead of
+                            36); the other calls carry the zeros through, and they stay zero.
+                            0: decorated particles (default). */
 } vp_config;
 
 /* The dipole equation d(q*)/dt = p* phi_h''(Q) needs a second derivative that a P1 potential

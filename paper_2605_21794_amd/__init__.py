@@ -43,13 +43,13 @@ PROJECTIONS = {"elem": L.VP_PROJ_ELEM, "nodal": L.VP_PROJ_NODAL,
 
 
 def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096,
-                solver="scan", projection="elem"):
+                solver="scan", projection="elem", monopole_only=False):
     return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
                        dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
                        hist_cap=int(hist_cap),
                        solver=SOLVERS[solver] if isinstance(solver, str) else int(solver),
                        projection=PROJECTIONS[projection] if isinstance(projection, str)
-                       else int(projection))
+                       else int(projection), monopole_only=1 if monopole_only else 0)
 
 
 def workspace_bytes(cfg) -> int:
@@ -88,15 +88,25 @@ class Engine:
         return t.from_numpy(np.ascontiguousarray(a)).to(device=self.device, dtype=self.dtype)
 
     def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
-              sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem"):
-        """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`."""
+              sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem",
+              monopole_only: bool = False):
+        """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`.
+        monopole_only: plain particle-in-cell particles (p* = q* = 0; qs, ps may be left out
+        of `state`, and are zeroed on admission)."""
         t = self._torch
-        tens = {k: self._tensor(state[k]) for k in FIELDS}
+        tens = {k: self._tensor(state[k]) for k in FIELDS if k in state}
+        if monopole_only:
+            for k in ("qs", "ps"):
+                if k not in tens:
+                    tens[k] = t.zeros_like(tens["Q"])
+        missing = [k for k in FIELDS if k not in tens]
+        if missing:
+            raise ValueError(f"state lacks {missing}")
         n = int(tens["Q"].numel())
         if any(int(v.numel()) != n for v in tens.values()):
             raise ValueError("state arrays differ in length")
         cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver,
-                          projection)
+                          projection, monopole_only)
         ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
@@ -240,6 +250,7 @@ class Simulation(Engine):
 
     def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
                  sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
-                 stream=None, solver="scan", projection="elem"):
+                 stream=None, solver="scan", projection="elem", monopole_only=False):
         super().__init__(precision, 1, device, stream)
-        self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection)
+        self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection,
+                   monopole_only)

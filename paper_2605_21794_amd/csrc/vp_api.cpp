@@ -64,6 +64,8 @@ vp_status validate(const vp_config* c) {
   if (c->projection != VP_PROJ_ELEM && c->projection != VP_PROJ_NODAL &&
       c->projection != VP_PROJ_CONSISTENT)
     return fail(VP_ERR_ARG, "bad projection %d", c->projection);
+  if (c->monopole_only != 0 && c->monopole_only != 1)
+    return fail(VP_ERR_ARG, "monopole_only must be 0 or 1");
   return VP_OK;
 }
 
@@ -94,6 +96,7 @@ struct vp_handle {
   Tile* d_tiles = nullptr;
   size_t tiles_cap = 0;
   int ntiles = 0;
+  int ntiles_dip = 0;      // tiles of decorated instances (they come first)
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
@@ -130,10 +133,17 @@ vp_status rebuild_tables(vp_handle* h) {
   h->h_tiles.clear();
   h->h_occ.clear();
   h->max_ng = VP_MIN_NG;
-  for (int s = 0; s < h->max_slots; ++s) {
+  for (int s = 0; s < h->max_slots; ++s)
+    if (h->slots[s].used) h->h_occ.push_back(s);
+  // tiles of decorated instances first, then those of monopole-only ones: one fused launch
+  // per kind and step
+  std::vector<int> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int s : h->h_occ)
+      if ((h->slots[s].cfg.monopole_only != 0) == (pass == 1)) order.push_back(s);
+  h->ntiles_dip = 0;
+  for (int s : order) {
     Slot& sl = h->slots[s];
-    if (!sl.used) continue;
-    h->h_occ.push_back(s);
     h->max_ng = std::max(h->max_ng, sl.cfg.ng);
     const long long n = sl.cfg.n;
     const int nt = (int)((n + tile_n - 1) / tile_n);
@@ -151,6 +161,7 @@ vp_status rebuild_tables(vp_handle* h) {
     if (nt > d.kin_cap) return fail(VP_ERR_STATE, "slot %d: %d tiles exceed the kinetic-sum ring (%d)", s, nt, d.kin_cap);
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
+    if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
   }
   h->ntiles = (int)h->h_tiles.size();
   h->any_fft = false;
@@ -186,10 +197,21 @@ vp_status check_slot(const vp_handle* h, int slot) {
 
 int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
 
+// One fused step of every instance in phase ph: a launch over the decorated instances'
+// tiles and one over the monopole-only instances' tiles (either may be empty).
+hipError_t fused_step(vp_handle* h, int ph) {
+  hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0,
+                                   h->ntiles_dip, h->tun.ppt, h->max_ng, h->any_fft, ph, true,
+                                   h->stream);
+  if (e != hipSuccess) return e;
+  return vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, h->ntiles_dip,
+                           h->ntiles - h->ntiles_dip, h->tun.ppt, h->max_ng, h->any_fft, ph,
+                           false, h->stream);
+}
+
 vp_status launch_steps_direct(vp_handle* h, int nsteps) {
   for (int i = 0; i < nsteps; ++i) {
-    VP_HIP(vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                             h->max_ng, h->any_fft, h->phase, h->stream));
+    VP_HIP(fused_step(h, h->phase));
     h->phase = next_phase(h->phase);
   }
   return VP_OK;
@@ -209,8 +231,7 @@ vp_status ensure_graph(vp_handle* h) {
   hipError_t le = hipSuccess;
   int ph = h->phase;
   for (int i = 0; i < len && le == hipSuccess; ++i) {
-    le = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0, h->ntiles, h->tun.ppt,
-                           h->max_ng, h->any_fft, ph, h->stream);
+    le = fused_step(h, ph);
     ph = next_phase(ph);
   }
   hipGraph_t g = nullptr;
@@ -438,6 +459,11 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   VP_HIP(hipMemcpyAsync(d.inv_lam, il.data(), ng * sizeof(double), hipMemcpyHostToDevice, h->stream));
   VP_HIP(hipMemcpyAsync(d.cw, cw.data(), cw.size() * sizeof(double), hipMemcpyHostToDevice,
                         h->stream));
+  if (cfg->monopole_only) {  // p* = q* = 0 from the start
+    const size_t bytes = (size_t)cfg->n * state_elem_size(cfg->precision);
+    VP_HIP(vpk::launch_fill_zero(parts.qs, bytes, h->stream));
+    VP_HIP(vpk::launch_fill_zero(parts.ps, bytes, h->stream));
+  }
   VP_HIP(hipStreamSynchronize(h->stream));
 
   Slot& sl = h->slots[slot];

@@ -87,9 +87,11 @@ int kin_capacity(long long n);
 
 size_t particle_lds_bytes(int mode, int max_ng);
 
-// `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS).
+// `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS);
+// `dipoles` false when every tile of the launch is of a monopole-only instance.
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, hipStream_t s);
+                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
+                        hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,

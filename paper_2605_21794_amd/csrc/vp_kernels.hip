@@ -683,7 +683,9 @@ __device__ void write_record(const InstDev& d, long long step, double K, double 
 // this step's half-kick, the drift, and the deposit of the drifted particle into the LDS
 // grid (eq. rhs-assembly).  (Q, P, q*, p*) are updated in place in storage precision.  The
 // float64 modes compute in float64 from the stored values in the oracle's operation order.
-template <int MODE, typename T>
+// DIP = false: a monopole-only particle (p* = q* = 0, plain P1 particle-in-cell): the dipole
+// terms are left out, which gives the same values as carrying zeros through them.
+template <int MODE, typename T, bool DIP = true>
 __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
                                               double* sacc, int pend, T& Qr, T& Pr, T& qsr,
                                               T& psr, const T psir, double& Ks, double& Ms,
@@ -696,49 +698,82 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const float psi = psir;
     const float xq = Q * ihf;
     const int i = cell_of_f(xq, ng);
-    const float Ei = (float)fE[i], gi = curv_at_f(d.proj, fG, i, xq, ng);
-    if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
-    const double Pd = P, qd = qs, wd = psi;
-    Ks += 0.5 * wd * Pd * Pd + qd * Pd;
-    Ms += wd * Pd + qd;
-    Cs += wd;
-    P = P + hf * Ei;
-    qs = qs + hf * ps * gi;
+    const float Ei = (float)fE[i];
+    if constexpr (DIP) {
+      const float gi = curv_at_f(d.proj, fG, i, xq, ng);
+      if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
+      const double Pd = P, qd = qs, wd = psi;
+      Ks += 0.5 * wd * Pd * Pd + qd * Pd;
+      Ms += wd * Pd + qd;
+      Cs += wd;
+      P = P + hf * Ei;
+      qs = qs + hf * ps * gi;
+    } else {
+      if (pend) P = P + hf * Ei;
+      const double Pd = P, wd = psi;
+      Ks += 0.5 * wd * Pd * Pd;
+      Ms += wd * Pd;
+      Cs += wd;
+      P = P + hf * Ei;
+    }
     float Qn = Q + dtf * P;
     if (Qn < 0.0f) Qn += Lf;
     if (Qn >= Lf) Qn -= Lf;
-    ps = ps - dtf * qs;
+    if constexpr (DIP) ps = ps - dtf * qs;
     const float x = Qn * ihf;
     const int j = cell_of_f(x, ng);
     const float s = frac01_f(x, j);
-    atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
-    atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
-    Qr = Qn; Pr = P; qsr = qs; psr = ps;
+    if constexpr (DIP) {
+      atomicAdd(fa + j, psi * (1.0f - s) + ps * ihf);
+      atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s - ps * ihf);
+    } else {
+      atomicAdd(fa + j, psi * (1.0f - s));
+      atomicAdd(fa + ((j + 1) & (ng - 1)), psi * s);
+    }
+    Qr = Qn; Pr = P;
+    if constexpr (DIP) { qsr = qs; psr = ps; }
   } else {
     const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
     const double Q = Qr, psi = psir;
     double P = Pr, qs = qsr, ps = psr;
     const double xq = Q * inv_h;
     const int i = cell_of(xq, ng);
-    const double Ei = fE[i], gi = curv_at(d.proj, fG, i, xq, ng);
-    if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
-    Ks += 0.5 * psi * P * P + qs * P;
-    Ms += psi * P + qs;
-    Cs += psi;
-    P = P + half * Ei;
-    qs = qs + half * ps * gi;
+    const double Ei = fE[i];
+    if constexpr (DIP) {
+      const double gi = curv_at(d.proj, fG, i, xq, ng);
+      if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
+      Ks += 0.5 * psi * P * P + qs * P;
+      Ms += psi * P + qs;
+      Cs += psi;
+      P = P + half * Ei;
+      qs = qs + half * ps * gi;
+    } else {
+      if (pend) P = P + half * Ei;
+      Ks += 0.5 * psi * P * P;
+      Ms += psi * P;
+      Cs += psi;
+      P = P + half * Ei;
+    }
     double Qn = Q + dt * P;
     if (Qn < 0.0) Qn += L;
     if (Qn >= L) Qn -= L;
-    const double psn = ps - dt * qs;
-    const T Qs = (T)Qn, pss = (T)psn;
-    const double Qd = Qs, psd = pss;
+    const T Qs = (T)Qn;
+    const double Qd = Qs;
     const double x = Qd * inv_h;
     const int j = cell_of(x, ng);
     const double s = frac01(x, j);
-    lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
-    Qr = Qs; Pr = (T)P; qsr = (T)qs; psr = pss;
+    if constexpr (DIP) {
+      const double psn = ps - dt * qs;
+      const T pss = (T)psn;
+      const double psd = pss;
+      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      qsr = (T)qs; psr = pss;
+    } else {
+      lds_add<MODE>(sacc, j, psi * (1.0 - s));
+      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s);
+    }
+    Qr = Qs; Pr = (T)P;
   }
 }
 
@@ -760,7 +795,9 @@ __host__ __device__ constexpr size_t fused_lds_doubles(bool fft) { return fft ? 
 template <int MODE, int TPB>
 __host__ __device__ constexpr int group_of() { return (MODE == kFP64 && TPB == 1024) ? 2 : 4; }
 
-template <int MODE, int TPB>
+// DIP = false: every tile of the launch belongs to a monopole-only instance; p* and q* are
+// neither read nor written (20 bytes of particle traffic per update instead of 36).
+template <int MODE, int TPB, bool DIP>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
                                                int ppt, int phase) {
@@ -802,8 +839,12 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       g.v[u] = (k0 + u < ppt) && (loc < tl.count);
       g.idx[u] = tl.begin + loc;
       if (g.v[u]) {
-        g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.a[u] = ntld(qsp + g.idx[u]);
-        g.b[u] = ntld(psp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
+        g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
+        if constexpr (DIP) {
+          g.a[u] = ntld(qsp + g.idx[u]); g.b[u] = ntld(psp + g.idx[u]);
+        } else {
+          g.a[u] = T(0); g.b[u] = T(0);
+        }
       }
     }
   };
@@ -857,8 +898,9 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     for (int u = 0; u < kGroup; ++u) {
       if (!g.v[u]) continue;
       T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
-      push_particle<MODE>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs);
-      ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P); ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps);
+      push_particle<MODE, T, DIP>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs);
+      ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P);
+      if constexpr (DIP) { ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps); }
     }
   };
 
@@ -1376,9 +1418,12 @@ __global__ void k_slot_status(const InstDev* __restrict__ insts, const int* __re
   out[2 * t + 1] = sc->nonfinite;
 }
 
-__global__ void k_fill_zero(unsigned long long* p, size_t n8) {
+// Zero n8 64-bit words, then a trailing 32-bit word when tail4 (an odd count of floats).
+__global__ void k_fill_zero(unsigned long long* p, size_t n8, bool tail4) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) p[i] = 0ull;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (size_t i = t; i < n8; i += stride) p[i] = 0ull;
+  if (tail4 && t == 0) reinterpret_cast<unsigned*>(p + n8)[0] = 0u;
 }
 
 template <typename T>
@@ -1523,11 +1568,31 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
   } while (0)
 
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
-                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, hipStream_t s) {
+                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
+                        hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
-  VP_DISPATCH(mode, tpb, k_fused, dim3(ntiles), dim3(tpb), lds, s, d_inst, d_tiles, tile0, ppt,
-              phase);
+#define VP_FUSED(M, TB)                                                                      \
+  do {                                                                                       \
+    if (dipoles)                                                                             \
+      hipLaunchKernelGGL((k_fused<M, TB, true>), dim3(ntiles), dim3(TB), lds, s, d_inst,     \
+                         d_tiles, tile0, ppt, phase);                                        \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_fused<M, TB, false>), dim3(ntiles), dim3(TB), lds, s, d_inst,    \
+                         d_tiles, tile0, ppt, phase);                                        \
+  } while (0)
+#define VP_FUSED_TPB(M)                                                                      \
+  do {                                                                                       \
+    if (tpb == 1024) VP_FUSED(M, 1024);                                                      \
+    else if (tpb == 512) VP_FUSED(M, 512);                                                   \
+    else VP_FUSED(M, 256);                                                                   \
+  } while (0)
+  if (mode == kFP32TwoSum) VP_FUSED_TPB(kFP32TwoSum);
+  else if (mode == kFP64) VP_FUSED_TPB(kFP64);
+  else if (mode == kFP32Comp) VP_FUSED_TPB(kFP32Comp);
+  else VP_FUSED_TPB(kFP32);
+#undef VP_FUSED_TPB
+#undef VP_FUSED
   return hipGetLastError();
 }
 
@@ -1651,12 +1716,15 @@ hipError_t launch_slot_status(const InstDev* d_inst, const int* d_slots, int nsl
 }
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  // bytes: a multiple of 4 (whole float or double elements)
   const size_t n8 = bytes / 8;
-  if (n8 == 0) return hipSuccess;
+  const bool tail4 = (bytes % 8) >= 4;
+  if (n8 == 0 && !tail4) return hipSuccess;
   size_t blocks = (n8 + 255) / 256;
+  if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s,
-                     static_cast<unsigned long long*>(p), n8);
+                     static_cast<unsigned long long*>(p), n8, tail4);
   return hipGetLastError();
 }
 
