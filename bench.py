@@ -4,13 +4,16 @@
     python bench.py [--steps K] [--warmup W] [--workload two_stream|probe|landau_nonlinear]
     python bench.py --workload landau_sweep      batched (256 uneven instances) vs plain
     python bench.py --workload served            continuous batching of a job stream
+    python bench.py --workload sw_vs_pic         particle count against accuracy, decorated
+                                                 particles against plain particle-in-cell
     python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
     python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
     python bench.py --pmc-summary FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR --workload W
 
-One step = one pass of the whole hot path over the batch of particles: pending half-kick,
-kinetic diagnostics, half-kick, drift, deposit, and the Poisson solve (run by the last
-workgroup of the fused kernel).  Default workload: the two-stream instability, N = 2^20
+One step = one pass of the whole hot path over the batch of particles: the Poisson solve of
+the previous deposit (every workgroup of the fused kernel solves it in its prologue),
+pending half-kick, kinetic diagnostics, half-kick, drift, deposit.  --monopole runs the same
+workload as plain particle-in-cell particles (p* = q* = 0, 20 bytes per update).  Default workload: the two-stream instability, N = 2^20
 decorated particles, Ng = 512, dt = 0.05, FP32 state with compensated deposition.
 
 Prints ONE JSON line on stdout.  `value` = N * K / wall time of the K timed steps
@@ -36,6 +39,7 @@ METRIC = "decorated-particle updates/s (1 GPU, % HBM roofline); served p50/p99 s
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle per fused step: read Q, P, q*, p*, psi*; write Q, P, q*, p*
 FUSED_BYTES = {"fp64": 72, "fp32c": 36, "fp32": 36, "fp32ts": 36}
+MONOPOLE_BYTES = {"fp64": 40, "fp32c": 20, "fp32": 20, "fp32ts": 20}  # Q, P, psi* in; Q, P out
 
 
 def log(*a):
@@ -345,6 +349,103 @@ def run_served(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sw_vs_pic(args):
+    """Particle count against accuracy, decorated particles against plain particle-in-cell
+    (the paper's quantitative comparison, on synthetic inputs): strong Landau damping
+    (L = 12, A = 0.5, Ng = 128, dt = 0.2), float64, every run in one engine (one fused
+    launch per kind and step).
+
+    Methods at N = 128 x nv particles: decorated lattice (nx = Ng columns, nv rows),
+    monopole-only on the same lattice (quiet start), monopole-only random markers (the
+    standard start).  Reference: monopole-only lattice of 1024 x 2048 particles, with a
+    decorated run of the same size beside it.  Error: relative L2 of E_amp(t) against the
+    reference over t <= 10 and t <= 20.  Bytes per update: 36 (decorated) and 20
+    (monopole-only) in float32 storage; degrees of freedom 5 and 3 per particle."""
+    import numpy as np
+    import torch
+    import paper_2605_21794_amd as vp
+    import workloads as W
+    steps = 100
+    nvs = [8, 16, 32, 64, 128, 256, 512, 1024]
+    runs = [("reference_pic", W.landau_strong(nx=1024, nv=2048), "lattice", True),
+            ("reference_sw", W.landau_strong(nx=1024, nv=2048), "lattice", False)]
+    for nv in nvs:
+        w = W.landau_strong(nx=128, nv=nv)
+        runs += [(f"sw_{nv}", w, "lattice", False), (f"pic_lattice_{nv}", w, "lattice", True),
+                 (f"pic_random_{nv}", w, "random", True)]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    eng = vp.Engine("fp64", max_slots=len(runs), stream=stream)
+    t0 = time.perf_counter()
+    for s_, (name, w, init, mono) in enumerate(runs):
+        st = W.random_markers(w, w.n, seed=s_) if init == "random" else w.state()
+        eng.admit(s_, st, w.L, w.ng, w.dt, hist_cap=steps + 8, monopole_only=mono)
+    log(f"sw_vs_pic: {len(runs)} runs admitted in {time.perf_counter() - t0:.1f} s")
+    eng.set_tuning(threads=512, ppt=4, acc_copies=4, graph_steps=33)
+    eng.step(steps)
+    torch.cuda.synchronize()
+    status = eng.slot_status()
+
+    def e_amp(slot):
+        stp, fin = status[slot]
+        h = eng.history(slot, 0, min(stp, steps), allow_nonfinite=True)
+        if fin and stp >= steps:
+            h.append(eng.diagnostics(slot))
+        return np.array([r["e_amp"] for r in h]), fin
+
+    ref, _ = e_amp(0)
+    windows = {"t<=10": 51, "t<=20": 101}
+
+    def errors(e):
+        out = {}
+        for k, m in windows.items():
+            out[k] = (float(np.linalg.norm(e[:m] - ref[:m]) / np.linalg.norm(ref[:m]))
+                      if e.size >= m and np.all(np.isfinite(e[:m])) else None)
+        return out
+
+    rows = []
+    sw_ref, _ = e_amp(1)
+    for s_, (name, w, init, mono) in enumerate(runs[2:], start=2):
+        e, fin = e_amp(s_)
+        r = {"run": name, "n": w.n, "method": "pic" if mono else "sw", "init": init,
+             "bytes_per_update_f32": 20 if mono else 36, "dofs": (3 if mono else 5) * w.n,
+             "finite_to_end": bool(fin and e.size > steps), "steps_done": int(status[s_][0]),
+             "error": errors(e)}
+        rows.append(r)
+        log(f"{name:16s} N={w.n:7d} err t<=10 {r['error']['t<=10']}  t<=20 {r['error']['t<=20']}"
+            f"  steps {r['steps_done']}")
+
+    def n_for(method, init, win, target):
+        """Smallest N of the sweep whose error is at or below target (None if none)."""
+        for r in rows:
+            if r["method"] == method and r["init"] == init:
+                e = r["error"][win]
+                if e is not None and e <= target:
+                    return r["n"]
+        return None
+
+    targets = (0.05, 0.02, 0.01)
+    summary = {win: {f"{t:g}": {"sw_lattice": n_for("sw", "lattice", win, t),
+                                "pic_lattice": n_for("pic", "lattice", win, t),
+                                "pic_random": n_for("pic", "random", win, t)}
+                     for t in targets} for win in windows}
+    head = summary["t<=10"]["0.02"]
+    ratio = (head["pic_random"] / head["sw_lattice"]
+             if head["sw_lattice"] and head["pic_random"] else None)
+    out = {"metric": "particles for 2% E_amp error over t <= 10: random-marker PIC / decorated",
+           "value": ratio, "unit": "x", "n_gpus": 1, "steps": steps, "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "landau_strong sw_vs_pic", "L": 12.0, "alpha": 0.5,
+                      "ng": 128, "dt": 0.2, "nx": 128, "nv": nvs,
+                      "reference": "monopole-only lattice 1024 x 2048"},
+           "sw_vs_pic": {"reference_sw_vs_pic": errors(sw_ref),
+                         "particles_for_error": summary, "rows": rows}}
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
 GOLDEN_LN = os.path.join(ROOT, "tests", "golden", "landau_nonlinear_oracle.npz")
 
 
@@ -498,6 +599,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="sort particles by cell every this many steps (0: never)")
     ap.add_argument("--sort-chunk", type=int, default=0, help="particles per sorted chunk")
+    ap.add_argument("--monopole", action="store_true",
+                    help="run the workload as monopole-only (plain particle-in-cell) particles")
     ap.add_argument("--primitives", action="store_true",
                     help="time vp_deposit and vp_gather_push on their own")
     ap.add_argument("--precision-study", action="store_true",
@@ -536,6 +639,9 @@ def main():
     if args.workload == "served":
         run_served(args)
         return
+    if args.workload == "sw_vs_pic":
+        run_sw_vs_pic(args)
+        return
     if args.precision_study:
         run_precision_study(args)
         return
@@ -553,13 +659,17 @@ def main():
     log(f"workload {w.name}: N={w.n} Ng={w.ng} dt={w.dt} precision={prec}")
     t0 = time.perf_counter()
     state = w.state(np.float64 if prec == "fp64" else np.float32)
+    if args.monopole:  # plain particle-in-cell: the same lattice without its dipole moments
+        state["qs"][:] = 0
+        state["ps"][:] = 0
     log(f"initial state built in {time.perf_counter() - t0:.1f} s")
 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()          # a non-null stream, so steps can be graph-captured
     torch.cuda.set_stream(stream)
     sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8),
-                        sort_every=args.sort_every, sort_chunk=args.sort_chunk)
+                        sort_every=args.sort_every, sort_chunk=args.sort_chunk,
+                        monopole_only=args.monopole)
     tuning_us = None
     if args.launch:
         sim.set_tuning(**parse_launch(args.launch))
@@ -605,12 +715,14 @@ def main():
     finite = bool(np.isfinite(diag["H"]))
     n = w.n
     value = n * args.steps / elapsed
-    bytes_per_launch = FUSED_BYTES[prec] * n
-    achieved = bytes_per_launch / kern_avg_s / 1e9
     persistent = bool(tun.get("persistent", 0))
+    # the persistent kernel carries monopole-only particles through the decorated path
+    bytes_per_launch = (MONOPOLE_BYTES if args.monopole and not persistent else FUSED_BYTES)[prec] * n
+    achieved = bytes_per_launch / kern_avg_s / 1e9
     # counters were taken on the one-launch-per-step kernel; the persistent kernel is a
     # different kernel (and moves far fewer bytes), so it reports none
-    traffic = None if persistent else load_traffic(args.workload, n)
+    traffic_key = args.workload + ("_monopole" if args.monopole else "")
+    traffic = None if persistent else load_traffic(traffic_key, n)
     out = {
         "metric": METRIC,
         "value": value,
@@ -625,7 +737,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": w.name, "n": n, "ng": w.ng, "L": w.L, "dt": w.dt,
+            "workload": w.name + ("_monopole" if args.monopole else ""), "n": n, "ng": w.ng,
+            "L": w.L, "dt": w.dt,
             "precision": prec, "instances": 1, "launch": tun,
             "sort_every": args.sort_every, "sort_chunk": args.sort_chunk,
             "state_finite_after_run": finite, "t_end": diag["t"],

@@ -16,6 +16,9 @@ that builds the initial decorated-particle arrays from `workloads.lattice`.
                      2048 x 2048 lattice (N = 2^22), v in [-6, 6], dt = 0.05, 2000 steps.
   served_stream      Poisson arrivals of mixed Landau / two-stream / bump-on-tail jobs with
                      N log-uniform in [2^12, 2^20], Ng in {64 .. 1024}, horizons 100-2000.
+  landau_strong      The paper's strong Landau damping case: L = 12, A = 0.5, k = 2 pi / L,
+                     dt = 0.2, Ng = 128; with `random_markers`, the standard particle-in-cell
+                     start of the same f0 (the particle-count study).
 
 Particles are stored in a seeded random order (like the arbitrary cluster order of a
 k-means initialisation); `order="lattice"` keeps the v-major lattice order.
@@ -99,6 +102,29 @@ def landau_nonlinear(seed: int = 0, nx: int = 2048, nv: int = 2048, ng: int = 25
     return Workload("landau_nonlinear", L=2 * math.pi / k, ng=ng, nx=nx, nv=nv, vmin=-6.0,
                     vmax=6.0, dt=0.05, nsteps=2000, kind="landau",
                     params={"alpha": 0.5, "k": k}, seed=seed)
+
+
+def landau_strong(seed: int = 0, nx: int = 128, nv: int = 128, ng: int = 128) -> Workload:
+    """Strong Landau damping with the paper's parameters (L = 12, A = 0.5, k = 2 pi / L,
+    dt = 0.2); Ng = 128 (a power of two) in place of the paper's 100 mesh points."""
+    L = 12.0
+    return Workload("landau_strong", L=L, ng=ng, nx=nx, nv=nv, vmin=-6.0, vmax=6.0, dt=0.2,
+                    nsteps=500, kind="landau", params={"alpha": 0.5, "k": 2 * math.pi / L},
+                    seed=seed)
+
+
+def random_markers(w: Workload, n: int, seed: int = 0) -> dict:
+    """Standard particle-in-cell start for a Landau workload (f0 = (1 + alpha cos kx) f_M(v),
+    f_M the unit Maxwellian): x uniform on [0, L), v drawn from f_M, weight
+    (1 + alpha cos kx) L / n, so the weights carry the density perturbation.  Monopoles only
+    (Q, P, psi)."""
+    if w.kind != "landau":
+        raise ValueError("random markers are defined for Landau workloads")
+    r = np.random.default_rng(np.random.SeedSequence(seed))
+    x = r.uniform(0.0, w.L, n)
+    v = r.standard_normal(n)
+    a, k = w.params["alpha"], w.params["k"]
+    return {"Q": x, "P": v, "psi": (1.0 + a * np.cos(k * x)) * (w.L / n)}
 
 
 def landau_sweep(seed: int = 0, n_inst: int = 256, nsteps: int = 500) -> list:
