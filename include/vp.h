@@ -278,6 +278,34 @@ vp_status vp_occupancy(const vp_handle* h, int32_t* slots_out, int64_t* particle
 #define VP_SLOT_NONFINITE 2
 vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* host_flags);
 
+/* ---------------------------------------------------------------- initialisation */
+
+/* Decorated particles from marker particles, the paper's Algorithm 1 with the periodic
+ * moments of its torus subsection.  k-means of the markers in (q, p): `iters` Lloyd
+ * iterations from the k markers init_idx (nearest centre by Euclidean distance in (q, p),
+ * ties to the lowest centre; centres move to the weighted mean of their markers, weights
+ * wm; an empty cluster keeps its centre), then a final assignment.  Each non-empty cluster
+ * S_a, in cluster order, gives one decorated particle:
+ *   psi*_a = sum of its weights (eq. psi-star);
+ *   (Q_a, P_a) = the member nearest the cluster's weighted mean (first in marker order on
+ *                ties);
+ *   p*_a = sum wm_A (L / 2 pi) sin(2 pi (Q_a - Qm_A) / L),  q*_a = -sum wm_A (P_a - Pm_A)
+ *          (eq. moment-def with the periodic c).
+ * All sums run over the members in increasing marker order, so results are reproducible.
+ * Inputs (device, float64, 8-byte aligned, not modified): Qm in [0, L), Pm, wm > 0, m of
+ * each; init_idx: k distinct marker indices in [0, m) (device int32; checked on the host,
+ * VP_ERR_ARG if out of range).  1 <= k <= m < 2^31, iters >= 0, L > 0.
+ * workspace: vp_cluster_workspace_bytes(m, k) bytes of device memory, 256-byte aligned.
+ * Outputs (device, float64, capacity k each): Q, P, qs (q*), ps (p*), psi of the non-empty
+ * clusters; assign_out (device int32, m, or NULL): final cluster of each marker;
+ * *n_out (host): the number of decorated particles written.  Runs on `stream` (a
+ * hipStream_t, or NULL) and synchronises it.  Errors: VP_ERR_ARG, VP_ERR_HIP. */
+vp_status vp_cluster_workspace_bytes(int64_t m, int32_t k, size_t* bytes_out);
+vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* wm, int64_t m,
+                             int32_t k, const int32_t* init_idx, int32_t iters, double L,
+                             void* workspace, void* stream, double* Q, double* P, double* qs,
+                             double* ps, double* psi, int32_t* assign_out, int32_t* n_out);
+
 const char* vp_status_string(vp_status s);
 const char* vp_last_error(void);
 int32_t vp_abi_version(void);

@@ -59,6 +59,52 @@ def workspace_bytes(cfg) -> int:
     return int(b.value)
 
 
+def cluster_markers(Q, P, w, k: int, L_: float, iters: int = 10, init_idx=None, seed: int = 0,
+                    return_assign: bool = False, stream=None):
+    """Decorated particles from markers (the paper's Algorithm 1), on the GPU.
+
+    Q, P, w: marker positions in [0, L), velocities and positive weights (device or host
+    arrays, taken as float64).  k clusters from `iters` Lloyd iterations starting at the
+    markers init_idx (by default k distinct markers drawn with `seed`).  Returns a dict of
+    device float64 tensors Q, P, qs, ps, psi (one entry per non-empty cluster), plus
+    `assign` (int32, the final cluster of each marker) when return_assign."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the decorated-particle path runs only on the GPU")
+    lib = L.load()
+    dev = torch.device("cuda")
+
+    def t64(a):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=dev, dtype=torch.float64).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    q, p, wt = t64(Q), t64(P), t64(w)
+    m = int(q.numel())
+    if init_idx is None:
+        g = torch.Generator().manual_seed(int(seed))
+        init_idx = torch.randperm(m, generator=g)[:int(k)]
+    idx = (init_idx.to(device=dev, dtype=torch.int32).contiguous()
+           if isinstance(init_idx, torch.Tensor)
+           else torch.from_numpy(np.ascontiguousarray(init_idx, dtype=np.int32)).to(dev))
+    b = c_size_t()
+    L.check(lib.vp_cluster_workspace_bytes(m, int(k), byref(b)), "vp_cluster_workspace_bytes")
+    ws = torch.empty(max(256, int(b.value)), dtype=torch.uint8, device=dev)
+    out = {f: torch.empty(int(k), dtype=torch.float64, device=dev) for f in FIELDS}
+    assign = torch.empty(m, dtype=torch.int32, device=dev) if return_assign else None
+    n = c_int32()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    L.check(lib.vp_cluster_markers(
+        c_void_p(q.data_ptr()), c_void_p(p.data_ptr()), c_void_p(wt.data_ptr()), m, int(k),
+        c_void_p(idx.data_ptr()), int(iters), float(L_), c_void_p(ws.data_ptr()),
+        c_void_p(s.cuda_stream), *(c_void_p(out[f].data_ptr()) for f in FIELDS),
+        c_void_p(assign.data_ptr()) if assign is not None else None, byref(n)),
+        "vp_cluster_markers")
+    res = {f: out[f][:n.value] for f in FIELDS}
+    if return_assign:
+        res["assign"] = assign
+    return res
+
+
 class Engine:
     """A set of slots, each holding one simulation instance, advanced together."""
 

@@ -75,6 +75,11 @@ SIGNATURES = {
     "vp_tune": (c_int32, [H, c_void_p, c_int32, POINTER(vp_tuning), POINTER(c_double)]),
     "vp_occupancy": (c_int32, [H, POINTER(c_int32), POINTER(c_int64)]),
     "vp_slot_status": (c_int32, [H, c_int32, POINTER(c_int64), POINTER(c_int32)]),
+    "vp_cluster_workspace_bytes": (c_int32, [c_int64, c_int32, POINTER(c_size_t)]),
+    "vp_cluster_markers": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p,
+                                     c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p,
+                                     POINTER(c_int32)]),
     "vp_status_string": (c_char_p, [c_int32]),
     "vp_last_error": (c_char_p, []),
     "vp_abi_version": (c_int32, []),

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvp.so")
-SOURCES = ["vp_kernels.hip", "vp_api.cpp"]
+SOURCES = ["vp_kernels.hip", "vp_cluster.hip", "vp_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

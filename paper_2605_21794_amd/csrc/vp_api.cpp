@@ -782,6 +782,51 @@ vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* 
   return VP_OK;
 }
 
+static vp_status cluster_check(int64_t m, int32_t k) {
+  if (m < 1 || m > 0x7fffffffLL) return fail(VP_ERR_ARG, "marker count %lld out of range", (long long)m);
+  if (k < 1 || k > m) return fail(VP_ERR_ARG, "cluster count %d must lie in [1, m]", k);
+  return VP_OK;
+}
+
+vp_status vp_cluster_workspace_bytes(int64_t m, int32_t k, size_t* bytes_out) {
+  if (!bytes_out) return fail(VP_ERR_ARG, "NULL argument");
+  VP_TRY(cluster_check(m, k));
+  *bytes_out = vpk::cluster_layout(m, k).total;
+  return VP_OK;
+}
+
+vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* wm, int64_t m,
+                             int32_t k, const int32_t* init_idx, int32_t iters, double L,
+                             void* workspace, void* stream, double* Q, double* P, double* qs,
+                             double* ps, double* psi, int32_t* assign_out, int32_t* n_out) {
+  VP_TRY(cluster_check(m, k));
+  if (!Qm || !Pm || !wm || !init_idx || !Q || !P || !qs || !ps || !psi || !n_out)
+    return fail(VP_ERR_ARG, "NULL argument");
+  const void* dptr[9] = {Qm, Pm, wm, Q, P, qs, ps, psi, init_idx};
+  for (int i = 0; i < 9; ++i)
+    if (!aligned(dptr[i], i < 8 ? 8 : 4)) return fail(VP_ERR_ARG, "argument %d misaligned", i);
+  if (assign_out && !aligned(assign_out, 4)) return fail(VP_ERR_ARG, "assign_out misaligned");
+  if (!(iters >= 0)) return fail(VP_ERR_ARG, "iters must be >= 0");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(VP_ERR_ARG, "L must be positive and finite");
+  if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every starting marker index must address a marker
+  std::vector<int32_t> idx(k);
+  VP_HIP(hipMemcpyAsync(idx.data(), init_idx, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  VP_HIP(hipStreamSynchronize(s));
+  for (int32_t a = 0; a < k; ++a)
+    if (idx[a] < 0 || idx[a] >= m) return fail(VP_ERR_ARG, "init_idx[%d] = %d outside [0, %lld)", a, idx[a], (long long)m);
+  const vpk::ClusterWs lay = vpk::cluster_layout(m, k);
+  double mm[2] = {0.0, 0.0};
+  VP_HIP(vpk::cluster_p_range(Pm, m, workspace, lay, mm, s));
+  if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) return fail(VP_ERR_ARG, "non-finite marker velocities");
+  int n = 0;
+  VP_HIP(vpk::cluster_run(Qm, Pm, wm, m, k, init_idx, iters, L, mm[0], mm[1], workspace, lay, Q, P,
+                          qs, ps, psi, assign_out, &n, s));
+  *n_out = n;
+  return VP_OK;
+}
+
 vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   if (!h || !bytes_out) return fail(VP_ERR_ARG, "NULL argument");
   size_t b = 0;

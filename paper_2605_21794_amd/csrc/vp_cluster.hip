@@ -1,0 +1,556 @@
+// HIP kernels (gfx950) for the decorated-particle initialisation of arXiv 2605.21794,
+// Algorithm 1 ("Decorated Particle Initialization") with the periodic moments of the torus
+// subsection: k-means of marker particles in (q, p), then one decorated particle per
+// non-empty cluster.
+//
+// Design:
+//  * nearest centre: the centres are binned into a uniform (q, p) grid of about one centre
+//    per cell (rebuilt every iteration); each marker searches square rings of cells around
+//    its own and stops once the ring bound r * min(cell width, cell height) exceeds its best
+//    distance.  The result is the exact nearest centre, ties to the lowest centre index,
+//    whatever order the cells list their centres in.
+//  * per-cluster sums: the marker indices are sorted by cluster with a stable radix sort
+//    (so each cluster's members stay in increasing marker order), and one thread adds its
+//    cluster's terms in that order.  The sums are therefore those of a sequential pass over
+//    the markers, bit for bit, and the centres, the assignments and the moments are
+//    reproducible run to run.
+//  * every index that reaches memory is clamped or counted exactly: cell coordinates are
+//    clamped into the grid, group positions come from exact integer counts.
+
+#include "vp_internal.h"
+
+#include <math.h>
+
+namespace vpk {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;
+
+struct Grid {
+  int gx, gp;
+  double sx, sp, pmin;  // cell width in q, height in p, lower edge in p
+};
+
+__device__ __forceinline__ int grid_cell(const Grid& g, double q, double p, int* cx, int* cy) {
+  double fx = floor(q / g.sx);
+  double fy = floor((p - g.pmin) / g.sp);
+  int x = !(fx >= 0.0) ? 0 : (fx >= (double)(g.gx - 1) ? g.gx - 1 : (int)fx);
+  int y = !(fy >= 0.0) ? 0 : (fy >= (double)(g.gp - 1) ? g.gp - 1 : (int)fy);
+  *cx = x;
+  *cy = y;
+  return y * g.gx + x;
+}
+
+// ---------------------------------------------------------------- small helpers
+__global__ void k_fill_int(int* p, long long n, int v) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Per-block min / max of p (the markers' velocity range), then one block folds them.
+__global__ __launch_bounds__(256) void k_minmax_partial(const double* __restrict__ p, long long m,
+                                                        double* __restrict__ part) {
+  __shared__ double smin[256], smax[256];
+  double lo = INFINITY, hi = -INFINITY;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const double v = p[i];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smin[0];
+    part[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_minmax_final(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ out) {
+  __shared__ double smin[256], smax[256];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    lo = fmin(lo, part[2 * i]);
+    hi = fmax(hi, part[2 * i + 1]);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+  }
+}
+
+// Exclusive prefix sum of n ints into out[0..n] (out[n] = total), one workgroup walking the
+// array in chunks of 1024 with a running carry.
+__global__ __launch_bounds__(1024) void k_scan_int(const int* __restrict__ in, int n,
+                                                   int* __restrict__ out) {
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    const int v = i < n ? in[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+      const int t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < n) out[i] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+// ---------------------------------------------------------------- k-means
+__global__ void k_init_centres(const double* __restrict__ q, const double* __restrict__ p,
+                               const int* __restrict__ init_idx, int k, double* __restrict__ cq,
+                               double* __restrict__ cp) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  const int i = init_idx[a];  // checked against [0, m) on the host
+  cq[a] = q[i];
+  cp[a] = p[i];
+}
+
+__global__ void k_cell_count(const double* __restrict__ cq, const double* __restrict__ cp, int k,
+                             Grid g, int* __restrict__ cell_of, int* __restrict__ ccnt) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  int cx, cy;
+  const int c = grid_cell(g, cq[a], cp[a], &cx, &cy);
+  cell_of[a] = c;
+  atomicAdd(ccnt + c, 1);
+}
+
+__global__ void k_cell_fill(const int* __restrict__ cell_of, int k, const int* __restrict__ coff,
+                            int* __restrict__ ccur, int* __restrict__ clist) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  const int c = cell_of[a];
+  clist[coff[c] + atomicAdd(ccur + c, 1)] = a;
+}
+
+// Nearest centre of each marker by the ring search (see the file comment).
+__global__ __launch_bounds__(256) void k_assign(const double* __restrict__ q,
+                                                const double* __restrict__ p, long long m,
+                                                const double* __restrict__ cq,
+                                                const double* __restrict__ cp, Grid g,
+                                                const int* __restrict__ coff,
+                                                const int* __restrict__ clist,
+                                                int* __restrict__ assign) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double qi = q[i], pi = p[i];
+  int cx, cy;
+  grid_cell(g, qi, pi, &cx, &cy);
+  const double smin = fmin(g.sx, g.sp);
+  const int rmax = g.gx > g.gp ? g.gx : g.gp;
+  double best = INFINITY;
+  int bi = 0x7fffffff;
+  for (int r = 0; r <= rmax; ++r) {
+    for (int dy = -r; dy <= r; ++dy) {
+      const int y = cy + dy;
+      if (y < 0 || y >= g.gp) continue;
+      const bool edge = dy == -r || dy == r;
+      const int step = edge ? 1 : 2 * r;  // interior rows: only the two ends of the ring
+      for (int dx = -r; dx <= r; dx += (step > 0 ? step : 1)) {
+        const int x = cx + dx;
+        if (x < 0 || x >= g.gx) continue;
+        const int c = y * g.gx + x;
+        for (int t = coff[c]; t < coff[c + 1]; ++t) {
+          const int a = clist[t];
+          const double dq = qi - cq[a], dp = pi - cp[a];
+          const double d2 = dq * dq + dp * dp;
+          if (d2 < best || (d2 == best && a < bi)) {
+            best = d2;
+            bi = a;
+          }
+        }
+      }
+    }
+    // every centre not yet seen lies at least r * smin away
+    const double bound = (double)r * smin;
+    if (bi != 0x7fffffff && best < bound * bound * (1.0 - 1e-9)) break;
+  }
+  // every centre is binned, so the full square found one, unless every distance was NaN
+  // (non-finite or zero-weight input): keep the index in range even then
+  assign[i] = bi == 0x7fffffff ? 0 : bi;
+}
+
+__global__ void k_group_count(const int* __restrict__ assign, long long m, int* __restrict__ cnt) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) atomicAdd(cnt + assign[i], 1);
+}
+
+// Stable LSD radix sort of (key, value) pairs by 8-bit digits: per-chunk digit counts, a
+// digit-major scan of them, then a stable scatter in which each chunk keeps its elements in
+// order.  Chunks of kRadixChunk elements, one 256-thread workgroup each.
+__global__ __launch_bounds__(256) void k_radix_hist(const int* __restrict__ keys, long long m,
+                                                    int shift, int nb, int* __restrict__ hist) {
+  __shared__ int cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const long long b0 = (long long)blockIdx.x * kRadixChunk;
+  const long long e0 = b0 + kRadixChunk < m ? b0 + kRadixChunk : m;
+  for (long long i = b0 + threadIdx.x; i < e0; i += 256)
+    atomicAdd(cnt + ((keys[i] >> shift) & 255), 1);
+  __syncthreads();
+  hist[(long long)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const int* __restrict__ kin,
+                                                       const int* __restrict__ vin, long long m,
+                                                       int shift, int nb,
+                                                       const int* __restrict__ hoff,
+                                                       int* __restrict__ kout,
+                                                       int* __restrict__ vout) {
+  __shared__ int run[256];
+  __shared__ int dig[256];
+  run[threadIdx.x] = hoff[(long long)threadIdx.x * nb + blockIdx.x];
+  const long long b0 = (long long)blockIdx.x * kRadixChunk;
+  const long long e0 = b0 + kRadixChunk < m ? b0 + kRadixChunk : m;
+  for (long long s0 = b0; s0 < e0; s0 += 256) {
+    const long long i = s0 + threadIdx.x;
+    const bool valid = i < e0;
+    const int key = valid ? kin[i] : 0;
+    const int d = valid ? ((key >> shift) & 255) : -1;
+    __syncthreads();  // run[] settled, dig[] free
+    dig[threadIdx.x] = d;
+    __syncthreads();
+    int rank = 0, total = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int same = dig[t] == d;
+      rank += (t < (int)threadIdx.x) & same;
+      total += same;
+    }
+    if (valid) {
+      const int pos = run[d] + rank;
+      kout[pos] = key;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();  // every thread has read run[d]
+    if (valid && rank + 1 == total) run[d] += total;  // the batch's last element of digit d
+  }
+}
+
+__global__ void k_iota(int* __restrict__ v, long long m) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) v[i] = (int)i;
+}
+
+// New centre of each cluster: weighted mean of its members, summed in marker order; a
+// cluster with no members keeps its centre.
+__global__ void k_centres(const double* __restrict__ q, const double* __restrict__ p,
+                          const double* __restrict__ w, const int* __restrict__ off,
+                          const int* __restrict__ order, int k, double* __restrict__ cq,
+                          double* __restrict__ cp) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  const int b = off[a], e = off[a + 1];
+  if (b == e) return;
+  double W = 0.0, SQ = 0.0, SP = 0.0;
+  for (int t = b; t < e; ++t) {
+    const int i = order[t];
+    W += w[i];
+    SQ += w[i] * q[i];
+    SP += w[i] * p[i];
+  }
+  cq[a] = SQ / W;
+  cp[a] = SP / W;
+}
+
+// The decorated particle of each non-empty cluster (Algorithm 1): weight, centre member
+// nearest the weighted mean (first in marker order on ties), periodic spatial moment and
+// velocity moment, all summed in marker order.  flag[a] = 1 for a non-empty cluster.
+__global__ void k_moments(const double* __restrict__ q, const double* __restrict__ p,
+                          const double* __restrict__ w, const int* __restrict__ off,
+                          const int* __restrict__ order, int k, double L,
+                          double* __restrict__ tQ, double* __restrict__ tP,
+                          double* __restrict__ tqs, double* __restrict__ tps,
+                          double* __restrict__ tpsi, int* __restrict__ flag) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  const int b = off[a], e = off[a + 1];
+  if (b == e) {
+    flag[a] = 0;
+    return;
+  }
+  double W = 0.0, SQ = 0.0, SP = 0.0;
+  for (int t = b; t < e; ++t) {
+    const int i = order[t];
+    W += w[i];
+    SQ += w[i] * q[i];
+    SP += w[i] * p[i];
+  }
+  const double zq = SQ / W, zp = SP / W;
+  double best = INFINITY;
+  int a0 = order[b];
+  for (int t = b; t < e; ++t) {
+    const int i = order[t];
+    const double dq = q[i] - zq, dp = p[i] - zp;
+    const double d2 = dq * dq + dp * dp;
+    if (d2 < best) {
+      best = d2;
+      a0 = i;
+    }
+  }
+  const double Qa = q[a0], Pa = p[a0];
+  const double half_len = L / kTwoPi;
+  double sps = 0.0, sqs = 0.0;
+  for (int t = b; t < e; ++t) {
+    const int i = order[t];
+    sps += w[i] * (half_len * sin(kTwoPi * (Qa - q[i]) / L));
+    sqs += w[i] * (Pa - p[i]);
+  }
+  tQ[a] = Qa;
+  tP[a] = Pa;
+  tps[a] = sps;
+  tqs[a] = -sqs;
+  tpsi[a] = W;
+  flag[a] = 1;
+}
+
+__global__ void k_compact(const int* __restrict__ flag, const int* __restrict__ pos, int k,
+                          const double* __restrict__ tQ, const double* __restrict__ tP,
+                          const double* __restrict__ tqs, const double* __restrict__ tps,
+                          const double* __restrict__ tpsi, double* __restrict__ Q,
+                          double* __restrict__ P, double* __restrict__ qs,
+                          double* __restrict__ ps, double* __restrict__ psi) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k || !flag[a]) return;
+  const int j = pos[a];
+  Q[j] = tQ[a];
+  P[j] = tP[a];
+  qs[j] = tqs[a];
+  ps[j] = tps[a];
+  psi[j] = tpsi[a];
+}
+
+__global__ void k_copy_int(const int* __restrict__ in, long long n, int* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+unsigned blocks_for(long long n, int tpb) {
+  long long b = (n + tpb - 1) / tpb;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t fill_int(int* p, long long n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)b), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+ClusterWs cluster_layout(long long m, int k) {
+  ClusterWs w{};
+  const long long gmax = cluster_max_cells(k);
+  size_t o = 0;
+  w.cq = o;      o = a256(o + (size_t)k * sizeof(double));
+  w.cp = o;      o = a256(o + (size_t)k * sizeof(double));
+  w.assign = o;  o = a256(o + (size_t)m * sizeof(int));
+  w.cnt = o;     o = a256(o + (size_t)k * sizeof(int));
+  w.off = o;     o = a256(o + (size_t)(k + 1) * sizeof(int));
+  w.keys_a = o;  o = a256(o + (size_t)m * sizeof(int));
+  w.vals_a = o;  o = a256(o + (size_t)m * sizeof(int));
+  w.keys_b = o;  o = a256(o + (size_t)m * sizeof(int));
+  w.vals_b = o;  o = a256(o + (size_t)m * sizeof(int));
+  w.hist = o;    o = a256(o + (size_t)256 * radix_blocks(m) * sizeof(int));
+  w.hoff = o;    o = a256(o + ((size_t)256 * radix_blocks(m) + 1) * sizeof(int));
+  w.cell_of = o; o = a256(o + (size_t)k * sizeof(int));
+  w.ccnt = o;    o = a256(o + (size_t)gmax * sizeof(int));
+  w.coff = o;    o = a256(o + (size_t)(gmax + 1) * sizeof(int));
+  w.ccur = o;    o = a256(o + (size_t)gmax * sizeof(int));
+  w.clist = o;   o = a256(o + (size_t)k * sizeof(int));
+  w.mm = o;      o = a256(o + (size_t)(2 * kClusterMinMaxBlocks + 2) * sizeof(double));
+  w.tQ = o;      o = a256(o + (size_t)k * sizeof(double));
+  w.tP = o;      o = a256(o + (size_t)k * sizeof(double));
+  w.tqs = o;     o = a256(o + (size_t)k * sizeof(double));
+  w.tps = o;     o = a256(o + (size_t)k * sizeof(double));
+  w.tpsi = o;    o = a256(o + (size_t)k * sizeof(double));
+  w.flag = o;    o = a256(o + (size_t)k * sizeof(int));
+  w.pos = o;     o = a256(o + (size_t)(k + 1) * sizeof(int));
+  w.total = o;
+  return w;
+}
+
+hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
+                           double* host_minmax, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  double* part = reinterpret_cast<double*>(base + w.mm);
+  double* res = part + 2 * kClusterMinMaxBlocks;
+  long long nb = (m + 255) / 256;
+  if (nb > kClusterMinMaxBlocks) nb = kClusterMinMaxBlocks;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_minmax_partial, dim3((unsigned)nb), dim3(256), 0, s, p, m, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, part, (int)nb, res);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(host_minmax, res, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// Group the markers by their assignment: counts and segment offsets per cluster, and the
+// marker indices sorted by cluster (stable, so in marker order within each cluster).
+static hipError_t group_markers(long long m, int k, const int* assign, int* cnt, int* off,
+                                int* keys_a, int* vals_a, int* keys_b, int* vals_b, int* hist,
+                                int* hoff, int** order_out, hipStream_t s) {
+  hipError_t e = fill_int(cnt, k, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_group_count, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, cnt, k, off);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, keys_a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, vals_a, m);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nb = (int)((m + kRadixChunk - 1) / kRadixChunk);
+  int bits = 1;
+  while (bits < 31 && (1LL << bits) < (long long)k) ++bits;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(256), 0, s, keys_a, m, shift, nb, hist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, hist, 256 * nb, hoff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(256), 0, s, keys_a, vals_a, m, shift, nb,
+                       hoff, keys_b, vals_b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int* t = keys_a; keys_a = keys_b; keys_b = t;
+    t = vals_a; vals_a = vals_b; vals_b = t;
+  }
+  *order_out = vals_a;
+  return hipSuccess;
+}
+
+hipError_t cluster_run(const double* q, const double* p, const double* w, long long m, int k,
+                       const int* init_idx, int iters, double L, double pmin, double pmax,
+                       void* ws, const ClusterWs& lay, double* Q, double* P, double* qs,
+                       double* ps, double* psi, int* assign_out, int* host_n, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  double* cq = reinterpret_cast<double*>(base + lay.cq);
+  double* cp = reinterpret_cast<double*>(base + lay.cp);
+  int* assign = reinterpret_cast<int*>(base + lay.assign);
+  int* cnt = reinterpret_cast<int*>(base + lay.cnt);
+  int* off = reinterpret_cast<int*>(base + lay.off);
+  int* keys_a = reinterpret_cast<int*>(base + lay.keys_a);
+  int* vals_a = reinterpret_cast<int*>(base + lay.vals_a);
+  int* keys_b = reinterpret_cast<int*>(base + lay.keys_b);
+  int* vals_b = reinterpret_cast<int*>(base + lay.vals_b);
+  int* hist = reinterpret_cast<int*>(base + lay.hist);
+  int* hoff = reinterpret_cast<int*>(base + lay.hoff);
+  int* order = nullptr;
+  int* cell_of = reinterpret_cast<int*>(base + lay.cell_of);
+  int* ccnt = reinterpret_cast<int*>(base + lay.ccnt);
+  int* coff = reinterpret_cast<int*>(base + lay.coff);
+  int* ccur = reinterpret_cast<int*>(base + lay.ccur);
+  int* clist = reinterpret_cast<int*>(base + lay.clist);
+  double* tQ = reinterpret_cast<double*>(base + lay.tQ);
+  double* tP = reinterpret_cast<double*>(base + lay.tP);
+  double* tqs = reinterpret_cast<double*>(base + lay.tqs);
+  double* tps = reinterpret_cast<double*>(base + lay.tps);
+  double* tpsi = reinterpret_cast<double*>(base + lay.tpsi);
+  int* flag = reinterpret_cast<int*>(base + lay.flag);
+  int* pos = reinterpret_cast<int*>(base + lay.pos);
+
+  // grid of about one centre per cell over [0, L) x [pmin, pmax]
+  Grid g{};
+  const double span = pmax > pmin ? pmax - pmin : 1.0;
+  const long long gmax = cluster_max_cells(k);
+  double cell = sqrt(L * span / (double)k);
+  for (;;) {
+    const double gx = ceil(L / cell), gp = ceil(span / cell);
+    if (gx * gp <= (double)gmax) {
+      g.gx = (int)(gx < 1 ? 1 : gx);
+      g.gp = (int)(gp < 1 ? 1 : gp);
+      break;
+    }
+    cell *= 1.25;
+  }
+  g.sx = L / g.gx;
+  g.sp = span / g.gp;
+  g.pmin = pmin;
+  const int G = g.gx * g.gp;
+
+  hipError_t e = hipSuccess;
+  hipLaunchKernelGGL(k_init_centres, dim3(blocks_for(k, 256)), dim3(256), 0, s, q, p, init_idx,
+                     k, cq, cp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int it = 0; it <= iters; ++it) {
+    // bin the centres
+    if ((e = fill_int(ccnt, G, 0, s)) != hipSuccess) return e;
+    if ((e = fill_int(ccur, G, 0, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(k, 256)), dim3(256), 0, s, cq, cp, k, g,
+                       cell_of, ccnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, ccnt, G, coff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(k, 256)), dim3(256), 0, s, cell_of, k, coff,
+                       ccur, clist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // assign, group
+    hipLaunchKernelGGL(k_assign, dim3(blocks_for(m, 256)), dim3(256), 0, s, q, p, m, cq, cp, g,
+                       coff, clist, assign);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = group_markers(m, k, assign, cnt, off, keys_a, vals_a, keys_b, vals_b, hist, hoff,
+                           &order, s)) != hipSuccess)
+      return e;
+    if (it < iters) {  // move the centres; the last pass only assigns
+      hipLaunchKernelGGL(k_centres, dim3(blocks_for(k, 64)), dim3(64), 0, s, q, p, w, off, order,
+                         k, cq, cp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_moments, dim3(blocks_for(k, 64)), dim3(64), 0, s, q, p, w, off, order, k,
+                     L, tQ, tP, tqs, tps, tpsi, flag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, flag, k, pos);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compact, dim3(blocks_for(k, 256)), dim3(256), 0, s, flag, pos, k, tQ, tP,
+                     tqs, tps, tpsi, Q, P, qs, ps, psi);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (assign_out) {
+    hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m,
+                       assign_out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = hipMemcpyAsync(host_n, pos + k, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace vpk

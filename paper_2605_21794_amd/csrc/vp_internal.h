@@ -116,6 +116,28 @@ hipError_t launch_ring(int mode, const InstDev* d_inst, const int* d_slots, int 
                        int phase, hipStream_t s);
 hipError_t launch_slot_scalars(const InstDev* d_inst, const int* d_slots, int nslots, int op,
                                int phase, hipStream_t s);
+// ---------------------------------------------------------------- initialisation (Algorithm 1)
+constexpr int kClusterMinMaxBlocks = 1024;  // partial min / max blocks of the velocity range
+constexpr int kRadixChunk = 1024;           // elements per workgroup in the radix sort
+inline long long cluster_max_cells(int k) { return 4LL * k + 64; }
+inline long long radix_blocks(long long m) { return (m + kRadixChunk - 1) / kRadixChunk; }
+
+// Byte offsets of the regions of the caller's clustering workspace (256-byte aligned).
+struct ClusterWs {
+  size_t cq, cp, assign, cnt, off, keys_a, vals_a, keys_b, vals_b, hist, hoff, cell_of, ccnt,
+      coff, ccur, clist, mm, tQ, tP, tqs, tps, tpsi, flag, pos, total;
+};
+ClusterWs cluster_layout(long long m, int k);
+// Velocity range of the markers (synchronises the stream).
+hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
+                           double* host_minmax, hipStream_t s);
+// Lloyd iterations, final assignment, moments and compaction; *host_n = decorated particles
+// written (synchronises the stream).
+hipError_t cluster_run(const double* q, const double* p, const double* w, long long m, int k,
+                       const int* init_idx, int iters, double L, double pmin, double pmax,
+                       void* ws, const ClusterWs& lay, double* Q, double* P, double* qs,
+                       double* ps, double* psi, int* assign_out, int* host_n, hipStream_t s);
+
 // out[2t] = step, out[2t+1] = nonfinite of instance slots[t], t < nslots.
 hipError_t launch_slot_status(const InstDev* d_inst, const int* d_slots, int nslots,
                               long long* out, hipStream_t s);
