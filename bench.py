@@ -357,7 +357,9 @@ def run_sw_vs_pic(args):
 
     Methods at N = 128 x nv particles: decorated lattice (nx = Ng columns, nv rows),
     monopole-only on the same lattice (quiet start), monopole-only random markers (the
-    standard start).  Reference: monopole-only lattice of 1024 x 2048 particles, with a
+    standard start), and decorated particles clustered from ten times as many random
+    markers by the GPU k-means initialisation (the paper's Algorithm 1; the paper clusters
+    1e5 markers into 1e4 decorated particles).  Reference: monopole-only lattice of 1024 x 2048 particles, with a
     decorated run of the same size beside it.  Error: relative L2 of E_amp(t) against the
     reference over t <= 10 and t <= 20.  Bytes per update: 36 (decorated) and 20
     (monopole-only) in float32 storage; degrees of freedom 5 and 3 per particle."""
@@ -372,15 +374,28 @@ def run_sw_vs_pic(args):
     for nv in nvs:
         w = W.landau_strong(nx=128, nv=nv)
         runs += [(f"sw_{nv}", w, "lattice", False), (f"pic_lattice_{nv}", w, "lattice", True),
-                 (f"pic_random_{nv}", w, "random", True)]
+                 (f"pic_random_{nv}", w, "random", True), (f"sw_kmeans_{nv}", w, "kmeans", False)]
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     eng = vp.Engine("fp64", max_slots=len(runs), stream=stream)
     t0 = time.perf_counter()
+    cluster_s = 0.0
+    counts = []                      # particles admitted per run (k-means may leave clusters empty)
     for s_, (name, w, init, mono) in enumerate(runs):
-        st = W.random_markers(w, w.n, seed=s_) if init == "random" else w.state()
+        if init == "random":
+            st = W.random_markers(w, w.n, seed=s_)
+        elif init == "kmeans":
+            mk = W.random_markers(w, 10 * w.n, seed=s_)
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            st = vp.cluster_markers(mk["Q"], mk["P"], mk["psi"], w.n, w.L, iters=10, seed=s_)
+            torch.cuda.synchronize()
+            cluster_s += time.perf_counter() - tc
+        else:
+            st = w.state()
         eng.admit(s_, st, w.L, w.ng, w.dt, hist_cap=steps + 8, monopole_only=mono)
+        counts.append(int(st["Q"].shape[0]))
     log(f"sw_vs_pic: {len(runs)} runs admitted in {time.perf_counter() - t0:.1f} s")
     eng.set_tuning(threads=512, ppt=4, acc_copies=4, graph_steps=33)
     eng.step(steps)
@@ -408,12 +423,13 @@ def run_sw_vs_pic(args):
     sw_ref, _ = e_amp(1)
     for s_, (name, w, init, mono) in enumerate(runs[2:], start=2):
         e, fin = e_amp(s_)
-        r = {"run": name, "n": w.n, "method": "pic" if mono else "sw", "init": init,
-             "bytes_per_update_f32": 20 if mono else 36, "dofs": (3 if mono else 5) * w.n,
+        r = {"run": name, "n": counts[s_], "method": "pic" if mono else "sw",
+             "init": init,
+             "bytes_per_update_f32": 20 if mono else 36, "dofs": (3 if mono else 5) * counts[s_],
              "finite_to_end": bool(fin and e.size > steps), "steps_done": int(status[s_][0]),
              "error": errors(e)}
         rows.append(r)
-        log(f"{name:16s} N={w.n:7d} err t<=10 {r['error']['t<=10']}  t<=20 {r['error']['t<=20']}"
+        log(f"{name:16s} N={counts[s_]:7d} err t<=10 {r['error']['t<=10']}  t<=20 {r['error']['t<=20']}"
             f"  steps {r['steps_done']}")
 
     def n_for(method, init, win, target):
@@ -427,6 +443,7 @@ def run_sw_vs_pic(args):
 
     targets = (0.05, 0.02, 0.01)
     summary = {win: {f"{t:g}": {"sw_lattice": n_for("sw", "lattice", win, t),
+                                "sw_kmeans": n_for("sw", "kmeans", win, t),
                                 "pic_lattice": n_for("pic", "lattice", win, t),
                                 "pic_random": n_for("pic", "random", win, t)}
                      for t in targets} for win in windows}
@@ -440,7 +457,7 @@ def run_sw_vs_pic(args):
            "config": {"workload": "landau_strong sw_vs_pic", "L": 12.0, "alpha": 0.5,
                       "ng": 128, "dt": 0.2, "nx": 128, "nv": nvs,
                       "reference": "monopole-only lattice 1024 x 2048"},
-           "sw_vs_pic": {"reference_sw_vs_pic": errors(sw_ref),
+           "sw_vs_pic": {"reference_sw_vs_pic": errors(sw_ref), "kmeans_seconds": cluster_s,
                          "particles_for_error": summary, "rows": rows}}
     eng.close()
     print(json.dumps(out), flush=True)
