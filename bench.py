@@ -6,6 +6,7 @@
     python bench.py --workload served            continuous batching of a job stream
     python bench.py --workload sw_vs_pic         particle count against accuracy, decorated
                                                  particles against plain particle-in-cell
+    python bench.py --workload cluster           k-means initialisation from markers
     python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
     python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
     python bench.py --pmc-summary FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR --workload W
@@ -463,6 +464,57 @@ def run_sw_vs_pic(args):
     print(json.dumps(out), flush=True)
 
 
+def run_cluster(args):
+    """Time the initialisation from markers (Algorithm 1 on the GPU): M random markers of
+    the strong Landau case into M / 10 decorated particles (the paper's ratio), 10 Lloyd
+    iterations.  value = markers x (iterations + 1) / s; the CPU oracle is timed on a
+    bounded sample (a tenth of the markers and clusters, brute-force assignment)."""
+    import numpy as np
+    import torch
+    import paper_2605_21794_amd as vp
+    import workloads as W
+    m = args.markers
+    k = m // 10
+    iters = 10
+    w = W.landau_strong()
+    mk = W.random_markers(w, m, seed=0)
+    torch.cuda.set_device(0)
+    q, p, wt = (torch.from_numpy(mk[f]).cuda() for f in ("Q", "P", "psi"))
+    vp.cluster_markers(q, p, wt, k, w.L, iters=1, seed=1)      # warm the kernels
+    times = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dec = vp.cluster_markers(q, p, wt, k, w.L, iters=iters, seed=rep)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    n_out = int(dec["Q"].shape[0])
+    log(f"cluster: {m} markers -> {n_out} decorated particles, {iters} iterations: "
+        f"{best * 1e3:.1f} ms (runs {[round(t * 1e3, 1) for t in times]})")
+    out = {"metric": "marker assignments per second (k-means initialisation)",
+           "value": m * (iters + 1) / best, "unit": "marker-iterations/s", "n_gpus": 1,
+           "steps": iters, "warmup": 1, "ms_per_step": best * 1e3 / (iters + 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "cluster", "markers": m, "clusters": k,
+                      "decorated_out": n_out, "iterations": iters, "seconds": best}}
+    if not args.no_cpu:
+        import oracle as O
+        ms, ks = m // 10, k // 10
+        sub = {f: mk[f][:ms] for f in ("Q", "P", "psi")}
+        init = np.random.default_rng(0).choice(ms, ks, replace=False)
+        t0 = time.perf_counter()
+        O.cluster_markers(sub["Q"], sub["P"], sub["psi"], init, 2, w.L)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": ms * 3 / el, "unit": "marker-iterations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle k-means of {ms} markers into {ks} clusters, "
+                                         f"2 iterations + final assignment and moments "
+                                         f"(brute force), {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 GOLDEN_LN = os.path.join(ROOT, "tests", "golden", "landau_nonlinear_oracle.npz")
 
 
@@ -616,6 +668,7 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="sort particles by cell every this many steps (0: never)")
     ap.add_argument("--sort-chunk", type=int, default=0, help="particles per sorted chunk")
+    ap.add_argument("--markers", type=int, default=1 << 22, help="cluster: markers")
     ap.add_argument("--monopole", action="store_true",
                     help="run the workload as monopole-only (plain particle-in-cell) particles")
     ap.add_argument("--primitives", action="store_true",
@@ -658,6 +711,9 @@ def main():
         return
     if args.workload == "sw_vs_pic":
         run_sw_vs_pic(args)
+        return
+    if args.workload == "cluster":
+        run_cluster(args)
         return
     if args.precision_study:
         run_precision_study(args)
