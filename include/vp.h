@@ -8,7 +8,9 @@
  * stiffness system of eq. lin-sys with the zero-mean gauge, equations of motion of
  * eq. sw-evolution, advanced by the kick-drift-kick splitting of the discrete Hamiltonian
  * of eq. Hh.  Each particle carries (Q, P, q*, p*, psi*): position, velocity, momentum
- * dipole, spatial dipole, weight (the tuple of Section 4).
+ * dipole, spatial dipole, weight (the tuple of Section 4).  It also builds decorated
+ * particles from marker particles (Algorithm 1: vp_cluster_markers) and runs plain
+ * particle-in-cell instances, the p* = q* = 0 special case (vp_config.monopole_only).
  *
  * Conventions shared by every entry point
  *   - All pointers to particle or workspace memory are DEVICE pointers on the current HIP
