@@ -121,7 +121,8 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
     w_scale = COPY_BYTES / (cw_kib * 1024.0)
     fetch_b = fetch_kib * 1024.0 * f_scale
     write_b = write_kib * 1024.0 * w_scale
-    w, _ = make_workload(workload)
+    w, _ = make_workload(workload[:-len("_monopole")] if workload.endswith("_monopole")
+                         else workload)
     rec = {"kernel": "k_fused", "workload": workload, "n": w.n,
            "kernel_src_sha": kernel_src_sha(),
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,

@@ -126,6 +126,53 @@ __global__ __launch_bounds__(1024) void k_scan_int(const int* __restrict__ in, i
   if (threadIdx.x == 0) out[n] = carry;
 }
 
+// Large scans in three passes: the sum of every tile of kScanTile ints, an exclusive scan of
+// those sums (one workgroup), then every tile scanned on its own and offset by its sum.
+constexpr int kScanTile = 4096;  // 1024 threads x 4
+
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(const int* __restrict__ in, int n,
+                                                         int* __restrict__ sums) {
+  __shared__ int red[16];
+  const long long base = (long long)blockIdx.x * kScanTile + 4LL * threadIdx.x;
+  int v = 0;
+  for (int u = 0; u < 4; ++u)
+    if (base + u < n) v += in[base + u];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles(const int* __restrict__ in, int n,
+                                                     const int* __restrict__ tile_off,
+                                                     int* __restrict__ out) {
+  __shared__ int buf[1024];
+  const long long base = (long long)blockIdx.x * kScanTile + 4LL * threadIdx.x;
+  int x[4], t = 0;
+  for (int u = 0; u < 4; ++u) {
+    x[u] = base + u < n ? in[base + u] : 0;
+    t += x[u];
+  }
+  buf[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the per-thread sums
+    const int y = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += y;
+    __syncthreads();
+  }
+  int run = tile_off[blockIdx.x] + buf[threadIdx.x] - t;
+  for (int u = 0; u < 4; ++u) {
+    if (base + u < n) out[base + u] = run;
+    run += x[u];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_off[gridDim.x];
+}
+
 // ---------------------------------------------------------------- k-means
 __global__ void k_init_centres(const double* __restrict__ q, const double* __restrict__ p,
                                const int* __restrict__ init_idx, int k, double* __restrict__ cq,
@@ -156,15 +203,19 @@ __global__ void k_cell_fill(const int* __restrict__ cell_of, int k, const int* _
 }
 
 // Nearest centre of each marker by the ring search (see the file comment).
+// Markers are taken in the order perm (sorted by grid cell, so that neighbouring lanes
+// search the same cells).
 __global__ __launch_bounds__(256) void k_assign(const double* __restrict__ q,
                                                 const double* __restrict__ p, long long m,
+                                                const int* __restrict__ perm,
                                                 const double* __restrict__ cq,
                                                 const double* __restrict__ cp, Grid g,
                                                 const int* __restrict__ coff,
                                                 const int* __restrict__ clist,
                                                 int* __restrict__ assign) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const int i = perm[t];
   const double qi = q[i], pi = p[i];
   int cx, cy;
   grid_cell(g, qi, pi, &cx, &cy);
@@ -200,6 +251,14 @@ __global__ __launch_bounds__(256) void k_assign(const double* __restrict__ q,
   // every centre is binned, so the full square found one, unless every distance was NaN
   // (non-finite or zero-weight input): keep the index in range even then
   assign[i] = bi == 0x7fffffff ? 0 : bi;
+}
+
+__global__ void k_marker_cells(const double* __restrict__ q, const double* __restrict__ p,
+                               long long m, Grid g, int* __restrict__ cells) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int cx, cy;
+  cells[i] = grid_cell(g, q[i], p[i], &cx, &cy);
 }
 
 __global__ void k_group_count(const int* __restrict__ assign, long long m, int* __restrict__ cnt) {
@@ -371,6 +430,27 @@ hipError_t fill_int(int* p, long long n, int v, hipStream_t s) {
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Exclusive scan of n ints into out[0..n]; tmp holds 2 * (n / kScanTile + 2) ints.
+hipError_t scan_int(const int* in, int n, int* out, int* tmp, hipStream_t s) {
+  if (n <= kScanTile) {
+    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, in, n, out);
+    return hipGetLastError();
+  }
+  const int nt = (n + kScanTile - 1) / kScanTile;
+  int* sums = tmp;
+  int* toff = tmp + nt + 1;
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(nt), dim3(1024), 0, s, in, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, sums, nt, toff);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, in, n, toff, out);
+  return hipGetLastError();
+}
+
+// Ints of scan scratch for scans of up to n elements.
+long long scan_tmp_ints(long long n) { return 2 * (n / kScanTile + 2); }
+
 }  // namespace
 
 ClusterWs cluster_layout(long long m, int k) {
@@ -382,6 +462,7 @@ ClusterWs cluster_layout(long long m, int k) {
   w.assign = o;  o = a256(o + (size_t)m * sizeof(int));
   w.cnt = o;     o = a256(o + (size_t)k * sizeof(int));
   w.off = o;     o = a256(o + (size_t)(k + 1) * sizeof(int));
+  w.perm = o;    o = a256(o + (size_t)m * sizeof(int));
   w.keys_a = o;  o = a256(o + (size_t)m * sizeof(int));
   w.vals_a = o;  o = a256(o + (size_t)m * sizeof(int));
   w.keys_b = o;  o = a256(o + (size_t)m * sizeof(int));
@@ -401,6 +482,12 @@ ClusterWs cluster_layout(long long m, int k) {
   w.tpsi = o;    o = a256(o + (size_t)k * sizeof(double));
   w.flag = o;    o = a256(o + (size_t)k * sizeof(int));
   w.pos = o;     o = a256(o + (size_t)(k + 1) * sizeof(int));
+  {
+    long long nmax = 256 * radix_blocks(m);
+    if (nmax < k) nmax = k;
+    if (nmax < gmax) nmax = gmax;
+    w.scan = o;  o = a256(o + (size_t)scan_tmp_ints(nmax) * sizeof(int));
+  }
   w.total = o;
   return w;
 }
@@ -424,37 +511,50 @@ hipError_t cluster_p_range(const double* p, long long m, void* ws, const Cluster
   return hipStreamSynchronize(s);
 }
 
-// Group the markers by their assignment: counts and segment offsets per cluster, and the
-// marker indices sorted by cluster (stable, so in marker order within each cluster).
-static hipError_t group_markers(long long m, int k, const int* assign, int* cnt, int* off,
-                                int* keys_a, int* vals_a, int* keys_b, int* vals_b, int* hist,
-                                int* hoff, int** order_out, hipStream_t s) {
-  hipError_t e = fill_int(cnt, k, 0, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_group_count, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, cnt);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, cnt, k, off);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, keys_a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+// Stable sort of the marker indices 0..m-1 by keys (values below 2^bits) with 8-bit LSD
+// passes; keys_a holds the keys on entry (overwritten).  *out = the sorted indices (one of
+// vals_a / vals_b).
+static hipError_t sort_indices(long long m, int bits, int* keys_a, int* vals_a, int* keys_b,
+                               int* vals_b, int* hist, int* hoff, int* stmp, int** out,
+                               hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, vals_a, m);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int nb = (int)((m + kRadixChunk - 1) / kRadixChunk);
-  int bits = 1;
-  while (bits < 31 && (1LL << bits) < (long long)k) ++bits;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(256), 0, s, keys_a, m, shift, nb, hist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, hist, 256 * nb, hoff);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_int(hist, 256 * nb, hoff, stmp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(256), 0, s, keys_a, vals_a, m, shift, nb,
                        hoff, keys_b, vals_b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int* t = keys_a; keys_a = keys_b; keys_b = t;
     t = vals_a; vals_a = vals_b; vals_b = t;
   }
-  *order_out = vals_a;
+  *out = vals_a;
   return hipSuccess;
+}
+
+static int key_bits(long long nkeys) {
+  int bits = 1;
+  while (bits < 31 && (1LL << bits) < nkeys) ++bits;
+  return bits;
+}
+
+// Group the markers by their assignment: counts and segment offsets per cluster, and the
+// marker indices sorted by cluster (stable, so in marker order within each cluster).
+static hipError_t group_markers(long long m, int k, const int* assign, int* cnt, int* off,
+                                int* keys_a, int* vals_a, int* keys_b, int* vals_b, int* hist,
+                                int* hoff, int* stmp, int** order_out, hipStream_t s) {
+  hipError_t e = fill_int(cnt, k, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_group_count, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_int(cnt, k, off, stmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(m, 256)), dim3(256), 0, s, assign, m, keys_a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return sort_indices(m, key_bits(k), keys_a, vals_a, keys_b, vals_b, hist, hoff, stmp,
+                      order_out, s);
 }
 
 hipError_t cluster_run(const double* q, const double* p, const double* w, long long m, int k,
@@ -473,6 +573,7 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
   int* vals_b = reinterpret_cast<int*>(base + lay.vals_b);
   int* hist = reinterpret_cast<int*>(base + lay.hist);
   int* hoff = reinterpret_cast<int*>(base + lay.hoff);
+  int* stmp = reinterpret_cast<int*>(base + lay.scan);
   int* order = nullptr;
   int* cell_of = reinterpret_cast<int*>(base + lay.cell_of);
   int* ccnt = reinterpret_cast<int*>(base + lay.ccnt);
@@ -507,6 +608,19 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
   const int G = g.gx * g.gp;
 
   hipError_t e = hipSuccess;
+  // the markers in grid-cell order (the grid stays fixed): the assignment's visiting order
+  int* perm = reinterpret_cast<int*>(base + lay.perm);
+  {
+    hipLaunchKernelGGL(k_marker_cells, dim3(blocks_for(m, 256)), dim3(256), 0, s, q, p, m, g,
+                       keys_a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int* sorted = nullptr;
+    if ((e = sort_indices(m, key_bits(G), keys_a, vals_a, keys_b, vals_b, hist, hoff, stmp,
+                          &sorted, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(m, 256)), dim3(256), 0, s, sorted, m, perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_init_centres, dim3(blocks_for(k, 256)), dim3(256), 0, s, q, p, init_idx,
                      k, cq, cp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -517,17 +631,16 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
     hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(k, 256)), dim3(256), 0, s, cq, cp, k, g,
                        cell_of, ccnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, ccnt, G, coff);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_int(ccnt, G, coff, stmp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(k, 256)), dim3(256), 0, s, cell_of, k, coff,
                        ccur, clist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // assign, group
-    hipLaunchKernelGGL(k_assign, dim3(blocks_for(m, 256)), dim3(256), 0, s, q, p, m, cq, cp, g,
-                       coff, clist, assign);
+    hipLaunchKernelGGL(k_assign, dim3(blocks_for(m, 256)), dim3(256), 0, s, q, p, m, perm, cq,
+                       cp, g, coff, clist, assign);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = group_markers(m, k, assign, cnt, off, keys_a, vals_a, keys_b, vals_b, hist, hoff,
-                           &order, s)) != hipSuccess)
+                           stmp, &order, s)) != hipSuccess)
       return e;
     if (it < iters) {  // move the centres; the last pass only assigns
       hipLaunchKernelGGL(k_centres, dim3(blocks_for(k, 64)), dim3(64), 0, s, q, p, w, off, order,
@@ -538,8 +651,7 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
   hipLaunchKernelGGL(k_moments, dim3(blocks_for(k, 64)), dim3(64), 0, s, q, p, w, off, order, k,
                      L, tQ, tP, tqs, tps, tpsi, flag);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_int, dim3(1), dim3(1024), 0, s, flag, k, pos);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_int(flag, k, pos, stmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_compact, dim3(blocks_for(k, 256)), dim3(256), 0, s, flag, pos, k, tQ, tP,
                      tqs, tps, tpsi, Q, P, qs, ps, psi);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -124,8 +124,8 @@ inline long long radix_blocks(long long m) { return (m + kRadixChunk - 1) / kRad
 
 // Byte offsets of the regions of the caller's clustering workspace (256-byte aligned).
 struct ClusterWs {
-  size_t cq, cp, assign, cnt, off, keys_a, vals_a, keys_b, vals_b, hist, hoff, cell_of, ccnt,
-      coff, ccur, clist, mm, tQ, tP, tqs, tps, tpsi, flag, pos, total;
+  size_t cq, cp, assign, cnt, off, perm, keys_a, vals_a, keys_b, vals_b, hist, hoff, cell_of, ccnt,
+      coff, ccur, clist, mm, tQ, tP, tqs, tps, tpsi, flag, pos, scan, total;
 };
 ClusterWs cluster_layout(long long m, int k);
 // Velocity range of the markers (synchronises the stream).
