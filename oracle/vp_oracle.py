@@ -38,6 +38,11 @@ Functions and the passages they follow:
   curvature_at        -- phi_h''(Q_a) from any of the three projections
   kick_values, kick,
   drift               -- exact sub-flows of eq. sw-evolution split as above
+  external_field,
+  external_energy     -- a prescribed potential V(q) = A (1 - cos(kappa q)) added to the
+                         field (eq. sw_prescribed_potential, eq. swpic_test_particle), and
+                         its part of the Hamiltonian; `self_field=False` drops the particles'
+                         own field (charge e = 0, the paper's test-particle example)
   diagnostics         -- eq. Hh (discrete Hamiltonian), eq. Eamp, charge, momentum
   sort_perm           -- chunked stable counting sort by cell (a layout step of the
                          GPU path; its meaning is fixed here, not by the paper)
@@ -55,7 +60,8 @@ __all__ = [
     "inv_h", "cell_index", "deposit", "neutralize", "poisson_eigenvalues",
     "poisson_solve", "element_field", "projected_curvature", "mass_eigenvalues",
     "nodal_curvature", "curvature_at", "solve_field", "kick_values", "kick", "drift", "wrap",
-    "diagnostics", "sort_perm", "step", "run", "PROJECTIONS",
+    "diagnostics", "sort_perm", "step", "run", "PROJECTIONS", "external_field",
+    "external_energy",
 ]
 
 # Readings of the projection step for phi_h'': element-constant from the lumped projection
@@ -229,12 +235,44 @@ def kick_values(P, qs, ps, Ea, ga, tau: float):
     return P, qs
 
 
-def kick(Q, P, qs, ps, E, g, L: float, tau: float, projection: str = "elem"):
-    """Exact flow of H_field = (1/2) Phi^T A Phi for time tau with the mesh field:
-    Ea = E[i_a] read from the basis, ga = phi_h''(Q_a) from the projection."""
+def external_field(Q, L: float, ext):
+    """Field and curvature of the prescribed potential V(q) = A (1 - cos(kappa q)),
+    kappa = 2 pi m / L (ext = {"amp": A, "mode": m}): E = -V'(Q) = -(A kappa) sin(kappa Q),
+    phi'' = V''(Q) = (A kappa^2) cos(kappa Q)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    k = 2.0 * np.pi * ext["mode"] / L
+    ak = ext["amp"] * k
+    akk = ak * k
+    return -(ak * np.sin(k * Q)), akk * np.cos(k * Q)
+
+
+def external_energy(Q, ps, psi, L: float, ext):
+    """The prescribed potential's part of H_SWPIC: sum psi* V(Q) - p* V'(Q)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    k = 2.0 * np.pi * ext["mode"] / L
+    a = float(ext["amp"])
+    ak = a * k
+    return float(np.sum(np.asarray(psi) * (a * (1.0 - np.cos(k * Q)))
+                        - np.asarray(ps) * (ak * np.sin(k * Q))))
+
+
+def kick(Q, P, qs, ps, E, g, L: float, tau: float, projection: str = "elem", ext=None,
+         self_field: bool = True):
+    """Exact flow of the field part of the Hamiltonian for time tau with the mesh field:
+    Ea = E[i_a] read from the basis, ga = phi_h''(Q_a) from the projection; without the
+    self field these are zero; a prescribed potential adds its field and curvature."""
     ng = np.asarray(E).shape[0]
     i, _ = cell_index(Q, L, ng)
-    return kick_values(P, qs, ps, np.asarray(E)[i], curvature_at(Q, g, L, projection), tau)
+    Ea = np.asarray(E)[i]
+    ga = curvature_at(Q, g, L, projection)
+    if not self_field:
+        Ea = np.zeros_like(Ea)
+        ga = np.zeros_like(ga)
+    if ext is not None:
+        ee, ge = external_field(Q, L, ext)
+        Ea = Ea + ee
+        ga = ga + ge
+    return kick_values(P, qs, ps, Ea, ga, tau)
 
 
 def wrap(Qn, L: float):
@@ -257,10 +295,11 @@ def drift(Q, P, qs, ps, L: float, tau: float):
     return Qn, psn
 
 
-def diagnostics(P, qs, psi, fld, L: float):
-    """FP64 invariants: K, W, H (eq. Hh), charge, momentum, E_amp (eq. Eamp), E mode 1.
+def diagnostics(P, qs, psi, fld, L: float, Q=None, ps=None, ext=None, self_field: bool = True):
+    """FP64 invariants: K, W, U, H (eq. Hh), charge, momentum, E_amp (eq. Eamp), E mode 1.
 
-    K = sum psi* P^2 / 2 + q* P; W = (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2;
+    K = sum psi* P^2 / 2 + q* P; W = (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2 (zero without
+    the self field); U = the prescribed potential's energy (zero without one); H = K + U + W;
     momentum = sum (psi* P + q*) (first p-moment of the ansatz); charge = sum psi*;
     E_amp = sqrt((1/L) int E^2) = sqrt(2 W / L);
     E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng).
@@ -268,13 +307,14 @@ def diagnostics(P, qs, psi, fld, L: float):
     P = np.asarray(P, dtype=np.float64)
     qs = np.asarray(qs, dtype=np.float64)
     psi = np.asarray(psi, dtype=np.float64)
-    E = fld["E"]
+    E = fld["E"] if self_field else np.zeros_like(fld["E"])
     ng = E.shape[0]
     K = float(np.sum(0.5 * psi * P * P + qs * P))
-    W = float(fld["W"])
+    W = float(fld["W"]) if self_field else 0.0
+    U = external_energy(Q, ps, psi, L, ext) if ext is not None else 0.0
     e1 = np.sum(E * np.exp(-2j * np.pi * np.arange(ng) / ng)) / ng
     return {
-        "K": K, "W": W, "H": K + W,
+        "K": K, "W": W, "U": U, "H": K + U + W,
         "charge": float(np.sum(psi)),
         "momentum": float(np.sum(psi * P + qs)),
         "e_amp": float(np.sqrt(2.0 * W / L)),
@@ -294,26 +334,31 @@ def sort_perm(cells, chunk: int):
     return out
 
 
-def step(state, fld, L: float, ng: int, dt: float):
+def step(state, fld, L: float, ng: int, dt: float, ext=None, self_field: bool = True):
     """One kick(dt/2) - drift(dt) - [deposit, solve] - kick(dt/2) step."""
     Q, P, qs, ps, psi = state
     proj = fld.get("projection", "elem")
-    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj)
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj, ext, self_field)
     Q, ps = drift(Q, P, qs, ps, L, dt)
     fld = solve_field(Q, ps, psi, L, ng, proj)
-    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj)
+    P, qs = kick(Q, P, qs, ps, fld["E"], fld["g"], L, 0.5 * dt, proj, ext, self_field)
     return (Q, P, qs, ps, psi), fld
 
 
 def run(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, record=True,
-        projection: str = "elem"):
+        projection: str = "elem", ext=None, self_field: bool = True):
     """Run nsteps KDK steps from the given state.  Returns (state, field, history),
-    where history is a list of diagnostics dicts at t = 0, dt, ..., nsteps dt."""
+    where history is a list of diagnostics dicts at t = 0, dt, ..., nsteps dt.
+    ext = {"amp": A, "mode": m} adds the potential A (1 - cos(2 pi m q / L));
+    self_field=False drops the particles' own field (charge e = 0)."""
     state = tuple(np.asarray(a, dtype=np.float64).copy() for a in (Q, P, qs, ps, psi))
     fld = solve_field(state[0], state[3], state[4], L, ng, projection)
-    hist = [diagnostics(state[1], state[2], state[4], fld, L)] if record else []
+
+    def diag(st):
+        return diagnostics(st[1], st[2], st[4], fld, L, st[0], st[3], ext, self_field)
+    hist = [diag(state)] if record else []
     for _ in range(nsteps):
-        state, fld = step(state, fld, L, ng, dt)
+        state, fld = step(state, fld, L, ng, dt, ext, self_field)
         if record:
-            hist.append(diagnostics(state[1], state[2], state[4], fld, L))
+            hist.append(diag(state))
     return state, fld, hist

@@ -652,3 +652,63 @@ def test_bump_on_tail_root_value():
     Maxwellians is read correctly (the density of the bump sets the growth rate)."""
     om = PH.bump_on_tail_root(0.3)
     assert abs(om.real - 1.0012) < 2e-3 and abs(om.imag - 0.1981) < 2e-3, om
+
+
+# ---------------------------------------------------------------- prescribed potential
+def test_run_without_self_field_is_the_test_particle_system():
+    """O.run with a prescribed potential and no self field is exactly the splitting of
+    eq. swpic_test_particle (the hand-written field of the test above, bitwise), and its
+    H = K + U is the paper's H_SWPIC."""
+    L = 10.0
+    kappa = 2 * np.pi / L
+    st0 = ([2.0, 5.0, 8.0], [0.5, -0.3, 1.0], [0.1, -0.05, 0.02], [0.05, 0.1, -0.03],
+           [10.0, 10.0, 10.0])
+    dt, n = 0.05, 200
+    ref = _kdk_prescribed(st0, kappa, L, dt, n)
+    got, _, hist = O.run(*(np.array(a) for a in st0), L, 16, dt, n,
+                         ext={"amp": 1.0, "mode": 1}, self_field=False)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    Q, P, qs, ps, psi = ref
+    h_swpic = float(np.sum(0.5 * psi * P * P + P * qs + psi * (1 - np.cos(kappa * Q))
+                           - ps * kappa * np.sin(kappa * Q)))
+    assert abs(hist[-1]["H"] - h_swpic) < 1e-12 * abs(h_swpic)
+    assert hist[-1]["W"] == 0.0 and hist[-1]["e_amp"] == 0.0
+
+
+def test_external_energy_gradients_are_the_external_field():
+    """dU/dp*_a = -V'(Q_a) = E_ext(Q_a) and dU/dQ_a = psi*_a V'(Q_a) - p*_a V''(Q_a),
+    by central differences (U is smooth)."""
+    rng = np.random.default_rng(8)
+    L, ext = 7.0, {"amp": 0.7, "mode": 2}
+    Q = rng.uniform(0, L, 5)
+    ps = rng.normal(size=5) * 0.1
+    psi = rng.uniform(0.5, 1.5, 5)
+    E, g = O.external_field(Q, L, ext)
+    eps = 1e-6
+    for a in range(5):
+        d = np.zeros(5)
+        d[a] = eps
+        dU_dps = (O.external_energy(Q, ps + d, psi, L, ext)
+                  - O.external_energy(Q, ps - d, psi, L, ext)) / (2 * eps)
+        dU_dQ = (O.external_energy(Q + d, ps, psi, L, ext)
+                 - O.external_energy(Q - d, ps, psi, L, ext)) / (2 * eps)
+        assert abs(dU_dps - E[a]) < 1e-8
+        assert abs(dU_dQ - (psi[a] * (-E[a]) - ps[a] * g[a])) < 1e-7
+
+
+def test_energy_with_self_field_and_potential_is_bounded():
+    """Landau plasma in an added potential (self field on): H = K + U + W stays within a
+    band over 100 steps: 2e-4 in the PIC special case, 5e-3 with dipoles (whose P1 load
+    jumps at node crossings, R7); the potential does work (U of order H)."""
+    w = W.landau_linear(nx=64, nv=64, ng=64)
+    st = w.state()
+    ext = {"amp": 0.05, "mode": 1}
+    z = np.zeros_like(st["Q"])
+    for dip, bound in ((True, 5e-3), (False, 2e-4)):
+        qs, ps = (st["qs"], st["ps"]) if dip else (z, z)
+        _, _, hist = O.run(st["Q"], st["P"], qs, ps, st["psi"], w.L, w.ng, w.dt, 100, ext=ext)
+        H = np.array([h["H"] for h in hist])
+        U = np.array([h["U"] for h in hist])
+        assert np.max(np.abs(U)) > 0.05 * abs(H[0])
+        assert np.max(np.abs(H - H[0])) / abs(H[0]) < bound, dip
