@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 5
+#define VP_ABI_VERSION 6
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -86,6 +86,17 @@ typedef struct vp_config {
                             writes them (20 bytes of particle traffic per update instead of
                             36); the other calls carry the zeros through, and they stay zero.
                             0: decorated particles (default). */
+  int32_t no_self_field; /* 1: the particles feel no field of their own (charge e = 0; the
+                            paper's test-particle example, eq. swpic_test_particle): the load
+                            vector and its field are still computed and returned by
+                            vp_diagnostics' grid, but the kicks ignore them and W, E_amp and
+                            E1 read 0.  0: self-consistent field (default). */
+  int32_t ext_mode;      /* prescribed potential V(q) = ext_amplitude (1 - cos(2 pi ext_mode
+                            q / L)) added to the field (eq. sw_prescribed_potential): the kick
+                            takes E - V'(Q) and phi'' + V''(Q), and U = sum psi* V(Q) -
+                            p* V'(Q) enters H.  ext_mode >= 1 with ext_amplitude != 0 turns it
+                            on; 0 (default): none. */
+  double ext_amplitude;
 } vp_config;
 
 /* The dipole equation d(q*)/dt = p* phi_h''(Q) needs a second derivative that a P1 potential
@@ -125,12 +136,14 @@ typedef struct vp_diag {
   double t;         /* step * dt */
   double K;         /* sum psi* P^2 / 2 + q* P  (kinetic part of eq. Hh)          */
   double W;         /* (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2 (field part of eq. Hh) */
-  double H;         /* K + W */
+  double H;         /* K + U + W */
   double charge;    /* sum psi* */
   double momentum;  /* sum psi* P + q* */
   double e_amp;     /* sqrt((1/L) int E^2) (eq. Eamp) = sqrt(2 W / L) */
   double e1_re;     /* (1/Ng) sum_e E_e exp(-2 pi i e / Ng), real part */
   double e1_im;     /*   ... imaginary part */
+  double U;         /* prescribed potential's energy sum psi* V(Q) - p* V'(Q) (0 without one);
+                       H = K + U + W */
 } vp_diag;
 
 /* Launch shape of the particle kernels; chosen by vp_tune or set by the caller. */

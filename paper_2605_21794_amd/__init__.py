@@ -43,13 +43,17 @@ PROJECTIONS = {"elem": L.VP_PROJ_ELEM, "nodal": L.VP_PROJ_NODAL,
 
 
 def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096,
-                solver="scan", projection="elem", monopole_only=False):
+                solver="scan", projection="elem", monopole_only=False, self_field=True,
+                external=None):
     return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
                        dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
                        hist_cap=int(hist_cap),
                        solver=SOLVERS[solver] if isinstance(solver, str) else int(solver),
                        projection=PROJECTIONS[projection] if isinstance(projection, str)
-                       else int(projection), monopole_only=1 if monopole_only else 0)
+                       else int(projection), monopole_only=1 if monopole_only else 0,
+                       no_self_field=0 if self_field else 1,
+                       ext_mode=int(external["mode"]) if external else 0,
+                       ext_amplitude=float(external["amp"]) if external else 0.0)
 
 
 def workspace_bytes(cfg) -> int:
@@ -135,10 +139,12 @@ class Engine:
 
     def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
               sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem",
-              monopole_only: bool = False):
+              monopole_only: bool = False, self_field: bool = True, external=None):
         """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`.
         monopole_only: plain particle-in-cell particles (p* = q* = 0; qs, ps may be left out
-        of `state`, and are zeroed on admission)."""
+        of `state`, and are zeroed on admission).  self_field=False: the particles feel no
+        field of their own (charge e = 0).  external = {"amp": A, "mode": m}: the prescribed
+        potential A (1 - cos(2 pi m q / L))."""
         t = self._torch
         tens = {k: self._tensor(state[k]) for k in FIELDS if k in state}
         if monopole_only:
@@ -152,7 +158,7 @@ class Engine:
         if any(int(v.numel()) != n for v in tens.values()):
             raise ValueError("state arrays differ in length")
         cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver,
-                          projection, monopole_only)
+                          projection, monopole_only, self_field, external)
         ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
@@ -296,7 +302,8 @@ class Simulation(Engine):
 
     def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
                  sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
-                 stream=None, solver="scan", projection="elem", monopole_only=False):
+                 stream=None, solver="scan", projection="elem", monopole_only=False,
+                 self_field=True, external=None):
         super().__init__(precision, 1, device, stream)
         self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection,
-                   monopole_only)
+                   monopole_only, self_field, external)

@@ -66,6 +66,10 @@ vp_status validate(const vp_config* c) {
     return fail(VP_ERR_ARG, "bad projection %d", c->projection);
   if (c->monopole_only != 0 && c->monopole_only != 1)
     return fail(VP_ERR_ARG, "monopole_only must be 0 or 1");
+  if (c->no_self_field != 0 && c->no_self_field != 1)
+    return fail(VP_ERR_ARG, "no_self_field must be 0 or 1");
+  if (c->ext_mode < 0 || !std::isfinite(c->ext_amplitude))
+    return fail(VP_ERR_ARG, "ext_mode must be >= 0 and ext_amplitude finite");
   return VP_OK;
 }
 
@@ -97,6 +101,7 @@ struct vp_handle {
   size_t tiles_cap = 0;
   int ntiles = 0;
   int ntiles_dip = 0;      // tiles of decorated instances (they come first)
+  int group_end[4] = {0, 0, 0, 0};  // tile ranges by kind: decorated / monopole-only x fast / general
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
@@ -135,13 +140,18 @@ vp_status rebuild_tables(vp_handle* h) {
   h->max_ng = VP_MIN_NG;
   for (int s = 0; s < h->max_slots; ++s)
     if (h->slots[s].used) h->h_occ.push_back(s);
-  // tiles of decorated instances first, then those of monopole-only ones: one fused launch
-  // per kind and step
+  // tiles grouped by kind, one fused launch per non-empty group and step: decorated then
+  // monopole-only instances, each without then with general options
+  auto group_of = [&](int s) {
+    const InstDev& d = h->h_inst[s];
+    return (h->slots[s].cfg.monopole_only ? 2 : 0) + (d.general ? 1 : 0);
+  };
   std::vector<int> order;
-  for (int pass = 0; pass < 2; ++pass)
+  for (int gi = 0; gi < 4; ++gi)
     for (int s : h->h_occ)
-      if ((h->slots[s].cfg.monopole_only != 0) == (pass == 1)) order.push_back(s);
+      if (group_of(s) == gi) order.push_back(s);
   h->ntiles_dip = 0;
+  for (int gi = 0; gi < 4; ++gi) h->group_end[gi] = 0;
   for (int s : order) {
     Slot& sl = h->slots[s];
     h->max_ng = std::max(h->max_ng, sl.cfg.ng);
@@ -162,6 +172,7 @@ vp_status rebuild_tables(vp_handle* h) {
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
+    for (int gi = group_of(s); gi < 4; ++gi) h->group_end[gi] += nt;
   }
   h->ntiles = (int)h->h_tiles.size();
   h->any_fft = false;
@@ -197,16 +208,21 @@ vp_status check_slot(const vp_handle* h, int slot) {
 
 int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
 
-// One fused step of every instance in phase ph: a launch over the decorated instances'
-// tiles and one over the monopole-only instances' tiles (either may be empty).
+// One fused step of every instance in phase ph: one launch per non-empty group of tiles
+// (decorated / monopole-only instances, without / with general options).
 hipError_t fused_step(vp_handle* h, int ph) {
-  hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, 0,
-                                   h->ntiles_dip, h->tun.ppt, h->max_ng, h->any_fft, ph, true,
-                                   h->stream);
-  if (e != hipSuccess) return e;
-  return vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles, h->ntiles_dip,
-                           h->ntiles - h->ntiles_dip, h->tun.ppt, h->max_ng, h->any_fft, ph,
-                           false, h->stream);
+  int b = 0;
+  for (int gi = 0; gi < 4; ++gi) {
+    const int e_ = h->group_end[gi];
+    if (e_ > b) {
+      const hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles,
+                                             b, e_ - b, h->tun.ppt, h->max_ng, h->any_fft, ph,
+                                             gi < 2, (gi & 1) != 0, h->stream);
+      if (e != hipSuccess) return e;
+    }
+    b = e_;
+  }
+  return hipSuccess;
 }
 
 vp_status launch_steps_direct(vp_handle* h, int nsteps) {
@@ -321,10 +337,12 @@ void to_diag(const double* r, vp_diag* o) {
   o->e_amp = r[7];
   o->e1_re = r[8];
   o->e1_im = r[9];
+  o->U = r[10];
 }
 
 bool diag_finite(const vp_diag& d) {
-  return std::isfinite(d.K) && std::isfinite(d.W) && std::isfinite(d.H) && std::isfinite(d.charge) &&
+  return std::isfinite(d.K) && std::isfinite(d.W) && std::isfinite(d.U) && std::isfinite(d.H) &&
+         std::isfinite(d.charge) &&
          std::isfinite(d.momentum) && std::isfinite(d.e_amp) && std::isfinite(d.e1_re) &&
          std::isfinite(d.e1_im);
 }
@@ -422,6 +440,13 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.inv_lam = reinterpret_cast<double*>(ws + w.inv_lam);
   d.cw = reinterpret_cast<double*>(ws + w.cw);
   d.proj = cfg->projection;
+  d.self_on = cfg->no_self_field ? 0 : 1;
+  d.ext_on = (cfg->ext_mode >= 1 && cfg->ext_amplitude != 0.0) ? 1 : 0;
+  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on) ? 1 : 0;
+  d.ext_a = cfg->ext_amplitude;
+  d.ext_k = 6.283185307179586 * (double)cfg->ext_mode / cfg->L;  // 2 pi m / L
+  d.ext_ak = d.ext_a * d.ext_k;
+  d.ext_akk = d.ext_ak * d.ext_k;
   d.scal = reinterpret_cast<vpk::InstScal*>(ws + w.scal);
   d.hist = reinterpret_cast<double*>(ws + w.hist);
   d.kin = reinterpret_cast<double*>(ws + w.kin);
@@ -664,14 +689,16 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   host_out->step = sc.step;
   host_out->t = (double)sc.step * sl.cfg.dt;
   const int p = h->phase;
+  const bool self = !sl.cfg.no_self_field;  // without a field of their own: W, E_amp, E1 are 0
   host_out->K = sc.Kd;
-  host_out->W = sc.W[p];
-  host_out->H = sc.Kd + sc.W[p];
+  host_out->U = sc.Ud;
+  host_out->W = self ? sc.W[p] : 0.0;
+  host_out->H = sc.Kd + sc.Ud + host_out->W;
   host_out->charge = sc.chgd;
   host_out->momentum = sc.momd;
-  host_out->e_amp = std::sqrt(2.0 * sc.W[p] / sl.cfg.L);
-  host_out->e1_re = sc.e1r[p];
-  host_out->e1_im = sc.e1i[p];
+  host_out->e_amp = std::sqrt(2.0 * host_out->W / sl.cfg.L);
+  host_out->e1_re = self ? sc.e1r[p] : 0.0;
+  host_out->e1_im = self ? sc.e1i[p] : 0.0;
   if (sc.timeout) return fail(VP_ERR_HIP, "slot %d: a persistent step's wait for its tiles timed out", slot);
   if (!diag_finite(*host_out) || sc.nonfinite)
     return fail(VP_ERR_NONFINITE, "slot %d: non-finite diagnostics at step %lld", slot, sc.step);

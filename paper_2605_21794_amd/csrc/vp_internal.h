@@ -9,8 +9,8 @@
 namespace vpk {
 
 constexpr int kBlock = 256;      // threads per workgroup for every particle kernel
-constexpr int kHistFields = 10;  // doubles per diagnostic record (layout of vp_diag)
-constexpr int kKinFields = 4;    // per-tile kinetic sums: K, momentum, charge, (unused)
+constexpr int kHistFields = 11;  // doubles per diagnostic record (layout of vp_diag)
+constexpr int kKinFields = 4;    // per-tile sums: K, momentum, charge, prescribed-potential U
 constexpr int kMinTile = 256;    // fewest particles per tile (256 threads x 1 particle)
 
 enum Mode { kFP64 = 0, kFP32Comp = 1, kFP32 = 2, kFP32TwoSum = 3 };
@@ -31,7 +31,7 @@ constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
   double W[kRing], e1r[kRing], e1i[kRing];  // summary of the field solved from ring entry r
-  double Kd, momd, chgd;                    // partial sums of the diagnostic kernel
+  double Kd, momd, chgd, Ud;                // partial sums of the diagnostic kernel
   long long step;                           // integer step of the state (fused path)
   int pend[kRing];                          // 1 when P, q* owe the half-kick with the field of entry r
   int nonfinite;                            // set when a diagnostic came out NaN or Inf
@@ -67,6 +67,11 @@ struct InstDev {
   double* kin;      // kRing x kin_cap x kKinFields per-tile kinetic sums of phase r's pass
   int kin_cap;      // tiles the kinetic-sum ring can hold (ceil(n / 256))
   int proj;         // vp_projection
+  int general;      // any of: a nodal projection, no self field, a prescribed potential
+  int self_on;      // the particles feel their own field
+  int ext_on;       // a prescribed potential acts
+  int pad2_;
+  double ext_a, ext_k, ext_ak, ext_akk;  // A, kappa = 2 pi m / L, A kappa, A kappa^2
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.
@@ -88,10 +93,11 @@ int kin_capacity(long long n);
 size_t particle_lds_bytes(int mode, int max_ng);
 
 // `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS);
-// `dipoles` false when every tile of the launch is of a monopole-only instance.
+// `dipoles` false when every tile of the launch is of a monopole-only instance; `general`
+// true when some instance of the launch has general options (InstDev::general).
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        hipStream_t s);
+                        bool general, hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,

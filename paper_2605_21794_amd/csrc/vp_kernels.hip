@@ -121,6 +121,26 @@ __device__ __forceinline__ float curv_at_f(int proj, const F* g, int i, float x,
   return (1.0f - s) * gi + s * (float)g[(i + 1) & (ng - 1)];
 }
 
+// The field on a particle of an instance with general options (d.general): the mesh field
+// and the projection's curvature when the particles feel their own field (else zero), plus
+// the prescribed potential's field -V'(Q) and curvature V''(Q); U gets psi* V(Q) - p* V'(Q)
+// of the particle (integer-step Q and p*).  Float64, in the plain definition's order.
+template <typename F>
+__device__ __forceinline__ void general_field(const InstDev& d, const F* fE, const F* fG, int i,
+                                              double x, double Q, double psi, double ps,
+                                              double& Ei, double& gi, double& U) {
+  Ei = d.self_on ? (double)fE[i] : 0.0;
+  gi = d.self_on ? curv_at(d.proj, fG, i, x, d.ng) : 0.0;
+  U = 0.0;
+  if (d.ext_on) {
+    const double ph = d.ext_k * Q;
+    const double sn = sin(ph), cs = cos(ph);
+    Ei = Ei - d.ext_ak * sn;
+    gi = gi + d.ext_akk * cs;
+    U = psi * (d.ext_a * (1.0 - cs)) - ps * (d.ext_ak * sn);
+  }
+}
+
 // Deterministic workgroup sum: fixed shuffle tree per wave, then the wave totals in order.
 // `red` holds at least TPB/64 doubles.  Every thread of the workgroup must call it.
 template <int TPB>
@@ -316,8 +336,8 @@ constexpr int kSolveThreads = 256;
 constexpr int kSolveWaves = kSolveThreads / 64;
 constexpr int kSolvePer = VP_MAX_NG / kSolveThreads;
 // LDS doubles for the solve's wave totals: mean | scan carries | gauge sums | W | Re E1 |
-// Im E1 | K | momentum | charge
-constexpr int kSolveRed = 9 * kSolveWaves;
+// Im E1 | K | momentum | charge | U
+constexpr int kSolveRed = 10 * kSolveWaves;
 
 __device__ __forceinline__ int ring_next(int r) { return r == kRing - 1 ? 0 : r + 1; }
 __device__ __forceinline__ int ring_prev(int r) { return r == 0 ? kRing - 1 : r - 1; }
@@ -337,33 +357,32 @@ struct SolveIn {
   double b[kSolvePer];
   double c[kSolvePer];
   double s[kSolvePer];
-  double kin[3];  // this thread's share of the previous pass's per-tile kinetic sums
+  double kin[kKinFields];  // this thread's share of the previous pass's per-tile sums
 };
 
 // Sum over tiles t = tid, tid + kSolveThreads, ... (in that order) of the per-tile kinetic
 // sums of ring entry r, four tiles' loads in flight at a time.
-template <bool DEV>
-__device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[3]) {
-  kin[0] = kin[1] = kin[2] = 0.0;
+// NF = 3 leaves out the prescribed-potential sums (launches without general options).
+template <bool DEV, int NF = kKinFields>
+__device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[kKinFields]) {
+  kin[0] = kin[1] = kin[2] = kin[3] = 0.0;
   VPG double* base = gp(d.kin) + (size_t)r * d.kin_cap * kKinFields;
   for (int t0 = threadIdx.x; t0 < d.ntiles; t0 += 4 * kSolveThreads) {
-    double v[4][3];
+    double v[4][kKinFields];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = t0 + u * kSolveThreads;
-      v[u][0] = v[u][1] = v[u][2] = 0.0;
+#pragma unroll
+      for (int f = 0; f < kKinFields; ++f) v[u][f] = 0.0;
       if (t < d.ntiles) {
-        v[u][0] = ldx<DEV>(base + (size_t)t * kKinFields);
-        v[u][1] = ldx<DEV>(base + (size_t)t * kKinFields + 1);
-        v[u][2] = ldx<DEV>(base + (size_t)t * kKinFields + 2);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[u][f] = ldx<DEV>(base + (size_t)t * kKinFields + f);
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      kin[0] += v[u][0];
-      kin[1] += v[u][1];
-      kin[2] += v[u][2];
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) kin[f] += v[u][f];
   }
 }
 
@@ -422,20 +441,20 @@ __device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, 
 // Issue the solve's loads (load vector of ring entry r; with want_sum also the Fourier
 // weights and the kinetic sums of the previous pass, ring entry r-1): all of them before
 // any use, so they overlap other work of the caller.
-template <int MODE, bool DEV = false>
+template <int MODE, bool DEV = false, bool GEN = true>
 __device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_sum, SolveIn& in) {
   const int ng = d.ng, tid = threadIdx.x;
   const int per = solve_per(ng), j0 = tid * per;
 #pragma unroll
   for (int k = 0; k < kSolvePer; ++k) in.b[k] = in.c[k] = in.s[k] = 0.0;
-  in.kin[0] = in.kin[1] = in.kin[2] = 0.0;
+  in.kin[0] = in.kin[1] = in.kin[2] = in.kin[3] = 0.0;
   if (tid >= kSolveThreads) return;
   if (j0 < ng) {
     if (per == 1) solve_load_per<MODE, 1, DEV>(d, r, j0, want_sum, in);
     else if (per == 2) solve_load_per<MODE, 2, DEV>(d, r, j0, want_sum, in);
     else solve_load_per<MODE, kSolvePer, DEV>(d, r, j0, want_sum, in);
   }
-  if (want_sum) load_kin<DEV>(d, ring_prev(r), in.kin);  // after the grid loads: waits overlap
+  if (want_sum) load_kin<DEV, GEN ? kKinFields : 3>(d, ring_prev(r), in.kin);  // waits overlap
 }
 
 // Sum of one value per solving thread (fixed DPP tree, then the wave totals in order),
@@ -457,12 +476,12 @@ __device__ __forceinline__ double solve_total(const double* red, int slot) {
 //   g_e  = -(b~_e + b~_{e+1}) / (2h): the lumped L2 projection of E onto P1, differentiated;
 //   phi  (only when `phi` is given): nodal potential, zero mean;
 // and, with want_sum, sum[0..2] = W = (1/2) h sum_e E_e^2 and
-// E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng), sum[3..5] = K, momentum, charge of the previous
-// pass (its per-tile sums in tile order), in every thread.
+// E1 = (1/Ng) sum_e E_e exp(-2 pi i e / Ng), sum[3..6] = K, momentum, charge, U of the
+// previous pass (its per-tile sums in tile order), in every thread.
 // `fft` is LDS scratch of 3 Ng doubles (FFT solver only).  All threads of the workgroup call
 // it (it holds workgroup barriers; want_sum must be uniform); on return bt, E, g (and phi)
 // are visible to all threads.
-template <int TPB>
+template <int TPB, bool GEN = true>
 __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum, double* bt,
                               double* E, double* g, double* red, double* fft, double* phi,
                               double* sum) {
@@ -482,6 +501,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
       solve_wave_total(in.kin[0], red, 6);
       solve_wave_total(in.kin[1], red, 7);
       solve_wave_total(in.kin[2], red, 8);
+      if constexpr (GEN) solve_wave_total(in.kin[3], red, 9);
     }
   }
   if (use_fft) {  // twiddles for the wavefront FFT
@@ -593,6 +613,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     sum[3] = solve_total(red, 6);
     sum[4] = solve_total(red, 7);
     sum[5] = solve_total(red, 8);
+    sum[6] = GEN ? solve_total(red, 9) : 0.0;
   }
   if (d.proj == VP_PROJ_ELEM) {
     const double half_inv_h = 0.5 * d.inv_h;
@@ -645,22 +666,24 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
   __syncthreads();
 }
 
-// Record of integer step `step` (kinetic sums of that step's pass, field summary of its
-// field) into the history ring; flags non-finite values.  One thread.
+// Record of integer step `step` (kinetic and potential sums of that step's pass, field
+// summary of its field) into the history ring; flags non-finite values.  One thread.
 __device__ void write_record(const InstDev& d, long long step, double K, double mom, double chg,
-                             double W, double e1r, double e1i) {
+                             double U, double W, double e1r, double e1i) {
+  if (!d.self_on) W = e1r = e1i = 0.0;  // no field of their own acts on the particles
   VPG double* r = gp(d.hist) + (size_t)(step % d.hist_cap) * kHistFields;
   r[0] = (double)step;
   r[1] = (double)step * d.dt;
   r[2] = K;
   r[3] = W;
-  r[4] = K + W;
+  r[4] = K + U + W;
   r[5] = chg;
   r[6] = mom;
   r[7] = sqrt(2.0 * W / d.L);
   r[8] = e1r;
   r[9] = e1i;
-  if (!isfinite(K) || !isfinite(W)) gp(d.scal)->nonfinite = 1;
+  r[10] = U;
+  if (!isfinite(K) || !isfinite(W) || !isfinite(U)) gp(d.scal)->nonfinite = 1;
 }
 
 // ------------------------------------------------------------------ particle passes
@@ -685,11 +708,11 @@ __device__ void write_record(const InstDev& d, long long step, double K, double 
 // float64 modes compute in float64 from the stored values in the oracle's operation order.
 // DIP = false: a monopole-only particle (p* = q* = 0, plain P1 particle-in-cell): the dipole
 // terms are left out, which gives the same values as carrying zeros through them.
-template <int MODE, typename T, bool DIP = true>
+template <int MODE, typename T, bool DIP = true, bool GEN = true>
 __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
                                               double* sacc, int pend, T& Qr, T& Pr, T& qsr,
                                               T& psr, const T psir, double& Ks, double& Ms,
-                                              double& Cs) {
+                                              double& Cs, double& Us) {
   const int ng = d.ng;
   if constexpr (MODE == kFP32) {
     float* fa = reinterpret_cast<float*>(sacc);
@@ -698,9 +721,19 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const float psi = psir;
     const float xq = Q * ihf;
     const int i = cell_of_f(xq, ng);
-    const float Ei = (float)fE[i];
+    float Ei, gi;
+    if (!GEN || !d.general) {
+      Ei = (float)fE[i];
+      gi = DIP ? (float)fG[i] : 0.0f;
+    } else {
+      double e, g, u;
+      general_field(d, fE, fG, i, (double)Q * d.inv_h, (double)Q, (double)psi, (double)ps, e, g,
+                    u);
+      Ei = (float)e;
+      gi = (float)g;
+      Us += u;
+    }
     if constexpr (DIP) {
-      const float gi = curv_at_f(d.proj, fG, i, xq, ng);
       if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
       const double Pd = P, qd = qs, wd = psi;
       Ks += 0.5 * wd * Pd * Pd + qd * Pd;
@@ -738,9 +771,16 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     double P = Pr, qs = qsr, ps = psr;
     const double xq = Q * inv_h;
     const int i = cell_of(xq, ng);
-    const double Ei = fE[i];
+    double Ei, gi;
+    if (!GEN || !d.general) {
+      Ei = fE[i];
+      gi = DIP ? fG[i] : 0.0;
+    } else {
+      double u;
+      general_field(d, fE, fG, i, xq, Q, psi, ps, Ei, gi, u);
+      Us += u;
+    }
     if constexpr (DIP) {
-      const double gi = curv_at(d.proj, fG, i, xq, ng);
       if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
       Ks += 0.5 * psi * P * P + qs * P;
       Ms += psi * P + qs;
@@ -797,12 +837,14 @@ __host__ __device__ constexpr int group_of() { return (MODE == kFP64 && TPB == 1
 
 // DIP = false: every tile of the launch belongs to a monopole-only instance; p* and q* are
 // neither read nor written (20 bytes of particle traffic per update instead of 36).
-template <int MODE, int TPB, bool DIP>
+// GEN = false: no instance of the launch has general options (d.general), so the field on a
+// particle is read straight from the mesh arrays.
+template <int MODE, int TPB, bool DIP, bool GEN>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
                                                int ppt, int phase) {
   extern __shared__ double smem[];
-  __shared__ double red[3 * (TPB / 64)];
+  __shared__ double red[4 * (TPB / 64)];
   __shared__ double sred[kSolveRed];
   using T = typename StateType<MODE>::T;
   constexpr int kGroup = group_of<MODE, TPB>();
@@ -854,7 +896,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   Group g;
   load_group(0, g);
   SolveIn sin_;
-  solve_load<MODE>(d, r0, first, sin_);
+  solve_load<MODE, false, GEN>(d, r0, first, sin_);
   for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
   const int pend = sc->pend[r0];
   // the first tile records the previous step (if it was a fused step of this instance):
@@ -867,10 +909,10 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     rec[1] = sc->e1r[r2];
     rec[2] = sc->e1i[r2];
   }
-  double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+  double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
   {
-    double sum[6];
-    solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+    double sum[7];
+    solve_compute<TPB, GEN>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
     if (first) {
       const int copies = d.acc_copies;
       for (int c = 0; c < copies; ++c)
@@ -882,7 +924,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         }
       if (threadIdx.x == 0) {
         if (pend && step >= 1)
-          write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
+          write_record(d, step - 1, sum[3], sum[4], sum[5], sum[6], rec[0], rec[1], rec[2]);
         sc->W[r0] = sum[0];
         sc->e1r[r0] = sum[1];
         sc->e1i[r0] = sum[2];
@@ -898,7 +940,8 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     for (int u = 0; u < kGroup; ++u) {
       if (!g.v[u]) continue;
       T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
-      push_particle<MODE, T, DIP>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs);
+      push_particle<MODE, T, DIP, GEN>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs,
+                                       Us);
       ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P);
       if constexpr (DIP) { ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps); }
     }
@@ -916,23 +959,27 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   Ks = wave_sum(Ks);
   Ms = wave_sum(Ms);
   Cs = wave_sum(Cs);
+  if constexpr (GEN) Us = wave_sum(Us);
   if (lane == 0) {
-    red[3 * wid] = Ks;
-    red[3 * wid + 1] = Ms;
-    red[3 * wid + 2] = Cs;
+    red[4 * wid] = Ks;
+    red[4 * wid + 1] = Ms;
+    red[4 * wid + 2] = Cs;
+    if constexpr (GEN) red[4 * wid + 3] = Us;
   }
   __syncthreads();  // also completes every LDS deposit of the workgroup
   if (threadIdx.x == 0) {
-    double kb = 0.0, mb = 0.0, cbs = 0.0;
+    double kb = 0.0, mb = 0.0, cbs = 0.0, ub = 0.0;
     for (int w = 0; w < TPB / 64; ++w) {
-      kb += red[3 * w];
-      mb += red[3 * w + 1];
-      cbs += red[3 * w + 2];
+      kb += red[4 * w];
+      mb += red[4 * w + 1];
+      cbs += red[4 * w + 2];
+      if constexpr (GEN) ub += red[4 * w + 3];
     }
     VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
     slot[0] = kb;
     slot[1] = mb;
     slot[2] = cbs;
+    if constexpr (GEN) slot[3] = ub;  // else it stays zero (no potential in this instance)
   }
   flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
 }
@@ -955,7 +1002,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
                                                  const Tile* __restrict__ tiles, int phase0,
                                                  int nsteps) {
   extern __shared__ double smem[];
-  __shared__ double red[3 * (TPB / 64)];
+  __shared__ double red[4 * (TPB / 64)];
   __shared__ double sred[kSolveRed];
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[blockIdx.x];
@@ -1020,9 +1067,9 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     SolveIn sin_;
     solve_load<MODE, true>(d, r0, first, sin_);
     for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
-    double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+    double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
     {
-      double sum[6];
+      double sum[7];
       solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
       if (first) {
         const int copies = d.acc_copies;
@@ -1035,7 +1082,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
           }
         if (threadIdx.x == 0) {
           if (pend && step >= 1)
-            write_record(d, step - 1, sum[3], sum[4], sum[5], rec[0], rec[1], rec[2]);
+            write_record(d, step - 1, sum[3], sum[4], sum[5], sum[6], rec[0], rec[1], rec[2]);
           sc->W[r0] = sum[0];
           sc->e1r[r0] = sum[1];
           sc->e1i[r0] = sum[2];
@@ -1051,30 +1098,35 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
-      if (v[u]) push_particle<MODE>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u], w[u], Ks, Ms, Cs);
+      if (v[u])
+        push_particle<MODE>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u], w[u], Ks, Ms, Cs, Us);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Ks = wave_sum(Ks);
     Ms = wave_sum(Ms);
     Cs = wave_sum(Cs);
+    Us = wave_sum(Us);
     if (lane == 0) {
-      red[3 * wid] = Ks;
-      red[3 * wid + 1] = Ms;
-      red[3 * wid + 2] = Cs;
+      red[4 * wid] = Ks;
+      red[4 * wid + 1] = Ms;
+      red[4 * wid + 2] = Cs;
+      red[4 * wid + 3] = Us;
     }
     __syncthreads();  // also completes every LDS deposit of the workgroup
     if (threadIdx.x == 0) {
-      double kb = 0.0, mb = 0.0, cbs = 0.0;
+      double kb = 0.0, mb = 0.0, cbs = 0.0, ub = 0.0;
       for (int ww = 0; ww < TPB / 64; ++ww) {
-        kb += red[3 * ww];
-        mb += red[3 * ww + 1];
-        cbs += red[3 * ww + 2];
+        kb += red[4 * ww];
+        mb += red[4 * ww + 1];
+        cbs += red[4 * ww + 2];
+        ub += red[4 * ww + 3];
       }
       VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
       gst(slot, kb);
       gst(slot + 1, mb);
       gst(slot + 2, cbs);
+      gst(slot + 3, ub);
     }
     flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
     if (st + 1 < nsteps) {
@@ -1189,8 +1241,18 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
       float Q = q[u], P = p[u], qs = a[u], ps = b[u];
       const float xq = Q * ihf;
       const int i = cell_of_f(xq, ng);
-      P = P + kf * fE[i];
-      qs = qs + kf * ps * curv_at_f(d.proj, fG, i, xq, ng);
+      float Ei, gi;
+      if (!d.general) {
+        Ei = fE[i];
+        gi = fG[i];
+      } else {
+        double e, g, uu;
+        general_field(d, fE, fG, i, (double)Q * d.inv_h, (double)Q, 0.0, 0.0, e, g, uu);
+        Ei = (float)e;
+        gi = (float)g;
+      }
+      P = P + kf * Ei;
+      qs = qs + kf * ps * gi;
       float Qn = Q + df * P;
       if (Qn < 0.0f) Qn += Lf;
       if (Qn >= Lf) Qn -= Lf;
@@ -1213,8 +1275,16 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
       double P = p[u], qs = a[u], ps = b[u];
       const double xq = Q * inv_h;
       const int i = cell_of(xq, ng);
-      P = P + kick * smem[i];
-      qs = qs + kick * ps * curv_at(d.proj, smem + ng, i, xq, ng);
+      double Ei, gi;
+      if (!d.general) {
+        Ei = smem[i];
+        gi = smem[ng + i];
+      } else {
+        double uu;
+        general_field(d, smem, smem + ng, i, xq, (double)Q, 0.0, 0.0, Ei, gi, uu);
+      }
+      P = P + kick * Ei;
+      qs = qs + kick * ps * gi;
       double Qn = Q + drift * P;
       if (Qn < 0.0) Qn += L;
       if (Qn >= L) Qn -= L;
@@ -1245,7 +1315,7 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   const VPG T* __restrict__ psp = gp<T>(d.ps);
   const VPG T* __restrict__ psip = gp<T>(d.psi);
   const int pend = gp(d.scal)->pend[phase];
-  double Ks = 0.0, Ms = 0.0, Cs = 0.0;
+  double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
   if constexpr (MODE == kFP32) {
     const float* fE = reinterpret_cast<const float*>(smem);
     const float* fG = fE + ng;
@@ -1256,11 +1326,23 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
       if (!v[u]) continue;
       const float Q = Qp[idx[u]], psi = psip[idx[u]], ps = psp[idx[u]];
       float P = Pp[idx[u]], qs = qsp[idx[u]];
+      const float xq = Q * ihf;
+      const int i = cell_of_f(xq, ng);
+      float Ei, gi;
+      if (!d.general) {
+        Ei = fE[i];
+        gi = fG[i];
+      } else {
+        double e, g, uu;
+        general_field(d, fE, fG, i, (double)Q * d.inv_h, (double)Q, (double)psi, (double)ps, e,
+                      g, uu);
+        Ei = (float)e;
+        gi = (float)g;
+        Us += uu;
+      }
       if (pend) {
-        const float xq = Q * ihf;
-        const int i = cell_of_f(xq, ng);
-        P = P + hf * fE[i];
-        qs = qs + hf * ps * curv_at_f(d.proj, fG, i, xq, ng);
+        P = P + hf * Ei;
+        qs = qs + hf * ps * gi;
       }
       const double Pd = P, qd = qs, wd = psi;
       Ks += 0.5 * wd * Pd * Pd + qd * Pd;
@@ -1276,11 +1358,20 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
       if (!v[u]) continue;
       const double Q = Qp[idx[u]], psi = psip[idx[u]], ps = psp[idx[u]];
       double P = Pp[idx[u]], qs = qsp[idx[u]];
+      const double xq = Q * inv_h;
+      const int i = cell_of(xq, ng);
+      double Ei, gi;
+      if (!d.general) {
+        Ei = smem[i];
+        gi = smem[ng + i];
+      } else {
+        double uu;
+        general_field(d, smem, smem + ng, i, xq, Q, psi, ps, Ei, gi, uu);
+        Us += uu;
+      }
       if (pend) {
-        const double xq = Q * inv_h;
-        const int i = cell_of(xq, ng);
-        P = P + half * smem[i];
-        qs = qs + half * ps * curv_at(d.proj, smem + ng, i, xq, ng);
+        P = P + half * Ei;
+        qs = qs + half * ps * gi;
       }
       Ks += 0.5 * psi * P * P + qs * P;
       Ms += psi * P + qs;
@@ -1291,11 +1382,13 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
   const double Kb = block_sum<TPB>(Ks, red);
   const double Mb = block_sum<TPB>(Ms, red);
   const double Cb = block_sum<TPB>(Cs, red);
+  const double Ub = block_sum<TPB>(Us, red);
   if (threadIdx.x == 0) {
     VPG InstScal* sc = gp(d.scal);
     gadd(&sc->Kd, Kb);
     gadd(&sc->momd, Mb);
     gadd(&sc->chgd, Cb);
+    gadd(&sc->Ud, Ub);
   }
 }
 
@@ -1317,7 +1410,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(const InstDev* __restri
   double* fft = smem + 4 * ng;
   SolveIn sin_;
   solve_load<MODE>(d, phase, true, sin_);
-  double sum[6];
+  double sum[7];
   solve_compute<kSolveThreads>(d, sin_, true, bt, fE, fG, sred, fft, phi, sum);
   VPG double* bt_g = gp(d.bt);
   VPG double* E_g = gp(d.E);
@@ -1338,7 +1431,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(const InstDev* __restri
     VPG InstScal* sc = gp(d.scal);
     const int r2 = ring_prev(phase);
     if (sc->pend[phase] && sc->step >= 1)
-      write_record(d, sc->step - 1, sum[3], sum[4], sum[5], sc->W[r2], sc->e1r[r2], sc->e1i[r2]);
+      write_record(d, sc->step - 1, sum[3], sum[4], sum[5], sum[6], sc->W[r2], sc->e1r[r2],
+                   sc->e1i[r2]);
     sc->W[phase] = sum[0];
     sc->e1r[phase] = sum[1];
     sc->e1i[phase] = sum[2];
@@ -1373,8 +1467,8 @@ __global__ __launch_bounds__(256) void k_ring(const InstDev* __restrict__ insts,
     // thread 0 adds the 256 partial sums in thread order (fixed order, deterministic).
     __shared__ double part[256];
     VPG double* kin = gp(d.kin);
-    for (int rf = 0; rf < kRing * 3; ++rf) {
-      const int r = rf / 3, f = rf % 3;
+    for (int rf = 0; rf < kRing * kKinFields; ++rf) {
+      const int r = rf / kKinFields, f = rf % kKinFields;
       VPG double* base = kin + (size_t)r * d.kin_cap * kKinFields + f;
       double acc_t = 0.0;
       for (int t = threadIdx.x; t < d.kin_cap; t += 256) acc_t += base[(size_t)t * kKinFields];
@@ -1399,6 +1493,7 @@ __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __r
   VPG InstScal* sc = gp(insts[slots[t]].scal);
   if (op == kScalClearDiag) {
     sc->Kd = 0.0;
+    sc->Ud = 0.0;
     sc->momd = 0.0;
     sc->chgd = 0.0;
   } else if (op == kScalClearPending) {
@@ -1569,17 +1664,21 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
 
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        hipStream_t s) {
+                        bool general, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
+#define VP_FUSED_K(M, TB, D, G)                                                              \
+  hipLaunchKernelGGL((k_fused<M, TB, D, G>), dim3(ntiles), dim3(TB), lds, s, d_inst, d_tiles, \
+                     tile0, ppt, phase)
 #define VP_FUSED(M, TB)                                                                      \
   do {                                                                                       \
-    if (dipoles)                                                                             \
-      hipLaunchKernelGGL((k_fused<M, TB, true>), dim3(ntiles), dim3(TB), lds, s, d_inst,     \
-                         d_tiles, tile0, ppt, phase);                                        \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_fused<M, TB, false>), dim3(ntiles), dim3(TB), lds, s, d_inst,    \
-                         d_tiles, tile0, ppt, phase);                                        \
+    if (dipoles) {                                                                           \
+      if (general) VP_FUSED_K(M, TB, true, true);                                            \
+      else VP_FUSED_K(M, TB, true, false);                                                   \
+    } else {                                                                                 \
+      if (general) VP_FUSED_K(M, TB, false, true);                                           \
+      else VP_FUSED_K(M, TB, false, false);                                                  \
+    }                                                                                        \
   } while (0)
 #define VP_FUSED_TPB(M)                                                                      \
   do {                                                                                       \
@@ -1593,6 +1692,7 @@ hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_
   else VP_FUSED_TPB(kFP32);
 #undef VP_FUSED_TPB
 #undef VP_FUSED
+#undef VP_FUSED_K
   return hipGetLastError();
 }
 

@@ -48,7 +48,8 @@ def test_workspace_sizing_and_validation(lib):
     bad = [dict(ng=12), dict(ng=4), dict(ng=2048), dict(n=0), dict(L=-1.0), dict(dt=0.0),
            dict(precision=7), dict(sort_chunk=5000), dict(hist_cap=0), dict(solver=2),
            dict(L=float("nan")), dict(sort_every=-2), dict(projection=3),
-           dict(projection=-1), dict(monopole_only=2)]
+           dict(projection=-1), dict(monopole_only=2), dict(no_self_field=3), dict(ext_mode=-1),
+           dict(ext_mode=1, ext_amplitude=float("inf"))]
     for kw in bad:
         args = dict(n=1000, ng=64, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
         args.update(kw)
@@ -69,4 +70,4 @@ def test_null_handles_rejected(lib):
     assert lib.vp_deposit(None) == L.VP_ERR_ARG
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
-    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 5
+    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 6
