@@ -324,9 +324,10 @@ def run_served(args):
         capacity = len(base) / sat["wall_s"]
         log(f"served: capacity {capacity:.1f} jobs/s ({sat['updates_per_s']:.3g} updates/s)")
         loads = [float(x) for x in args.loads.split(",")]
-        # the largest job holds about 21 MB and a full engine of the mix about 0.3 GB, so a
-        # cap of 128 MiB makes jobs queue for bytes where the whole device never does
-        cap_bytes = int((args.budget_gib or 0.125) * (1 << 30))
+        # the largest job holds about 21.5 MB, and at these loads about 30 MB of the mix is
+        # resident on average, so a cap of 32 MiB makes jobs queue for bytes where the whole
+        # device never does
+        cap_bytes = int((args.budget_gib or 1.0 / 32) * (1 << 30))
         head = None
         for budget, tag in ((cap_bytes, f"{cap_bytes / (1 << 30):g} GiB"), (full_budget, "device")):
             for f in loads:
@@ -685,7 +686,7 @@ def main():
     ap.add_argument("--slots", type=int, default=64, help="served: engine slots")
     ap.add_argument("--chunk", type=int, default=33, help="served: steps between decisions")
     ap.add_argument("--budget-gib", type=float, default=None,
-                    help="served: device bytes cap (default: 0.125 GiB for the capped runs)")
+                    help="served: device bytes cap (default: 1/32 GiB for the capped runs)")
     ap.add_argument("--launch", default=None,
                     help="threads,ppt,acc_copies[,persistent] of the fused step (with --no-tune)")
     ap.add_argument("--copy-calibration", action="store_true")
