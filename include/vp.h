@@ -217,8 +217,9 @@ vp_status vp_deposit(vp_handle* h);
 vp_status vp_poisson(vp_handle* h);
 
 /* Exact sub-flows of the splitting with the current field (eq. sw-evolution):
- * kick:  P += kick * E[i],  q* += kick * p* * phi_h''(Q)   (Q, p* frozen; phi_h''(Q) per
- *        cfg.projection),
+ * kick:  P += kick * E_a,  q* += kick * p* * g_a   (Q, p* frozen), where E_a = E[i] and
+ *        g_a = phi_h''(Q) per cfg.projection (both 0 with cfg.no_self_field), plus
+ *        -V'(Q) and V''(Q) of a prescribed potential (cfg.ext_mode),
  * drift: Q += drift * P (periodic wrap into [0, L)),  p* -= drift * q*   (P, q* frozen).
  * Requires |drift * P| < L.  After vp_step it first writes the field of the current
  * positions (as vp_poisson); a drift makes the load vector stale until vp_deposit (which
@@ -258,7 +259,8 @@ vp_status vp_cell_index(vp_handle* h, int32_t slot, int32_t* dev_cells);
 
 /* Synchronises the stream.  Diagnostics of one slot at its current integer step (a
  * pending half-kick is accounted for without modifying the state).  host_grid, if
- * non-NULL, receives 4*Ng float64 values: b~, Phi, E, g of the current field.
+ * non-NULL, receives 4*Ng float64 values: b~, Phi, E, g of the particles' own mesh field
+ * (also when cfg.no_self_field keeps it from acting).
  * Returns VP_ERR_NONFINITE (after filling *host_out) if any value is NaN or Inf. */
 vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* host_grid);
 
@@ -308,8 +310,9 @@ vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* 
  *          (eq. moment-def with the periodic c).
  * All sums run over the members in increasing marker order, so results are reproducible.
  * Inputs (device, float64, 8-byte aligned, not modified): Qm in [0, L), Pm, wm > 0, m of
- * each; init_idx: k distinct marker indices in [0, m) (device int32; checked on the host,
- * VP_ERR_ARG if out of range).  1 <= k <= m < 2^31, iters >= 0, L > 0.
+ * each; init_idx: k marker indices in [0, m) (device int32; checked on the host,
+ * VP_ERR_ARG if out of range; normally distinct, as a repeated index starts a centre that
+ * the lower-numbered twin always wins, so it stays empty).  1 <= k <= m < 2^31, iters >= 0, L > 0.
  * workspace: vp_cluster_workspace_bytes(m, k) bytes of device memory, 256-byte aligned.
  * Outputs (device, float64, capacity k each): Q, P, qs (q*), ps (p*), psi of the non-empty
  * clusters; assign_out (device int32, m, or NULL): final cluster of each marker;
