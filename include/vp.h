@@ -311,8 +311,8 @@ vp_status vp_slot_status(vp_handle* h, int32_t n, int64_t* host_steps, int32_t* 
  * All sums run over the members in increasing marker order, so results are reproducible.
  * Inputs (device, float64, 8-byte aligned, not modified): Qm in [0, L), Pm, wm > 0, m of
  * each; init_idx: k marker indices in [0, m) (device int32; checked on the host,
- * VP_ERR_ARG if out of range; normally distinct, as a repeated index starts a centre that
- * the lower-numbered twin always wins, so it stays empty).  1 <= k <= m < 2^31, iters >= 0, L > 0.
+ * VP_ERR_ARG if out of range; normally distinct: a repeated index starts two centres at
+ * one place, and the higher-numbered one gets no markers in the first assignment).  1 <= k <= m < 2^31, iters >= 0, L > 0.
  * workspace: vp_cluster_workspace_bytes(m, k) bytes of device memory, 256-byte aligned.
  * Outputs (device, float64, capacity k each): Q, P, qs (q*), ps (p*), psi of the non-empty
  * clusters; assign_out (device int32, m, or NULL): final cluster of each marker;
