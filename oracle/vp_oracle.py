@@ -44,6 +44,8 @@ Functions and the passages they follow:
                          its part of the Hamiltonian; `self_field=False` drops the particles'
                          own field (charge e = 0, the paper's test-particle example)
   diagnostics         -- eq. Hh (discrete Hamiltonian), eq. Eamp, charge, momentum
+  deposit_p2 ... run_p2 -- the same cycle with P2 elements (degree-2 Lagrange basis,
+                         assembled stiffness, exact phi_h''), from their definitions
   sort_perm           -- chunked stable counting sort by cell (a layout step of the
                          GPU path; its meaning is fixed here, not by the paper)
   run                 -- the whole cycle, one field solve per step
@@ -61,7 +63,8 @@ __all__ = [
     "poisson_solve", "element_field", "projected_curvature", "mass_eigenvalues",
     "nodal_curvature", "curvature_at", "solve_field", "kick_values", "kick", "drift", "wrap",
     "diagnostics", "sort_perm", "step", "run", "PROJECTIONS", "external_field",
-    "external_energy",
+    "external_energy", "p2_basis", "deposit_p2", "p2_node_weights", "neutralize_p2",
+    "p2_stiffness", "poisson_solve_p2", "field_p2", "solve_field_p2", "kick_p2", "run_p2",
 ]
 
 # Readings of the projection step for phi_h'': element-constant from the lumped projection
@@ -361,4 +364,143 @@ def run(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, record=Tru
         state, fld = step(state, fld, L, ng, dt, ext, self_field)
         if record:
             hist.append(diag(state))
+    return state, fld, hist
+
+
+# ---------------------------------------------------------------- P2 elements
+# Degree-2 Lagrange elements on the same uniform periodic mesh (the paper's finite elements
+# of degree k, here k = 2): on element e, local coordinate s in [0, 1), the three basis
+# functions are N0 = (1 - s)(1 - 2s) at vertex e, N1 = 4 s (1 - s) at the midpoint and
+# N2 = s (2s - 1) at vertex e+1.  Unknowns: Ng vertex values and Ng midpoint values.
+# Everything below follows the definitions: the load vector of eq. rhs-assembly against
+# these functions, the stiffness matrix assembled element by element, a solve of the
+# assembled system with the zero-mean gauge, the field -phi_h' read from the basis, and
+# phi_h'' read from the basis too (it exists for P2, so no projection is needed).
+
+def p2_basis(s):
+    """(N0, N1, N2) and their s-derivatives at local coordinate s."""
+    s = np.asarray(s, dtype=np.float64)
+    N = ((1.0 - s) * (1.0 - 2.0 * s), 4.0 * s * (1.0 - s), s * (2.0 * s - 1.0))
+    dN = (4.0 * s - 3.0, 4.0 - 8.0 * s, 4.0 * s - 1.0)
+    return N, dN
+
+
+def deposit_p2(Q, ps, psi, L: float, ng: int):
+    """P2 load vector: b_k = sum_a psi*_a phi_k(Q_a) - p*_a phi_k'(Q_a); returns (vertex
+    loads, midpoint loads), Ng each."""
+    ps = np.asarray(ps, dtype=np.float64)
+    psi = np.asarray(psi, dtype=np.float64)
+    i, s = cell_index(Q, L, ng)
+    ih = inv_h(L, ng)
+    N, dN = p2_basis(s)
+    bv = np.bincount(i, weights=psi * N[0] - ps * (dN[0] * ih), minlength=ng)
+    bv = bv + np.bincount((i + 1) % ng, weights=psi * N[2] - ps * (dN[2] * ih), minlength=ng)
+    bm = np.bincount(i, weights=psi * N[1] - ps * (dN[1] * ih), minlength=ng)
+    return bv, bm
+
+
+def p2_node_weights(L: float, ng: int):
+    """Integrals of the basis functions: h/3 for a vertex function, 2h/3 for a midpoint."""
+    h = float(L) / ng
+    return h / 3.0, 2.0 * h / 3.0
+
+
+def neutralize_p2(bv, bm, L: float, ng: int):
+    """Subtract the uniform background n0 = sum(b) / L against each basis function."""
+    wv, wm = p2_node_weights(L, ng)
+    n0 = (np.sum(bv) + np.sum(bm)) / float(L)
+    return np.asarray(bv) - n0 * wv, np.asarray(bm) - n0 * wm
+
+
+def p2_stiffness(L: float, ng: int):
+    """Assembled periodic P2 stiffness matrix over the unknowns ordered
+    (v_0, m_0, v_1, m_1, ...): element matrix (1/3h) [[7, -8, 1], [-8, 16, -8], [1, -8, 7]]."""
+    h = float(L) / ng
+    n = 2 * ng
+    K = np.array([[7.0, -8.0, 1.0], [-8.0, 16.0, -8.0], [1.0, -8.0, 7.0]]) / (3.0 * h)
+    A = np.zeros((n, n))
+    for e in range(ng):
+        idx = (2 * e, 2 * e + 1, (2 * e + 2) % n)
+        for a in range(3):
+            for b in range(3):
+                A[idx[a], idx[b]] += K[a, b]
+    return A
+
+
+_P2_SOLVERS = {}
+
+
+def poisson_solve_p2(btv, btm, L: float):
+    """A Phi = b~ with the gauge integral(phi_h) = 0 (sum_k w_k Phi_k = 0), by the bordered
+    system [[A, w], [w^T, 0]] (inverted once per mesh).  Returns (vertex, midpoint) Phi."""
+    btv = np.asarray(btv, dtype=np.float64)
+    ng = btv.shape[0]
+    key = (float(L), ng)
+    if key not in _P2_SOLVERS:
+        A = p2_stiffness(L, ng)
+        wv, wm = p2_node_weights(L, ng)
+        w = np.tile([wv, wm], ng)
+        B = np.zeros((2 * ng + 1, 2 * ng + 1))
+        B[:2 * ng, :2 * ng] = A
+        B[:2 * ng, 2 * ng] = w
+        B[2 * ng, :2 * ng] = w
+        _P2_SOLVERS[key] = np.linalg.inv(B)
+    rhs = np.zeros(2 * ng + 1)
+    rhs[0:2 * ng:2] = btv
+    rhs[1:2 * ng:2] = btm
+    x = _P2_SOLVERS[key] @ rhs
+    return x[0:2 * ng:2], x[1:2 * ng:2]
+
+
+def field_p2(Phv, Phm, L: float):
+    """On element e: E(s) = -phi_h'(s) = E0_e + s E1_e from the basis derivatives, and
+    phi_h'' = g_e (constant on the element)."""
+    Phv = np.asarray(Phv, dtype=np.float64)
+    Phm = np.asarray(Phm, dtype=np.float64)
+    ng = Phv.shape[0]
+    ih = inv_h(L, ng)
+    Pn = np.roll(Phv, -1)
+    # -phi' = -(Phi_e N0'(s) + Phi_m N1'(s) + Phi_{e+1} N2'(s)) / h
+    E0 = -(-3.0 * Phv + 4.0 * Phm - 1.0 * Pn) * ih
+    E1 = -(4.0 * Phv - 8.0 * Phm + 4.0 * Pn) * ih
+    g = (4.0 * Phv - 8.0 * Phm + 4.0 * Pn) * ih * ih
+    return E0, E1, g
+
+
+def solve_field_p2(Q, ps, psi, L: float, ng: int):
+    """P2 counterpart of solve_field: dict with bv, bm (loads), btv, btm, Phv, Phm, E0, E1,
+    g, the element-average field E (= E0 + E1 / 2) and W = (1/2) Phi^T A Phi."""
+    bv, bm = deposit_p2(Q, ps, psi, L, ng)
+    btv, btm = neutralize_p2(bv, bm, L, ng)
+    Phv, Phm = poisson_solve_p2(btv, btm, L)
+    E0, E1, g = field_p2(Phv, Phm, L)
+    phi = np.empty(2 * ng)
+    phi[0::2] = Phv
+    phi[1::2] = Phm
+    W = 0.5 * float(phi @ (p2_stiffness(L, ng) @ phi))
+    return {"bv": bv, "bm": bm, "btv": btv, "btm": btm, "Phv": Phv, "Phm": Phm, "E0": E0,
+            "E1": E1, "g": g, "E": E0 + 0.5 * E1, "W": W, "order": 2}
+
+
+def kick_p2(Q, P, qs, ps, fld, L: float, tau: float):
+    """Exact flow of the field part with the P2 field: E(Q) from the basis, phi_h''(Q)."""
+    ng = fld["E0"].shape[0]
+    i, s = cell_index(Q, L, ng)
+    return kick_values(P, qs, ps, fld["E0"][i] + s * fld["E1"][i], fld["g"][i], tau)
+
+
+def run_p2(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int):
+    """KDK run with P2 elements; history as run() (E1 and E_amp from the element-average
+    field and W)."""
+    state = tuple(np.asarray(a, dtype=np.float64).copy() for a in (Q, P, qs, ps, psi))
+    fld = solve_field_p2(state[0], state[3], state[4], L, ng)
+    hist = [diagnostics(state[1], state[2], state[4], fld, L)]
+    for _ in range(nsteps):
+        Q, P, qs, ps, psi = state
+        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt)
+        Q, ps = drift(Q, P, qs, ps, L, dt)
+        fld = solve_field_p2(Q, ps, psi, L, ng)
+        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt)
+        state = (Q, P, qs, ps, psi)
+        hist.append(diagnostics(state[1], state[2], state[4], fld, L))
     return state, fld, hist

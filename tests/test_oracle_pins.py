@@ -712,3 +712,122 @@ def test_energy_with_self_field_and_potential_is_bounded():
         U = np.array([h["U"] for h in hist])
         assert np.max(np.abs(U)) > 0.05 * abs(H[0])
         assert np.max(np.abs(H - H[0])) / abs(H[0]) < bound, dip
+
+
+# ---------------------------------------------------------------- P2 elements
+def _p2_fn(x, kind, j, L, ng):
+    """Periodic P2 basis function from its definition: the vertex function of node j is
+    (1 - s)(1 - 2s) on element j and s(2s - 1) on element j - 1; the midpoint function of
+    element j is 4 s (1 - s) on element j; zero elsewhere."""
+    h = L / ng
+    x = np.asarray(x, dtype=np.float64) % L
+    e = np.floor(x / h).astype(int) % ng
+    s = x / h - np.floor(x / h)
+    if kind == "v":
+        return np.where(e == j, (1 - s) * (1 - 2 * s),
+                        np.where(e == (j - 1) % ng, s * (2 * s - 1), 0.0))
+    return np.where(e == j, 4 * s * (1 - s), 0.0)
+
+
+def _p2_slope(x, kind, j, L, ng, d=1e-7):
+    return (_p2_fn(x + d, kind, j, L, ng) - _p2_fn(x - d, kind, j, L, ng)) / (2 * d)
+
+
+def test_p2_deposit_brute_force():
+    rng = np.random.default_rng(21)
+    L, ng = 3.0, 6
+    Q, _, _, ps, psi = _rand_particles(rng, 40, L, ng)
+    bv, bm = O.deposit_p2(Q, ps, psi, L, ng)
+    for j in range(ng):
+        rv = sum(psi[a] * _p2_fn(Q[a], "v", j, L, ng) - ps[a] * _p2_slope(Q[a], "v", j, L, ng)
+                 for a in range(Q.size))
+        rm = sum(psi[a] * _p2_fn(Q[a], "m", j, L, ng) - ps[a] * _p2_slope(Q[a], "m", j, L, ng)
+                 for a in range(Q.size))
+        assert abs(bv[j] - rv) < 1e-6 and abs(bm[j] - rm) < 1e-6
+    assert abs(bv.sum() + bm.sum() - psi.sum()) < 1e-12 * psi.sum()   # the basis sums to one
+
+
+def test_p2_stiffness_by_quadrature():
+    """A_kl = integral of phi_k' phi_l' (3-point Gauss-Legendre per element on slopes of the
+    brute-force basis) equals the assembled element matrices."""
+    L, ng = 2.0, 5
+    h = L / ng
+    xg, wg = np.polynomial.legendre.leggauss(3)
+    fns = [("v", j) for j in range(ng)] + [("m", j) for j in range(ng)]
+    A = O.p2_stiffness(L, ng)
+    order = lambda kind, j: 2 * j + (0 if kind == "v" else 1)  # noqa: E731
+    for ka, ja in fns:
+        for kb, jb in fns:
+            tot = 0.0
+            for e in range(ng):
+                x = e * h + 0.5 * h * (xg + 1)
+                tot += np.sum(0.5 * h * wg * _p2_slope(x, ka, ja, L, ng) * _p2_slope(x, kb, jb, L, ng))
+            assert abs(A[order(ka, ja), order(kb, jb)] - tot) < 1e-5 / h
+
+
+def test_p2_monopole_is_exact_at_vertices_and_energy_identity():
+    """Theorem 1 for degree 2: one monopole's Galerkin potential equals the continuous
+    periodic solution at the vertices up to the gauge constant; and W = (1/2) Phi^T A Phi
+    equals (1/2) integral of E^2 with E from the basis."""
+    L, ng = 1.0, 16
+    h = L / ng
+    for Q in (0.31 * L, 0.5 * L + 0.2 * h):
+        f = O.solve_field_p2(np.array([Q]), np.zeros(1), np.ones(1), L, ng)
+        v = np.arange(ng) * h
+        r = (v - Q) % L
+        G = r * r / (2 * L) - r / 2 + L / 12
+        d = f["Phv"] - G
+        assert np.ptp(d) < 1e-12
+        xg, wg = np.polynomial.legendre.leggauss(4)
+        s = 0.5 * (xg + 1)
+        WE = 0.5 * sum(np.sum(0.5 * wg * h * (f["E0"][e] + s * f["E1"][e]) ** 2) for e in range(ng))
+        assert abs(WE - f["W"]) < 1e-12 * f["W"]
+
+
+def test_p2_smooth_solution_converges_at_third_order():
+    """For the load of rho - n0 = a cos(kx) (by quadrature against the basis) the P2
+    potential approaches (a / k^2) cos(kx) in L2 as h^3, and its exact second derivative
+    tracks -a cos(kx) at second order."""
+    L, a = 2 * np.pi, 0.4
+    errs, gerrs = [], []
+    for ng in (8, 16, 32):
+        h = L / ng
+        xg, wg = np.polynomial.legendre.leggauss(6)
+        bv, bm = np.zeros(ng), np.zeros(ng)
+        for e in range(ng):
+            x = e * h + 0.5 * h * (xg + 1)
+            s = 0.5 * (xg + 1)
+            N, _ = O.p2_basis(s)
+            rho = a * np.cos(x)
+            bv[e] += np.sum(0.5 * h * wg * rho * N[0])
+            bv[(e + 1) % ng] += np.sum(0.5 * h * wg * rho * N[2])
+            bm[e] += np.sum(0.5 * h * wg * rho * N[1])
+        Phv, Phm = O.poisson_solve_p2(bv, bm, L)
+        err2 = 0.0
+        for e in range(ng):
+            x = e * h + 0.5 * h * (xg + 1)
+            s = 0.5 * (xg + 1)
+            N, _ = O.p2_basis(s)
+            ph = Phv[e] * N[0] + Phm[e] * N[1] + Phv[(e + 1) % ng] * N[2]
+            err2 += np.sum(0.5 * h * wg * (ph - a * np.cos(x)) ** 2)
+        errs.append(math.sqrt(err2))
+        # phi_h'' (exact for P2, constant per element) tracks phi'' = -a cos(x)
+        _, _, g = O.field_p2(Phv, Phm, L)
+        xm = (np.arange(ng) + 0.5) * h
+        gerrs.append(np.max(np.abs(g + a * np.cos(xm))))
+    assert 7.0 < errs[0] / errs[1] < 9.0 and 7.0 < errs[1] / errs[2] < 9.0, errs
+    assert gerrs[2] < 0.01 * a and gerrs[1] / gerrs[2] > 3.5, gerrs
+
+
+def test_p2_field_energy_of_the_landau_lattice_converges():
+    """With several particles per element across x, the P2 field energy of the linear
+    Landau state approaches (1/2)(alpha/k)^2 L/2; with one particle column per element the
+    midpoint unknowns resolve the particles' discreteness and the energy is far off."""
+    exact = 0.5 * (0.01 / 0.5) ** 2 * (4 * np.pi) / 2
+    w = W.landau_linear(nx=1024, nv=64, ng=64)
+    st = w.state()
+    f = O.solve_field_p2(st["Q"], st["ps"], st["psi"], w.L, w.ng)
+    assert abs(f["W"] - exact) < 1e-3 * exact
+    w = W.landau_linear(nx=64, nv=64, ng=64)
+    st = w.state()
+    assert O.solve_field_p2(st["Q"], st["ps"], st["psi"], w.L, w.ng)["W"] > 5 * exact
