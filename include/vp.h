@@ -3,8 +3,8 @@
  *
  * The library advances decorated particles of the Scovel-Weinstein monopole-dipole model
  * (k = 2) for the normalised 1D1V periodic Vlasov-Poisson system (e = m = eps0 = 1) as
- * discretised in Section 5 of arXiv 2605.21794: P1 continuous-Galerkin potential on a
- * uniform periodic mesh of Ng elements over [0, L), load vector of eq. rhs-assembly,
+ * discretised in Section 5 of arXiv 2605.21794: P1 (or P2) continuous-Galerkin potential on
+ * a uniform periodic mesh of Ng elements over [0, L), load vector of eq. rhs-assembly,
  * stiffness system of eq. lin-sys with the zero-mean gauge, equations of motion of
  * eq. sw-evolution, advanced by the kick-drift-kick splitting of the discrete Hamiltonian
  * of eq. Hh.  Each particle carries (Q, P, q*, p*, psi*): position, velocity, momentum
@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 6
+#define VP_ABI_VERSION 7
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -97,6 +97,16 @@ typedef struct vp_config {
                             p* V'(Q) enters H.  ext_mode >= 1 with ext_amplitude != 0 turns it
                             on; 0 (default): none. */
   double ext_amplitude;
+  int32_t element_order; /* degree k of the Lagrange space V_h^(k) of eq. galerkin.  1 (or 0, the
+                            default): P1, one node per element.  2: continuous P2, a vertex and
+                            a midpoint node per element; the load vector is taken against the
+                            quadratic basis, the stiffness system is solved with the gauge
+                            integral(phi_h) = 0 (eq. galerkin), E = -phi_h' is linear on each
+                            element and phi_h'' is read from the basis itself (constant per
+                            element, so cfg.projection must be VP_PROJ_ELEM and plays no
+                            part).  P2 needs a precision other than VP_FP32 and is not run by
+                            persistent tuning. */
+  int32_t reserved_;     /* 0 */
 } vp_config;
 
 /* The dipole equation d(q*)/dt = p* phi_h''(Q) needs a second derivative that a P1 potential
@@ -213,7 +223,14 @@ vp_status vp_deposit(vp_handle* h);
  * sum_e E_e = 0, or an in-LDS FFT, per cfg.solver), element field
  * E_e = -(Phi_{e+1} - Phi_e)/h, projected curvature g (per element or per node, per
  * cfg.projection), W = (1/2) sum h E_e^2.  Writes the field arrays that vp_gather_push and
- * vp_diagnostics read.  One workgroup per instance. */
+ * vp_diagnostics read.  One workgroup per instance.
+ * P2 elements (cfg.element_order = 2): b~ subtracts the background against each basis
+ * function's integral (h/3 at a vertex, 2h/3 at a midpoint).  Eliminating each element's
+ * midpoint unknown leaves the P1 system above with the load c_e = b~_e + (b~_{m,e-1} +
+ * b~_{m,e})/2, solved as above; its E_e is the field at the midpoint of element e, the
+ * field on the element is E_e - h g_e (s - 1/2) at local coordinate s, g_e = phi_h'' =
+ * -3 b~_{m,e} / (2h), W = (1/2) sum h E_e^2 + (3h/32) sum b~_{m,e}^2, and the midpoint
+ * potential is (3h b~_{m,e} + 8 (Phi_e + Phi_{e+1})) / 16. */
 vp_status vp_poisson(vp_handle* h);
 
 /* Exact sub-flows of the splitting with the current field (eq. sw-evolution):
@@ -260,7 +277,9 @@ vp_status vp_cell_index(vp_handle* h, int32_t slot, int32_t* dev_cells);
 /* Synchronises the stream.  Diagnostics of one slot at its current integer step (a
  * pending half-kick is accounted for without modifying the state).  host_grid, if
  * non-NULL, receives 4*Ng float64 values: b~, Phi, E, g of the particles' own mesh field
- * (also when cfg.no_self_field keeps it from acting).
+ * (also when cfg.no_self_field keeps it from acting).  With P2 elements it receives 6*Ng:
+ * b~ of the Ng vertices then of the Ng midpoints, Phi likewise (gauge integral(phi_h) = 0),
+ * E_e at each element's midpoint (the element average of the linear field), g_e.
  * Returns VP_ERR_NONFINITE (after filling *host_out) if any value is NaN or Inf. */
 vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* host_grid);
 

@@ -482,25 +482,40 @@ def solve_field_p2(Q, ps, psi, L: float, ng: int):
             "E1": E1, "g": g, "E": E0 + 0.5 * E1, "W": W, "order": 2}
 
 
-def kick_p2(Q, P, qs, ps, fld, L: float, tau: float):
-    """Exact flow of the field part with the P2 field: E(Q) from the basis, phi_h''(Q)."""
+def kick_p2(Q, P, qs, ps, fld, L: float, tau: float, ext=None, self_field: bool = True):
+    """Exact flow of the field part with the P2 field: E(Q) from the basis, phi_h''(Q);
+    without the self field these are zero, and a prescribed potential adds its own (as in
+    kick)."""
     ng = fld["E0"].shape[0]
     i, s = cell_index(Q, L, ng)
-    return kick_values(P, qs, ps, fld["E0"][i] + s * fld["E1"][i], fld["g"][i], tau)
+    Ea = fld["E0"][i] + s * fld["E1"][i]
+    ga = fld["g"][i]
+    if not self_field:
+        Ea = np.zeros_like(Ea)
+        ga = np.zeros_like(ga)
+    if ext is not None:
+        ee, ge = external_field(Q, L, ext)
+        Ea = Ea + ee
+        ga = ga + ge
+    return kick_values(P, qs, ps, Ea, ga, tau)
 
 
-def run_p2(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int):
+def run_p2(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, ext=None,
+           self_field: bool = True):
     """KDK run with P2 elements; history as run() (E1 and E_amp from the element-average
-    field and W)."""
+    field and W); ext and self_field as in run()."""
     state = tuple(np.asarray(a, dtype=np.float64).copy() for a in (Q, P, qs, ps, psi))
     fld = solve_field_p2(state[0], state[3], state[4], L, ng)
-    hist = [diagnostics(state[1], state[2], state[4], fld, L)]
+
+    def diag(st):
+        return diagnostics(st[1], st[2], st[4], fld, L, st[0], st[3], ext, self_field)
+    hist = [diag(state)]
     for _ in range(nsteps):
         Q, P, qs, ps, psi = state
-        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt)
+        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
         Q, ps = drift(Q, P, qs, ps, L, dt)
         fld = solve_field_p2(Q, ps, psi, L, ng)
-        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt)
+        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
         state = (Q, P, qs, ps, psi)
-        hist.append(diagnostics(state[1], state[2], state[4], fld, L))
+        hist.append(diag(state))
     return state, fld, hist

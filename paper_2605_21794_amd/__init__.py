@@ -44,7 +44,7 @@ PROJECTIONS = {"elem": L.VP_PROJ_ELEM, "nodal": L.VP_PROJ_NODAL,
 
 def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096,
                 solver="scan", projection="elem", monopole_only=False, self_field=True,
-                external=None):
+                external=None, element_order=1):
     return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
                        dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
                        hist_cap=int(hist_cap),
@@ -53,7 +53,8 @@ def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4
                        else int(projection), monopole_only=1 if monopole_only else 0,
                        no_self_field=0 if self_field else 1,
                        ext_mode=int(external["mode"]) if external else 0,
-                       ext_amplitude=float(external["amp"]) if external else 0.0)
+                       ext_amplitude=float(external["amp"]) if external else 0.0,
+                       element_order=int(element_order))
 
 
 def workspace_bytes(cfg) -> int:
@@ -139,12 +140,14 @@ class Engine:
 
     def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
               sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem",
-              monopole_only: bool = False, self_field: bool = True, external=None):
+              monopole_only: bool = False, self_field: bool = True, external=None,
+              element_order: int = 1):
         """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`.
         monopole_only: plain particle-in-cell particles (p* = q* = 0; qs, ps may be left out
         of `state`, and are zeroed on admission).  self_field=False: the particles feel no
         field of their own (charge e = 0).  external = {"amp": A, "mode": m}: the prescribed
-        potential A (1 - cos(2 pi m q / L))."""
+        potential A (1 - cos(2 pi m q / L)).  element_order=2: P2 elements (a vertex and a
+        midpoint node per element; phi_h'' from the basis)."""
         t = self._torch
         tens = {k: self._tensor(state[k]) for k in FIELDS if k in state}
         if monopole_only:
@@ -158,7 +161,7 @@ class Engine:
         if any(int(v.numel()) != n for v in tens.values()):
             raise ValueError("state arrays differ in length")
         cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver,
-                          projection, monopole_only, self_field, external)
+                          projection, monopole_only, self_field, external, element_order)
         ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
@@ -228,8 +231,10 @@ class Engine:
     # ---------------------------------------------------------------- diagnostics
     def diagnostics(self, slot: int = 0, grid: bool = False, allow_nonfinite: bool = False):
         d = L.vp_diag()
-        ng = int(self.slots[int(slot)]["cfg"].ng)
-        buf = np.zeros(4 * ng) if grid else None
+        cfg = self.slots[int(slot)]["cfg"]
+        ng = int(cfg.ng)
+        na = 2 * ng if int(cfg.element_order) == 2 else ng   # nodes of b~ and Phi
+        buf = np.zeros(2 * na + 2 * ng) if grid else None
         ptr = buf.ctypes.data_as(c_void_p) if grid else None
         st = self.lib.vp_diagnostics(self.h, int(slot), byref(d), ptr)
         if not (allow_nonfinite and st == L.VP_ERR_NONFINITE):
@@ -237,7 +242,8 @@ class Engine:
         out = d.as_dict()
         out["finite"] = st == L.VP_OK   # False once the instance went NaN / Inf (and froze)
         if grid:
-            out.update(bt=buf[:ng], Phi=buf[ng:2 * ng], E=buf[2 * ng:3 * ng], g=buf[3 * ng:])
+            out.update(bt=buf[:na], Phi=buf[na:2 * na], E=buf[2 * na:2 * na + ng],
+                       g=buf[2 * na + ng:])
         return out
 
     def history(self, slot: int, first: int, count: int, allow_nonfinite: bool = False):
@@ -303,7 +309,7 @@ class Simulation(Engine):
     def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
                  sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
                  stream=None, solver="scan", projection="elem", monopole_only=False,
-                 self_field=True, external=None):
+                 self_field=True, external=None, element_order=1):
         super().__init__(precision, 1, device, stream)
         self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection,
-                   monopole_only, self_field, external)
+                   monopole_only, self_field, external, element_order)

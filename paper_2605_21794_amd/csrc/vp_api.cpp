@@ -70,8 +70,20 @@ vp_status validate(const vp_config* c) {
     return fail(VP_ERR_ARG, "no_self_field must be 0 or 1");
   if (c->ext_mode < 0 || !std::isfinite(c->ext_amplitude))
     return fail(VP_ERR_ARG, "ext_mode must be >= 0 and ext_amplitude finite");
+  if (c->element_order < 0 || c->element_order > 2)
+    return fail(VP_ERR_ARG, "element_order = %d must be 0, 1 or 2", c->element_order);
+  if (c->element_order == 2) {
+    if (c->precision == VP_FP32)
+      return fail(VP_ERR_ARG, "P2 elements need a precision other than VP_FP32");
+    if (c->projection != VP_PROJ_ELEM)
+      return fail(VP_ERR_ARG, "P2 elements take phi_h'' from the basis: projection must be "
+                              "VP_PROJ_ELEM");
+  }
+  if (c->reserved_ != 0) return fail(VP_ERR_ARG, "reserved_ must be 0");
   return VP_OK;
 }
+
+int order_of(const vp_config& c) { return c.element_order == 2 ? 2 : 1; }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -101,11 +113,12 @@ struct vp_handle {
   size_t tiles_cap = 0;
   int ntiles = 0;
   int ntiles_dip = 0;      // tiles of decorated instances (they come first)
-  int group_end[4] = {0, 0, 0, 0};  // tile ranges by kind: decorated / monopole-only x fast / general
+  // tile ranges by kind (kTileGroups): decorated / monopole-only x fast / general / P2
+  int group_end[6] = {0, 0, 0, 0, 0, 0};
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
-  int max_ng = VP_MIN_NG;
+  int max_ng = VP_MIN_NG;   // largest ng of the slots, doubled for P2 (sizes the launches' LDS)
   bool any_fft = false;     // some slot uses the FFT solver (fused launches need more LDS)
   vp_tuning tun{1024, 4, 4, 1, 33, 0};
   hipGraph_t graph = nullptr;
@@ -141,20 +154,20 @@ vp_status rebuild_tables(vp_handle* h) {
   for (int s = 0; s < h->max_slots; ++s)
     if (h->slots[s].used) h->h_occ.push_back(s);
   // tiles grouped by kind, one fused launch per non-empty group and step: decorated then
-  // monopole-only instances, each without then with general options
+  // monopole-only instances, each without general options, with them, and with P2 elements
   auto group_of = [&](int s) {
     const InstDev& d = h->h_inst[s];
-    return (h->slots[s].cfg.monopole_only ? 2 : 0) + (d.general ? 1 : 0);
+    return (h->slots[s].cfg.monopole_only ? 3 : 0) + (d.order == 2 ? 2 : d.general ? 1 : 0);
   };
   std::vector<int> order;
-  for (int gi = 0; gi < 4; ++gi)
+  for (int gi = 0; gi < 6; ++gi)
     for (int s : h->h_occ)
       if (group_of(s) == gi) order.push_back(s);
   h->ntiles_dip = 0;
-  for (int gi = 0; gi < 4; ++gi) h->group_end[gi] = 0;
+  for (int gi = 0; gi < 6; ++gi) h->group_end[gi] = 0;
   for (int s : order) {
     Slot& sl = h->slots[s];
-    h->max_ng = std::max(h->max_ng, sl.cfg.ng);
+    h->max_ng = std::max(h->max_ng, order_of(sl.cfg) * sl.cfg.ng);  // LDS sizing
     const long long n = sl.cfg.n;
     const int nt = (int)((n + tile_n - 1) / tile_n);
     sl.tile_begin = (int)h->h_tiles.size();
@@ -172,7 +185,7 @@ vp_status rebuild_tables(vp_handle* h) {
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
-    for (int gi = group_of(s); gi < 4; ++gi) h->group_end[gi] += nt;
+    for (int gi = group_of(s); gi < 6; ++gi) h->group_end[gi] += nt;
   }
   h->ntiles = (int)h->h_tiles.size();
   h->any_fft = false;
@@ -209,15 +222,16 @@ vp_status check_slot(const vp_handle* h, int slot) {
 int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
 
 // One fused step of every instance in phase ph: one launch per non-empty group of tiles
-// (decorated / monopole-only instances, without / with general options).
+// (decorated / monopole-only instances, without general options, with them, with P2).
 hipError_t fused_step(vp_handle* h, int ph) {
   int b = 0;
-  for (int gi = 0; gi < 4; ++gi) {
+  for (int gi = 0; gi < 6; ++gi) {
     const int e_ = h->group_end[gi];
     if (e_ > b) {
+      const int kind = gi % 3;
       const hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles,
                                              b, e_ - b, h->tun.ppt, h->max_ng, h->any_fft, ph,
-                                             gi < 2, (gi & 1) != 0, h->stream);
+                                             gi < 3, kind != 0, kind == 2, h->stream);
       if (e != hipSuccess) return e;
     }
     b = e_;
@@ -370,7 +384,7 @@ const char* vp_last_error(void) { return g_err.c_str(); }
 vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out) {
   VP_TRY(validate(cfg));
   if (!bytes_out) return fail(VP_ERR_ARG, "bytes_out is NULL");
-  *bytes_out = vpk::workspace_layout(cfg->ng, cfg->hist_cap, cfg->n).total;
+  *bytes_out = vpk::workspace_layout(cfg->ng, order_of(*cfg), cfg->hist_cap, cfg->n).total;
   return VP_OK;
 }
 
@@ -416,13 +430,17 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
     if (!arrs[k] || !aligned(arrs[k], es)) return fail(VP_ERR_ARG, "particle array %d NULL or misaligned", k);
   if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
 
-  const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, cfg->hist_cap, cfg->n);
+  if (h->tun.persistent && order_of(*cfg) == 2)
+    return fail(VP_ERR_ARG, "P2 elements are not run by persistent tuning");
+  const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, order_of(*cfg), cfg->hist_cap, cfg->n);
   char* ws = static_cast<char*>(workspace);
   InstDev d{};
   d.Q = parts.Q; d.P = parts.P; d.qs = parts.qs; d.ps = parts.ps; d.psi = parts.psi;
   d.n = cfg->n;
   d.ng = cfg->ng;
   d.log2ng = ilog2(cfg->ng);
+  d.order = order_of(*cfg);
+  d.nacc = d.order * cfg->ng;
   d.hist_cap = cfg->hist_cap;
   d.solver = cfg->solver;
   d.L = cfg->L;
@@ -442,7 +460,7 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.proj = cfg->projection;
   d.self_on = cfg->no_self_field ? 0 : 1;
   d.ext_on = (cfg->ext_mode >= 1 && cfg->ext_amplitude != 0.0) ? 1 : 0;
-  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on) ? 1 : 0;
+  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on || d.order == 2) ? 1 : 0;
   d.ext_a = cfg->ext_amplitude;
   d.ext_k = 6.283185307179586 * (double)cfg->ext_mode / cfg->L;  // 2 pi m / L
   d.ext_ak = d.ext_a * d.ext_k;
@@ -678,12 +696,13 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
                           h->max_ng, h->phase, h->stream));
   vpk::InstScal sc{};
   VP_HIP(hipMemcpyAsync(&sc, d.scal, sizeof sc, hipMemcpyDeviceToHost, h->stream));
-  if (host_grid) {
-    const int ng = sl.cfg.ng;
-    VP_HIP(hipMemcpyAsync(host_grid, d.bt, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    VP_HIP(hipMemcpyAsync(host_grid + ng, d.Phi, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    VP_HIP(hipMemcpyAsync(host_grid + 2 * ng, d.E, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    VP_HIP(hipMemcpyAsync(host_grid + 3 * ng, d.g, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (host_grid) {  // b~ and Phi have nacc nodes (2 ng for P2), E and g ng elements
+    const int ng = sl.cfg.ng, na = d.nacc;
+    VP_HIP(hipMemcpyAsync(host_grid, d.bt, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + na, d.Phi, na * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + 2 * na, d.E, ng * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    VP_HIP(hipMemcpyAsync(host_grid + 2 * na + ng, d.g, ng * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
   }
   VP_HIP(hipStreamSynchronize(h->stream));
   host_out->step = sc.step;
@@ -753,6 +772,9 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
   if (t->persistent) {
     if (!(t->threads == 512 || t->threads == 1024) || !(t->ppt == 2 || t->ppt == 4 || t->ppt == 8))
       return fail(VP_ERR_ARG, "persistent steps need threads 512 or 1024 and ppt 2, 4 or 8");
+    for (int s : h->h_occ)
+      if (order_of(h->slots[s].cfg) == 2)
+        return fail(VP_ERR_ARG, "slot %d has P2 elements, which persistent steps do not run", s);
   }
   const vp_tuning old = h->tun;
   h->tun = *t;
@@ -860,7 +882,7 @@ vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
     b += ((size_t)5 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
-    b += vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap, sl.cfg.n).total;
+    b += vpk::workspace_layout(sl.cfg.ng, order_of(sl.cfg), sl.cfg.hist_cap, sl.cfg.n).total;
   }
   *bytes_out = b;
   return VP_OK;
@@ -882,7 +904,7 @@ vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
       else VP_HIP(hipMemcpyAsync(arrs[k], sp, sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
     }
     off += ((size_t)5 * sl.cfg.n * es + 255) & ~size_t(255);
-    const size_t wb = vpk::workspace_layout(sl.cfg.ng, sl.cfg.hist_cap, sl.cfg.n).total;
+    const size_t wb = vpk::workspace_layout(sl.cfg.ng, order_of(sl.cfg), sl.cfg.hist_cap, sl.cfg.n).total;
     if (save) VP_HIP(hipMemcpyAsync(scratch + off, sl.ws, wb, hipMemcpyDeviceToDevice, h->stream));
     else VP_HIP(hipMemcpyAsync(sl.ws, scratch + off, wb, hipMemcpyDeviceToDevice, h->stream));
     off += wb;

@@ -49,16 +49,18 @@ struct InstDev {
   void* psi;
   long long n;
   int ng, log2ng;
+  int order;        // Lagrange degree of the potential: 1 (P1) or 2 (P2)
+  int nacc;         // load-vector nodes: ng (P1), 2 ng (P2: vertices [0, ng), midpoints [ng, 2 ng))
   int ntiles, acc_copies;
   int hist_cap, solver;
   double L, inv_h, h, dt;
-  double* acc;      // kRing x VP_MAX_ACC_COPIES x ng load accumulators (float for kFP32)
+  double* acc;      // kRing x VP_MAX_ACC_COPIES x nacc load accumulators (float for kFP32)
   double* E;        // element field, ng
   double* g;        // projected curvature phi_h'', ng
   float* Ef;        // float copies for the kFP32 gather
   float* gf;
-  double* Phi;      // nodal potential, ng
-  double* bt;       // neutralised load, ng
+  double* Phi;      // nodal potential, nacc
+  double* bt;       // neutralised load, nacc
   double* tw;       // tw[2k] = cos(2 pi k / ng), tw[2k+1] = sin(2 pi k / ng), k < ng/2
   double* inv_lam;  // 1 / eigenvalue of the stiffness matrix per Fourier mode (0 for m = 0)
   double* cw;       // consistent projection: kConsTaps weights of -M^-1 (see cons_taps)
@@ -67,10 +69,9 @@ struct InstDev {
   double* kin;      // kRing x kin_cap x kKinFields per-tile kinetic sums of phase r's pass
   int kin_cap;      // tiles the kinetic-sum ring can hold (ceil(n / 256))
   int proj;         // vp_projection
-  int general;      // any of: a nodal projection, no self field, a prescribed potential
+  int general;      // any of: a nodal projection, no self field, a prescribed potential, P2
   int self_on;      // the particles feel their own field
   int ext_on;       // a prescribed potential acts
-  int pad2_;
   double ext_a, ext_k, ext_ak, ext_akk;  // A, kappa = 2 pi m / L, A kappa, A kappa^2
 };
 
@@ -87,17 +88,20 @@ struct Tile {
 struct WsLayout {
   size_t acc, E, g, Ef, gf, Phi, bt, tw, inv_lam, cw, scal, hist, kin, total;
 };
-WsLayout workspace_layout(int ng, int hist_cap, long long n);
+WsLayout workspace_layout(int ng, int order, int hist_cap, long long n);
 int kin_capacity(long long n);
 
 size_t particle_lds_bytes(int mode, int max_ng);
+// The `max_ng` of every launch below sizes its LDS: the largest ng of the instances it
+// serves, doubled for a P2 instance (whose load vector has 2 ng nodes).
 
 // `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS);
 // `dipoles` false when every tile of the launch is of a monopole-only instance; `general`
-// true when some instance of the launch has general options (InstDev::general).
+// true when some instance of the launch has general options (InstDev::general); `p2` true
+// when some has P2 elements (then `general` must be true too).
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        bool general, hipStream_t s);
+                        bool general, bool p2, hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,

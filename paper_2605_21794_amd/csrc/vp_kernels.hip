@@ -125,12 +125,15 @@ __device__ __forceinline__ float curv_at_f(int proj, const F* g, int i, float x,
 // and the projection's curvature when the particles feel their own field (else zero), plus
 // the prescribed potential's field -V'(Q) and curvature V''(Q); U gets psi* V(Q) - p* V'(Q)
 // of the particle (integer-step Q and p*).  Float64, in the plain definition's order.
+// P2 elements: fE holds the field at each element's midpoint and fG the element's exact
+// phi_h''; the field is linear on the element, E(s) = fE[i] - h fG[i] (s - 1/2).
 template <typename F>
 __device__ __forceinline__ void general_field(const InstDev& d, const F* fE, const F* fG, int i,
                                               double x, double Q, double psi, double ps,
                                               double& Ei, double& gi, double& U) {
   Ei = d.self_on ? (double)fE[i] : 0.0;
   gi = d.self_on ? curv_at(d.proj, fG, i, x, d.ng) : 0.0;
+  if (d.order == 2 && d.self_on) Ei = Ei - d.h * gi * (frac01(x, i) - 0.5);
   U = 0.0;
   if (d.ext_on) {
     const double ph = d.ext_k * Q;
@@ -157,8 +160,9 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ------------------------------------------------------------------ LDS layout
-// [0, 2*Ng) doubles: field E then g (float copies for kFP32); [2*Ng, 3*Ng): accumulator
-// (Ng doubles / Ng packed float (hi, lo) pairs / Ng floats).  The solve reuses [0, 4*Ng).
+// [0, 2*Ng) doubles: field E then g (float copies for kFP32); [2*Ng, 2*Ng + nacc):
+// accumulator (nacc doubles / packed float (hi, lo) pairs / floats; nacc = Ng, or 2 Ng for
+// P2).  The solve reuses [0, 4*Ng).
 __host__ __device__ constexpr size_t lds_doubles_per_node() { return 4; }
 
 template <int MODE, int TPB>
@@ -184,7 +188,7 @@ __device__ void stage(const InstDev& d, double* fld, double* sacc, bool need_fie
     }
   }
   if (need_acc)
-    for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
+    for (int j = threadIdx.x; j < d.nacc; j += TPB) sacc[j] = 0.0;
   __syncthreads();
 }
 
@@ -218,11 +222,30 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
   }
 }
 
+// P2 load of one particle at local coordinate s of element j (eq. galerkin with the
+// quadratic basis N0 = (1-s)(1-2s), N1 = 4s(1-s), N2 = s(2s-1) of the element's left vertex,
+// midpoint and right vertex): node k gets psi* N_k(s) - p* N_k'(s) / h.  Midpoint j is LDS
+// entry ng + j.  With DIP false p* is zero and its terms are left out.
+template <int MODE, bool DIP>
+__device__ __forceinline__ void deposit_p2(double* sacc, int ng, int j, double s, double psi,
+                                           double ps, double inv_h) {
+  const double n0 = (1.0 - s) * (1.0 - 2.0 * s), n1 = 4.0 * s * (1.0 - s), n2 = s * (2.0 * s - 1.0);
+  if constexpr (DIP) {
+    lds_add<MODE>(sacc, j, psi * n0 - ps * ((4.0 * s - 3.0) * inv_h));
+    lds_add<MODE>(sacc, ng + j, psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h));
+    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2 - ps * ((4.0 * s - 1.0) * inv_h));
+  } else {
+    lds_add<MODE>(sacc, j, psi * n0);
+    lds_add<MODE>(sacc, ng + j, psi * n1);
+    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2);
+  }
+}
+
 // Add the LDS grid into accumulator copy `copy` of ring entry r of the instance (device-scope
 // atomics; only non-zero nodes).
 template <int MODE, int TPB>
 __device__ void flush(const InstDev& d, const double* sacc, int r, int copy) {
-  const int ng = d.ng;
+  const int ng = d.nacc;
   const size_t off = ((size_t)r * VP_MAX_ACC_COPIES + (size_t)copy) * (size_t)ng;
   if constexpr (MODE == kFP32) {
     const float* a = reinterpret_cast<const float*>(sacc);
@@ -344,7 +367,7 @@ __device__ __forceinline__ int ring_prev(int r) { return r == 0 ? kRing - 1 : r 
 
 // Element offset of accumulator copy c of ring entry r (in doubles, or in floats for kFP32).
 __device__ __forceinline__ size_t acc_off(const InstDev& d, int r, int c) {
-  return ((size_t)r * VP_MAX_ACC_COPIES + (size_t)c) * (size_t)d.ng;
+  return ((size_t)r * VP_MAX_ACC_COPIES + (size_t)c) * (size_t)d.nacc;
 }
 
 __device__ __forceinline__ int solve_per(int ng) {
@@ -355,6 +378,7 @@ __device__ __forceinline__ int solve_per(int ng) {
 // summary is wanted, the Fourier weights cos / sin(2 pi e / Ng) of those nodes.
 struct SolveIn {
   double b[kSolvePer];
+  double bm[kSolvePer];    // P2: the loads of the midpoints of the same elements
   double c[kSolvePer];
   double s[kSolvePer];
   double kin[kKinFields];  // this thread's share of the previous pass's per-tile sums
@@ -391,6 +415,7 @@ __device__ __forceinline__ void load_kin(const InstDev& d, int r, double (&kin)[
 template <int MODE, int COPIES, int PER, bool DEV>
 __device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0,
                                             double (&b)[kSolvePer]) {
+  // j0 counts from the start of a copy: nodes [ng, 2 ng) are a P2 instance's midpoints
   constexpr int kBatch = (8 / PER) < COPIES ? (8 / PER) : COPIES;
 #pragma unroll
   for (int k = 0; k < PER; ++k) b[k] = 0.0;
@@ -416,15 +441,23 @@ __device__ __forceinline__ void load_copies(const InstDev& d, int r, int j0,
 // The node count per thread and the copy count are template parameters, so every load is
 // unconditional and all of them are in flight before the first use.
 template <int MODE, int PER, bool DEV>
+__device__ __forceinline__ void load_node_copies(const InstDev& d, int r, int j0,
+                                                 double (&b)[kSolvePer]) {
+  switch (d.acc_copies) {
+    case 1: load_copies<MODE, 1, PER, DEV>(d, r, j0, b); break;
+    case 2: load_copies<MODE, 2, PER, DEV>(d, r, j0, b); break;
+    case 3: load_copies<MODE, 3, PER, DEV>(d, r, j0, b); break;
+    case 4: load_copies<MODE, 4, PER, DEV>(d, r, j0, b); break;
+    default: load_copies<MODE, VP_MAX_ACC_COPIES, PER, DEV>(d, r, j0, b); break;
+  }
+}
+
+template <int MODE, int PER, bool DEV, bool P2>
 __device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, bool want_sum,
                                                SolveIn& in) {
-  switch (d.acc_copies) {
-    case 1: load_copies<MODE, 1, PER, DEV>(d, r, j0, in.b); break;
-    case 2: load_copies<MODE, 2, PER, DEV>(d, r, j0, in.b); break;
-    case 3: load_copies<MODE, 3, PER, DEV>(d, r, j0, in.b); break;
-    case 4: load_copies<MODE, 4, PER, DEV>(d, r, j0, in.b); break;
-    default: load_copies<MODE, VP_MAX_ACC_COPIES, PER, DEV>(d, r, j0, in.b); break;
-  }
+  load_node_copies<MODE, PER, DEV>(d, r, j0, in.b);
+  if constexpr (P2)
+    if (d.order == 2) load_node_copies<MODE, PER, DEV>(d, r, d.ng + j0, in.bm);
   if (want_sum) {
     const VPG double* tw = gp(d.tw);
     const int halfn = d.ng >> 1;
@@ -441,18 +474,19 @@ __device__ __forceinline__ void solve_load_per(const InstDev& d, int r, int j0, 
 // Issue the solve's loads (load vector of ring entry r; with want_sum also the Fourier
 // weights and the kinetic sums of the previous pass, ring entry r-1): all of them before
 // any use, so they overlap other work of the caller.
-template <int MODE, bool DEV = false, bool GEN = true>
+// P2 = false: no instance of the launch has P2 elements (its midpoint loads are not read).
+template <int MODE, bool DEV = false, bool GEN = true, bool P2 = GEN>
 __device__ __forceinline__ void solve_load(const InstDev& d, int r, bool want_sum, SolveIn& in) {
   const int ng = d.ng, tid = threadIdx.x;
   const int per = solve_per(ng), j0 = tid * per;
 #pragma unroll
-  for (int k = 0; k < kSolvePer; ++k) in.b[k] = in.c[k] = in.s[k] = 0.0;
+  for (int k = 0; k < kSolvePer; ++k) in.b[k] = in.bm[k] = in.c[k] = in.s[k] = 0.0;
   in.kin[0] = in.kin[1] = in.kin[2] = in.kin[3] = 0.0;
   if (tid >= kSolveThreads) return;
   if (j0 < ng) {
-    if (per == 1) solve_load_per<MODE, 1, DEV>(d, r, j0, want_sum, in);
-    else if (per == 2) solve_load_per<MODE, 2, DEV>(d, r, j0, want_sum, in);
-    else solve_load_per<MODE, kSolvePer, DEV>(d, r, j0, want_sum, in);
+    if (per == 1) solve_load_per<MODE, 1, DEV, P2>(d, r, j0, want_sum, in);
+    else if (per == 2) solve_load_per<MODE, 2, DEV, P2>(d, r, j0, want_sum, in);
+    else solve_load_per<MODE, kSolvePer, DEV, P2>(d, r, j0, want_sum, in);
   }
   if (want_sum) load_kin<DEV, GEN ? kKinFields : 3>(d, ring_prev(r), in.kin);  // waits overlap
 }
@@ -481,20 +515,37 @@ __device__ __forceinline__ double solve_total(const double* red, int slot) {
 // `fft` is LDS scratch of 3 Ng doubles (FFT solver only).  All threads of the workgroup call
 // it (it holds workgroup barriers; want_sum must be uniform); on return bt, E, g (and phi)
 // are visible to all threads.
-template <int TPB, bool GEN = true>
+// P2 elements (GEN only): the background n0 = sum(b) / L is subtracted against each basis
+// function's integral, n0 h / 3 = mean / 3 at a vertex and 2 mean / 3 at a midpoint (mean =
+// sum(b) / Ng).  Static condensation of the midpoint unknowns, whose rows read
+// (1/3h)(16 Phi_m - 8 Phi_e - 8 Phi_{e+1}) = b~_m, turns the vertex rows into the P1 system
+// with the load c_e = b~_e + (b~_{m,e-1} + b~_{m,e}) / 2 = b_e + (b_{m,e-1} + b_{m,e}) / 2 -
+// mean, solved as above (bt holds c~): E_e is then the field at element e's midpoint and
+// g_e = -3 b~_{m,e} / (2h) the exact phi_h'' on the element.  The field is linear on the
+// element with slope 3 b~_{m,e} / (2h), so W gains (1/2) h (3/16) sum_e b~_{m,e}^2.  With
+// `p2b` given, b~ of the vertices and midpoints go to p2b[0, Ng) and p2b[Ng, 2 Ng).  g holds
+// the raw midpoint loads until the final pass.
+template <int TPB, bool GEN = true, bool P2 = GEN>
 __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum, double* bt,
                               double* E, double* g, double* red, double* fft, double* phi,
-                              double* sum) {
+                              double* sum, double* p2b = nullptr) {
   const int ng = d.ng, mask = ng - 1, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int per = solve_per(ng), j0 = tid * per;
   const bool solver_thread = tid < kSolveThreads;           // whole waves
   const bool act = solver_thread && j0 < ng;
   const bool use_fft = d.solver == VP_SOLVE_FFT;
+  const bool p2 = P2 && d.order == 2;
 
   double part = 0.0;
 #pragma unroll
   for (int k = 0; k < kSolvePer; ++k)
-    if (act && k < per) part += in.b[k];
+    if (act && k < per) {
+      part += in.b[k];
+      if (p2) {
+        part += in.bm[k];
+        g[j0 + k] = in.bm[k];
+      }
+    }
   if (solver_thread) {
     solve_wave_total(part, red, 0);
     if (want_sum) {
@@ -512,13 +563,24 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
   const double mean = solve_total(red, 0) / (double)ng;
 
   double S[kSolvePer];
-  double tot = 0.0, wsum = 0.0;
+  double tot = 0.0, wsum = 0.0, wmid = 0.0;
 #pragma unroll
   for (int k = 0; k < kSolvePer; ++k) {
     S[k] = 0.0;
     if (act && k < per) {
       const int j = j0 + k;
-      const double x = in.b[k] - mean;
+      double x;
+      if (p2) {
+        x = (in.b[k] + 0.5 * (g[(j - 1) & mask] + g[j])) - mean;
+        const double bmt = in.bm[k] - (2.0 / 3.0) * mean;
+        wmid += bmt * bmt;
+        if (p2b) {
+          p2b[j] = in.b[k] - mean / 3.0;
+          p2b[ng + j] = bmt;
+        }
+      } else {
+        x = in.b[k] - mean;
+      }
       bt[j] = x;
       if (j > 0) {
         tot += x;
@@ -551,6 +613,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
         }
     }
     if (want_sum && solver_thread) {
+      if (p2) wp += 0.1875 * wmid;
       solve_wave_total(wp, red, 3);
       solve_wave_total(er, red, 4);
       solve_wave_total(ei, red, 5);
@@ -599,6 +662,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
             ei -= Ee * in.s[k];
           }
       if (solver_thread) {
+        if (p2) wp += 0.1875 * wmid;
         solve_wave_total(wp, red, 3);
         solve_wave_total(er, red, 4);
         solve_wave_total(ei, red, 5);
@@ -615,7 +679,11 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     sum[5] = solve_total(red, 8);
     sum[6] = GEN ? solve_total(red, 9) : 0.0;
   }
-  if (d.proj == VP_PROJ_ELEM) {
+  if (p2) {
+    // each thread rewrites only entries it reads (the neighbours' reads ended at a barrier)
+    const double bg = (2.0 / 3.0) * mean, a = 1.5 * d.inv_h;
+    for (int e = tid; e < ng; e += TPB) g[e] = -(g[e] - bg) * a;
+  } else if (d.proj == VP_PROJ_ELEM) {
     const double half_inv_h = 0.5 * d.inv_h;
     for (int e = tid; e < ng; e += TPB) g[e] = -(bt[e] + bt[(e + 1) & mask]) * half_inv_h;
   } else if (d.proj == VP_PROJ_NODAL) {
@@ -708,7 +776,7 @@ __device__ void write_record(const InstDev& d, long long step, double K, double 
 // float64 modes compute in float64 from the stored values in the oracle's operation order.
 // DIP = false: a monopole-only particle (p* = q* = 0, plain P1 particle-in-cell): the dipole
 // terms are left out, which gives the same values as carrying zeros through them.
-template <int MODE, typename T, bool DIP = true, bool GEN = true>
+template <int MODE, typename T, bool DIP = true, bool GEN = true, bool P2 = GEN>
 __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
                                               double* sacc, int pend, T& Qr, T& Pr, T& qsr,
                                               T& psr, const T psir, double& Ks, double& Ms,
@@ -802,23 +870,34 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const double x = Qd * inv_h;
     const int j = cell_of(x, ng);
     const double s = frac01(x, j);
+    const bool p2 = P2 && d.order == 2;
     if constexpr (DIP) {
       const double psn = ps - dt * qs;
       const T pss = (T)psn;
       const double psd = pss;
-      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      if (p2) {
+        deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h);
+      } else {
+        lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      }
       qsr = (T)qs; psr = pss;
     } else {
-      lds_add<MODE>(sacc, j, psi * (1.0 - s));
-      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s);
+      if (p2) {
+        deposit_p2<MODE, false>(sacc, ng, j, s, psi, 0.0, inv_h);
+      } else {
+        lds_add<MODE>(sacc, j, psi * (1.0 - s));
+        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s);
+      }
     }
     Qr = Qs; Pr = (T)P;
   }
 }
 
 // LDS of the fused kernel, in doubles: E [0, Ng), g [Ng, 2Ng), deposit grid [2Ng, 3Ng),
-// b~ [3Ng, 4Ng), FFT scratch [4Ng, 7Ng) (FFT solver only).
+// b~ [3Ng, 4Ng), FFT scratch [4Ng, 7Ng) (FFT solver only).  A P2 instance's deposit grid
+// has 2Ng nodes, which moves b~ and the scratch up by Ng: the launch sizes its LDS for
+// twice its largest P2 mesh (the `max_ng` of the launch functions).
 __host__ __device__ constexpr size_t fused_lds_doubles(bool fft) { return fft ? 7 : 4; }
 
 // One fused step of every tile, in phase r:
@@ -838,8 +917,9 @@ __host__ __device__ constexpr int group_of() { return (MODE == kFP64 && TPB == 1
 // DIP = false: every tile of the launch belongs to a monopole-only instance; p* and q* are
 // neither read nor written (20 bytes of particle traffic per update instead of 36).
 // GEN = false: no instance of the launch has general options (d.general), so the field on a
-// particle is read straight from the mesh arrays.
-template <int MODE, int TPB, bool DIP, bool GEN>
+// particle is read straight from the mesh arrays.  P2 = true (with GEN): the launch's
+// instances have P2 elements (a separate instance keeps the others' registers as they were).
+template <int MODE, int TPB, bool DIP, bool GEN, bool P2>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
                                                int ppt, int phase) {
@@ -857,11 +937,12 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   VPG T* __restrict__ qsp = gp<T>(d.qs);
   VPG T* __restrict__ psp = gp<T>(d.ps);
   const VPG T* __restrict__ psip = gp<T>(d.psi);
+  const int nacc = P2 ? d.nacc : ng;  // load-vector nodes (2 ng for P2)
   double* fE = smem;
   double* fG = smem + ng;
   double* sacc = smem + 2 * ng;
-  double* bt = smem + 3 * ng;
-  double* fft = smem + 4 * ng;
+  double* bt = sacc + nacc;
+  double* fft = bt + ng;
   VPG InstScal* sc = gp(d.scal);
   // An instance whose diagnostics went NaN / Inf is frozen: its state is no longer a
   // solution, and its particles would all land in element 0.  (Uniform per workgroup.)
@@ -896,8 +977,8 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   Group g;
   load_group(0, g);
   SolveIn sin_;
-  solve_load<MODE, false, GEN>(d, r0, first, sin_);
-  for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
+  solve_load<MODE, false, GEN, P2>(d, r0, first, sin_);
+  for (int j = threadIdx.x; j < nacc; j += TPB) sacc[j] = 0.0;
   const int pend = sc->pend[r0];
   // the first tile records the previous step (if it was a fused step of this instance):
   // its inputs are read now and written after the solve
@@ -912,11 +993,11 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
   {
     double sum[7];
-    solve_compute<TPB, GEN>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+    solve_compute<TPB, GEN, P2>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
     if (first) {
       const int copies = d.acc_copies;
       for (int c = 0; c < copies; ++c)
-        for (int j = threadIdx.x; j < ng; j += TPB) {
+        for (int j = threadIdx.x; j < nacc; j += TPB) {
           if constexpr (MODE == kFP32)
             gp<float>(d.acc)[acc_off(d, r2, c) + j] = 0.0f;
           else
@@ -940,8 +1021,8 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     for (int u = 0; u < kGroup; ++u) {
       if (!g.v[u]) continue;
       T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
-      push_particle<MODE, T, DIP, GEN>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms, Cs,
-                                       Us);
+      push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms,
+                                           Cs, Us);
       ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P);
       if constexpr (DIP) { ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps); }
     }
@@ -994,7 +1075,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
 // other workgroups of the launch wrote (the load vector, the per-tile kinetic sums, the
 // cleared ring entry) is read and written at device scope; the ring protocol, the records
 // and the arithmetic are those of k_fused, so nsteps persistent steps equal nsteps fused
-// launches.
+// launches.  P2 instances are not taken (the host refuses persistent tuning for them).
 constexpr unsigned kSpinLimit = 1u << 22;
 
 template <int MODE, int TPB, int PPT>
@@ -1065,12 +1146,12 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       __syncthreads();
     }
     SolveIn sin_;
-    solve_load<MODE, true>(d, r0, first, sin_);
+    solve_load<MODE, true, true, false>(d, r0, first, sin_);
     for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
     double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
     {
       double sum[7];
-      solve_compute<TPB>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+      solve_compute<TPB, true, false>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
       if (first) {
         const int copies = d.acc_copies;
         for (int c = 0; c < copies; ++c)
@@ -1099,7 +1180,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
       if (v[u])
-        push_particle<MODE>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u], w[u], Ks, Ms, Cs, Us);
+        push_particle<MODE, T, true, true, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
+                                                  w[u], Ks, Ms, Cs, Us);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1180,6 +1262,7 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
     VP_TILE_LOOP_END
   } else {
     const double inv_h = d.inv_h;
+    const bool p2 = d.order == 2;
     VP_TILE_LOOP_BEGIN
     T q[4], b[4], w[4];
 #pragma unroll
@@ -1192,8 +1275,12 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
       const double x = (double)q[u] * inv_h;
       const int j = cell_of(x, ng);
       const double s = frac01(x, j);
-      lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-      lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      if (p2) {
+        deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h);
+      } else {
+        lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
+        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+      }
     }
     VP_TILE_LOOP_END
   }
@@ -1403,29 +1490,68 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(const InstDev* __restri
   __shared__ double sred[kSolveRed];
   const InstDev& d = insts[slots[blockIdx.x]];
   const int ng = d.ng;
+  const bool p2 = d.order == 2;
   double* fE = smem;
   double* fG = smem + ng;
   double* phi = smem + 2 * ng;
   double* bt = smem + 3 * ng;
   double* fft = smem + 4 * ng;
+  // P2: b~ of vertices and midpoints, after the FFT scratch when this instance uses it
+  double* p2b = smem + (d.solver == VP_SOLVE_FFT ? 7 : 4) * ng;
   SolveIn sin_;
   solve_load<MODE>(d, phase, true, sin_);
   double sum[7];
-  solve_compute<kSolveThreads>(d, sin_, true, bt, fE, fG, sred, fft, phi, sum);
+  solve_compute<kSolveThreads>(d, sin_, true, bt, fE, fG, sred, fft, phi, sum,
+                               p2 ? p2b : nullptr);
   VPG double* bt_g = gp(d.bt);
   VPG double* E_g = gp(d.E);
   VPG double* g_g = gp(d.g);
   VPG double* Phi_g = gp(d.Phi);
   VPG float* Ef_g = gp(d.Ef);
   VPG float* gf_g = gp(d.gf);
-  for (int e = threadIdx.x; e < ng; e += kSolveThreads) {
-    const double Ee = fE[e], ge = fG[e];
-    bt_g[e] = bt[e];
-    E_g[e] = Ee;
-    Ef_g[e] = (float)Ee;
-    g_g[e] = ge;
-    gf_g[e] = (float)ge;
-    Phi_g[e] = phi[e];
+  if (!p2) {
+    for (int e = threadIdx.x; e < ng; e += kSolveThreads) {
+      const double Ee = fE[e], ge = fG[e];
+      bt_g[e] = bt[e];
+      E_g[e] = Ee;
+      Ef_g[e] = (float)Ee;
+      g_g[e] = ge;
+      gf_g[e] = (float)ge;
+      Phi_g[e] = phi[e];
+    }
+  } else {
+    // midpoint potentials from their own rows, Phi_m = (3h b~_m + 8 (Phi_e + Phi_{e+1})) / 16;
+    // then the P2 gauge: shift by c so that (h/3) sum Phi_v + (2h/3) sum Phi_m = 0
+    const int per = solve_per(ng);
+    double pm[kSolvePer];
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSolvePer; ++k) {
+      pm[k] = 0.0;
+      const int e = threadIdx.x * per + k;
+      if (k < per && e < ng) {
+        pm[k] = (3.0 * d.h * p2b[ng + e] + 8.0 * (phi[e] + phi[(e + 1) & (ng - 1)])) / 16.0;
+        part += phi[e] + 2.0 * pm[k];
+      }
+    }
+    const double c = -block_sum<kSolveThreads>(part, sred) / (3.0 * (double)ng);
+#pragma unroll
+    for (int k = 0; k < kSolvePer; ++k) {
+      const int e = threadIdx.x * per + k;
+      if (k < per && e < ng) {
+        bt_g[e] = p2b[e];
+        bt_g[ng + e] = p2b[ng + e];
+        Phi_g[e] = phi[e] + c;
+        Phi_g[ng + e] = pm[k] + c;
+      }
+    }
+    for (int e = threadIdx.x; e < ng; e += kSolveThreads) {
+      const double Ee = fE[e], ge = fG[e];
+      E_g[e] = Ee;
+      Ef_g[e] = (float)Ee;
+      g_g[e] = ge;
+      gf_g[e] = (float)ge;
+    }
   }
   if (threadIdx.x == 0) {
     VPG InstScal* sc = gp(d.scal);
@@ -1445,9 +1571,9 @@ template <typename A>
 __global__ __launch_bounds__(256) void k_ring(const InstDev* __restrict__ insts,
                                               const int* __restrict__ slots, int op, int phase) {
   const InstDev& d = insts[slots[blockIdx.x]];
-  const int ng = d.ng;
+  const int nacc = d.nacc;
   VPG A* acc = gp<A>(reinterpret_cast<A*>(d.acc));
-  for (int j = threadIdx.x; j < ng; j += 256) {
+  for (int j = threadIdx.x; j < nacc; j += 256) {
     if (op == kRingFold) {
       double s = 0.0;
       for (int c = 0; c < VP_MAX_ACC_COPIES; ++c) s += (double)acc[acc_off(d, phase, c) + j];
@@ -1615,16 +1741,17 @@ __global__ __launch_bounds__(kBlock) void k_sort(const InstDev* __restrict__ ins
 // ------------------------------------------------------------------ host launchers
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-WsLayout workspace_layout(int ng, int hist_cap, long long n) {
+WsLayout workspace_layout(int ng, int order, int hist_cap, long long n) {
   WsLayout w{};
   size_t o = 0;
-  w.acc = o;     o = align256(o + (size_t)kRing * VP_MAX_ACC_COPIES * ng * sizeof(double));
+  const size_t nacc = (size_t)(order == 2 ? 2 : 1) * ng;
+  w.acc = o;     o = align256(o + (size_t)kRing * VP_MAX_ACC_COPIES * nacc * sizeof(double));
   w.E = o;       o = align256(o + (size_t)ng * sizeof(double));
   w.g = o;       o = align256(o + (size_t)ng * sizeof(double));
   w.Ef = o;      o = align256(o + (size_t)ng * sizeof(float));
   w.gf = o;      o = align256(o + (size_t)ng * sizeof(float));
-  w.Phi = o;     o = align256(o + (size_t)ng * sizeof(double));
-  w.bt = o;      o = align256(o + (size_t)ng * sizeof(double));
+  w.Phi = o;     o = align256(o + nacc * sizeof(double));
+  w.bt = o;      o = align256(o + nacc * sizeof(double));
   w.tw = o;      o = align256(o + (size_t)ng * sizeof(double));
   w.inv_lam = o; o = align256(o + (size_t)ng * sizeof(double));
   w.cw = o;      o = align256(o + (size_t)kConsTapsMax * sizeof(double));
@@ -1664,20 +1791,23 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
 
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        bool general, hipStream_t s) {
+                        bool general, bool p2, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (p2 && !general) return hipErrorInvalidValue;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
-#define VP_FUSED_K(M, TB, D, G)                                                              \
-  hipLaunchKernelGGL((k_fused<M, TB, D, G>), dim3(ntiles), dim3(TB), lds, s, d_inst, d_tiles, \
-                     tile0, ppt, phase)
+#define VP_FUSED_K(M, TB, D, G, P)                                                           \
+  hipLaunchKernelGGL((k_fused<M, TB, D, G, P>), dim3(ntiles), dim3(TB), lds, s, d_inst,      \
+                     d_tiles, tile0, ppt, phase)
 #define VP_FUSED(M, TB)                                                                      \
   do {                                                                                       \
     if (dipoles) {                                                                           \
-      if (general) VP_FUSED_K(M, TB, true, true);                                            \
-      else VP_FUSED_K(M, TB, true, false);                                                   \
+      if (p2) VP_FUSED_K(M, TB, true, true, true);                                           \
+      else if (general) VP_FUSED_K(M, TB, true, true, false);                                \
+      else VP_FUSED_K(M, TB, true, false, false);                                            \
     } else {                                                                                 \
-      if (general) VP_FUSED_K(M, TB, false, true);                                           \
-      else VP_FUSED_K(M, TB, false, false);                                                  \
+      if (p2) VP_FUSED_K(M, TB, false, true, true);                                          \
+      else if (general) VP_FUSED_K(M, TB, false, true, false);                               \
+      else VP_FUSED_K(M, TB, false, false, false);                                           \
     }                                                                                        \
   } while (0)
 #define VP_FUSED_TPB(M)                                                                      \

@@ -49,7 +49,10 @@ def test_workspace_sizing_and_validation(lib):
            dict(precision=7), dict(sort_chunk=5000), dict(hist_cap=0), dict(solver=2),
            dict(L=float("nan")), dict(sort_every=-2), dict(projection=3),
            dict(projection=-1), dict(monopole_only=2), dict(no_self_field=3), dict(ext_mode=-1),
-           dict(ext_mode=1, ext_amplitude=float("inf"))]
+           dict(ext_mode=1, ext_amplitude=float("inf")), dict(element_order=3),
+           dict(element_order=-1), dict(element_order=2, precision=L.VP_FP32),
+           dict(element_order=2, projection=L.VP_PROJ_NODAL),
+           dict(element_order=2, projection=L.VP_PROJ_CONSISTENT), dict(reserved_=1)]
     for kw in bad:
         args = dict(n=1000, ng=64, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
         args.update(kw)
@@ -62,6 +65,18 @@ def test_workspace_sizing_and_validation(lib):
         assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
     c = L.vp_config(n=1000, ng=64, precision=L.VP_FP64, L=1.0, dt=0.1, sort_chunk=2049, hist_cap=1)
     assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_ERR_ARG
+    # P2: twice the load-vector nodes (accumulator ring, b~, Phi), in every other precision
+    sizes = {}
+    for order in (0, 1, 2):
+        c = L.vp_config(n=1000, ng=1024, precision=L.VP_FP64, L=1.0, dt=0.1, hist_cap=1,
+                        element_order=order)
+        assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
+        sizes[order] = b.value
+    assert sizes[0] == sizes[1]
+    assert sizes[2] - sizes[1] >= (3 * L.VP_MAX_ACC_COPIES + 2) * 1024 * 8
+    for prec in (L.VP_FP64, L.VP_FP32_COMP, L.VP_FP32_TWOSUM):
+        c = L.vp_config(n=1000, ng=64, precision=prec, L=1.0, dt=0.1, hist_cap=1, element_order=2)
+        assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
 
 
 def test_null_handles_rejected(lib):
@@ -70,4 +85,4 @@ def test_null_handles_rejected(lib):
     assert lib.vp_deposit(None) == L.VP_ERR_ARG
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
-    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 6
+    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 7

@@ -831,3 +831,28 @@ def test_p2_field_energy_of_the_landau_lattice_converges():
     w = W.landau_linear(nx=64, nv=64, ng=64)
     st = w.state()
     assert O.solve_field_p2(st["Q"], st["ps"], st["psi"], w.L, w.ng)["W"] > 5 * exact
+
+
+def test_p2_without_self_field_is_the_element_free_test_particle_flow():
+    """With no field of their own the particles see only the prescribed potential, so the
+    P2 run and the P1 run agree exactly (the mesh takes no part in the kicks), and a
+    particle at rest at the potential's minimum with no dipoles stays there."""
+    rng = np.random.default_rng(12)
+    L, ng, n = 10.0, 16, 40
+    Q = rng.uniform(0, L, n)
+    P = rng.normal(0, 0.5, n)
+    qs = rng.normal(0, 0.05, n)
+    ps = rng.normal(0, 0.05, n)
+    psi = rng.uniform(0.5, 1.5, n)
+    Q[0], P[0], qs[0], ps[0] = 0.0, 0.0, 0.0, 0.0
+    ext = {"amp": 0.7, "mode": 2}
+    a, _, ha = O.run_p2(Q, P, qs, ps, psi, L, ng, 0.05, 30, ext=ext, self_field=False)
+    b, _, hb = O.run(Q, P, qs, ps, psi, L, ng, 0.05, 30, ext=ext, self_field=False)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert [h["H"] for h in ha] == [h["H"] for h in hb]
+    assert all(h["W"] == 0.0 for h in ha)
+    assert a[0][0] == 0.0 and a[1][0] == 0.0
+    # with the self field the P2 field does act (a different trajectory from P1)
+    c, _, _ = O.run_p2(Q, P, qs, ps, psi, L, ng, 0.05, 30, ext=ext)
+    assert not np.allclose(c[1], b[1])
