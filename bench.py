@@ -14,8 +14,10 @@
 One step = one pass of the whole hot path over the batch of particles: the Poisson solve of
 the previous deposit (every workgroup of the fused kernel solves it in its prologue),
 pending half-kick, kinetic diagnostics, half-kick, drift, deposit.  --monopole runs the same
-workload as plain particle-in-cell particles (p* = q* = 0, 20 bytes per update).  Default workload: the two-stream instability, N = 2^20
-decorated particles, Ng = 512, dt = 0.05, FP32 state with compensated deposition.
+workload as plain particle-in-cell particles (p* = q* = 0, 20 bytes per update);
+--element-order 2 runs it with P2 elements (the same 36 bytes per update, a load vector of
+2 Ng nodes).  Default workload: the two-stream instability, N = 2^20 decorated particles,
+Ng = 512, dt = 0.05, FP32 state with compensated deposition.
 
 Prints ONE JSON line on stdout.  `value` = N * K / wall time of the K timed steps
 (particle state resident in HBM, graph-replayed steps).  `roofline` divides the fused
@@ -107,6 +109,14 @@ def copy_calibration():
     log(f"copied {COPY_BYTES} bytes 3 times")
 
 
+def base_workload(name: str) -> str:
+    """The workload a bench line's name derives from (without its _p2 / _monopole suffixes)."""
+    for suffix in ("_p2", "_monopole"):
+        if name.endswith(suffix):
+            name = name[:-len(suffix)]
+    return name
+
+
 def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
     """Write profiles/pmc_k_fused_<workload>.json: FETCH_SIZE + WRITE_SIZE per fused launch,
     each scaled by the ratio of known bytes to what the same counter reads for a copy."""
@@ -121,8 +131,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
     w_scale = COPY_BYTES / (cw_kib * 1024.0)
     fetch_b = fetch_kib * 1024.0 * f_scale
     write_b = write_kib * 1024.0 * w_scale
-    w, _ = make_workload(workload[:-len("_monopole")] if workload.endswith("_monopole")
-                         else workload)
+    w, _ = make_workload(base_workload(workload))
     rec = {"kernel": "k_fused", "workload": workload, "n": w.n,
            "kernel_src_sha": kernel_src_sha(),
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
@@ -631,23 +640,29 @@ def run_primitives(args):
                       "primitives": res}), flush=True)
 
 
-def cpu_baseline(state, w, budget_s: float, max_steps: int):
-    """FP64 oracle steps on the same initial state until the time budget is spent."""
+def cpu_baseline(state, w, budget_s: float, max_steps: int, order: int = 1):
+    """FP64 oracle steps on the same initial state until the time budget is spent (P2
+    steps with order 2)."""
     import numpy as np
     import oracle as O
     st = tuple(np.asarray(state[k], dtype=np.float64).copy() for k in ("Q", "P", "qs", "ps", "psi"))
-    fld = O.solve_field(st[0], st[3], st[4], w.L, w.ng)
+    if order == 2:
+        fld = O.solve_field_p2(st[0], st[3], st[4], w.L, w.ng)
+        step, name = O.step_p2, "oracle.step_p2"
+    else:
+        fld = O.solve_field(st[0], st[3], st[4], w.L, w.ng)
+        step, name = O.step, "oracle.step"
     t0 = time.perf_counter()
     k = 0
     while k < max_steps:
-        st, fld = O.step(st, fld, w.L, w.ng, w.dt)
+        st, fld = step(st, fld, w.L, w.ng, w.dt)
         k += 1
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
     return {"value": w.n * k / el, "unit": "decorated-particle updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{k} oracle.step calls (FP64 NumPy, single thread) on the full "
+            "sample": f"{k} {name} calls (FP64 NumPy, single thread) on the full "
                       f"{w.name} state, N={w.n}, Ng={w.ng}, from t=0; {el:.1f} s"}
 
 
@@ -673,6 +688,8 @@ def main():
     ap.add_argument("--markers", type=int, default=1 << 22, help="cluster: markers")
     ap.add_argument("--monopole", action="store_true",
                     help="run the workload as monopole-only (plain particle-in-cell) particles")
+    ap.add_argument("--element-order", type=int, default=1, choices=(1, 2),
+                    help="2: P2 elements (vertex and midpoint nodes) in place of P1")
     ap.add_argument("--primitives", action="store_true",
                     help="time vp_deposit and vp_gather_push on their own")
     ap.add_argument("--precision-study", action="store_true",
@@ -744,7 +761,7 @@ def main():
     torch.cuda.set_stream(stream)
     sim = vp.Simulation(state, w.L, w.ng, w.dt, prec, hist_cap=max(64, args.steps + args.warmup + 8),
                         sort_every=args.sort_every, sort_chunk=args.sort_chunk,
-                        monopole_only=args.monopole)
+                        monopole_only=args.monopole, element_order=args.element_order)
     tuning_us = None
     if args.launch:
         sim.set_tuning(**parse_launch(args.launch))
@@ -796,7 +813,8 @@ def main():
     achieved = bytes_per_launch / kern_avg_s / 1e9
     # counters were taken on the one-launch-per-step kernel; the persistent kernel is a
     # different kernel (and moves far fewer bytes), so it reports none
-    traffic_key = args.workload + ("_monopole" if args.monopole else "")
+    suffix = ("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
+    traffic_key = args.workload + suffix
     traffic = None if persistent else load_traffic(traffic_key, n)
     out = {
         "metric": METRIC,
@@ -812,7 +830,7 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": w.name + ("_monopole" if args.monopole else ""), "n": n, "ng": w.ng,
+            "workload": w.name + suffix, "n": n, "ng": w.ng, "element_order": args.element_order,
             "L": w.L, "dt": w.dt,
             "precision": prec, "instances": 1, "launch": tun,
             "sort_every": args.sort_every, "sort_chunk": args.sort_chunk,
@@ -828,7 +846,7 @@ def main():
     }
     if not args.no_cpu:
         log("timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 200)
+        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 200, args.element_order)
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -64,7 +64,8 @@ __all__ = [
     "nodal_curvature", "curvature_at", "solve_field", "kick_values", "kick", "drift", "wrap",
     "diagnostics", "sort_perm", "step", "run", "PROJECTIONS", "external_field",
     "external_energy", "p2_basis", "deposit_p2", "p2_node_weights", "neutralize_p2",
-    "p2_stiffness", "poisson_solve_p2", "field_p2", "solve_field_p2", "kick_p2", "run_p2",
+    "p2_stiffness", "poisson_solve_p2", "field_p2", "solve_field_p2", "kick_p2", "step_p2",
+    "run_p2",
 ]
 
 # Readings of the projection step for phi_h'': element-constant from the lumped projection
@@ -500,6 +501,16 @@ def kick_p2(Q, P, qs, ps, fld, L: float, tau: float, ext=None, self_field: bool 
     return kick_values(P, qs, ps, Ea, ga, tau)
 
 
+def step_p2(state, fld, L: float, ng: int, dt: float, ext=None, self_field: bool = True):
+    """One KDK step with P2 elements (as step(): half-kick, drift, solve, half-kick)."""
+    Q, P, qs, ps, psi = state
+    P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
+    Q, ps = drift(Q, P, qs, ps, L, dt)
+    fld = solve_field_p2(Q, ps, psi, L, ng)
+    P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
+    return (Q, P, qs, ps, psi), fld
+
+
 def run_p2(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, ext=None,
            self_field: bool = True):
     """KDK run with P2 elements; history as run() (E1 and E_amp from the element-average
@@ -511,11 +522,6 @@ def run_p2(Q, P, qs, ps, psi, L: float, ng: int, dt: float, nsteps: int, ext=Non
         return diagnostics(st[1], st[2], st[4], fld, L, st[0], st[3], ext, self_field)
     hist = [diag(state)]
     for _ in range(nsteps):
-        Q, P, qs, ps, psi = state
-        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
-        Q, ps = drift(Q, P, qs, ps, L, dt)
-        fld = solve_field_p2(Q, ps, psi, L, ng)
-        P, qs = kick_p2(Q, P, qs, ps, fld, L, 0.5 * dt, ext, self_field)
-        state = (Q, P, qs, ps, psi)
+        state, fld = step_p2(state, fld, L, ng, dt, ext, self_field)
         hist.append(diag(state))
     return state, fld, hist
