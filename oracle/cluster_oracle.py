@@ -22,12 +22,23 @@ What is computed (readings where the paper leaves a choice are marked):
 Every sum runs over the members in increasing marker index (np.bincount adds in input
 order), so a GPU implementation that sums in the same order agrees bit for bit except
 where it evaluates sin.
+
+The paper allows MiniBatch k-means in place of Lloyd's iteration for large runs.  The
+variant here is the weighted, batched form of Sculley's mini-batch k-means ("Web-scale
+k-means clustering", WWW 2010): per batch of markers (indices given as input; the random
+draw is the caller's), assign each to its nearest current centre, then move every centre
+that received members to the weighted mean of all the batch members it has ever received,
+its previous value standing in for the earlier ones:
+    v_c <- v_c + W_c,   centre_c <- (centre_c v_c(old) + S_c) / v_c(new),
+with W_c, S_c the weight and the weighted coordinate sums of its members in this batch
+(batch order).  No reassignment of starved centres and no stopping test (readings).
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["nearest_centre", "lloyd", "cluster_moments", "cluster_markers", "kmeans_objective"]
+__all__ = ["nearest_centre", "lloyd", "cluster_moments", "cluster_markers", "kmeans_objective",
+           "minibatch", "cluster_markers_minibatch"]
 
 
 def nearest_centre(q, p, cq, cp, chunk: int = 2048):
@@ -114,3 +125,44 @@ def cluster_markers(q, p, w, init_idx, iters: int, L: float):
     Returns (decorated state dict, final assignment)."""
     cq, cp, a = lloyd(q, p, w, init_idx, iters)
     return cluster_moments(q, p, w, a, np.asarray(init_idx).shape[0], L), a
+
+
+def minibatch(q, p, w, init_idx, batches, record: bool = False):
+    """Mini-batch k-means from the markers init_idx, one update per batch (each batch an
+    array of marker indices; a repeated index counts once per occurrence).  Returns the
+    centres and the weight v each has absorbed, and with record=True also the assignment
+    of every batch (a list of arrays)."""
+    q = np.asarray(q, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    init_idx = np.asarray(init_idx)
+    k = init_idx.shape[0]
+    cq = q[init_idx].copy()
+    cp = p[init_idx].copy()
+    v = np.zeros(k)
+    seen = []
+    for B in batches:
+        B = np.asarray(B)
+        qb, pb, wb = q[B], p[B], w[B]
+        a = nearest_centre(qb, pb, cq, cp)
+        cnt = np.bincount(a, minlength=k)
+        W = np.bincount(a, weights=wb, minlength=k)
+        SQ = np.bincount(a, weights=wb * qb, minlength=k)
+        SP = np.bincount(a, weights=wb * pb, minlength=k)
+        live = cnt > 0
+        vn = v[live] + W[live]
+        cq[live] = (cq[live] * v[live] + SQ[live]) / vn
+        cp[live] = (cp[live] * v[live] + SP[live]) / vn
+        v[live] = vn
+        if record:
+            seen.append(a)
+    return (cq, cp, v, seen) if record else (cq, cp, v)
+
+
+def cluster_markers_minibatch(q, p, w, init_idx, batches, L: float):
+    """Algorithm 1 with mini-batch k-means: the centres after the batches, a final
+    assignment of every marker to them, then the decorated particle of each cluster.
+    Returns (decorated state dict, final assignment, absorbed weights v)."""
+    cq, cp, v = minibatch(q, p, w, init_idx, batches)
+    a = nearest_centre(q, p, cq, cp)
+    return cluster_moments(q, p, w, a, np.asarray(init_idx).shape[0], L), a, v

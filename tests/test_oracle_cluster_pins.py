@@ -149,3 +149,88 @@ def test_decorated_load_beats_monopoles_at_the_centres():
         b_mono = O.deposit(dec["Q"], np.zeros_like(dec["Q"]), dec["psi"], L, ng)
         ratios.append(np.linalg.norm(b_dec - b_mark) / np.linalg.norm(b_mono - b_mark))
     assert ratios[0] < 0.1 and ratios[0] < ratios[1] < ratios[2] < 0.5, ratios
+
+
+# ---------------------------------------------------------------- mini-batch k-means
+
+def test_minibatch_one_full_batch_is_one_lloyd_iteration():
+    """From zero absorbed weight, a batch of every marker once moves each centre to the
+    weighted mean of its markers: exactly Lloyd's update."""
+    rng = np.random.default_rng(6)
+    q, p, w = _markers(rng, 3000, 7.0)
+    init = rng.choice(q.size, 60, replace=False)
+    cq, cp, v = O.minibatch(q, p, w, init, [np.arange(q.size)])
+    lq, lp, _ = O.lloyd(q, p, w, init, 1)
+    assert np.array_equal(cq, lq) and np.array_equal(cp, lp)
+    a = O.nearest_centre(q, p, q[init], p[init])
+    assert np.allclose(v, np.bincount(a, weights=w, minlength=60), rtol=1e-15, atol=0)
+
+
+def test_minibatch_centres_are_running_weighted_means():
+    """After any sequence of batches (repeated indices included) every centre that received
+    members equals the weighted mean of all the batch members it received, at the time
+    they were assigned; the others keep their starting markers; the absorbed weights add up
+    to the weight of every drawn index."""
+    rng = np.random.default_rng(7)
+    q, p, w = _markers(rng, 2000, 5.0)
+    k = 40
+    init = rng.choice(q.size, k, replace=False)
+    batches = [rng.integers(0, q.size, 300) for _ in range(12)]
+    cq, cp, v, seen = O.minibatch(q, p, w, init, batches, record=True)
+    allb = np.concatenate(batches)
+    alla = np.concatenate(seen)
+    assert abs(v.sum() - w[allb].sum()) < 1e-12 * w[allb].sum()
+    for c in range(k):
+        m = alla == c
+        if not m.any():
+            assert cq[c] == q[init[c]] and cp[c] == p[init[c]] and v[c] == 0.0
+            continue
+        W = w[allb][m].sum()
+        assert abs(cq[c] - np.sum(w[allb][m] * q[allb][m]) / W) < 1e-12 * 5.0
+        assert abs(cp[c] - np.sum(w[allb][m] * p[allb][m]) / W) < 1e-12 * 3.0
+        assert abs(v[c] - W) < 1e-12 * W
+    # the final assignment of Algorithm 1 takes every marker to its nearest final centre
+    # (brute force over the centres for a sample of markers)
+    _, a, v2 = O.cluster_markers_minibatch(q, p, w, init, batches, 5.0)
+    assert np.array_equal(v2, v)
+    for i in rng.choice(q.size, 60, replace=False):
+        d2 = [(q[i] - cq[c]) ** 2 + (p[i] - cp[c]) ** 2 for c in range(k)]
+        assert a[i] == int(np.argmin(d2))
+
+
+def test_minibatch_recovers_separated_blobs():
+    rng = np.random.default_rng(8)
+    centres = np.array([[1.0, -2.0], [4.0, 0.5], [7.5, 2.0], [2.5, 2.5], [6.0, -1.5]])
+    lab = np.repeat(np.arange(5), 80)
+    q = centres[lab, 0] + 0.05 * rng.standard_normal(lab.size)
+    p = centres[lab, 1] + 0.05 * rng.standard_normal(lab.size)
+    w = rng.uniform(0.5, 1.5, lab.size)
+    perm = rng.permutation(lab.size)
+    q, p, w, lab = q[perm], p[perm], w[perm], lab[perm]
+    init = np.array([np.nonzero(lab == c)[0][0] for c in range(5)])
+    batches = [rng.integers(0, lab.size, 40) for _ in range(20)]
+    dec, a, _ = O.cluster_markers_minibatch(q, p, w, init, batches, 10.0)
+    assert np.array_equal(a, lab)
+    assert np.array_equal(dec["psi"], np.bincount(lab, weights=w))
+
+
+def test_minibatch_objective_is_close_to_lloyds():
+    """The paper allows mini-batch k-means for large runs on the ground that the results are
+    nearly the same: on Landau markers (40 per cluster) 30 batches of a fifth of the markers
+    land within 15% of the within-cluster sum of squares of 10 Lloyd iterations."""
+    import workloads as W
+    w_ = W.landau_linear()
+    w_.params["alpha"] = 0.3
+    w_.L = 4 * math.pi
+    w_.params["k"] = 2 * math.pi / w_.L
+    st = W.random_markers(w_, 20000, seed=3)
+    q, p, w = st["Q"], st["P"], st["psi"]
+    rng = np.random.default_rng(0)
+    init = rng.choice(q.size, 500, replace=False)
+    cq, cp, a = O.lloyd(q, p, w, init, 10)
+    lloyd_obj = O.kmeans_objective(q, p, w, cq, cp, a)
+    batches = [rng.integers(0, q.size, 4000) for _ in range(30)]
+    mq, mp, _ = O.minibatch(q, p, w, init, batches)
+    mb_obj = O.kmeans_objective(q, p, w, mq, mp, O.nearest_centre(q, p, mq, mp))
+    start_obj = O.kmeans_objective(q, p, w, q[init], p[init], O.nearest_centre(q, p, q[init], p[init]))
+    assert mb_obj < 1.15 * lloyd_obj and mb_obj < 0.7 * start_obj, (mb_obj, lloyd_obj, start_obj)
