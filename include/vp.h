@@ -343,6 +343,36 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
                              void* workspace, void* stream, double* Q, double* P, double* qs,
                              double* ps, double* psi, int32_t* assign_out, int32_t* n_out);
 
+/* Algorithm 1 with mini-batch k-means in place of Lloyd's iteration, which the paper allows
+ * for large runs (Section 4, before Algorithm 1).  The update is the weighted, batched form
+ * of Sculley's mini-batch k-means ("Web-scale k-means clustering", 2010).  From the k
+ * markers init_idx, nbatch batches are taken in turn; batch t is the `batch` marker indices
+ * batch_idx[t*batch .. (t+1)*batch) (device int32, nbatch*batch of them, each in [0, m),
+ * repeats allowed and counted once per occurrence; the caller draws them).  Per batch:
+ * every batch marker goes to its nearest current centre (as in vp_cluster_markers), then
+ * every centre c that received members moves to the weighted mean of all the batch members
+ * it has received so far, its old value standing in for the earlier ones:
+ *   v_c <- v_c + W_c,   centre_c <- (centre_c * v_c(old) + S_c) / v_c(new),
+ * W_c and S_c being the weight and weighted (q, p) sums of its members in this batch, summed
+ * in batch order (v starts at 0, so a centre's first update is the plain weighted mean).
+ * No reassignment of starved centres and no stopping test.  Then, as vp_cluster_markers
+ * after its iterations: a final assignment of every marker and one decorated particle per
+ * non-empty cluster.  Arguments as for vp_cluster_markers, plus: 1 <= batch <= m,
+ * nbatch >= 1, batch * nbatch < 2^31; workspace of
+ * vp_cluster_minibatch_workspace_bytes(m, k, batch) bytes; absorbed_out (device float64,
+ * k, or NULL) receives each centre's v.  Every batch index is checked on the device before
+ * use (VP_ERR_ARG if any lies outside [0, m)).  Synchronises the stream.  Errors:
+ * VP_ERR_ARG, VP_ERR_HIP. */
+vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
+                                               size_t* bytes_out);
+vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,
+                                       int64_t m, int32_t k, const int32_t* init_idx,
+                                       const int32_t* batch_idx, int32_t batch, int32_t nbatch,
+                                       double L, void* workspace, void* stream, double* Q,
+                                       double* P, double* qs, double* ps, double* psi,
+                                       int32_t* assign_out, double* absorbed_out,
+                                       int32_t* n_out);
+
 const char* vp_status_string(vp_status s);
 const char* vp_last_error(void);
 int32_t vp_abi_version(void);

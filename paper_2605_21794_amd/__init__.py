@@ -65,14 +65,19 @@ def workspace_bytes(cfg) -> int:
 
 
 def cluster_markers(Q, P, w, k: int, L_: float, iters: int = 10, init_idx=None, seed: int = 0,
-                    return_assign: bool = False, stream=None):
+                    return_assign: bool = False, stream=None, batch=None, nbatch: int = 0,
+                    batch_idx=None):
     """Decorated particles from markers (the paper's Algorithm 1), on the GPU.
 
     Q, P, w: marker positions in [0, L), velocities and positive weights (device or host
     arrays, taken as float64).  k clusters from `iters` Lloyd iterations starting at the
-    markers init_idx (by default k distinct markers drawn with `seed`).  Returns a dict of
-    device float64 tensors Q, P, qs, ps, psi (one entry per non-empty cluster), plus
-    `assign` (int32, the final cluster of each marker) when return_assign."""
+    markers init_idx (by default k distinct markers drawn with `seed`).  With `batch`, the
+    clusters come from `nbatch` mini-batch updates instead (batches of `batch` marker
+    indices drawn with replacement with `seed`, or the given batch_idx of shape
+    (nbatch, batch)); `iters` is then not used.  Returns a dict of device float64 tensors
+    Q, P, qs, ps, psi (one entry per non-empty cluster), plus `assign` (int32, the final
+    cluster of each marker) when return_assign, and `absorbed` (each centre's absorbed
+    weight) in the mini-batch case."""
     import torch
     if not torch.cuda.is_available():
         raise RuntimeError("no GPU visible: the decorated-particle path runs only on the GPU")
@@ -83,30 +88,55 @@ def cluster_markers(Q, P, w, k: int, L_: float, iters: int = 10, init_idx=None, 
         if isinstance(a, torch.Tensor):
             return a.to(device=dev, dtype=torch.float64).contiguous()
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    def t32(a):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=dev, dtype=torch.int32).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
     q, p, wt = t64(Q), t64(P), t64(w)
     m = int(q.numel())
+    g = torch.Generator().manual_seed(int(seed))
     if init_idx is None:
-        g = torch.Generator().manual_seed(int(seed))
         init_idx = torch.randperm(m, generator=g)[:int(k)]
-    idx = (init_idx.to(device=dev, dtype=torch.int32).contiguous()
-           if isinstance(init_idx, torch.Tensor)
-           else torch.from_numpy(np.ascontiguousarray(init_idx, dtype=np.int32)).to(dev))
+    idx = t32(init_idx)
+    mini = batch is not None or batch_idx is not None
+    if mini:
+        if batch_idx is None:
+            batch_idx = torch.randint(0, m, (int(nbatch), int(batch)), generator=g)
+        bidx = t32(batch_idx)
+        if bidx.dim() != 2:
+            raise ValueError("batch_idx must have shape (nbatch, batch)")
+        nbatch, batch = int(bidx.shape[0]), int(bidx.shape[1])
     b = c_size_t()
-    L.check(lib.vp_cluster_workspace_bytes(m, int(k), byref(b)), "vp_cluster_workspace_bytes")
+    if mini:
+        L.check(lib.vp_cluster_minibatch_workspace_bytes(m, int(k), batch, byref(b)),
+                "vp_cluster_minibatch_workspace_bytes")
+    else:
+        L.check(lib.vp_cluster_workspace_bytes(m, int(k), byref(b)), "vp_cluster_workspace_bytes")
     ws = torch.empty(max(256, int(b.value)), dtype=torch.uint8, device=dev)
     out = {f: torch.empty(int(k), dtype=torch.float64, device=dev) for f in FIELDS}
     assign = torch.empty(m, dtype=torch.int32, device=dev) if return_assign else None
+    absorbed = torch.empty(int(k), dtype=torch.float64, device=dev) if mini else None
     n = c_int32()
     s = stream if stream is not None else torch.cuda.current_stream(dev)
-    L.check(lib.vp_cluster_markers(
-        c_void_p(q.data_ptr()), c_void_p(p.data_ptr()), c_void_p(wt.data_ptr()), m, int(k),
-        c_void_p(idx.data_ptr()), int(iters), float(L_), c_void_p(ws.data_ptr()),
-        c_void_p(s.cuda_stream), *(c_void_p(out[f].data_ptr()) for f in FIELDS),
-        c_void_p(assign.data_ptr()) if assign is not None else None, byref(n)),
-        "vp_cluster_markers")
+    outs = [c_void_p(out[f].data_ptr()) for f in FIELDS]
+    ap = c_void_p(assign.data_ptr()) if assign is not None else None
+    if mini:
+        L.check(lib.vp_cluster_markers_minibatch(
+            c_void_p(q.data_ptr()), c_void_p(p.data_ptr()), c_void_p(wt.data_ptr()), m, int(k),
+            c_void_p(idx.data_ptr()), c_void_p(bidx.data_ptr()), batch, nbatch, float(L_),
+            c_void_p(ws.data_ptr()), c_void_p(s.cuda_stream), *outs, ap,
+            c_void_p(absorbed.data_ptr()), byref(n)), "vp_cluster_markers_minibatch")
+    else:
+        L.check(lib.vp_cluster_markers(
+            c_void_p(q.data_ptr()), c_void_p(p.data_ptr()), c_void_p(wt.data_ptr()), m, int(k),
+            c_void_p(idx.data_ptr()), int(iters), float(L_), c_void_p(ws.data_ptr()),
+            c_void_p(s.cuda_stream), *outs, ap, byref(n)), "vp_cluster_markers")
     res = {f: out[f][:n.value] for f in FIELDS}
     if return_assign:
         res["assign"] = assign
+    if mini:
+        res["absorbed"] = absorbed
     return res
 
 

@@ -82,6 +82,13 @@ SIGNATURES = {
                                      c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_void_p,
                                      POINTER(c_int32)]),
+    "vp_cluster_minibatch_workspace_bytes": (c_int32, [c_int64, c_int32, c_int32,
+                                                       POINTER(c_size_t)]),
+    "vp_cluster_markers_minibatch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                                               c_void_p, c_void_p, c_int32, c_int32, c_double,
+                                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                               c_void_p, c_void_p, c_void_p, c_void_p,
+                                               POINTER(c_int32)]),
     "vp_status_string": (c_char_p, [c_int32]),
     "vp_last_error": (c_char_p, []),
     "vp_abi_version": (c_int32, []),

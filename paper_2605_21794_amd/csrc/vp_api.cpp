@@ -844,10 +844,13 @@ vp_status vp_cluster_workspace_bytes(int64_t m, int32_t k, size_t* bytes_out) {
   return VP_OK;
 }
 
-vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* wm, int64_t m,
-                             int32_t k, const int32_t* init_idx, int32_t iters, double L,
-                             void* workspace, void* stream, double* Q, double* P, double* qs,
-                             double* ps, double* psi, int32_t* assign_out, int32_t* n_out) {
+// Shared body of the two initialisation entry points (nbatch = 0: Lloyd only).
+static vp_status cluster_impl(const double* Qm, const double* Pm, const double* wm, int64_t m,
+                              int32_t k, const int32_t* init_idx, const int32_t* batch_idx,
+                              int32_t batch, int32_t nbatch, int32_t iters, double L,
+                              void* workspace, void* stream, double* Q, double* P, double* qs,
+                              double* ps, double* psi, int32_t* assign_out,
+                              double* absorbed_out, int32_t* n_out) {
   VP_TRY(cluster_check(m, k));
   if (!Qm || !Pm || !wm || !init_idx || !Q || !P || !qs || !ps || !psi || !n_out)
     return fail(VP_ERR_ARG, "NULL argument");
@@ -855,9 +858,12 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
   for (int i = 0; i < 9; ++i)
     if (!aligned(dptr[i], i < 8 ? 8 : 4)) return fail(VP_ERR_ARG, "argument %d misaligned", i);
   if (assign_out && !aligned(assign_out, 4)) return fail(VP_ERR_ARG, "assign_out misaligned");
+  if (absorbed_out && !aligned(absorbed_out, 8)) return fail(VP_ERR_ARG, "absorbed_out misaligned");
   if (!(iters >= 0)) return fail(VP_ERR_ARG, "iters must be >= 0");
   if (!(L > 0.0) || !std::isfinite(L)) return fail(VP_ERR_ARG, "L must be positive and finite");
   if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
+  if (nbatch > 0 && (!batch_idx || !aligned(batch_idx, 4)))
+    return fail(VP_ERR_ARG, "batch_idx NULL or misaligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
   // every starting marker index must address a marker
   std::vector<int32_t> idx(k);
@@ -865,15 +871,58 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
   VP_HIP(hipStreamSynchronize(s));
   for (int32_t a = 0; a < k; ++a)
     if (idx[a] < 0 || idx[a] >= m) return fail(VP_ERR_ARG, "init_idx[%d] = %d outside [0, %lld)", a, idx[a], (long long)m);
-  const vpk::ClusterWs lay = vpk::cluster_layout(m, k);
+  const vpk::ClusterWs lay = vpk::cluster_layout(m, k, nbatch > 0 ? batch : 0);
+  if (nbatch > 0) {  // and so must every batch index
+    int bad = 0;
+    VP_HIP(vpk::cluster_count_bad(batch_idx, (long long)batch * nbatch, m, workspace, lay, &bad, s));
+    if (bad) return fail(VP_ERR_ARG, "%d batch indices outside [0, %lld)", bad, (long long)m);
+  }
   double mm[2] = {0.0, 0.0};
   VP_HIP(vpk::cluster_p_range(Pm, m, workspace, lay, mm, s));
   if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) return fail(VP_ERR_ARG, "non-finite marker velocities");
   int n = 0;
-  VP_HIP(vpk::cluster_run(Qm, Pm, wm, m, k, init_idx, iters, L, mm[0], mm[1], workspace, lay, Q, P,
-                          qs, ps, psi, assign_out, &n, s));
+  VP_HIP(vpk::cluster_run(Qm, Pm, wm, m, k, init_idx, batch_idx, batch, nbatch, iters, L, mm[0],
+                          mm[1], workspace, lay, Q, P, qs, ps, psi, assign_out, absorbed_out, &n,
+                          s));
   *n_out = n;
   return VP_OK;
+}
+
+vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* wm, int64_t m,
+                             int32_t k, const int32_t* init_idx, int32_t iters, double L,
+                             void* workspace, void* stream, double* Q, double* P, double* qs,
+                             double* ps, double* psi, int32_t* assign_out, int32_t* n_out) {
+  return cluster_impl(Qm, Pm, wm, m, k, init_idx, nullptr, 0, 0, iters, L, workspace, stream, Q,
+                      P, qs, ps, psi, assign_out, nullptr, n_out);
+}
+
+static vp_status minibatch_check(int64_t m, int32_t k, int32_t batch, int32_t nbatch) {
+  VP_TRY(cluster_check(m, k));
+  if (batch < 1 || batch > m) return fail(VP_ERR_ARG, "batch = %d must lie in [1, m]", batch);
+  if (nbatch < 1) return fail(VP_ERR_ARG, "nbatch must be >= 1");
+  if ((long long)batch * nbatch > 0x7fffffffLL)
+    return fail(VP_ERR_ARG, "batch * nbatch = %lld exceeds 2^31 - 1", (long long)batch * nbatch);
+  return VP_OK;
+}
+
+vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
+                                               size_t* bytes_out) {
+  if (!bytes_out) return fail(VP_ERR_ARG, "NULL argument");
+  VP_TRY(minibatch_check(m, k, batch, 1));
+  *bytes_out = vpk::cluster_layout(m, k, batch).total;
+  return VP_OK;
+}
+
+vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,
+                                       int64_t m, int32_t k, const int32_t* init_idx,
+                                       const int32_t* batch_idx, int32_t batch, int32_t nbatch,
+                                       double L, void* workspace, void* stream, double* Q,
+                                       double* P, double* qs, double* ps, double* psi,
+                                       int32_t* assign_out, double* absorbed_out,
+                                       int32_t* n_out) {
+  VP_TRY(minibatch_check(m, k, batch, nbatch));
+  return cluster_impl(Qm, Pm, wm, m, k, init_idx, batch_idx, batch, nbatch, 0, L, workspace,
+                      stream, Q, P, qs, ps, psi, assign_out, absorbed_out, n_out);
 }
 
 vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {

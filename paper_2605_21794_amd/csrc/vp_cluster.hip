@@ -343,6 +343,53 @@ __global__ void k_centres(const double* __restrict__ q, const double* __restrict
   cp[a] = SP / W;
 }
 
+// Mini-batch k-means, the weighted batched form of Sculley's update ("Web-scale k-means
+// clustering", 2010): gather the batch's markers (indices clamped into [0, m); the host has
+// checked them), then move each centre that received members of this batch to the weighted
+// mean of every batch member it has received, its old value standing in for the earlier
+// ones: v <- v + W, centre <- (centre v_old + S) / v.  W and S are summed over the members
+// in batch order (the grouping sort is stable), so the result is that of a sequential pass.
+__global__ void k_gather_batch(const double* __restrict__ q, const double* __restrict__ p,
+                               const double* __restrict__ w, long long m,
+                               const int* __restrict__ idx, int b, double* __restrict__ bq,
+                               double* __restrict__ bp, double* __restrict__ bw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b) return;
+  long long i = idx[t];
+  i = i < 0 ? 0 : (i >= m ? m - 1 : i);
+  bq[t] = q[i];
+  bp[t] = p[i];
+  bw[t] = w[i];
+}
+
+// Count the batch indices outside [0, m) (host check before any use).
+__global__ void k_count_bad(const int* __restrict__ idx, long long n, long long m,
+                            int* __restrict__ bad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && (idx[t] < 0 || (long long)idx[t] >= m)) atomicAdd(bad, 1);
+}
+
+__global__ void k_minibatch_update(const double* __restrict__ bq, const double* __restrict__ bp,
+                                   const double* __restrict__ bw, const int* __restrict__ off,
+                                   const int* __restrict__ order, int k, double* __restrict__ cq,
+                                   double* __restrict__ cp, double* __restrict__ v) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= k) return;
+  const int b = off[a], e = off[a + 1];
+  if (b == e) return;
+  double W = 0.0, SQ = 0.0, SP = 0.0;
+  for (int t = b; t < e; ++t) {
+    const int i = order[t];
+    W += bw[i];
+    SQ += bw[i] * bq[i];
+    SP += bw[i] * bp[i];
+  }
+  const double vo = v[a], vn = vo + W;
+  cq[a] = (cq[a] * vo + SQ) / vn;
+  cp[a] = (cp[a] * vo + SP) / vn;
+  v[a] = vn;
+}
+
 // The decorated particle of each non-empty cluster (Algorithm 1): weight, centre member
 // nearest the weighted mean (first in marker order on ties), periodic spatial moment and
 // velocity moment, all summed in marker order.  flag[a] = 1 for a non-empty cluster.
@@ -453,7 +500,7 @@ long long scan_tmp_ints(long long n) { return 2 * (n / kScanTile + 2); }
 
 }  // namespace
 
-ClusterWs cluster_layout(long long m, int k) {
+ClusterWs cluster_layout(long long m, int k, int batch) {
   ClusterWs w{};
   const long long gmax = cluster_max_cells(k);
   size_t o = 0;
@@ -488,8 +535,31 @@ ClusterWs cluster_layout(long long m, int k) {
     if (nmax < gmax) nmax = gmax;
     w.scan = o;  o = a256(o + (size_t)scan_tmp_ints(nmax) * sizeof(int));
   }
+  // mini-batch regions (batch <= m: the batch's assignment and grouping reuse the marker
+  // arrays above)
+  const size_t nb = batch > 0 ? (size_t)batch : 0;
+  w.v = o;       o = a256(o + (batch > 0 ? (size_t)k : 0) * sizeof(double));
+  w.bq = o;      o = a256(o + nb * sizeof(double));
+  w.bp = o;      o = a256(o + nb * sizeof(double));
+  w.bw = o;      o = a256(o + nb * sizeof(double));
+  w.bperm = o;   o = a256(o + nb * sizeof(int));
+  w.bad = o;     o = a256(o + sizeof(int));
   w.total = o;
   return w;
+}
+
+hipError_t cluster_count_bad(const int* idx, long long n, long long m, void* ws,
+                             const ClusterWs& w, int* host_bad, hipStream_t s) {
+  int* bad = reinterpret_cast<int*>(static_cast<char*>(ws) + w.bad);
+  hipError_t e = fill_int(bad, 1, 0, s);
+  if (e != hipSuccess) return e;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_count_bad, dim3(blocks_for(n, 256)), dim3(256), 0, s, idx, n, m, bad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = hipMemcpyAsync(host_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(s);
 }
 
 hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
@@ -558,9 +628,11 @@ static hipError_t group_markers(long long m, int k, const int* assign, int* cnt,
 }
 
 hipError_t cluster_run(const double* q, const double* p, const double* w, long long m, int k,
-                       const int* init_idx, int iters, double L, double pmin, double pmax,
-                       void* ws, const ClusterWs& lay, double* Q, double* P, double* qs,
-                       double* ps, double* psi, int* assign_out, int* host_n, hipStream_t s) {
+                       const int* init_idx, const int* batch_idx, int batch, int nbatch,
+                       int iters, double L, double pmin, double pmax, void* ws,
+                       const ClusterWs& lay, double* Q, double* P, double* qs, double* ps,
+                       double* psi, int* assign_out, double* absorbed_out, int* host_n,
+                       hipStream_t s) {
   char* base = static_cast<char*>(ws);
   double* cq = reinterpret_cast<double*>(base + lay.cq);
   double* cp = reinterpret_cast<double*>(base + lay.cp);
@@ -624,17 +696,53 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
   hipLaunchKernelGGL(k_init_centres, dim3(blocks_for(k, 256)), dim3(256), 0, s, q, p, init_idx,
                      k, cq, cp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int it = 0; it <= iters; ++it) {
-    // bin the centres
-    if ((e = fill_int(ccnt, G, 0, s)) != hipSuccess) return e;
-    if ((e = fill_int(ccur, G, 0, s)) != hipSuccess) return e;
+  // bin the current centres into the grid (cell lists for the ring search)
+  auto bin_centres = [&]() -> hipError_t {
+    hipError_t be = fill_int(ccnt, G, 0, s);
+    if (be != hipSuccess) return be;
+    if ((be = fill_int(ccur, G, 0, s)) != hipSuccess) return be;
     hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(k, 256)), dim3(256), 0, s, cq, cp, k, g,
                        cell_of, ccnt);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = scan_int(ccnt, G, coff, stmp, s)) != hipSuccess) return e;
+    if ((be = hipGetLastError()) != hipSuccess) return be;
+    if ((be = scan_int(ccnt, G, coff, stmp, s)) != hipSuccess) return be;
     hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(k, 256)), dim3(256), 0, s, cell_of, k, coff,
                        ccur, clist);
+    return hipGetLastError();
+  };
+  if (nbatch > 0) {
+    // mini-batch updates; the batch's assignment and grouping use the marker arrays (b <= m)
+    double* v = reinterpret_cast<double*>(base + lay.v);
+    double* bq = reinterpret_cast<double*>(base + lay.bq);
+    double* bp = reinterpret_cast<double*>(base + lay.bp);
+    double* bw = reinterpret_cast<double*>(base + lay.bw);
+    int* bperm = reinterpret_cast<int*>(base + lay.bperm);
+    if ((e = launch_fill_zero(v, (size_t)k * sizeof(double), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iota, dim3(blocks_for(batch, 256)), dim3(256), 0, s, bperm,
+                       (long long)batch);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int t = 0; t < nbatch; ++t) {
+      if ((e = bin_centres()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_gather_batch, dim3(blocks_for(batch, 256)), dim3(256), 0, s, q, p, w,
+                         m, batch_idx + (size_t)t * batch, batch, bq, bp, bw);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_assign, dim3(blocks_for(batch, 256)), dim3(256), 0, s, bq, bp,
+                         (long long)batch, bperm, cq, cp, g, coff, clist, assign);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = group_markers(batch, k, assign, cnt, off, keys_a, vals_a, keys_b, vals_b, hist,
+                             hoff, stmp, &order, s)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_minibatch_update, dim3(blocks_for(k, 64)), dim3(64), 0, s, bq, bp, bw,
+                         off, order, k, cq, cp, v);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (absorbed_out) {
+      if ((e = hipMemcpyAsync(absorbed_out, v, (size_t)k * sizeof(double),
+                              hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return e;
+    }
+  }
+  for (int it = 0; it <= iters; ++it) {
+    if ((e = bin_centres()) != hipSuccess) return e;
     // assign, group
     hipLaunchKernelGGL(k_assign, dim3(blocks_for(m, 256)), dim3(256), 0, s, q, p, m, perm, cq,
                        cp, g, coff, clist, assign);

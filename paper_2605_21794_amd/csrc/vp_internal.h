@@ -133,20 +133,30 @@ inline long long cluster_max_cells(int k) { return 4LL * k + 64; }
 inline long long radix_blocks(long long m) { return (m + kRadixChunk - 1) / kRadixChunk; }
 
 // Byte offsets of the regions of the caller's clustering workspace (256-byte aligned).
+// `batch` > 0 adds the mini-batch regions (absorbed weights v, the gathered batch, its
+// visiting order) for batches of that many markers (batch <= m).
 struct ClusterWs {
   size_t cq, cp, assign, cnt, off, perm, keys_a, vals_a, keys_b, vals_b, hist, hoff, cell_of, ccnt,
-      coff, ccur, clist, mm, tQ, tP, tqs, tps, tpsi, flag, pos, scan, total;
+      coff, ccur, clist, mm, tQ, tP, tqs, tps, tpsi, flag, pos, scan, v, bq, bp, bw, bperm, bad,
+      total;
 };
-ClusterWs cluster_layout(long long m, int k);
+ClusterWs cluster_layout(long long m, int k, int batch = 0);
+// *host_bad = how many of the n device indices idx lie outside [0, m) (synchronises).
+hipError_t cluster_count_bad(const int* idx, long long n, long long m, void* ws,
+                             const ClusterWs& w, int* host_bad, hipStream_t s);
 // Velocity range of the markers (synchronises the stream).
 hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
                            double* host_minmax, hipStream_t s);
-// Lloyd iterations, final assignment, moments and compaction; *host_n = decorated particles
-// written (synchronises the stream).
+// nbatch mini-batch updates (batches of `batch` marker indices, batch_idx[t * batch ..]),
+// then Lloyd iterations, final assignment, moments and compaction; *host_n = decorated
+// particles written; absorbed_out (k doubles, or NULL) = the weight each centre absorbed in
+// the batches (synchronises the stream).
 hipError_t cluster_run(const double* q, const double* p, const double* w, long long m, int k,
-                       const int* init_idx, int iters, double L, double pmin, double pmax,
-                       void* ws, const ClusterWs& lay, double* Q, double* P, double* qs,
-                       double* ps, double* psi, int* assign_out, int* host_n, hipStream_t s);
+                       const int* init_idx, const int* batch_idx, int batch, int nbatch,
+                       int iters, double L, double pmin, double pmax, void* ws,
+                       const ClusterWs& lay, double* Q, double* P, double* qs, double* ps,
+                       double* psi, int* assign_out, double* absorbed_out, int* host_n,
+                       hipStream_t s);
 
 // out[2t] = step, out[2t+1] = nonfinite of instance slots[t], t < nslots.
 hipError_t launch_slot_status(const InstDev* d_inst, const int* d_slots, int nslots,

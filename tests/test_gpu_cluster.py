@@ -103,3 +103,79 @@ def test_decorated_particles_run_in_the_engine(vp):
     for f, r in zip(("Q", "P", "qs", "ps", "psi"), ref_state):
         assert np.allclose(got[f], r, rtol=0, atol=1e-10), f
     sim.close()
+
+
+# ---------------------------------------------------------------- mini-batch k-means
+
+def compare_minibatch(vp, q, p, w, k, L, init, batches):
+    got = vp.cluster_markers(q, p, w, k, L, init_idx=init, batch_idx=batches, return_assign=True)
+    ref, a, v = O.cluster_markers_minibatch(q, p, w, init, list(batches), L)
+    assert np.array_equal(got["absorbed"].cpu().numpy(), v)
+    assert np.array_equal(got["assign"].cpu().numpy(), a.astype(np.int32))
+    assert got["Q"].shape[0] == ref["Q"].shape[0]
+    for f in ("Q", "P", "psi", "qs"):
+        assert np.array_equal(got[f].cpu().numpy(), ref[f]), f
+    ps = got["ps"].cpu().numpy()
+    assert np.max(np.abs(ps - ref["ps"])) <= 1e-13 * max(1e-300, np.abs(ref["ps"]).max())
+    return got, ref
+
+
+@pytest.mark.parametrize("m,k,batch,nbatch", [(20000, 500, 4000, 10), (7777, 300, 1000, 25),
+                                              (5000, 1, 100, 3), (3000, 50, 3000, 1),
+                                              (4096, 4096, 512, 4)])
+def test_minibatch_matches_oracle(vp, m, k, batch, nbatch):
+    """Mini-batch updates: the absorbed weights, the final assignment and the decorated
+    particles bit-exact (p* to 1e-13), batches drawn with replacement (repeats count)."""
+    q, p, w, L = landau_markers(m, seed=m + k + 1)
+    rng = np.random.default_rng(k + batch)
+    init = rng.choice(m, k, replace=False)
+    batches = rng.integers(0, m, (nbatch, batch))
+    compare_minibatch(vp, q, p, w, k, L, init, batches)
+
+
+def test_minibatch_one_full_batch_equals_one_lloyd_iteration(vp):
+    """A single batch of every marker once is one Lloyd iteration: the same clusters as the
+    Lloyd entry point with one iteration."""
+    q, p, w, L = landau_markers(6000, seed=4)
+    init = np.random.default_rng(1).choice(6000, 200, replace=False)
+    a = vp.cluster_markers(q, p, w, 200, L, init_idx=init, batch_idx=np.arange(6000)[None, :],
+                           return_assign=True)
+    b = vp.cluster_markers(q, p, w, 200, L, iters=1, init_idx=init, return_assign=True)
+    assert np.array_equal(a["assign"].cpu().numpy(), b["assign"].cpu().numpy())
+    for f in ("Q", "P", "psi", "qs", "ps"):
+        assert np.array_equal(a[f].cpu().numpy(), b[f].cpu().numpy()), f
+
+
+def test_minibatch_rejects_bad_batches(vp):
+    q, p, w, L = landau_markers(1000, seed=2)
+    init = np.arange(10)
+    with pytest.raises(vp.VPError):      # an index outside [0, m)
+        vp.cluster_markers(q, p, w, 10, L, init_idx=init,
+                           batch_idx=np.array([[0, 5, 1000, 3]]))
+    with pytest.raises(vp.VPError):
+        vp.cluster_markers(q, p, w, 10, L, init_idx=init, batch_idx=np.array([[-1, 2]]))
+    with pytest.raises(vp.VPError):      # batch > m
+        vp.cluster_markers(q, p, w, 10, L, init_idx=init, batch=1001, nbatch=2)
+    with pytest.raises(vp.VPError):      # no batch
+        vp.cluster_markers(q, p, w, 10, L, init_idx=init, batch=10, nbatch=0)
+
+
+def test_minibatch_full_size_properties(vp):
+    """2^20 markers, 2^16 clusters, 12 batches of 2^17: the absorbed weights add up to the
+    weight of every drawn index, the decorated particles are the oracle's moments of the
+    device's own assignment (bit-exact but p*), and every marker's weight is carried."""
+    m, k = 1 << 20, 1 << 16
+    q, p, w, L = landau_markers(m, seed=12)
+    rng = np.random.default_rng(9)
+    batches = rng.integers(0, m, (12, 1 << 17))
+    got = vp.cluster_markers(q, p, w, k, L, seed=3, batch_idx=batches, return_assign=True)
+    v = got["absorbed"].cpu().numpy()
+    drawn = w[batches.ravel()].sum()
+    assert abs(v.sum() - drawn) < 1e-10 * drawn
+    a = got["assign"].cpu().numpy()
+    assert a.min() >= 0 and a.max() < k
+    ref = O.cluster_moments(q, p, w, a, k, L)
+    for f in ("Q", "P", "psi", "qs"):
+        assert np.array_equal(got[f].cpu().numpy(), ref[f]), f
+    assert np.max(np.abs(got["ps"].cpu().numpy() - ref["ps"])) <= 1e-13 * np.abs(ref["ps"]).max()
+    assert abs(got["psi"].cpu().numpy().sum() - w.sum()) < 1e-12 * w.sum()
