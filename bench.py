@@ -479,7 +479,9 @@ def run_cluster(args):
     """Time the initialisation from markers (Algorithm 1 on the GPU): M random markers of
     the strong Landau case into M / 10 decorated particles (the paper's ratio), 10 Lloyd
     iterations.  value = markers x (iterations + 1) / s; the CPU oracle is timed on a
-    bounded sample (a tenth of the markers and clusters, brute-force assignment)."""
+    bounded sample (a fortieth of the markers and clusters, brute-force assignment).  The
+    config also reports mini-batch k-means (20 batches of M / 8) against it: time and
+    within-cluster sum of squares."""
     import numpy as np
     import torch
     import paper_2605_21794_amd as vp
@@ -492,27 +494,66 @@ def run_cluster(args):
     torch.cuda.set_device(0)
     q, p, wt = (torch.from_numpy(mk[f]).cuda() for f in ("Q", "P", "psi"))
     vp.cluster_markers(q, p, wt, k, w.L, iters=1, seed=1)      # warm the kernels
+    # the starting markers are drawn before the timed calls (a host permutation of m)
+    inits = [torch.randperm(m, generator=torch.Generator().manual_seed(rep))[:k]
+             .to(torch.int32).cuda() for rep in range(3)]
     times = []
     for rep in range(3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dec = vp.cluster_markers(q, p, wt, k, w.L, iters=iters, seed=rep)
+        dec = vp.cluster_markers(q, p, wt, k, w.L, iters=iters, init_idx=inits[rep])
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     best = min(times)
     n_out = int(dec["Q"].shape[0])
     log(f"cluster: {m} markers -> {n_out} decorated particles, {iters} iterations: "
         f"{best * 1e3:.1f} ms (runs {[round(t * 1e3, 1) for t in times]})")
+    def wcss(assign):
+        """Within-cluster weighted sum of squares of an assignment (centres at the means)."""
+        a = assign.cpu().numpy()
+        x, v, ww = mk["Q"], mk["P"], mk["psi"]
+        W_ = np.bincount(a, weights=ww, minlength=k)
+        live = W_ > 0
+        mq = np.zeros(k)
+        mp = np.zeros(k)
+        mq[live] = np.bincount(a, weights=ww * x, minlength=k)[live] / W_[live]
+        mp[live] = np.bincount(a, weights=ww * v, minlength=k)[live] / W_[live]
+        return float(np.sum(ww * ((x - mq[a]) ** 2 + (v - mp[a]) ** 2)))
+
+    lloyd_wcss = wcss(vp.cluster_markers(q, p, wt, k, w.L, iters=iters, init_idx=inits[0],
+                                         return_assign=True)["assign"])
+    # mini-batch k-means (the paper's option for large runs): nbatch batches of m / 8
+    # markers drawn with replacement, against the Lloyd run's time and clustering quality
+    batch, nbatch = max(1, m // 8), 20
+    bidx = torch.from_numpy(np.random.default_rng(5).integers(0, m, (nbatch, batch),
+                                                               dtype=np.int32)).cuda()
+    vp.cluster_markers(q, p, wt, k, w.L, init_idx=inits[0], batch_idx=bidx[:1])   # warm up
+    mb_times = []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mb = vp.cluster_markers(q, p, wt, k, w.L, init_idx=inits[0], batch_idx=bidx,
+                                return_assign=True)
+        torch.cuda.synchronize()
+        mb_times.append(time.perf_counter() - t0)
+    mb_wcss = wcss(mb["assign"])
+    log(f"mini-batch: {nbatch} batches of {batch}: {min(mb_times) * 1e3:.1f} ms; "
+        f"within-cluster sum of squares {mb_wcss:.6g} against {lloyd_wcss:.6g} for Lloyd")
     out = {"metric": "marker assignments per second (k-means initialisation)",
            "value": m * (iters + 1) / best, "unit": "marker-iterations/s", "n_gpus": 1,
            "steps": iters, "warmup": 1, "ms_per_step": best * 1e3 / (iters + 1),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": "cluster", "markers": m, "clusters": k,
-                      "decorated_out": n_out, "iterations": iters, "seconds": best}}
+                      "decorated_out": n_out, "iterations": iters, "seconds": best,
+                      "lloyd_wcss": lloyd_wcss,
+                      "minibatch": {"batch": batch, "nbatch": nbatch,
+                                    "seconds": min(mb_times), "wcss": mb_wcss,
+                                    "wcss_over_lloyd": mb_wcss / lloyd_wcss,
+                                    "decorated_out": int(mb["Q"].shape[0])}}}
     if not args.no_cpu:
         import oracle as O
-        ms, ks = m // 10, k // 10
+        ms, ks = m // 40, k // 40
         sub = {f: mk[f][:ms] for f in ("Q", "P", "psi")}
         init = np.random.default_rng(0).choice(ms, ks, replace=False)
         t0 = time.perf_counter()

@@ -717,13 +717,22 @@ hipError_t cluster_run(const double* q, const double* p, const double* w, long l
     double* bw = reinterpret_cast<double*>(base + lay.bw);
     int* bperm = reinterpret_cast<int*>(base + lay.bperm);
     if ((e = launch_fill_zero(v, (size_t)k * sizeof(double), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_iota, dim3(blocks_for(batch, 256)), dim3(256), 0, s, bperm,
-                       (long long)batch);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int t = 0; t < nbatch; ++t) {
       if ((e = bin_centres()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_gather_batch, dim3(blocks_for(batch, 256)), dim3(256), 0, s, q, p, w,
                          m, batch_idx + (size_t)t * batch, batch, bq, bp, bw);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      // visit the batch in grid-cell order (a random batch in its own order would send the
+      // lanes of a wavefront to unrelated cells); the order does not change any result
+      hipLaunchKernelGGL(k_marker_cells, dim3(blocks_for(batch, 256)), dim3(256), 0, s, bq, bp,
+                         (long long)batch, g, keys_a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      int* sorted = nullptr;
+      if ((e = sort_indices(batch, key_bits(G), keys_a, vals_a, keys_b, vals_b, hist, hoff, stmp,
+                            &sorted, s)) != hipSuccess)
+        return e;
+      hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(batch, 256)), dim3(256), 0, s, sorted,
+                         (long long)batch, bperm);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_assign, dim3(blocks_for(batch, 256)), dim3(256), 0, s, bq, bp,
                          (long long)batch, bperm, cq, cp, g, coff, clist, assign);
