@@ -374,17 +374,22 @@ def run_sw_vs_pic(args):
     1e5 markers into 1e4 decorated particles).  Reference: monopole-only lattice of 1024 x 2048 particles, with a
     decorated run of the same size beside it.  Error: relative L2 of E_amp(t) against the
     reference over t <= 10 and t <= 20.  Bytes per update: 36 (decorated) and 20
-    (monopole-only) in float32 storage; degrees of freedom 5 and 3 per particle."""
+    (monopole-only) in float32 storage; degrees of freedom 5 and 3 per particle.
+    --element-order 2 runs every instance, the references included, with P2 elements on 32
+    elements (64 nodes; four lattice columns per element, which P2 needs); --ng sets the
+    mesh."""
     import numpy as np
     import torch
     import paper_2605_21794_amd as vp
     import workloads as W
     steps = 100
+    order = args.element_order
+    ng = args.ng if args.ng > 0 else (128 if order == 1 else 32)
     nvs = [8, 16, 32, 64, 128, 256, 512, 1024]
-    runs = [("reference_pic", W.landau_strong(nx=1024, nv=2048), "lattice", True),
-            ("reference_sw", W.landau_strong(nx=1024, nv=2048), "lattice", False)]
+    runs = [("reference_pic", W.landau_strong(nx=1024, nv=2048, ng=ng), "lattice", True),
+            ("reference_sw", W.landau_strong(nx=1024, nv=2048, ng=ng), "lattice", False)]
     for nv in nvs:
-        w = W.landau_strong(nx=128, nv=nv)
+        w = W.landau_strong(nx=128, nv=nv, ng=ng)
         runs += [(f"sw_{nv}", w, "lattice", False), (f"pic_lattice_{nv}", w, "lattice", True),
                  (f"pic_random_{nv}", w, "random", True), (f"sw_kmeans_{nv}", w, "kmeans", False)]
     torch.cuda.set_device(0)
@@ -406,7 +411,8 @@ def run_sw_vs_pic(args):
             cluster_s += time.perf_counter() - tc
         else:
             st = w.state()
-        eng.admit(s_, st, w.L, w.ng, w.dt, hist_cap=steps + 8, monopole_only=mono)
+        eng.admit(s_, st, w.L, w.ng, w.dt, hist_cap=steps + 8, monopole_only=mono,
+                  element_order=order)
         counts.append(int(st["Q"].shape[0]))
     log(f"sw_vs_pic: {len(runs)} runs admitted in {time.perf_counter() - t0:.1f} s")
     eng.set_tuning(threads=512, ppt=4, acc_copies=4, graph_steps=33)
@@ -467,7 +473,7 @@ def run_sw_vs_pic(args):
            "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "landau_strong sw_vs_pic", "L": 12.0, "alpha": 0.5,
-                      "ng": 128, "dt": 0.2, "nx": 128, "nv": nvs,
+                      "ng": ng, "element_order": order, "dt": 0.2, "nx": 128, "nv": nvs,
                       "reference": "monopole-only lattice 1024 x 2048"},
            "sw_vs_pic": {"reference_sw_vs_pic": errors(sw_ref), "kmeans_seconds": cluster_s,
                          "particles_for_error": summary, "rows": rows}}
@@ -731,6 +737,8 @@ def main():
                     help="run the workload as monopole-only (plain particle-in-cell) particles")
     ap.add_argument("--element-order", type=int, default=1, choices=(1, 2),
                     help="2: P2 elements (vertex and midpoint nodes) in place of P1")
+    ap.add_argument("--ng", type=int, default=0,
+                    help="sw_vs_pic: mesh elements (default 128 for P1, 32 for P2)")
     ap.add_argument("--primitives", action="store_true",
                     help="time vp_deposit and vp_gather_push on their own")
     ap.add_argument("--precision-study", action="store_true",
