@@ -972,12 +972,13 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     }
   };
 
-  // The first group's loads go out first: the solve's own loads queue behind them, so both
-  // latencies overlap instead of adding up.
-  Group g;
-  load_group(0, g);
+  // The solve's loads go out first and the first group's particle loads right behind them:
+  // both latencies overlap, and the solve can start once its own loads are back (the loads
+  // return in order) while the particle loads are still in flight.
   SolveIn sin_;
   solve_load<MODE, false, GEN, P2>(d, r0, first, sin_);
+  Group g;
+  load_group(0, g);
   for (int j = threadIdx.x; j < nacc; j += TPB) sacc[j] = 0.0;
   const int pend = sc->pend[r0];
   // the first tile records the previous step (if it was a fused step of this instance):
