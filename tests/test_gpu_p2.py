@@ -95,6 +95,25 @@ def test_trajectory_matches_oracle(vp, solver, threads, ppt, copies, graph):
     sim.close()
 
 
+@pytest.mark.parametrize("solver", ["scan", "fft"])
+def test_largest_mesh_trajectory(vp, solver):
+    """The largest mesh (Ng 1024: four vertices and four midpoints per solving thread, a
+    2048-node deposit grid in LDS) through fused steps."""
+    w = lattice(1024, 4096, 16, alpha=0.1)
+    st = w.state()
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=16, solver=solver,
+                        element_order=2)
+    sim.set_tuning(threads=1024, ppt=2, acc_copies=4, graph_steps=3)
+    sim.step(6)
+    got = sim.state_numpy(0)
+    ref, fld, _ = oracle_run(st, w.L, w.ng, w.dt, 6)
+    for k, r in zip(FIELDS, ref):
+        assert np.allclose(got[k], r, rtol=0, atol=1e-9), k
+    d = sim.diagnostics(0, grid=True)
+    assert close(d["E"], fld["E"], field_tol(1024)) and close(d["g"], fld["g"], field_tol(1024))
+    sim.close()
+
+
 def test_primitive_steps_equal_one_oracle_step(vp):
     """The unfused composition (gather_push, deposit, poisson, gather_push) with P2."""
     w = lattice(16, 64, 24, alpha=0.2)
