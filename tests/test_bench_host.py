@@ -1,0 +1,72 @@
+"""Host logic of bench.py (CPU): the one-GPU refusal, the workload-name suffixes, the PMC
+summary's per-dispatch means and copy scaling, and the source-hash gate on the traffic
+figure (a changed kernel source reports no traffic)."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_workload_suffixes():
+    assert bench.base_workload("two_stream") == "two_stream"
+    assert bench.base_workload("two_stream_monopole") == "two_stream"
+    assert bench.base_workload("two_stream_p2") == "two_stream"
+    assert bench.base_workload("two_stream_monopole_p2") == "two_stream"
+
+
+def _write_counters(d, counter, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "pmc_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                           "Counter_Value"])
+        w.writeheader()
+        for disp, name, value in rows:
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
+    """Per-dispatch means of the fused kernel only (other kernels and per-channel rows of one
+    dispatch summed first), each scaled by known bytes over the copy's reading."""
+    src = tmp_path / "paper_2605_21794_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "vp_kernels.hip").write_text("// kernel source stand-in\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    k = "void vpk::k_fused<1, 512, true, false, false>(...)"
+    _write_counters(tmp_path / "f", "FETCH_SIZE", [(1, k, 100.0), (1, k, 50.0), (2, k, 250.0),
+                                                   (3, "k_ring", 1e9)])
+    _write_counters(tmp_path / "w", "WRITE_SIZE", [(1, k, 400.0), (2, k, 600.0)])
+    gib_kib = (1 << 30) / 1024.0
+    _write_counters(tmp_path / "cf", "FETCH_SIZE", [(1, "copy", gib_kib / 2), (2, "fill", 3.0)])
+    _write_counters(tmp_path / "cw", "WRITE_SIZE", [(1, "copy", gib_kib)])
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                      str(tmp_path / "cw"), "two_stream")
+    rec = json.load(open(tmp_path / "profiles" / "pmc_k_fused_two_stream.json"))
+    assert rec["dispatches"] == [2, 2]
+    assert rec["fetch_kib_per_dispatch"] == pytest.approx(200.0)
+    assert rec["write_kib_per_dispatch"] == pytest.approx(500.0)
+    assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
+    assert rec["traffic_bytes_per_launch"] == pytest.approx((2 * 200.0 + 500.0) * 1024.0)
+    n = rec["n"]
+    assert rec["traffic_bytes_per_particle"] == pytest.approx(rec["traffic_bytes_per_launch"] / n)
+    # the traffic figure is served only while the kernel source and the particle count match
+    assert bench.load_traffic("two_stream", n) == pytest.approx(rec["traffic_bytes_per_launch"])
+    assert bench.load_traffic("two_stream", n + 1) is None
+    (src / "vp_kernels.hip").write_text("// edited\n")
+    assert bench.load_traffic("two_stream", n) is None
+
