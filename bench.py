@@ -49,6 +49,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def arith_dtype(prec: str) -> str:
+    """The type the path computes in: float64 particle arithmetic and accumulation in every
+    mode but the naive float32 one (the other float32 modes store float32 state only)."""
+    return "f32" if prec == "fp32" else "f64"
+
+
 def kernel_src_sha() -> str:
     p = os.path.join(ROOT, "paper_2605_21794_amd", "csrc", "vp_kernels.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -257,7 +263,7 @@ def run_sweep(args):
         "metric": METRIC, "value": value, "unit": "decorated-particle updates/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": el_b * 1e3 / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "dtype": arith_dtype(prec), "data": "synthetic",
         "config": {"workload": "landau_sweep", "instances": len(ws), "n_total": ntot,
                    "precision": prec, "launch": tun,
                    "plain_value": upd_p / el_p,
@@ -351,7 +357,7 @@ def run_served(args):
         "metric": METRIC, "value": head["updates_per_s"], "unit": "decorated-particle updates/s",
         "n_gpus": 1, "steps": None, "warmup": None, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32", "data": "synthetic",
+        "dtype": arith_dtype(prec), "data": "synthetic",
         "config": {"workload": "served", "jobs": len(base), "slots": args.slots,
                    "chunk": args.chunk, "precision": prec,
                    "rate_jobs_per_s": head["rate_jobs_per_s"],
@@ -630,8 +636,8 @@ def run_precision_study(args):
     out = {"metric": METRIC, "value": modes["fp32c"]["updates_per_s"],
            "unit": "decorated-particle updates/s", "n_gpus": 1, "steps": steps, "warmup": 0,
            "ms_per_step": modes["fp32c"]["ms"] / steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "landau_nonlinear", "n": w.n, "ng": w.ng, "dt": w.dt,
+           "scaling": "weak", "vs_baseline": None, "dtype": arith_dtype("fp32c"),
+           "data": "synthetic", "config": {"workload": "landau_nonlinear", "n": w.n, "ng": w.ng, "dt": w.dt,
                       "study": "precision"},
            "precision_study": modes, "oracle": oracle}
     print(json.dumps(out), flush=True)
@@ -876,7 +882,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32",
+        "dtype": arith_dtype(prec),
         "data": "synthetic",
         "config": {
             "workload": w.name + suffix, "n": n, "ng": w.ng, "element_order": args.element_order,
