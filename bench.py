@@ -901,7 +901,7 @@ def main():
     }
     if not args.no_cpu:
         log("timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 200, args.element_order)
+        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 500, args.element_order)
     sim.close()
     print(json.dumps(out), flush=True)
 
