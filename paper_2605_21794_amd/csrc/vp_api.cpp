@@ -113,8 +113,8 @@ struct vp_handle {
   size_t tiles_cap = 0;
   int ntiles = 0;
   int ntiles_dip = 0;      // tiles of decorated instances (they come first)
-  // tile ranges by kind (kTileGroups): decorated / monopole-only x fast / general / P2
-  int group_end[6] = {0, 0, 0, 0, 0, 0};
+  // tile ranges by kind: decorated / monopole-only x P1 / P2 x without / with general options
+  int group_end[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
@@ -154,17 +154,18 @@ vp_status rebuild_tables(vp_handle* h) {
   for (int s = 0; s < h->max_slots; ++s)
     if (h->slots[s].used) h->h_occ.push_back(s);
   // tiles grouped by kind, one fused launch per non-empty group and step: decorated then
-  // monopole-only instances, each without general options, with them, and with P2 elements
+  // monopole-only instances; within each, P1 then P2 elements, each without then with
+  // general options
   auto group_of = [&](int s) {
     const InstDev& d = h->h_inst[s];
-    return (h->slots[s].cfg.monopole_only ? 3 : 0) + (d.order == 2 ? 2 : d.general ? 1 : 0);
+    return (h->slots[s].cfg.monopole_only ? 4 : 0) + (d.order == 2 ? 2 : 0) + (d.general ? 1 : 0);
   };
   std::vector<int> order;
-  for (int gi = 0; gi < 6; ++gi)
+  for (int gi = 0; gi < 8; ++gi)
     for (int s : h->h_occ)
       if (group_of(s) == gi) order.push_back(s);
   h->ntiles_dip = 0;
-  for (int gi = 0; gi < 6; ++gi) h->group_end[gi] = 0;
+  for (int gi = 0; gi < 8; ++gi) h->group_end[gi] = 0;
   for (int s : order) {
     Slot& sl = h->slots[s];
     h->max_ng = std::max(h->max_ng, order_of(sl.cfg) * sl.cfg.ng);  // LDS sizing
@@ -185,7 +186,7 @@ vp_status rebuild_tables(vp_handle* h) {
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
-    for (int gi = group_of(s); gi < 6; ++gi) h->group_end[gi] += nt;
+    for (int gi = group_of(s); gi < 8; ++gi) h->group_end[gi] += nt;
   }
   h->ntiles = (int)h->h_tiles.size();
   h->any_fft = false;
@@ -222,16 +223,15 @@ vp_status check_slot(const vp_handle* h, int slot) {
 int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
 
 // One fused step of every instance in phase ph: one launch per non-empty group of tiles
-// (decorated / monopole-only instances, without general options, with them, with P2).
+// (decorated / monopole-only instances x P1 / P2 x without / with general options).
 hipError_t fused_step(vp_handle* h, int ph) {
   int b = 0;
-  for (int gi = 0; gi < 6; ++gi) {
+  for (int gi = 0; gi < 8; ++gi) {
     const int e_ = h->group_end[gi];
     if (e_ > b) {
-      const int kind = gi % 3;
       const hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles,
                                              b, e_ - b, h->tun.ppt, h->max_ng, h->any_fft, ph,
-                                             gi < 3, kind != 0, kind == 2, h->stream);
+                                             gi < 4, (gi & 1) != 0, (gi & 2) != 0, h->stream);
       if (e != hipSuccess) return e;
     }
     b = e_;
@@ -460,7 +460,7 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.proj = cfg->projection;
   d.self_on = cfg->no_self_field ? 0 : 1;
   d.ext_on = (cfg->ext_mode >= 1 && cfg->ext_amplitude != 0.0) ? 1 : 0;
-  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on || d.order == 2) ? 1 : 0;
+  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on) ? 1 : 0;
   d.ext_a = cfg->ext_amplitude;
   d.ext_k = 6.283185307179586 * (double)cfg->ext_mode / cfg->L;  // 2 pi m / L
   d.ext_ak = d.ext_a * d.ext_k;

@@ -69,7 +69,7 @@ struct InstDev {
   double* kin;      // kRing x kin_cap x kKinFields per-tile kinetic sums of phase r's pass
   int kin_cap;      // tiles the kinetic-sum ring can hold (ceil(n / 256))
   int proj;         // vp_projection
-  int general;      // any of: a nodal projection, no self field, a prescribed potential, P2
+  int general;      // any of: a nodal projection, no self field, a prescribed potential
   int self_on;      // the particles feel their own field
   int ext_on;       // a prescribed potential acts
   double ext_a, ext_k, ext_ak, ext_akk;  // A, kappa = 2 pi m / L, A kappa, A kappa^2
@@ -98,7 +98,7 @@ size_t particle_lds_bytes(int mode, int max_ng);
 // `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS);
 // `dipoles` false when every tile of the launch is of a monopole-only instance; `general`
 // true when some instance of the launch has general options (InstDev::general); `p2` true
-// when some has P2 elements (then `general` must be true too).
+// when its instances have P2 elements.
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
                         bool general, bool p2, hipStream_t s);

@@ -843,6 +843,9 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     if (!GEN || !d.general) {
       Ei = fE[i];
       gi = DIP ? fG[i] : 0.0;
+      // P2: the field is linear on the element (fE at its midpoint, slope -h phi_h'')
+      if constexpr (P2)
+        if (d.order == 2) Ei = Ei - d.h * fG[i] * (frac01(xq, i) - 0.5);
     } else {
       double u;
       general_field(d, fE, fG, i, xq, Q, psi, ps, Ei, gi, u);
@@ -917,8 +920,8 @@ __host__ __device__ constexpr int group_of() { return (MODE == kFP64 && TPB == 1
 // DIP = false: every tile of the launch belongs to a monopole-only instance; p* and q* are
 // neither read nor written (20 bytes of particle traffic per update instead of 36).
 // GEN = false: no instance of the launch has general options (d.general), so the field on a
-// particle is read straight from the mesh arrays.  P2 = true (with GEN): the launch's
-// instances have P2 elements (a separate instance keeps the others' registers as they were).
+// particle is read straight from the mesh arrays.  P2 = true: the launch's instances have P2
+// elements (separate instances keep the others' registers as they were).
 template <int MODE, int TPB, bool DIP, bool GEN, bool P2>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
@@ -1367,6 +1370,7 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
       if (!d.general) {
         Ei = smem[i];
         gi = smem[ng + i];
+        if (d.order == 2) Ei = Ei - d.h * gi * (frac01(xq, i) - 0.5);  // P2: linear field
       } else {
         double uu;
         general_field(d, smem, smem + ng, i, xq, (double)Q, 0.0, 0.0, Ei, gi, uu);
@@ -1452,6 +1456,7 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
       if (!d.general) {
         Ei = smem[i];
         gi = smem[ng + i];
+        if (d.order == 2) Ei = Ei - d.h * gi * (frac01(xq, i) - 0.5);  // P2: linear field
       } else {
         double uu;
         general_field(d, smem, smem + ng, i, xq, Q, psi, ps, Ei, gi, uu);
@@ -1794,7 +1799,6 @@ hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
                         bool general, bool p2, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (p2 && !general) return hipErrorInvalidValue;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
 #define VP_FUSED_K(M, TB, D, G, P)                                                           \
   hipLaunchKernelGGL((k_fused<M, TB, D, G, P>), dim3(ntiles), dim3(TB), lds, s, d_inst,      \
@@ -1802,13 +1806,21 @@ hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_
 #define VP_FUSED(M, TB)                                                                      \
   do {                                                                                       \
     if (dipoles) {                                                                           \
-      if (p2) VP_FUSED_K(M, TB, true, true, true);                                           \
-      else if (general) VP_FUSED_K(M, TB, true, true, false);                                \
-      else VP_FUSED_K(M, TB, true, false, false);                                            \
+      if (p2) {                                                                              \
+        if (general) VP_FUSED_K(M, TB, true, true, true);                                    \
+        else VP_FUSED_K(M, TB, true, false, true);                                           \
+      } else {                                                                               \
+        if (general) VP_FUSED_K(M, TB, true, true, false);                                   \
+        else VP_FUSED_K(M, TB, true, false, false);                                          \
+      }                                                                                      \
     } else {                                                                                 \
-      if (p2) VP_FUSED_K(M, TB, false, true, true);                                          \
-      else if (general) VP_FUSED_K(M, TB, false, true, false);                               \
-      else VP_FUSED_K(M, TB, false, false, false);                                           \
+      if (p2) {                                                                              \
+        if (general) VP_FUSED_K(M, TB, false, true, true);                                   \
+        else VP_FUSED_K(M, TB, false, false, true);                                          \
+      } else {                                                                               \
+        if (general) VP_FUSED_K(M, TB, false, true, false);                                  \
+        else VP_FUSED_K(M, TB, false, false, false);                                         \
+      }                                                                                      \
     }                                                                                        \
   } while (0)
 #define VP_FUSED_TPB(M)                                                                      \
