@@ -1,0 +1,58 @@
+"""The bench line's contract on the GPU: one JSON line with the metric, throughput, timing,
+roofline (achieved over peak, with the committed PMC traffic while the kernel source is
+unchanged) and configuration, from a short fixed-shape run of the default workload."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def run_bench(*args):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--no-tune", "--launch",
+                        "512,4,8", "--steps", "20", "--warmup", "9", "--no-cpu", *args],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1, r.stdout
+    return json.loads(lines[0])
+
+
+def test_default_bench_line():
+    d = run_bench()
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+              "roofline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 20 and d["warmup"] == 9
+    assert d["value"] > 0 and d["higher_is_better"] is True and d["dtype"] == "f64"
+    assert d["config"]["workload"] == "two_stream" and d["config"]["n"] == 1 << 20
+    assert d["config"]["state_finite_after_run"] is True
+    rf = d["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert rf["achieved"] == pytest.approx(36 * (1 << 20) / (rf["kernel_us"] * 1e-6) / 1e9)
+    assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"])
+    # the counters stand for the kernel only while its source is the one they were taken on
+    if committed_counters_current("two_stream"):
+        assert rf["traffic"] is not None and rf["traffic"] > 36 * (1 << 20)
+    else:
+        assert rf["traffic"] is None
+
+
+def committed_counters_current(workload):
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")))
+    return rec["kernel_src_sha"] == bench.kernel_src_sha()
+
+
+def test_p2_bench_line():
+    d = run_bench("--element-order", "2")
+    assert d["config"]["workload"] == "two_stream_p2" and d["config"]["element_order"] == 2
+    assert d["value"] > 0
+    assert (d["roofline"]["traffic"] is not None) == committed_counters_current("two_stream_p2")
