@@ -948,8 +948,9 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   double* fft = bt + ng;
   VPG InstScal* sc = gp(d.scal);
   // An instance whose diagnostics went NaN / Inf is frozen: its state is no longer a
-  // solution, and its particles would all land in element 0.  (Uniform per workgroup.)
-  if (sc->nonfinite) return;
+  // solution, and its particles would all land in element 0.  (Uniform per workgroup.)  The
+  // flag is tested once the first loads are out, so its latency overlaps theirs.
+  const int frozen = sc->nonfinite;
   const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
 
   // one group of particles per thread: thread t takes tile.begin + k * TPB + t, k0 <= k < k0 + kGroup
@@ -982,6 +983,7 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   solve_load<MODE, false, GEN, P2>(d, r0, first, sin_);
   Group g;
   load_group(0, g);
+  if (frozen) return;
   for (int j = threadIdx.x; j < nacc; j += TPB) sacc[j] = 0.0;
   const int pend = sc->pend[r0];
   // the first tile records the previous step (if it was a fused step of this instance):
