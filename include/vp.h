@@ -245,8 +245,10 @@ vp_status vp_gather_push(vp_handle* h, double kick, double drift);
 
 /* ---------------------------------------------------------------- fused stepping */
 
-/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused kernel per step:
- * every workgroup solves the field of the current positions from the load vector the
+/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused kernel launch per
+ * step and kind of instance (decorated or monopole-only, P1 or P2, with or without general
+ * options; a single launch when all instances are of one kind): every workgroup solves the
+ * field of the current positions from the load vector the
  * previous step deposited, then runs its particles through the pending half-kick, the
  * diagnostics at the integer step, the half-kick, the drift and the deposit of the new
  * load vector; optionally replayed from captured HIP graphs.  Equals the primitive
