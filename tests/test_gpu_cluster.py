@@ -179,3 +179,20 @@ def test_minibatch_full_size_properties(vp):
         assert np.array_equal(got[f].cpu().numpy(), ref[f]), f
     assert np.max(np.abs(got["ps"].cpu().numpy() - ref["ps"])) <= 1e-13 * np.abs(ref["ps"]).max()
     assert abs(got["psi"].cpu().numpy().sum() - w.sum()) < 1e-12 * w.sum()
+
+
+def test_minibatch_duplicates_ties_and_single_marker_batches(vp):
+    """Mini-batch updates over duplicate markers (equal distances: ties to the lower centre),
+    all at one velocity, with batches of a single marker and a batch that repeats one
+    index: bit-exact against the oracle."""
+    rng = np.random.default_rng(13)
+    L = 5.0
+    base = rng.uniform(0, L, 300)
+    q = np.concatenate([base, base])
+    p = np.full(q.size, -0.75)
+    w = rng.uniform(0.5, 1.5, q.size)
+    init = np.concatenate([np.arange(20), 300 + np.arange(20)])   # duplicate centres too
+    singles = rng.integers(0, q.size, (7, 1))
+    compare_minibatch(vp, q, p, w, init.size, L, init, singles)
+    repeated = np.full((1, 64), 17)
+    compare_minibatch(vp, q, p, w, init.size, L, init, repeated)
