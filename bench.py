@@ -9,7 +9,7 @@
     python bench.py --workload cluster           k-means initialisation from markers
     python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
     python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
-    python bench.py --pmc-summary FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR --workload W
+    python bench.py --pmc-summary F_DIR W_DIR COPY_F_DIR COPY_W_DIR --workload W --launch T,PPT,C
 
 One step = one pass of the whole hot path over the batch of particles: the Poisson solve of
 the previous deposit (every workgroup of the fused kernel solves it in its prologue),
@@ -60,14 +60,22 @@ def kernel_src_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str, n: int):
+def launch_key(tun: dict) -> list:
+    """The launch shape a counter reading belongs to: threads, particles per thread, copies."""
+    return [int(tun["threads"]), int(tun["ppt"]), int(tun["acc_copies"])]
+
+
+def load_traffic(workload: str, n: int, precision: str, launch: list):
     """HBM bytes per fused-kernel launch from the committed rocprofv3 PMC summary, or None
-    when there is none or the kernel source changed since the counters were taken."""
+    when there is none, when the kernel source changed since the counters were taken, or
+    when this run's particle count, precision or launch shape is not the one they were
+    taken at (the bytes scale with the storage type, the grid traffic with the shape)."""
     p = os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
-    if rec.get("kernel_src_sha") != kernel_src_sha() or rec.get("n") != n:
+    if (rec.get("kernel_src_sha") != kernel_src_sha() or rec.get("n") != n
+            or rec.get("precision") != precision or rec.get("launch") != list(launch)):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -123,9 +131,10 @@ def base_workload(name: str) -> str:
     return name
 
 
-def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precision, launch):
     """Write profiles/pmc_k_fused_<workload>.json: FETCH_SIZE + WRITE_SIZE per fused launch,
-    each scaled by the ratio of known bytes to what the same counter reads for a copy."""
+    each scaled by the ratio of known bytes to what the same counter reads for a copy.
+    `precision` and `launch` (threads, ppt, copies) name the counter runs' settings."""
     fetch_kib, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "k_fused")
     write_kib, nw = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", "k_fused")
     # the copy kernel is the largest dispatch in its run (torch launches a few small ones too)
@@ -139,6 +148,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload):
     write_b = write_kib * 1024.0 * w_scale
     w, _ = make_workload(base_workload(workload))
     rec = {"kernel": "k_fused", "workload": workload, "n": w.n,
+           "precision": precision, "launch": list(launch),
            "kernel_src_sha": kernel_src_sha(),
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
            "dispatches": [nf, nw],
@@ -771,7 +781,10 @@ def main():
     if args.steps is None:
         args.steps = 99 if args.workload == "landau_sweep" else 1000
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, args.workload)
+        if not args.launch:
+            raise SystemExit("--pmc-summary needs --launch: the shape the counter runs used")
+        pmc_summary(*args.pmc_summary, args.workload, args.precision or "fp32c",
+                    launch_key(parse_launch(args.launch)))
         return
     if args.copy_calibration:
         copy_calibration()
@@ -875,7 +888,7 @@ def main():
     # different kernel (and moves far fewer bytes), so it reports none
     suffix = ("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
     traffic_key = args.workload + suffix
-    traffic = None if persistent else load_traffic(traffic_key, n)
+    traffic = None if persistent else load_traffic(traffic_key, n, prec, launch_key(tun))
     out = {
         "metric": METRIC,
         "value": value,

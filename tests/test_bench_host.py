@@ -1,6 +1,6 @@
 """Host logic of bench.py (CPU): the one-GPU refusal, the workload-name suffixes, the PMC
-summary's per-dispatch means and copy scaling, and the source-hash gate on the traffic
-figure (a changed kernel source reports no traffic)."""
+summary's per-dispatch means and copy scaling, and the gate on the traffic figure (a
+changed kernel source, another precision or another launch shape reports no traffic)."""
 import csv
 import json
 import os
@@ -55,7 +55,7 @@ def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
     _write_counters(tmp_path / "cf", "FETCH_SIZE", [(1, "copy", gib_kib / 2), (2, "fill", 3.0)])
     _write_counters(tmp_path / "cw", "WRITE_SIZE", [(1, "copy", gib_kib)])
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
-                      str(tmp_path / "cw"), "two_stream")
+                      str(tmp_path / "cw"), "two_stream", "fp32c", [512, 4, 8])
     rec = json.load(open(tmp_path / "profiles" / "pmc_k_fused_two_stream.json"))
     assert rec["dispatches"] == [2, 2]
     assert rec["fetch_kib_per_dispatch"] == pytest.approx(200.0)
@@ -64,9 +64,33 @@ def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert rec["traffic_bytes_per_launch"] == pytest.approx((2 * 200.0 + 500.0) * 1024.0)
     n = rec["n"]
     assert rec["traffic_bytes_per_particle"] == pytest.approx(rec["traffic_bytes_per_launch"] / n)
-    # the traffic figure is served only while the kernel source and the particle count match
-    assert bench.load_traffic("two_stream", n) == pytest.approx(rec["traffic_bytes_per_launch"])
-    assert bench.load_traffic("two_stream", n + 1) is None
+    assert rec["precision"] == "fp32c" and rec["launch"] == [512, 4, 8]
+    # the traffic figure is served only while the kernel source, the particle count, the
+    # precision and the launch shape are those of the counter runs
+    shape = [512, 4, 8]
+    assert bench.load_traffic("two_stream", n, "fp32c", shape) == pytest.approx(
+        rec["traffic_bytes_per_launch"])
+    assert bench.load_traffic("two_stream", n + 1, "fp32c", shape) is None
+    assert bench.load_traffic("two_stream", n, "fp64", shape) is None
+    assert bench.load_traffic("two_stream", n, "fp32c", [1024, 4, 8]) is None
+    assert bench.load_traffic("two_stream", n, "fp32c", [512, 4, 4]) is None
     (src / "vp_kernels.hip").write_text("// edited\n")
-    assert bench.load_traffic("two_stream", n) is None
+    assert bench.load_traffic("two_stream", n, "fp32c", shape) is None
+
+
+def test_launch_key():
+    assert bench.launch_key({"threads": 512, "ppt": 4, "acc_copies": 8, "use_graph": 1,
+                             "graph_steps": 99, "persistent": 0}) == [512, 4, 8]
+
+
+def test_committed_counters_name_their_settings():
+    """Every committed counter summary records the precision and launch shape it was taken
+    at, so that no other run reports its bytes."""
+    import glob
+    files = glob.glob(os.path.join(ROOT, "profiles", "pmc_k_fused_*.json"))
+    assert files
+    for f in files:
+        rec = json.load(open(f))
+        assert rec["precision"] in ("fp64", "fp32c", "fp32ts", "fp32"), f
+        assert len(rec["launch"]) == 3 and all(isinstance(v, int) for v in rec["launch"]), f
 

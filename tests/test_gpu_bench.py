@@ -45,10 +45,23 @@ def test_default_bench_line():
 
 
 def committed_counters_current(workload):
+    """True when the committed counters stand for this test's runs: the same kernel source,
+    fp32c, and the launch shape the runs fix (512, 4, 8)."""
     sys.path.insert(0, ROOT)
     import bench
     rec = json.load(open(os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")))
-    return rec["kernel_src_sha"] == bench.kernel_src_sha()
+    return (rec["kernel_src_sha"] == bench.kernel_src_sha() and rec["precision"] == "fp32c"
+            and rec["launch"] == [512, 4, 8])
+
+
+def test_fp64_line_reports_no_fp32_counters():
+    """The counters were taken on float32 storage: a float64 run moves other bytes and must
+    not report them."""
+    d = run_bench("--precision", "fp64")
+    assert d["config"]["precision"] == "fp64" and d["dtype"] == "f64"
+    rf = d["roofline"]
+    assert rf["traffic"] is None
+    assert rf["achieved"] == pytest.approx(72 * (1 << 20) / (rf["kernel_us"] * 1e-6) / 1e9)
 
 
 def test_p2_bench_line():
