@@ -10,7 +10,8 @@ One fused step from the initial state, checked on the same input bits:
 
 Two-stream: N = 2^20, Ng = 512, fp32c, 512 threads x 4 particles per thread, 8 accumulator
 copies.  Batched sweep: all 256 instances (sum N = 6.05e6), 512 x 8, 1 copy; sampled
-instances are checked.  (Over several steps, FP32 states computed with different rounding
+instances are checked.  Nonlinear Landau (the precision study): N = 2^22, Ng = 256, in
+float64, fp32c and fp32ts, 512 x 8, 8 copies.  (Over several steps, FP32 states computed with different rounding
 sequences separate where a particle sits within an ulp of a node, so multi-step runs are
 compared through the field-energy history in the other test files.)"""
 import numpy as np
@@ -28,26 +29,28 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def first_fused_step_reference(st32, f0, w):
+def first_fused_step_reference(st, f0, w, store=np.float32):
     """The first fused step (no pending half-kick yet): half-kick with the initial field,
-    drift, all in float64 from the float32 state, each stored value rounded once."""
-    Q, P, qs, ps = (st32[k].astype(np.float64) for k in ("Q", "P", "qs", "ps"))
+    drift, all in float64 from the stored state, each stored value rounded once to the
+    storage type."""
+    Q, P, qs, ps = (st[k].astype(np.float64) for k in ("Q", "P", "qs", "ps"))
     P, qs = O.kick(Q, P, qs, ps, f0["E"], f0["g"], w.L, 0.5 * w.dt)
     Qn, psn = O.drift(Q, P, qs, ps, w.L, w.dt)
-    f32 = np.float32
-    return {"Q": Qn.astype(f32), "P": P.astype(f32), "qs": qs.astype(f32), "ps": psn.astype(f32)}
+    return {"Q": Qn.astype(store), "P": P.astype(store), "qs": qs.astype(store),
+            "ps": psn.astype(store)}
 
 
-def check_slot(eng, slot, st32, f0, w):
+def check_slot(eng, slot, st, f0, w, store=np.float32, field_tol=1e-5):
     raw = {k: v.detach().cpu().numpy() for k, v in eng.state(slot).items()}  # P, q* pending
-    ref = first_fused_step_reference(st32, f0, w)
+    ref = first_fused_step_reference(st, f0, w, store)
     for k in ("Q", "P", "qs", "ps"):
+        assert raw[k].dtype == store, (slot, k)
         assert np.array_equal(raw[k], ref[k]), (slot, k)
     d = eng.diagnostics(slot, grid=True)
     fld = O.solve_field(raw["Q"].astype(np.float64), raw["ps"].astype(np.float64),
                         raw["psi"].astype(np.float64), w.L, w.ng)
-    assert rel_l2(d["bt"], fld["bt"]) < 1e-5, slot
-    assert rel_l2(d["E"], fld["E"]) < 1e-5, slot
+    assert rel_l2(d["bt"], fld["bt"]) < field_tol, slot
+    assert rel_l2(d["E"], fld["E"]) < field_tol, slot
     cells = eng.cell_index(slot).cpu().numpy()
     i, _ = O.cell_index(raw["Q"], w.L, w.ng)
     assert np.array_equal(cells, i.astype(np.int32)), slot
@@ -80,3 +83,23 @@ def test_batched_sweep_full_size_fused_step(vp):
     for s in sample:
         check_slot(eng, s, sts[s], f0[s], ws[s])
     eng.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32ts"])
+def test_landau_nonlinear_full_size_fused_step(vp, prec):
+    """The precision study's workload at its full size (N = 2^22, Ng = 256) in the modes whose
+    push arithmetic is float64: one fused step, bit-exact particle update on the device's
+    own field, field of the stepped state against the oracle's (float64: summation order
+    only, 1e-11; float32 storage: the stated 1e-5), cell indices bit-exact.  Launch shape
+    512 threads x 8 particles per thread, 8 copies (1024 workgroups)."""
+    w = W.landau_nonlinear()
+    assert w.n == 1 << 22 and w.ng == 256
+    st32 = w.state(np.float32)
+    store = np.float64 if prec == "fp64" else np.float32
+    st = {k: v.astype(store) for k, v in st32.items()}
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=16)
+    sim.set_tuning(threads=512, ppt=8, acc_copies=8, use_graph=1, graph_steps=3)
+    f0 = sim.diagnostics(0, grid=True)
+    sim.step(1)
+    check_slot(sim, 0, st, f0, w, store, 1e-11 if prec == "fp64" else 1e-5)
+    sim.close()
