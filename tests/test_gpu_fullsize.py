@@ -11,7 +11,8 @@ One fused step from the initial state, checked on the same input bits:
 Two-stream: N = 2^20, Ng = 512, fp32c, 512 threads x 4 particles per thread, 8 accumulator
 copies.  Batched sweep: all 256 instances (sum N = 6.05e6), 512 x 8, 1 copy; sampled
 instances are checked.  Nonlinear Landau (the precision study): N = 2^22, Ng = 256, in
-float64, fp32c and fp32ts, 512 x 8, 8 copies.  (Over several steps, FP32 states computed with different rounding
+float64, fp32c and fp32ts, 512 x 8, 8 copies.  The two-stream workload as plain
+particle-in-cell particles, and with P2 elements (see its test for its bars).  (Over several steps, FP32 states computed with different rounding
 sequences separate where a particle sits within an ulp of a node, so multi-step runs are
 compared through the field-energy history in the other test files.)"""
 import numpy as np
@@ -102,4 +103,74 @@ def test_landau_nonlinear_full_size_fused_step(vp, prec):
     f0 = sim.diagnostics(0, grid=True)
     sim.step(1)
     check_slot(sim, 0, st, f0, w, store, 1e-11 if prec == "fp64" else 1e-5)
+    sim.close()
+
+
+def test_monopole_two_stream_full_size_fused_step(vp):
+    """The `--monopole` bench workload at full size: the two-stream lattice as plain
+    particle-in-cell particles (p* = q* = 0), N = 2^20, fp32c, 512 x 4, 8 copies.  The
+    monopole kernel instance never touches the dipole arrays, so the decorated reference
+    with zero dipoles is its reference: bit-exact particle update, field within 1e-5."""
+    w = W.two_stream()
+    st = w.state(np.float32)
+    st["qs"] = np.zeros_like(st["qs"])
+    st["ps"] = np.zeros_like(st["ps"])
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=16, monopole_only=True)
+    sim.set_tuning(threads=512, ppt=4, acc_copies=8, use_graph=1, graph_steps=3)
+    f0 = sim.diagnostics(0, grid=True)
+    sim.step(1)
+    check_slot(sim, 0, st, f0, w)
+    sim.close()
+
+
+def within_one_ulp32(a, b):
+    """Every float32 value of a is b's float64 value rounded to float32, give or take one
+    float32 ulp (the reference's float64 result differs from the device's by a few float64
+    ulps: one rounding to float32 can then land on a neighbour, never further)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mag = np.maximum(np.abs(a), np.abs(b)).astype(np.float32)
+    return bool(np.all(np.abs(a - b) <= np.spacing(mag).astype(np.float64)))
+
+
+def test_p2_two_stream_full_size_fp32c(vp):
+    """The `--element-order 2` bench workload at full size and in the bench's precision and
+    shape (N = 2^20, Ng 512, fp32c, 512 x 4, 4 copies), one fused step from the same float32
+    bits.
+
+    * The initial P2 field (midpoint E and phi_h'' per element) against the oracle's
+      solve, relative to the largest value: 1e-9.  The oracle takes phi_h'' as second
+      differences of the solved potential, which loses about five digits to cancellation
+      at this mesh (3.7e-11 measured); the device uses the equivalent condensed form
+      -(3 / 2h) times the neutralised midpoint load.
+    * The particle update is the oracle's kick and drift applied to the device's own field:
+      q* exactly (the same float64 products), Q, P and p* within one float32 ulp, because
+      the device evaluates the linear element field as its midpoint value plus a slope term
+      and the oracle as its left value plus the slope, which differ by float64 rounding.
+    * The field energy of the stepped state against the oracle's P2 solve on the device's
+      own stepped bits (relative 1e-5)."""
+    w = W.two_stream()
+    st = w.state(np.float32)
+    h = w.L / w.ng
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=16, element_order=2)
+    sim.set_tuning(threads=512, ppt=4, acc_copies=4, use_graph=1, graph_steps=3)
+    Q0, P0, qs0, ps0, psi = (st[k].astype(np.float64) for k in ("Q", "P", "qs", "ps", "psi"))
+    d0 = sim.diagnostics(0, grid=True)
+    ora = O.solve_field_p2(Q0, ps0, psi, w.L, w.ng)
+    for k in ("E", "g"):
+        assert np.max(np.abs(d0[k] - ora[k])) <= 1e-9 * np.max(np.abs(ora[k])), k
+    sim.step(1)
+    raw = {k: v.detach().cpu().numpy() for k, v in sim.state(0).items()}  # P, q* pending
+    own = {"E0": d0["E"] + 0.5 * h * d0["g"], "E1": -h * d0["g"], "g": d0["g"]}
+    P1, qs1 = O.kick_p2(Q0, P0, qs0, ps0, own, w.L, 0.5 * w.dt)
+    Q1, ps1 = O.drift(Q0, P1, qs1, ps0, w.L, w.dt)
+    assert raw["qs"].dtype == np.float32
+    assert np.array_equal(raw["qs"], qs1.astype(np.float32))
+    for k, r in (("Q", Q1), ("P", P1), ("ps", ps1)):
+        assert raw[k].dtype == np.float32, k
+        assert within_one_ulp32(raw[k], r), k
+    fld1 = O.solve_field_p2(raw["Q"].astype(np.float64), raw["ps"].astype(np.float64),
+                            raw["psi"].astype(np.float64), w.L, w.ng)
+    W1 = sim.diagnostics(0)["W"]
+    assert abs(W1 - fld1["W"]) <= 1e-5 * fld1["W"]
     sim.close()
