@@ -65,12 +65,18 @@ def launch_key(tun: dict) -> list:
     return [int(tun["threads"]), int(tun["ppt"]), int(tun["acc_copies"])]
 
 
+def pmc_path(workload: str, launch: list) -> str:
+    """Committed counter summary of the fused kernel for one workload and launch shape."""
+    t, p, c = launch
+    return os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}_{t}x{p}x{c}.json")
+
+
 def load_traffic(workload: str, n: int, precision: str, launch: list):
     """HBM bytes per fused-kernel launch from the committed rocprofv3 PMC summary, or None
     when there is none, when the kernel source changed since the counters were taken, or
     when this run's particle count, precision or launch shape is not the one they were
     taken at (the bytes scale with the storage type, the grid traffic with the shape)."""
-    p = os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")
+    p = pmc_path(workload, launch)
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
@@ -132,7 +138,7 @@ def base_workload(name: str) -> str:
 
 
 def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precision, launch):
-    """Write profiles/pmc_k_fused_<workload>.json: FETCH_SIZE + WRITE_SIZE per fused launch,
+    """Write profiles/pmc_k_fused_<workload>_<shape>.json: FETCH_SIZE + WRITE_SIZE per launch,
     each scaled by the ratio of known bytes to what the same counter reads for a copy.
     `precision` and `launch` (threads, ppt, copies) name the counter runs' settings."""
     fetch_kib, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "k_fused")
@@ -157,7 +163,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precisio
            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
            "traffic_bytes_per_launch": fetch_b + write_b,
            "traffic_bytes_per_particle": (fetch_b + write_b) / w.n}
-    out = os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")
+    out = pmc_path(workload, launch)
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))

@@ -56,7 +56,7 @@ def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
     _write_counters(tmp_path / "cw", "WRITE_SIZE", [(1, "copy", gib_kib)])
     bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
                       str(tmp_path / "cw"), "two_stream", "fp32c", [512, 4, 8])
-    rec = json.load(open(tmp_path / "profiles" / "pmc_k_fused_two_stream.json"))
+    rec = json.load(open(tmp_path / "profiles" / "pmc_k_fused_two_stream_512x4x8.json"))
     assert rec["dispatches"] == [2, 2]
     assert rec["fetch_kib_per_dispatch"] == pytest.approx(200.0)
     assert rec["write_kib_per_dispatch"] == pytest.approx(500.0)
@@ -93,4 +93,6 @@ def test_committed_counters_name_their_settings():
         rec = json.load(open(f))
         assert rec["precision"] in ("fp64", "fp32c", "fp32ts", "fp32"), f
         assert len(rec["launch"]) == 3 and all(isinstance(v, int) for v in rec["launch"]), f
+        assert os.path.basename(f) == os.path.basename(bench.pmc_path(rec["workload"],
+                                                                      rec["launch"])), f
 

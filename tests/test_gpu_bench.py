@@ -49,7 +49,7 @@ def committed_counters_current(workload):
     fp32c, and the launch shape the runs fix (512, 4, 8)."""
     sys.path.insert(0, ROOT)
     import bench
-    rec = json.load(open(os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}.json")))
+    rec = json.load(open(bench.pmc_path(workload, [512, 4, 8])))
     return (rec["kernel_src_sha"] == bench.kernel_src_sha() and rec["precision"] == "fp32c"
             and rec["launch"] == [512, 4, 8])
 
