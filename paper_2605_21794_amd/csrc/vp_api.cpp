@@ -368,7 +368,11 @@ extern "C" {
 int32_t vp_abi_version(void) { return VP_ABI_VERSION; }
 
 const char* vp_status_string(vp_status s) {
-  switch (s) {
+  // A caller may pass any int (a ctypes binding, a cast in C): read the argument's bits as
+  // an int, so that a value outside the enumeration is not loaded as the enum type.
+  int v;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case VP_OK: return "ok";
     case VP_ERR_ARG: return "invalid argument";
     case VP_ERR_HIP: return "HIP runtime error";

@@ -86,3 +86,12 @@ def test_null_handles_rejected(lib):
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
     assert lib.vp_abi_version() == L.VP_ABI_VERSION == 7
+
+
+def test_status_strings_of_any_int(lib):
+    """Every int has a status string; values outside the enumeration are "unknown status"
+    (the library reads the argument as an int, so no out-of-range enum value is loaded)."""
+    for v in (0, 1, 2, 3, 4, 5):
+        assert lib.vp_status_string(v)
+    for v in (-2, -1, 6, 64, 2 ** 31 - 1, -2 ** 31):
+        assert lib.vp_status_string(v) == b"unknown status"
