@@ -45,7 +45,8 @@ Functions and the passages they follow:
                          own field (charge e = 0, the paper's test-particle example)
   diagnostics         -- eq. Hh (discrete Hamiltonian), eq. Eamp, charge, momentum
   deposit_p2 ... run_p2 -- the same cycle with P2 elements (degree-2 Lagrange basis,
-                         assembled stiffness, exact phi_h''), from their definitions
+                         assembled stiffness, bordered solve refined in extended precision,
+                         exact phi_h''), from their definitions
   sort_perm           -- chunked stable counting sort by cell (a layout step of the
                          GPU path; its meaning is fixed here, not by the paper)
   run                 -- the whole cycle, one field solve per step
@@ -413,12 +414,12 @@ def neutralize_p2(bv, bm, L: float, ng: int):
     return np.asarray(bv) - n0 * wv, np.asarray(bm) - n0 * wm
 
 
-def p2_stiffness(L: float, ng: int):
-    """Assembled periodic P2 stiffness matrix over the unknowns ordered
-    (v_0, m_0, v_1, m_1, ...): element matrix (1/3h) [[7, -8, 1], [-8, 16, -8], [1, -8, 7]]."""
-    h = float(L) / ng
+def _p2_assembled(ng: int):
+    """3h times the assembled periodic P2 stiffness matrix over the unknowns ordered
+    (v_0, m_0, v_1, m_1, ...): the element matrices [[7, -8, 1], [-8, 16, -8], [1, -8, 7]]
+    added element by element.  Its entries are small integers, exact in any float type."""
     n = 2 * ng
-    K = np.array([[7.0, -8.0, 1.0], [-8.0, 16.0, -8.0], [1.0, -8.0, 7.0]]) / (3.0 * h)
+    K = np.array([[7.0, -8.0, 1.0], [-8.0, 16.0, -8.0], [1.0, -8.0, 7.0]])
     A = np.zeros((n, n))
     for e in range(ng):
         idx = (2 * e, 2 * e + 1, (2 * e + 2) % n)
@@ -428,44 +429,74 @@ def p2_stiffness(L: float, ng: int):
     return A
 
 
-_P2_SOLVERS = {}
+def p2_stiffness(L: float, ng: int):
+    """Assembled periodic P2 stiffness matrix over the unknowns ordered
+    (v_0, m_0, v_1, m_1, ...): element matrix (1/3h) [[7, -8, 1], [-8, 16, -8], [1, -8, 7]]."""
+    h = float(L) / ng
+    return _p2_assembled(ng) / (3.0 * h)
 
 
-def poisson_solve_p2(btv, btm, L: float):
-    """A Phi = b~ with the gauge integral(phi_h) = 0 (sum_k w_k Phi_k = 0), by the bordered
-    system [[A, w], [w^T, 0]] (inverted once per mesh).  Returns (vertex, midpoint) Phi."""
+_P2_SYSTEMS = {}
+
+
+def _p2_bordered(ng: int):
+    """The bordered matrix [[3h A, c], [c^T, 0]] of the P2 system with the integral gauge,
+    c = the basis functions' integrals in units of h/3 (1 at a vertex, 2 at a midpoint): all
+    entries integers, so the float64 and extended-precision copies are the exact matrix
+    (cached per mesh size)."""
+    if ng not in _P2_SYSTEMS:
+        c = np.tile([1.0, 2.0], ng)
+        B = np.zeros((2 * ng + 1, 2 * ng + 1))
+        B[:2 * ng, :2 * ng] = _p2_assembled(ng)
+        B[:2 * ng, 2 * ng] = c
+        B[2 * ng, :2 * ng] = c
+        _P2_SYSTEMS[ng] = (B, B.astype(np.longdouble))
+    return _P2_SYSTEMS[ng]
+
+
+def poisson_solve_p2(btv, btm, L: float, refine: int = 3):
+    """A Phi = b~ with the gauge integral(phi_h) = 0 (sum_k w_k Phi_k = 0), as the bordered
+    system [[3h A, c], [c^T, 0]] [Phi; mu] = [3h b~; 0] whose matrix has integer entries
+    (_p2_bordered).  Gaussian elimination with partial pivoting (np.linalg.solve), then
+    `refine` steps of iterative refinement whose residuals are formed in extended precision
+    (np.longdouble; Wilkinson's mixed-precision refinement).  The condition number grows like
+    Ng^2; since the matrix is exact, refinement brings Phi to the rounding of the extended
+    type, and phi_h'' read from second differences of Phi keeps its float64 digits.
+    Returns (vertex, midpoint) Phi in extended precision."""
     btv = np.asarray(btv, dtype=np.float64)
     ng = btv.shape[0]
-    key = (float(L), ng)
-    if key not in _P2_SOLVERS:
-        A = p2_stiffness(L, ng)
-        wv, wm = p2_node_weights(L, ng)
-        w = np.tile([wv, wm], ng)
-        B = np.zeros((2 * ng + 1, 2 * ng + 1))
-        B[:2 * ng, :2 * ng] = A
-        B[:2 * ng, 2 * ng] = w
-        B[2 * ng, :2 * ng] = w
-        _P2_SOLVERS[key] = np.linalg.inv(B)
-    rhs = np.zeros(2 * ng + 1)
-    rhs[0:2 * ng:2] = btv
-    rhs[1:2 * ng:2] = btm
-    x = _P2_SOLVERS[key] @ rhs
+    B, Bx = _p2_bordered(ng)
+    h3 = np.longdouble(3.0) * (np.longdouble(L) / np.longdouble(ng))
+    rhs = np.zeros(2 * ng + 1, dtype=np.longdouble)
+    rhs[0:2 * ng:2] = btv.astype(np.longdouble) * h3
+    rhs[1:2 * ng:2] = np.asarray(btm, dtype=np.float64).astype(np.longdouble) * h3
+    x = np.linalg.solve(B, rhs.astype(np.float64)).astype(np.longdouble)
+    for _ in range(refine):
+        r = rhs - Bx @ x
+        x = x + np.linalg.solve(B, r.astype(np.float64)).astype(np.longdouble)
     return x[0:2 * ng:2], x[1:2 * ng:2]
 
 
-def field_p2(Phv, Phm, L: float):
+def field_p2(Phv, Phm, L: float, average: bool = False):
     """On element e: E(s) = -phi_h'(s) = E0_e + s E1_e from the basis derivatives, and
-    phi_h'' = g_e (constant on the element)."""
-    Phv = np.asarray(Phv, dtype=np.float64)
-    Phm = np.asarray(Phm, dtype=np.float64)
+    phi_h'' = g_e (constant on the element); with average=True the element average
+    E0 + E1 / 2 alone.  Evaluated in the precision of Phi (extended for the output of
+    poisson_solve_p2), returned in float64."""
+    Phv = np.asarray(Phv)
+    Phm = np.asarray(Phm)
+    if Phv.dtype != np.longdouble:
+        Phv = Phv.astype(np.float64)
+        Phm = Phm.astype(np.float64)
     ng = Phv.shape[0]
-    ih = inv_h(L, ng)
+    ih = Phv.dtype.type(ng) / Phv.dtype.type(L)
     Pn = np.roll(Phv, -1)
     # -phi' = -(Phi_e N0'(s) + Phi_m N1'(s) + Phi_{e+1} N2'(s)) / h
     E0 = -(-3.0 * Phv + 4.0 * Phm - 1.0 * Pn) * ih
     E1 = -(4.0 * Phv - 8.0 * Phm + 4.0 * Pn) * ih
     g = (4.0 * Phv - 8.0 * Phm + 4.0 * Pn) * ih * ih
-    return E0, E1, g
+    if average:
+        return (E0 + 0.5 * E1).astype(np.float64)
+    return E0.astype(np.float64), E1.astype(np.float64), g.astype(np.float64)
 
 
 def solve_field_p2(Q, ps, psi, L: float, ng: int):
@@ -475,12 +506,16 @@ def solve_field_p2(Q, ps, psi, L: float, ng: int):
     btv, btm = neutralize_p2(bv, bm, L, ng)
     Phv, Phm = poisson_solve_p2(btv, btm, L)
     E0, E1, g = field_p2(Phv, Phm, L)
-    phi = np.empty(2 * ng)
+    # the element average of E (its value at the midpoint), from the extended-precision Phi
+    Eavg = field_p2(Phv, Phm, L, average=True)
+    phi = np.empty(2 * ng, dtype=np.longdouble)
     phi[0::2] = Phv
     phi[1::2] = Phm
-    W = 0.5 * float(phi @ (p2_stiffness(L, ng) @ phi))
-    return {"bv": bv, "bm": bm, "btv": btv, "btm": btm, "Phv": Phv, "Phm": Phm, "E0": E0,
-            "E1": E1, "g": g, "E": E0 + 0.5 * E1, "W": W, "order": 2}
+    h3 = np.longdouble(3.0) * (np.longdouble(L) / np.longdouble(ng))
+    W = float(0.5 * (phi @ (_p2_bordered(ng)[1][:2 * ng, :2 * ng] @ phi)) / h3)
+    return {"bv": bv, "bm": bm, "btv": btv, "btm": btm, "Phv": Phv.astype(np.float64),
+            "Phm": Phm.astype(np.float64), "E0": E0, "E1": E1, "g": g, "E": Eavg,
+            "W": W, "order": 2}
 
 
 def kick_p2(Q, P, qs, ps, fld, L: float, tau: float, ext=None, self_field: bool = True):

@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from fp32_reference import fp32_fused_reference as _fp32_fused_reference
 from fp32_reference import fp32_storage_reference as _fp32_storage_reference
 
 pytestmark = pytest.mark.gpu
@@ -178,52 +179,85 @@ def test_linear_landau_history_fp64(vp):
     assert np.max(np.abs(e1 - e1r)) < 1e-10 * np.max(np.abs(e1r))
 
 
-@pytest.mark.parametrize("prec", ["fp32c", "fp32ts", "fp32"])
-def test_linear_landau_history_fp32_vs_fp64_oracle(vp, prec):
-    """FP32 state against the FP64 oracle over the 200-step linear run.  Rounding the state
-    to float32 every step moves particles across nodes at different steps than in float64,
-    and the P1 dipole load jumps there, so the field-energy history departs from the
-    float64 one by about 1e-2 whatever the accumulation (an oracle run that only rounds its
-    state to float32 shows the same); the error is reported and bounded, not held to 1e-4.
-    The accumulation itself is held to 1e-5 per step by the same-bits tests."""
-    w = W.landau_linear(seed=1)
+def _fp32_c1(seed=1):
+    """Linear Landau (4096 particles, Ng 64, dt 0.1, 200 steps) in float32 state, and the
+    same initial bits in float64."""
+    w = W.landau_linear(seed=seed)
     st = w.state(np.float32)
-    eng = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=256)
-    eng.step(w.nsteps)
-    hist = eng.history(0, 0, w.nsteps) + [eng.diagnostics(0)]
-    s64 = {k: v.astype(np.float64) for k, v in st.items()}
-    _, _, ref = O.run(s64["Q"], s64["P"], s64["qs"], s64["ps"], s64["psi"], w.L, w.ng, w.dt,
-                      w.nsteps)
-    g = np.array([h["W"] for h in hist])
-    r = np.array([h["W"] for h in ref])
-    err = rel_l2(g, r)
-    print(f"\n[precision] {prec}: 200-step W history rel L2 vs FP64 oracle = {err:.3e}")
-    assert err < 0.3, err
-    H = np.array([h["H"] for h in hist])
-    assert np.max(np.abs(H - H[0])) / abs(H[0]) < 0.05
+    return w, st, {k: v.astype(np.float64) for k, v in st.items()}
 
 
-def test_fp32c_history_matches_fp32_storage_reference(vp):
-    """Compensated FP32 mode over 100 primitive steps against the oracle sub-flows with the
-    same float32 storage points: W history rel L2 <= 1e-5, final state close."""
-    w = W.landau_linear(seed=1)
-    st = w.state(np.float32)
-    s64 = {k: v.astype(np.float64) for k, v in st.items()}
-    nsteps = 100
-    eng = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c")
+@pytest.mark.parametrize("prec", ["fp32c", "fp32ts"])
+def test_fp32_primitive_history_matches_storage_reference(vp, prec):
+    """The primitive steps (gather_push, deposit, poisson, gather_push) in float32 state over
+    the whole 200-step linear run, against the oracle's sub-flows with the same float32
+    storage points: W history rel L2 <= 1e-5, final state rel L2 <= 1e-5."""
+    w, st, s64 = _fp32_c1()
+    eng = vp.Simulation(st, w.L, w.ng, w.dt, prec)
     Wg = [eng.diagnostics(0)["W"]]
-    for _ in range(nsteps):
+    for _ in range(w.nsteps):
         eng.gather_push(0.5 * w.dt, w.dt)
         eng.deposit()
         eng.poisson()
         eng.gather_push(0.5 * w.dt, 0.0)
         Wg.append(eng.diagnostics(0)["W"])
-    Wr, (Q, P, qs, ps) = _fp32_storage_reference(s64, w, nsteps)
+    Wr, (Q, P, qs, ps) = _fp32_storage_reference(s64, w, w.nsteps)
     err = rel_l2(Wg, Wr)
-    print(f"\n[precision] fp32c primitive path vs float32-storage reference: W rel L2 = {err:.3e}")
+    print(f"\n[precision] {prec} primitive path vs float32-storage reference: W rel L2 = {err:.3e}")
     assert err < 1e-5, err
     s = np_state(eng)
-    assert rel_l2(s["P"], P) < 1e-5 and rel_l2(s["ps"], ps) < 1e-5
+    for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
+        assert rel_l2(s[k], r) < 1e-5, k
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp32ts"])
+def test_fp32_fused_history_matches_storage_reference(vp, prec):
+    """The fused step (graph-replayed launches) in float32 state over the 200-step linear run,
+    against the oracle's sub-flows with the fused step's float32 storage points: W and H
+    histories rel L2 <= 1e-5, final state rel L2 <= 1e-5."""
+    w, st, s64 = _fp32_c1()
+    eng = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=256)
+    eng.set_tuning(threads=512, ppt=2, acc_copies=4, graph_steps=33)
+    eng.step(w.nsteps)
+    hist = eng.history(0, 0, w.nsteps) + [eng.diagnostics(0)]
+    Wr, Hr, (Q, P, qs, ps) = _fp32_fused_reference(s64, w, w.nsteps)
+    errW = rel_l2([h["W"] for h in hist], Wr)
+    errH = rel_l2([h["H"] for h in hist], Hr)
+    print(f"\n[precision] {prec} fused path vs float32-storage reference: W rel L2 = {errW:.3e}, "
+          f"H rel L2 = {errH:.3e}")
+    assert errW < 1e-5 and errH < 1e-5, (errW, errH)
+    s = np_state(eng)
+    for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
+        assert rel_l2(s[k], r) < 1e-5, k
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp32ts", "fp32"])
+def test_linear_landau_history_fp32_vs_fp64_oracle(vp, prec):
+    """Float32 state against the float64 oracle over the 200-step linear run.  Float32 storage
+    alone moves this W history away from the float64 one by a few percent (pinned on the CPU
+    by test_fp32_storage_departs_from_fp64_on_linear_landau), so the 1e-4 target is not met by
+    any float32 mode.  The compensated modes (fp32c, fp32ts) follow the fused step's
+    float32-storage reference to 1e-5, so their departure from the oracle must equal the
+    reference's own departure to within 2e-5.  The naive mode computes the push in float32
+    and has no such reference: its departure is held to the pinned band's top, 0.15."""
+    w, st, s64 = _fp32_c1()
+    eng = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=256)
+    eng.step(w.nsteps)
+    hist = eng.history(0, 0, w.nsteps) + [eng.diagnostics(0)]
+    _, _, ref = O.run(s64["Q"], s64["P"], s64["qs"], s64["ps"], s64["psi"], w.L, w.ng, w.dt,
+                      w.nsteps)
+    g = np.array([h["W"] for h in hist])
+    r = np.array([h["W"] for h in ref])
+    err = rel_l2(g, r)
+    err_ref = rel_l2(_fp32_fused_reference(s64, w, w.nsteps)[0], r)
+    print(f"\n[precision] {prec}: 200-step W history rel L2 vs FP64 oracle = {err:.3e} "
+          f"(float32-storage reference: {err_ref:.3e})")
+    if prec == "fp32":
+        assert err < 0.15, err
+    else:
+        assert abs(err - err_ref) < 2e-5, (err, err_ref)
+    H = np.array([h["H"] for h in hist])
+    assert np.max(np.abs(H - H[0])) / abs(H[0]) < 0.05
 
 
 @pytest.mark.parametrize("prec,chunk", [("fp64", 2048), ("fp64", 100), ("fp32c", 4096),
