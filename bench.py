@@ -55,9 +55,20 @@ def arith_dtype(prec: str) -> str:
     return "f32" if prec == "fp32" else "f64"
 
 
+# the files the kernels are compiled from (a counter reading belongs to their text)
+KERNEL_SOURCES = ("vp_device.h", "vp_internal.h", "vp_kernels.hip", "vp_fused.hip",
+                  "vp_persist.hip")
+
+
 def kernel_src_sha() -> str:
-    p = os.path.join(ROOT, "paper_2605_21794_amd", "csrc", "vp_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2605_21794_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        p = os.path.join(d, name)
+        if os.path.exists(p):
+            h.update(name.encode())
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def launch_key(tun: dict) -> list:

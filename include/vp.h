@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 7
+#define VP_ABI_VERSION 8
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -154,6 +154,11 @@ typedef struct vp_diag {
   double e1_im;     /*   ... imaginary part */
   double U;         /* prescribed potential's energy sum psi* V(Q) - p* V'(Q) (0 without one);
                        H = K + U + W */
+  double stamp;     /* records of vp_history: the device's constant-rate clock (ticks of
+                       vp_wall_clock_hz) when the record was written, which for a record
+                       written by vp_step is during the launch of the following step, so
+                       the difference of consecutive records' stamps is the time one step
+                       of the engine took; 0 from vp_diagnostics */
 } vp_diag;
 
 /* Launch shape of the particle kernels; chosen by vp_tune or set by the caller. */
@@ -260,6 +265,13 @@ vp_status vp_step(vp_handle* h, int32_t nsteps);
  * on: its state, step counter and history stop where they are, vp_diagnostics and
  * vp_history report VP_ERR_NONFINITE, and the other instances are unaffected. */
 
+/* Capture now every HIP graph that vp_step(h, nsteps) will replay (with graphs on: the
+ * graph of vp_tuning.graph_steps steps when nsteps reaches it, and the one-step graph of
+ * each ring phase that covers the remaining steps), so that vp_step itself replays only.
+ * Runs no step.  Nothing to do for persistent steps or with graphs off.  A later change of
+ * tuning or of the occupied slots drops the graphs. */
+vp_status vp_prepare_step(vp_handle* h, int32_t nsteps);
+
 /* Apply the pending half-kick of every occupied slot (P, q* back to integer time). */
 vp_status vp_sync_state(vp_handle* h);
 
@@ -284,6 +296,10 @@ vp_status vp_cell_index(vp_handle* h, int32_t slot, int32_t* dev_cells);
  * E_e at each element's midpoint (the element average of the linear field), g_e.
  * Returns VP_ERR_NONFINITE (after filling *host_out) if any value is NaN or Inf. */
 vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* host_grid);
+
+/* Ticks per second of the device clock of vp_diag.stamp (the current device's constant-rate
+ * wall clock).  Errors: VP_ERR_ARG (NULL), VP_ERR_HIP. */
+vp_status vp_wall_clock_hz(double* hz_out);
 
 /* Synchronises the stream.  Copies the per-step records written by vp_step for steps
  * first_step .. first_step+count-1 (each record is the state at that integer step,

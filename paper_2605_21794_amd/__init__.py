@@ -64,6 +64,14 @@ def workspace_bytes(cfg) -> int:
     return int(b.value)
 
 
+def wall_clock_hz() -> float:
+    """Ticks per second of the device clock that stamps history records (vp_wall_clock_hz)."""
+    lib = L.load()
+    hz = c_double()
+    L.check(lib.vp_wall_clock_hz(byref(hz)), "vp_wall_clock_hz")
+    return float(hz.value)
+
+
 def cluster_markers(Q, P, w, k: int, L_: float, iters: int = 10, init_idx=None, seed: int = 0,
                     return_assign: bool = False, stream=None, batch=None, nbatch: int = 0,
                     batch_idx=None):
@@ -226,6 +234,10 @@ class Engine:
     # ---------------------------------------------------------------- steps
     def step(self, nsteps: int = 1):
         L.check(self.lib.vp_step(self.h, int(nsteps)), "vp_step")
+
+    def prepare_step(self, nsteps: int):
+        """Capture the graphs a later step(nsteps) replays, without stepping."""
+        L.check(self.lib.vp_prepare_step(self.h, int(nsteps)), "vp_prepare_step")
 
     def sync_state(self):
         L.check(self.lib.vp_sync_state(self.h), "vp_sync_state")

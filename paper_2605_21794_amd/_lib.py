@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
-VP_ABI_VERSION = 7          # the layout of the structures declared below
+VP_ABI_VERSION = 8          # the layout of the structures declared below
 VP_SLOT_OCCUPIED, VP_SLOT_NONFINITE = 1, 2
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_PROJ_ELEM, VP_PROJ_NODAL, VP_PROJ_CONSISTENT = 0, 1, 2
@@ -36,7 +36,8 @@ class vp_particles(Structure):
 class vp_diag(Structure):
     _fields_ = [("step", c_int64), ("t", c_double), ("K", c_double), ("W", c_double),
                 ("H", c_double), ("charge", c_double), ("momentum", c_double),
-                ("e_amp", c_double), ("e1_re", c_double), ("e1_im", c_double), ("U", c_double)]
+                ("e_amp", c_double), ("e1_re", c_double), ("e1_im", c_double), ("U", c_double),
+                ("stamp", c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +92,8 @@ SIGNATURES = {
                                                POINTER(c_int32)]),
     "vp_status_string": (c_char_p, [c_int32]),
     "vp_last_error": (c_char_p, []),
+    "vp_wall_clock_hz": (c_int32, [POINTER(c_double)]),
+    "vp_prepare_step": (c_int32, [H, c_int32]),
     "vp_abi_version": (c_int32, []),
 }
 

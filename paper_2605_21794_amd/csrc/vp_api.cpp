@@ -123,6 +123,8 @@ struct vp_handle {
   vp_tuning tun{1024, 4, 4, 1, 33, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t step_graph[vpk::kRing] = {nullptr, nullptr, nullptr};  // one step at phase p
+  hipGraphExec_t step_exec[vpk::kRing] = {nullptr, nullptr, nullptr};
   int graph_len = 0;        // fused launches per graph (a multiple of the ring period)
   int graph_phase = 0;      // ring phase the graph was captured at
   bool graph_ok = false;
@@ -138,6 +140,12 @@ void drop_graph(vp_handle* h) {
   if (h->graph) (void)hipGraphDestroy(h->graph);
   h->gexec = nullptr;
   h->graph = nullptr;
+  for (int p = 0; p < vpk::kRing; ++p) {
+    if (h->step_exec[p]) (void)hipGraphExecDestroy(h->step_exec[p]);
+    if (h->step_graph[p]) (void)hipGraphDestroy(h->step_graph[p]);
+    h->step_exec[p] = nullptr;
+    h->step_graph[p] = nullptr;
+  }
   h->graph_ok = false;
   h->graph_len = 0;
 }
@@ -253,13 +261,10 @@ int graph_len_of(const vp_handle* h) {
   return (h->tun.graph_steps + vpk::kRing - 1) / vpk::kRing * vpk::kRing;
 }
 
-vp_status ensure_graph(vp_handle* h) {
-  if (h->graph_ok && h->graph_len == graph_len_of(h)) return VP_OK;
-  drop_graph(h);
-  const int len = graph_len_of(h);
+// Capture `len` fused steps starting at ring phase ph into *g / *ge.
+vp_status capture_steps(vp_handle* h, int ph, int len, hipGraph_t* g_out, hipGraphExec_t* ge_out) {
   VP_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
-  int ph = h->phase;
   for (int i = 0; i < len && le == hipSuccess; ++i) {
     le = fused_step(h, ph);
     ph = next_phase(ph);
@@ -271,11 +276,41 @@ vp_status ensure_graph(vp_handle* h) {
     return fail(VP_ERR_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
                 hipGetErrorString(ee));
   }
-  h->graph = g;
-  VP_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  hipGraphExec_t ge = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(VP_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+  }
+  *g_out = g;
+  *ge_out = ge;
+  return VP_OK;
+}
+
+vp_status ensure_graph(vp_handle* h) {
+  if (h->graph_ok && h->graph_len == graph_len_of(h)) return VP_OK;
+  drop_graph(h);
+  const int len = graph_len_of(h);
+  VP_TRY(capture_steps(h, h->phase, len, &h->graph, &h->gexec));
   h->graph_len = len;
   h->graph_phase = h->phase;
   h->graph_ok = true;
+  return VP_OK;
+}
+
+// The one-step graph of phase p (the steps a whole graph does not cover are replayed from
+// these, so that vp_step with graphs on runs no direct launch).
+vp_status ensure_step_graph(vp_handle* h, int p) {
+  if (h->step_exec[p]) return VP_OK;
+  return capture_steps(h, p, 1, &h->step_graph[p], &h->step_exec[p]);
+}
+
+vp_status launch_steps_graphed(vp_handle* h, int nsteps) {
+  for (int i = 0; i < nsteps; ++i) {
+    VP_TRY(ensure_step_graph(h, h->phase));
+    VP_HIP(hipGraphLaunch(h->step_exec[h->phase], h->stream));
+    h->phase = next_phase(h->phase);
+  }
   return VP_OK;
 }
 
@@ -295,23 +330,25 @@ vp_status advance_persistent(vp_handle* h, int k) {
   return VP_OK;
 }
 
-// Run k fused steps of every slot: graph replays where whole graphs fit (after at most
-// kRing-1 direct launches that bring the phase to the graph's), direct launches otherwise.
+// Run k fused steps of every slot.  With graphs on: replays of the whole graph where it
+// fits (after at most kRing-1 one-step replays that bring the phase to the graph's) and
+// one-step replays for the rest; direct launches with graphs off.
 vp_status advance(vp_handle* h, int k) {
   if (h->tun.persistent) return advance_persistent(h, k);
   const bool graphs = h->tun.use_graph && h->stream != nullptr;
-  if (graphs && k >= graph_len_of(h)) {
+  if (!graphs) return launch_steps_direct(h, k);
+  if (k >= graph_len_of(h)) {
     VP_TRY(ensure_graph(h));  // captured at the current phase if there was none
     const int lead = (h->graph_phase - h->phase + vpk::kRing) % vpk::kRing;
     if (k - lead >= h->graph_len) {
-      VP_TRY(launch_steps_direct(h, lead));
+      VP_TRY(launch_steps_graphed(h, lead));
       k -= lead;
       const int reps = k / h->graph_len;
       for (int r = 0; r < reps; ++r) VP_HIP(hipGraphLaunch(h->gexec, h->stream));
       k -= reps * h->graph_len;
     }
   }
-  return launch_steps_direct(h, k);
+  return launch_steps_graphed(h, k);
 }
 
 // Solve the listed slots from the live ring entry and write their field arrays (and the
@@ -352,6 +389,7 @@ void to_diag(const double* r, vp_diag* o) {
   o->e1_re = r[8];
   o->e1_im = r[9];
   o->U = r[10];
+  o->stamp = r[11];
 }
 
 bool diag_finite(const vp_diag& d) {
@@ -384,6 +422,16 @@ const char* vp_status_string(vp_status s) {
 }
 
 const char* vp_last_error(void) { return g_err.c_str(); }
+
+vp_status vp_wall_clock_hz(double* hz_out) {
+  if (!hz_out) return fail(VP_ERR_ARG, "hz_out is NULL");
+  int dev = 0, khz = 0;
+  VP_HIP(hipGetDevice(&dev));
+  VP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(VP_ERR_HIP, "device reports no wall-clock rate");
+  *hz_out = 1e3 * (double)khz;
+  return VP_OK;
+}
 
 vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out) {
   VP_TRY(validate(cfg));
@@ -652,6 +700,16 @@ vp_status vp_step(vp_handle* h, int32_t nsteps) {
   return VP_OK;
 }
 
+vp_status vp_prepare_step(vp_handle* h, int32_t nsteps) {
+  if (!h) return fail(VP_ERR_ARG, "handle is NULL");
+  if (nsteps < 0) return fail(VP_ERR_ARG, "nsteps < 0");
+  if (h->h_occ.empty() || nsteps == 0 || h->tun.persistent) return VP_OK;
+  if (!h->tun.use_graph || h->stream == nullptr) return VP_OK;
+  if (nsteps >= graph_len_of(h)) VP_TRY(ensure_graph(h));
+  for (int p = 0; p < vpk::kRing; ++p) VP_TRY(ensure_step_graph(h, p));
+  return VP_OK;
+}
+
 vp_status vp_sync_state(vp_handle* h) {
   if (!h) return fail(VP_ERR_ARG, "handle is NULL");
   if (h->h_occ.empty()) return VP_OK;
@@ -722,6 +780,7 @@ vp_status vp_diagnostics(vp_handle* h, int32_t slot, vp_diag* host_out, double* 
   host_out->e_amp = std::sqrt(2.0 * host_out->W / sl.cfg.L);
   host_out->e1_re = self ? sc.e1r[p] : 0.0;
   host_out->e1_im = self ? sc.e1i[p] : 0.0;
+  host_out->stamp = 0.0;
   if (sc.timeout) return fail(VP_ERR_HIP, "slot %d: a persistent step's wait for its tiles timed out", slot);
   if (!diag_finite(*host_out) || sc.nonfinite)
     return fail(VP_ERR_NONFINITE, "slot %d: non-finite diagnostics at step %lld", slot, sc.step);

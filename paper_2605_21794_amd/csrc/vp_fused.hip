@@ -1,0 +1,216 @@
+// The fused step kernel (k_fused) of the decorated-particle cycle, with its launch for one
+// precision mode.  This unit is compiled once per mode (VP_FUSED_MODE = 0..3, the vpk::Mode
+// values), so the modes' kernel instances build side by side.
+#include "vp_device.h"
+
+#ifndef VP_FUSED_MODE
+#error "compile with -DVP_FUSED_MODE=<mode>"
+#endif
+
+namespace vpk {
+
+// DIP = false: every tile of the launch belongs to a monopole-only instance; p* and q* are
+// neither read nor written (20 bytes of particle traffic per update instead of 36).
+// GEN = false: no instance of the launch has general options (d.general), so the field on a
+// particle is read straight from the mesh arrays.  P2 = true: the launch's instances have P2
+// elements (separate instances keep the others' registers as they were).
+template <int MODE, int TPB, bool DIP, bool GEN, bool P2>
+__global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
+                                               const Tile* __restrict__ tiles, int tile0,
+                                               int ppt, int phase) {
+  extern __shared__ double smem[];
+  __shared__ double red[4 * (TPB / 64)];
+  __shared__ double sred[kSolveRed];
+  using T = typename StateType<MODE>::T;
+  constexpr int kGroup = group_of<MODE, TPB>();
+  const Tile tl = tiles[tile0 + blockIdx.x];
+  const InstDev& d = insts[tl.inst];
+  const int ng = d.ng;
+  const int r0 = phase, r1 = ring_next(phase), r2 = ring_prev(phase);
+  VPG T* __restrict__ Qp = gp<T>(d.Q);
+  VPG T* __restrict__ Pp = gp<T>(d.P);
+  VPG T* __restrict__ qsp = gp<T>(d.qs);
+  VPG T* __restrict__ psp = gp<T>(d.ps);
+  const VPG T* __restrict__ psip = gp<T>(d.psi);
+  const int nacc = P2 ? d.nacc : ng;  // load-vector nodes (2 ng for P2)
+  double* fE = smem;
+  double* fG = smem + ng;
+  double* sacc = smem + 2 * ng;
+  double* bt = sacc + nacc;
+  double* fft = bt + ng;
+  VPG InstScal* sc = gp(d.scal);
+  // An instance whose diagnostics went NaN / Inf is frozen: its state is no longer a
+  // solution, and its particles would all land in element 0.  (Uniform per workgroup.)  The
+  // flag is tested once the first loads are out, so its latency overlaps theirs.
+  const int frozen = sc->nonfinite;
+  const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
+
+  // one group of particles per thread: thread t takes tile.begin + k * TPB + t, k0 <= k < k0 + kGroup
+  struct Group {
+    T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
+    long long idx[kGroup];
+    bool v[kGroup];
+  };
+  auto load_group = [&](int k0, Group& g) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int loc = (k0 + u) * TPB + (int)threadIdx.x;
+      g.v[u] = (k0 + u < ppt) && (loc < tl.count);
+      g.idx[u] = tl.begin + loc;
+      if (g.v[u]) {
+        g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
+        if constexpr (DIP) {
+          g.a[u] = ntld(qsp + g.idx[u]); g.b[u] = ntld(psp + g.idx[u]);
+        } else {
+          g.a[u] = T(0); g.b[u] = T(0);
+        }
+      }
+    }
+  };
+
+  // The solve's loads go out first and the first group's particle loads right behind them:
+  // both latencies overlap, and the solve can start once its own loads are back (the loads
+  // return in order) while the particle loads are still in flight.
+  SolveIn sin_;
+  solve_load<MODE, false, GEN, P2>(d, r0, first, sin_);
+  Group g;
+  load_group(0, g);
+  if (frozen) return;
+  for (int j = threadIdx.x; j < nacc; j += TPB) sacc[j] = 0.0;
+  const int pend = sc->pend[r0];
+  // the first tile records the previous step (if it was a fused step of this instance):
+  // its inputs are read now and written after the solve
+  long long step = 0;
+  double rec[3] = {0.0, 0.0, 0.0};
+  if (first) {
+    step = sc->step;
+    rec[0] = sc->W[r2];
+    rec[1] = sc->e1r[r2];
+    rec[2] = sc->e1i[r2];
+  }
+  double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
+  {
+    double sum[7];
+    solve_compute<TPB, GEN, P2>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
+    if (first) {
+      const int copies = d.acc_copies;
+      for (int c = 0; c < copies; ++c)
+        for (int j = threadIdx.x; j < nacc; j += TPB) {
+          if constexpr (MODE == kFP32)
+            gp<float>(d.acc)[acc_off(d, r2, c) + j] = 0.0f;
+          else
+            gp(d.acc)[acc_off(d, r2, c) + j] = 0.0;
+        }
+      if (threadIdx.x == 0) {
+        if (pend && step >= 1)
+          write_record(d, step - 1, sum[3], sum[4], sum[5], sum[6], rec[0], rec[1], rec[2]);
+        sc->W[r0] = sum[0];
+        sc->e1r[r0] = sum[1];
+        sc->e1i[r0] = sum[2];
+        if (!isfinite(sum[0])) sc->nonfinite = 1;
+        sc->pend[r1] = 1;
+        sc->step = step + 1;
+      }
+    }
+  }
+
+  auto run_group = [&](Group& g) {
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if (!g.v[u]) continue;
+      T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
+      push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms,
+                                           Cs, Us);
+      ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P);
+      if constexpr (DIP) { ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps); }
+    }
+  };
+
+  run_group(g);
+  for (int k0 = kGroup; k0 < ppt; k0 += kGroup) {
+    load_group(k0, g);
+    run_group(g);
+  }
+
+  // kinetic sums: wave trees, one barrier, one thread stores the workgroup totals in this
+  // tile's slot (the next pass's first tile adds the slots in tile order)
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  Ks = wave_sum(Ks);
+  Ms = wave_sum(Ms);
+  Cs = wave_sum(Cs);
+  if constexpr (GEN) Us = wave_sum(Us);
+  if (lane == 0) {
+    red[4 * wid] = Ks;
+    red[4 * wid + 1] = Ms;
+    red[4 * wid + 2] = Cs;
+    if constexpr (GEN) red[4 * wid + 3] = Us;
+  }
+  __syncthreads();  // also completes every LDS deposit of the workgroup
+  if (threadIdx.x == 0) {
+    double kb = 0.0, mb = 0.0, cbs = 0.0, ub = 0.0;
+    for (int w = 0; w < TPB / 64; ++w) {
+      kb += red[4 * w];
+      mb += red[4 * w + 1];
+      cbs += red[4 * w + 2];
+      if constexpr (GEN) ub += red[4 * w + 3];
+    }
+    VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
+    slot[0] = kb;
+    slot[1] = mb;
+    slot[2] = cbs;
+    if constexpr (GEN) slot[3] = ub;  // else it stays zero (no potential in this instance)
+  }
+  flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
+}
+
+
+
+template <int MODE>
+hipError_t launch_fused_mode(int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+                        int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
+                        bool general, bool p2, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
+#define VP_FUSED_K(M, TB, D, G, P)                                                           \
+  hipLaunchKernelGGL((k_fused<M, TB, D, G, P>), dim3(ntiles), dim3(TB), lds, s, d_inst,      \
+                     d_tiles, tile0, ppt, phase)
+#define VP_FUSED(M, TB)                                                                      \
+  do {                                                                                       \
+    if (dipoles) {                                                                           \
+      if (p2) {                                                                              \
+        if (general) VP_FUSED_K(M, TB, true, true, true);                                    \
+        else VP_FUSED_K(M, TB, true, false, true);                                           \
+      } else {                                                                               \
+        if (general) VP_FUSED_K(M, TB, true, true, false);                                   \
+        else VP_FUSED_K(M, TB, true, false, false);                                          \
+      }                                                                                      \
+    } else {                                                                                 \
+      if (p2) {                                                                              \
+        if (general) VP_FUSED_K(M, TB, false, true, true);                                   \
+        else VP_FUSED_K(M, TB, false, false, true);                                          \
+      } else {                                                                               \
+        if (general) VP_FUSED_K(M, TB, false, true, false);                                  \
+        else VP_FUSED_K(M, TB, false, false, false);                                         \
+      }                                                                                      \
+    }                                                                                        \
+  } while (0)
+#define VP_FUSED_TPB(M)                                                                      \
+  do {                                                                                       \
+    if (tpb == 1024) VP_FUSED(M, 1024);                                                      \
+    else if (tpb == 512) VP_FUSED(M, 512);                                                   \
+    else VP_FUSED(M, 256);                                                                   \
+  } while (0)
+  VP_FUSED_TPB(MODE);
+#undef VP_FUSED_TPB
+#undef VP_FUSED
+#undef VP_FUSED_K
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused_mode<VP_FUSED_MODE>(int tpb, const InstDev* d_inst,
+                                                     const Tile* d_tiles, int tile0, int ntiles,
+                                                     int ppt, int max_ng, bool lds_fft, int phase,
+                                                     bool dipoles, bool general, bool p2,
+                                                     hipStream_t s);
+
+}  // namespace vpk

@@ -9,7 +9,7 @@
 namespace vpk {
 
 constexpr int kBlock = 256;      // threads per workgroup for every particle kernel
-constexpr int kHistFields = 11;  // doubles per diagnostic record (layout of vp_diag)
+constexpr int kHistFields = 12;  // doubles per diagnostic record (layout of vp_diag)
 constexpr int kKinFields = 4;    // per-tile sums: K, momentum, charge, prescribed-potential U
 constexpr int kMinTile = 256;    // fewest particles per tile (256 threads x 1 particle)
 
@@ -28,6 +28,9 @@ constexpr int kConsTapsMax = 65;
 constexpr int cons_taps(int ng) { return ng <= 64 ? ng : kConsTapsMax; }
 constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
 
+constexpr int kArriveGroups = 8;   // arrival counters per instance (one per XCD)
+constexpr int kArriveStride = 32;  // unsigned words between counters (128 bytes)
+
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
   double W[kRing], e1r[kRing], e1i[kRing];  // summary of the field solved from ring entry r
@@ -36,8 +39,12 @@ struct InstScal {
   int pend[kRing];                          // 1 when P, q* owe the half-kick with the field of entry r
   int nonfinite;                            // set when a diagnostic came out NaN or Inf
   int frozen;                               // nonfinite as of the start of a persistent launch
-  unsigned arrive;                          // workgroup arrivals in a persistent launch
   int timeout;                              // a persistent launch's wait gave up (error)
+  // Workgroup arrivals in a persistent launch: tile t of the instance counts on group
+  // t mod kArriveGroups, each group's counter on a 128-byte line of its own.  Workgroups are
+  // handed to the 8 XCDs in turn, so a group collects the arrivals of one XCD, and a waiting
+  // workgroup reads the 8 counters at once instead of contending on one.
+  alignas(128) unsigned arrive[kArriveGroups * kArriveStride];
 };
 
 // Device descriptor of one instance (one slot of an engine).
@@ -102,6 +109,11 @@ size_t particle_lds_bytes(int mode, int max_ng);
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
                         bool general, bool p2, hipStream_t s);
+// The same for one precision mode (vpk::Mode), defined in the unit compiled for that mode.
+template <int MODE>
+hipError_t launch_fused_mode(int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
+                             int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
+                             bool general, bool p2, hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,

@@ -13,10 +13,13 @@ for the queue.
     srv = Server(precision="fp32c", max_slots=64, budget_bytes=8 << 30)
     report = srv.run(jobs)     # jobs: list of Job, each with its arrival time in seconds
 
-Reported: step latency (device time of one engine step, over every step of every job that
-took part in it), job latency (arrival to retirement, wall clock), admission wait, aggregate
-particle updates per second.  The device work goes through a backend with the Engine
-interface, so the scheduling logic can be exercised without a GPU.
+Reported: step latency (per job and step: the device clock between the history records of
+two consecutive steps, which the first workgroup of each job writes during each fused launch;
+a step that spans a scheduling decision includes the host's time there), job latency (arrival
+to retirement, wall clock), admission wait, aggregate particle updates per second.  The
+device work goes through a backend with the Engine interface, so the scheduling logic can be
+exercised without a GPU (a backend without device records reports the mean device time of
+each chunk of steps as its step latency instead).
 """
 from __future__ import annotations
 
@@ -44,6 +47,8 @@ class Job:
     step_time_s: float = 0.0    # device time of the engine steps this job took part in
     result: dict = None         # final diagnostics
     final_state: dict = None    # state at the horizon (device tensors)
+    history: list = None        # per-step records 0 .. steps-1 (with keep_history)
+    step_latency_s: list = None  # device time of each of the job's steps between records
 
     @property
     def n(self) -> int:
@@ -60,6 +65,7 @@ class Report:
     job_latency_s: dict = field(default_factory=dict)
     admission_wait_s: dict = field(default_factory=dict)
     nonfinite_jobs: int = 0
+    step_latency_source: str = "device records"
 
     @property
     def updates_per_s(self) -> float:
@@ -69,6 +75,7 @@ class Report:
         return {"jobs": len(self.jobs), "nonfinite_jobs": self.nonfinite_jobs,
                 "wall_s": self.wall_s, "updates": self.updates,
                 "updates_per_s": self.updates_per_s, "step_latency_us": self.step_latency_us,
+                "step_latency_source": self.step_latency_source,
                 "job_latency_s": self.job_latency_s, "admission_wait_s": self.admission_wait_s}
 
 
@@ -102,11 +109,12 @@ class Server:
     reaches its horizon sooner).
     retire_nonfinite: retire a job the engine has frozen (non-finite state) after the chunk
     in which it froze, instead of holding its slot until its horizon.
+    keep_history: keep each job's per-step records (job.history) when the backend has them.
     """
 
     def __init__(self, precision="fp32c", max_slots: int = 64, budget_bytes: int = None,
                  chunk: int = 33, backend=None, clock=time.perf_counter, keep_state=False,
-                 retire_nonfinite: bool = True):
+                 retire_nonfinite: bool = True, keep_history: bool = False):
         self.backend = backend if backend is not None else GpuBackend(precision, max_slots)
         self.max_slots = int(self.backend.max_slots)
         self.budget = budget_bytes if budget_bytes is not None else self.backend.default_budget()
@@ -114,6 +122,8 @@ class Server:
         self.clock = clock
         self.keep_state = keep_state
         self.retire_nonfinite = retire_nonfinite
+        self.keep_history = keep_history
+        self.device_records = hasattr(self.backend, "records")
 
     def run(self, jobs: list, sleep=time.sleep) -> Report:
         for j in jobs:
@@ -123,7 +133,8 @@ class Server:
         queue = []                       # arrived, not yet admitted (FIFO)
         resident = {}                    # slot -> job
         used_bytes = 0
-        step_samples = []                # (seconds per step, weight = job-steps)
+        step_samples = []                # (seconds per step, weight = job-steps), per chunk
+        record_samples = []              # seconds per step of a job, from device records
         t0 = self.clock()
         nxt = 0
         while nxt < len(pending) or queue or resident:
@@ -163,6 +174,17 @@ class Server:
             frozen = self.backend.frozen_slots() if self.retire_nonfinite else set()
             for slot in [s for s, j in resident.items() if j.steps_done >= j.horizon or s in frozen]:
                 job = resident.pop(slot)
+                if self.device_records:
+                    # records 0 .. done-1; the last of them is written at retirement (the
+                    # others during the fused launch of the following step), so the stamps of
+                    # records 0 .. done-2 bracket done-2 steps
+                    done = min(job.steps_done, self.backend.frozen_step(slot))
+                    recs = self.backend.records(slot, done) if done > 0 else []
+                    st_s = [r["stamp_s"] for r in recs[:max(0, done - 1)]]
+                    job.step_latency_s = list(np.diff(st_s)) if len(st_s) > 1 else []
+                    record_samples.extend(job.step_latency_s)
+                    if self.keep_history:
+                        job.history = recs
                 job.result = self.backend.diagnostics(slot)
                 st = self.backend.retire(slot)
                 job.final_state = st if self.keep_state else None
@@ -175,8 +197,12 @@ class Server:
                       for j in pending)
         rep = Report(jobs=list(pending), wall_s=wall, updates=updates)
         rep.nonfinite_jobs = sum(1 for j in pending if not j.result.get("finite", True))
-        rep.step_latency_us = _weighted_pcts([1e6 * v for v, _ in step_samples],
-                                             [w for _, w in step_samples])
+        if self.device_records:
+            rep.step_latency_us = _pcts([1e6 * v for v in record_samples])
+        else:
+            rep.step_latency_source = "chunk means"
+            rep.step_latency_us = _weighted_pcts([1e6 * v for v, _ in step_samples],
+                                                 [w for _, w in step_samples])
         rep.job_latency_s = _pcts([j.finished_at - j.arrival for j in pending])
         rep.admission_wait_s = _pcts([j.admitted_at - j.arrival for j in pending])
         return rep
@@ -197,6 +223,8 @@ class GpuBackend:
         self.precision = precision
         self.elem = 8 if precision == "fp64" else 4
         self._ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        from . import wall_clock_hz
+        self.clock_hz = wall_clock_hz()
 
     def default_budget(self) -> int:
         free, _ = self._torch.cuda.mem_get_info()
@@ -225,6 +253,17 @@ class GpuBackend:
 
     def frozen_slots(self) -> set:
         return {s for s, (_, finite) in self.engine.slot_status().items() if not finite}
+
+    def frozen_step(self, slot: int) -> int:
+        """Steps the slot has taken (a frozen instance stops counting)."""
+        return int(self.engine.slot_status()[slot][0])
+
+    def records(self, slot: int, count: int) -> list:
+        """Per-step records 0 .. count-1 of a slot, each with its stamp in seconds."""
+        recs = self.engine.history(slot, 0, count, allow_nonfinite=True)
+        for r in recs:
+            r["stamp_s"] = r["stamp"] / self.clock_hz
+        return recs
 
     def retire(self, slot: int) -> dict:
         return self.engine.retire(slot)

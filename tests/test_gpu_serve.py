@@ -1,9 +1,12 @@
 """Serving loop on the GPU: jobs that arrive while others run are admitted as slots and
-memory free up, run batched with the others, and end with the same result as alone."""
+memory free up, run batched with the others, and end with the same result as alone and as
+the oracle's run of the same job."""
 import numpy as np
 import pytest
 
+import oracle as O
 import workloads as W
+from fp32_reference import fp32_fused_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -36,12 +39,34 @@ def test_each_job_same_alone_and_in_the_mix(vp, prec):
     dtype = np.float64 if prec == "fp64" else np.float32
     ws, jobs = small_jobs(dtype)
     # three slots for five jobs, and a budget that holds about two of them: jobs queue
-    srv = Server(precision=prec, max_slots=3, chunk=9, keep_state=True)
+    srv = Server(precision=prec, max_slots=3, chunk=9, keep_state=True, keep_history=True)
     budget = sorted(srv.backend.job_bytes(j) for j in jobs)
     srv.budget = budget[-1] + budget[-2]
     rep = srv.run(jobs)
     assert rep.updates == sum(j.n * j.horizon for j in jobs)
+    assert rep.step_latency_source == "device records"
     assert rep.step_latency_us["p50"] > 0 and rep.step_latency_us["p99"] >= rep.step_latency_us["p50"]
+    for w, j in zip(ws, jobs):
+        # every served job against the oracle: float64 on the oracle's own run, float32
+        # state on the oracle's sub-flows with the fused step's float32 storage points
+        hist = j.history + [j.result]
+        got = {k: v.detach().cpu().numpy() for k, v in j.final_state.items()}
+        s64 = {k: np.asarray(v, dtype=np.float64) for k, v in j.state.items()}
+        if prec == "fp64":
+            ref_state, _, ref_hist = O.run(*(s64[k] for k in FIELDS), j.L, j.ng, j.dt,
+                                           j.horizon)
+            for k, r in zip(FIELDS, ref_state):
+                assert np.allclose(got[k], r, rtol=0, atol=1e-11), (j.name, k)
+            Wr = [h["W"] for h in ref_hist]
+            assert rel_l2([h["W"] for h in hist], Wr) < 1e-10, j.name
+        else:
+            Wr, _, (Q, P, qs, ps) = fp32_fused_reference(s64, w, j.horizon)
+            assert rel_l2([h["W"] for h in hist], Wr) < 1e-5, j.name
+            for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
+                assert rel_l2(got[k], r) < 1e-5, (j.name, k)
+        assert [h["step"] for h in hist] == list(range(j.horizon + 1)), j.name
+        # per-step device latencies: horizon - 2 samples per job, each a positive time
+        assert len(j.step_latency_s) == j.horizon - 2 and min(j.step_latency_s) > 0, j.name
     for j in jobs:
         assert j.steps_done == j.horizon and j.result["step"] == j.horizon
         alone = vp.Simulation(j.state, j.L, j.ng, j.dt, prec, solver=j.solver)

@@ -85,7 +85,10 @@ def test_null_handles_rejected(lib):
     assert lib.vp_deposit(None) == L.VP_ERR_ARG
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
-    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 7
+    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 8
+    assert ctypes.sizeof(L.vp_diag) == 8 * 12  # twelve 8-byte fields, stamp last
+    assert lib.vp_prepare_step(None, 1) == L.VP_ERR_ARG
+    assert lib.vp_wall_clock_hz(None) == L.VP_ERR_ARG
 
 
 def test_status_strings_of_any_int(lib):
