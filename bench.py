@@ -307,6 +307,49 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def served_block(prec: str, n_jobs: int = 32, slots: int = 64, chunk: int = 33,
+                 load: float = 0.7) -> dict:
+    """A short served stream for the default bench line: the first n_jobs of the seeded
+    served recipe (Landau / two-stream / bump-on-tail, N = 2^U[12, 20], Ng 64..1024, horizons
+    100-2000), continuously batched over one engine's slots on the whole device.  The
+    engine's capacity is measured with every job arriving at t = 0; the same jobs then arrive
+    as a Poisson stream at `load` times that capacity.  Step latency: per job and step, from
+    the device clock stamps of consecutive history records."""
+    import numpy as np
+    import workloads as W
+    from paper_2605_21794_amd.serve import Job, Server
+    dt_np = np.float64 if prec == "fp64" else np.float32
+    base = W.served_jobs(seed=0, n_jobs=n_jobs, rate=1.0)
+    states = [w.state(dt_np) for _, w in base]
+
+    def stream(rate):
+        return [Job(state=st, L=w.L, ng=w.ng, dt=w.dt, horizon=w.nsteps,
+                    arrival=(t / rate if rate else 0.0), name=w.name)
+                for st, (t, w) in zip(states, base)]
+
+    srv = Server(precision=prec, max_slots=slots, chunk=chunk)
+    w0 = base[0][1]
+    srv.run([Job(state=states[0], L=w0.L, ng=w0.ng, dt=w0.dt, horizon=66, name="warm")])
+    sat = srv.run(stream(None))
+    capacity = n_jobs / sat.wall_s
+    rep = srv.run(stream(load * capacity))
+    d = rep.as_dict()
+    srv.backend.engine.close()
+    log(f"served: capacity {capacity:.1f} jobs/s; at {load:g} x capacity {rep.updates_per_s:.3g} "
+        f"updates/s, step p50/p99 {d['step_latency_us']['p50']:.1f}/"
+        f"{d['step_latency_us']['p99']:.1f} us, job p50/p99 {d['job_latency_s']['p50']:.3f}/"
+        f"{d['job_latency_s']['p99']:.3f} s")
+    return {"workload": "served", "jobs": n_jobs, "slots": slots, "chunk": chunk,
+            "precision": prec, "capacity_jobs_per_s": capacity,
+            "saturated_updates_per_s": sat.updates_per_s, "load": load,
+            "rate_jobs_per_s": load * capacity, "updates_per_s": rep.updates_per_s,
+            "updates": rep.updates, "wall_s": rep.wall_s,
+            "step_latency_us": d["step_latency_us"],
+            "step_latency_source": d["step_latency_source"],
+            "job_latency_s": d["job_latency_s"], "admission_wait_s": d["admission_wait_s"],
+            "nonfinite_jobs": d["nonfinite_jobs"]}
+
+
 def run_served(args):
     """Served request stream: seeded Poisson arrivals of mixed Landau / two-stream /
     bump-on-tail jobs, continuously batched over the slots of one engine.
@@ -742,7 +785,7 @@ def cpu_baseline(state, w, budget_s: float, max_steps: int, order: int = 1):
             break
     el = time.perf_counter() - t0
     return {"value": w.n * k / el, "unit": "decorated-particle updates/s", "cores": 1,
-            "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
             "sample": f"{k} {name} calls (FP64 NumPy, single thread) on the full "
                       f"{w.name} state, N={w.n}, Ng={w.ng}, from t=0; {el:.1f} s"}
 
@@ -763,6 +806,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true",
+                    help="leave out the short served stream of the default line")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--instances", type=int, default=256, help="landau_sweep instances")
     ap.add_argument("--sort-every", type=int, default=0,
@@ -859,13 +904,24 @@ def main():
         best, tuning_us = sim.tune(steps_per_trial=99)
         log(f"tuned launch shape {best} ({tuning_us:.2f} us/step)")
     tun = sim.get_tuning()
+    persistent = bool(tun.get("persistent", 0))
+    if not persistent and tun["use_graph"]:
+        # a graph no longer than the timed steps (a multiple of the ring period of 3), and
+        # every graph the timed steps replay captured now, outside the timed region
+        gs = max(3, min(int(tun["graph_steps"]), 3 * (args.steps // 3)))
+        if gs != tun["graph_steps"]:
+            sim.set_tuning(graph_steps=gs)
+        sim.prepare_step(args.steps)
+        tun = sim.get_tuning()
+    timed_launches = ("persistent launches" if persistent else
+                      "graph replays" if tun["use_graph"] else "direct launches")
 
     sim.step(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
-    # HIP events on the library's stream bracket the timed region; every step is one launch
-    # of the fused kernel, replayed back to back from a graph, so elapsed / steps is the
-    # fused kernel's average launch duration
+    # HIP events on the library's stream bracket the timed region: with one launch per step
+    # (graph replays back to back) elapsed / steps is the fused kernel's average launch
+    # duration; a persistent launch runs up to 1024 steps
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -897,10 +953,14 @@ def main():
     finite = bool(np.isfinite(diag["H"]))
     n = w.n
     value = n * args.steps / elapsed
-    persistent = bool(tun.get("persistent", 0))
     # the persistent kernel carries monopole-only particles through the decorated path
-    bytes_per_launch = (MONOPOLE_BYTES if args.monopole and not persistent else FUSED_BYTES)[prec] * n
-    achieved = bytes_per_launch / kern_avg_s / 1e9
+    bytes_per_step = (MONOPOLE_BYTES if args.monopole and not persistent else FUSED_BYTES)[prec] * n
+    # a launch is one step, or up to 1024 steps of the persistent kernel
+    steps_per_launch = min(args.steps, 1024) if persistent else 1
+    launches = -(-args.steps // steps_per_launch)
+    bytes_per_launch = bytes_per_step * steps_per_launch
+    launch_s = ev0.elapsed_time(ev1) * 1e-3 / launches
+    achieved = bytes_per_launch / launch_s / 1e9
     # counters were taken on the one-launch-per-step kernel; the persistent kernel is a
     # different kernel (and moves far fewer bytes), so it reports none
     suffix = ("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
@@ -922,7 +982,7 @@ def main():
         "config": {
             "workload": w.name + suffix, "n": n, "ng": w.ng, "element_order": args.element_order,
             "L": w.L, "dt": w.dt,
-            "precision": prec, "instances": 1, "launch": tun,
+            "precision": prec, "instances": 1, "launch": tun, "timed_launches": timed_launches,
             "sort_every": args.sort_every, "sort_chunk": args.sort_chunk,
             "state_finite_after_run": finite, "t_end": diag["t"],
         },
@@ -930,14 +990,17 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_persist" if persistent else "k_fused",
-            "bytes_per_launch": bytes_per_launch,
-            "kernel_us": kern_avg_s * 1e6, "direct_launch_us": direct_us,
+            "bytes_per_launch": bytes_per_launch, "steps_per_launch": steps_per_launch,
+            "kernel_us": launch_s * 1e6, "us_per_step": kern_avg_s * 1e6,
+            "direct_launch_us": direct_us,
         },
     }
+    sim.close()
+    if not args.no_served:
+        out["served"] = served_block(prec)
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 500, args.element_order)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

@@ -7,5 +7,7 @@ from .vp_oracle import *  # noqa: F401,F403
 from .vp_oracle import __all__ as _cycle_all
 from .cluster_oracle import *  # noqa: F401,F403
 from .cluster_oracle import __all__ as _cluster_all
+from .k3_oracle import *  # noqa: F401,F403
+from .k3_oracle import __all__ as _k3_all
 
-__all__ = list(_cycle_all) + list(_cluster_all)
+__all__ = list(_cycle_all) + list(_cluster_all) + list(_k3_all)

@@ -65,7 +65,8 @@ __all__ = [
     "nodal_curvature", "curvature_at", "solve_field", "kick_values", "kick", "drift", "wrap",
     "diagnostics", "sort_perm", "step", "run", "PROJECTIONS", "external_field",
     "external_energy", "p2_basis", "deposit_p2", "p2_node_weights", "neutralize_p2",
-    "p2_stiffness", "poisson_solve_p2", "field_p2", "solve_field_p2", "kick_p2", "step_p2",
+    "p2_stiffness", "poisson_solve_p2", "field_p2", "solve_field_p2", "field_from_load_p2",
+    "kick_p2", "step_p2",
     "run_p2",
 ]
 
@@ -503,6 +504,11 @@ def solve_field_p2(Q, ps, psi, L: float, ng: int):
     """P2 counterpart of solve_field: dict with bv, bm (loads), btv, btm, Phv, Phm, E0, E1,
     g, the element-average field E (= E0 + E1 / 2) and W = (1/2) Phi^T A Phi."""
     bv, bm = deposit_p2(Q, ps, psi, L, ng)
+    return field_from_load_p2(bv, bm, L, ng)
+
+
+def field_from_load_p2(bv, bm, L: float, ng: int):
+    """The steps of solve_field_p2 after the deposit: neutralise, solve, read the field."""
     btv, btm = neutralize_p2(bv, bm, L, ng)
     Phv, Phm = poisson_solve_p2(btv, btm, L)
     E0, E1, g = field_p2(Phv, Phm, L)

@@ -316,6 +316,13 @@ vp_status launch_steps_graphed(vp_handle* h, int nsteps) {
 
 constexpr int kMaxPersistSteps = 1024;  // steps per cooperative launch (bounds its duration)
 
+// Some occupied slot has general options (the persistent kernel then takes their path).
+bool any_general(const vp_handle* h) {
+  for (int s : h->h_occ)
+    if (h->h_inst[s].general) return true;
+  return false;
+}
+
 // k steps as cooperative persistent launches (particles in registers between steps).
 vp_status advance_persistent(vp_handle* h, int k) {
   while (k > 0) {
@@ -323,7 +330,7 @@ vp_status advance_persistent(vp_handle* h, int k) {
     VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalPersistStart,
                                     h->phase, h->stream));
     VP_HIP(vpk::launch_persist(h->precision, h->tun.threads, h->tun.ppt, h->d_inst, h->d_tiles, h->ntiles,
-                               h->max_ng, h->any_fft, h->phase, c, h->stream));
+                               h->max_ng, h->any_fft, any_general(h), h->phase, c, h->stream));
     h->phase = (h->phase + c) % vpk::kRing;
     k -= c;
   }
@@ -845,7 +852,8 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
   h->tun.persistent = t->persistent ? 1 : 0;
   VP_TRY(rebuild_tables(h));
   if (h->tun.persistent) {
-    const int cap = vpk::persist_capacity(h->precision, h->tun.threads, h->tun.ppt, h->max_ng, h->any_fft);
+    const int cap = vpk::persist_capacity(h->precision, h->tun.threads, h->tun.ppt, h->max_ng,
+                                          h->any_fft, any_general(h));
     if (h->ntiles > cap) {
       const int need = h->ntiles;
       h->tun = old;
@@ -1057,7 +1065,8 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
           for (int s : h->h_occ) t += (h->slots[s].cfg.n + (long long)th * pp - 1) / ((long long)th * pp);
           return t;
         }();
-        if (tiles_needed <= vpk::persist_capacity(h->precision, th, pp, h->max_ng, h->any_fft))
+        if (tiles_needed <= vpk::persist_capacity(h->precision, th, pp, h->max_ng, h->any_fft,
+                                                  any_general(h)))
           for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 1});
       }
   vp_status st = VP_OK;

@@ -126,10 +126,11 @@ hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_t
 // Persistent form of the fused step: nsteps steps in one cooperative launch, the particles
 // of each tile held in registers between steps (ppt per thread, 2, 4 or 8).  Every tile of
 // the launch must be resident at once: persist_capacity gives how many workgroups can be.
+// `general`: some instance of the launch has general options (InstDev::general).
 hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
-                          int ntiles, int max_ng, bool lds_fft, int phase, int nsteps,
-                          hipStream_t s);
-int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft);
+                          int ntiles, int max_ng, bool lds_fft, bool general, int phase,
+                          int nsteps, hipStream_t s);
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general);
 // Solve the listed slots from ring entry `phase` and write the field arrays (materialise).
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
                         int max_ng, bool lds_fft, int phase, hipStream_t s);

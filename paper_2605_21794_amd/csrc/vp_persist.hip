@@ -8,15 +8,79 @@ namespace vpk {
 // nsteps fused steps in one cooperative launch (every workgroup resident at once).  The
 // particles of each tile stay in registers from the first step to the last.  Between steps
 // every workgroup of an instance waits until all of the instance's tiles have flushed the
-// previous step: an arrival counter, polled by one thread with a bounded spin (after
-// kSpinLimit polls the instance is flagged and the wait ends, so every wave finishes).  Data
-// other workgroups of the launch wrote (the load vector, the per-tile kinetic sums, the
-// cleared ring entry) is read and written at device scope; the ring protocol, the records
-// and the arithmetic are those of k_fused, so nsteps persistent steps equal nsteps fused
-// launches.  P2 instances are not taken (the host refuses persistent tuning for them).
+// previous step: each tile counts its arrival on one of kArriveGroups counters (tile index
+// mod kArriveGroups, which collects one XCD's tiles) and one lane per counter polls all of
+// them at once, with a bounded spin (after kSpinLimit polls the instance is flagged and the
+// wait ends, so every wave finishes).  Data other workgroups of the launch wrote (the load
+// vector, the per-tile kinetic sums, the cleared ring entry) is read and written at device
+// scope.  The ring protocol, the records and the arithmetic are those of k_fused, so nsteps
+// persistent steps equal nsteps fused launches.  P2 instances are not taken (the host
+// refuses persistent tuning for them).
+//
+// What no other tile needs is kept off the path between the barriers: every tile clears its
+// own slice of the ring entry the next step deposits into, and the instance's first tile
+// writes the record of step n-1 and the field summary of step n after it has counted its
+// arrival for step n, while the others are still on their way.
+// GEN = false: no instance of the launch has general options (fewer registers).
 constexpr unsigned kSpinLimit = 1u << 22;
 
-template <int MODE, int TPB, int PPT>
+// The first tile's bookkeeping after step n (every thread of the workgroup calls it): the
+// field summary of the field in LDS (W, E1; the same per-thread partials, wave trees and
+// wave order as the solve's), into rec_next and the instance's field-summary ring entry r0;
+// and, when write_rec, the record of integer step rec_step with the kinetic sums of ring
+// entry kin_r (every tile's slot is complete: they were stored before the barrier this
+// workgroup passed at the start of step n) and the field summary rec of that step.
+template <int TPB, bool GEN>
+__device__ void persist_bookkeeping(const InstDev& d, const double* fE, double* sred, int r0,
+                                    int kin_r, bool write_rec, long long rec_step,
+                                    const double (&rec)[3], double (&rec_next)[3]) {
+  const int ng = d.ng, tid = threadIdx.x;
+  const int per = solve_per(ng), j0 = tid * per;
+  const bool solver_thread = tid < kSolveThreads;
+  double kin[kKinFields] = {0.0, 0.0, 0.0, 0.0};
+  if (write_rec && solver_thread) load_kin<true, GEN ? kKinFields : 3>(d, kin_r, kin);
+  double wp = 0.0, er = 0.0, ei = 0.0;
+  if (solver_thread && j0 < ng) {
+    const VPG double* tw = gp(d.tw);
+    const int halfn = ng >> 1;
+    for (int k = 0; k < per; ++k) {
+      const int e = j0 + k, t = e & (halfn - 1);
+      const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
+      const double c = sg * tw[2 * t], sn = sg * tw[2 * t + 1];
+      const double Ee = fE[e];
+      wp += Ee * Ee;
+      er += Ee * c;
+      ei -= Ee * sn;
+    }
+  }
+  if (solver_thread) {
+    solve_wave_total(wp, sred, 3);
+    solve_wave_total(er, sred, 4);
+    solve_wave_total(ei, sred, 5);
+    solve_wave_total(kin[0], sred, 6);
+    solve_wave_total(kin[1], sred, 7);
+    solve_wave_total(kin[2], sred, 8);
+    solve_wave_total(kin[3], sred, 9);
+  }
+  __syncthreads();
+  rec_next[0] = 0.5 * d.h * solve_total(sred, 3);
+  rec_next[1] = solve_total(sred, 4) / (double)ng;
+  rec_next[2] = solve_total(sred, 5) / (double)ng;
+  if (tid == 0) {
+    if (write_rec)
+      write_record(d, rec_step, solve_total(sred, 6), solve_total(sred, 7),
+                   solve_total(sred, 8), GEN ? solve_total(sred, 9) : 0.0, rec[0], rec[1],
+                   rec[2]);
+    VPG InstScal* sc = gp(d.scal);
+    sc->W[r0] = rec_next[0];
+    sc->e1r[r0] = rec_next[1];
+    sc->e1i[r0] = rec_next[2];
+    if (!isfinite(rec_next[0])) sc->nonfinite = 1;
+  }
+  __syncthreads();  // sred is reused by the next solve
+}
+
+template <int MODE, int TPB, int PPT, bool GEN>
 __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ insts,
                                                  const Tile* __restrict__ tiles, int phase0,
                                                  int nsteps) {
@@ -53,11 +117,12 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       b[u] = ntld(psp + i); w[u] = ntld(psip + i);
     }
   }
-  int pend = sc->pend[phase0];
-  long long step = 0;
-  double rec[3] = {0.0, 0.0, 0.0};  // field summary of the previous step (first tile)
+  const int pend0 = sc->pend[phase0];
+  int pend = pend0;
+  long long step0 = 0;
+  double rec[3] = {0.0, 0.0, 0.0};  // field summary of the previous integer step (first tile)
   if (first) {
-    step = sc->step;
+    step0 = sc->step;
     rec[0] = sc->W[ring_prev(phase0)];
     rec[1] = sc->e1r[ring_prev(phase0)];
     rec[2] = sc->e1i[ring_prev(phase0)];
@@ -70,6 +135,10 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       threadIdx.x < kArriveGroups
           ? (unsigned)((d.ntiles - (int)threadIdx.x + kArriveGroups - 1) / kArriveGroups)
           : 0u;
+  // this tile's slice of a ring entry's copies, cleared for the step after next
+  const int ncl = d.acc_copies * ng;
+  const int cl_per = (ncl + d.ntiles - 1) / d.ntiles;
+  const int cl0 = min(ncl, tl.local * cl_per), cl1 = min(ncl, cl0 + cl_per);
 
   int r0 = phase0;
   for (int st = 0; st < nsteps; ++st) {
@@ -92,49 +161,33 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       __syncthreads();
     }
     SolveIn sin_;
-    solve_load<MODE, true, true, false>(d, r0, first, sin_);
+    solve_load<MODE, true, GEN, false>(d, r0, false, sin_);
     for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
     double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
     {
       double sum[7];
-      solve_compute<TPB, true, false>(d, sin_, first, bt, fE, fG, sred, fft, nullptr, sum);
-      if (first) {
-        const int copies = d.acc_copies;
-        for (int c = 0; c < copies; ++c)
-          for (int j = threadIdx.x; j < ng; j += TPB) {
-            if constexpr (MODE == kFP32)
-              gst(gp<float>(d.acc) + acc_off(d, r2, c) + j, 0.0f);
-            else
-              gst(gp(d.acc) + acc_off(d, r2, c) + j, 0.0);
-          }
-        if (threadIdx.x == 0) {
-          if (pend && step >= 1)
-            write_record(d, step - 1, sum[3], sum[4], sum[5], sum[6], rec[0], rec[1], rec[2]);
-          sc->W[r0] = sum[0];
-          sc->e1r[r0] = sum[1];
-          sc->e1i[r0] = sum[2];
-          if (!isfinite(sum[0])) sc->nonfinite = 1;
-          sc->pend[r1] = 1;
-          sc->step = step + 1;
-        }
-        step += 1;
-        rec[0] = sum[0];
-        rec[1] = sum[1];
-        rec[2] = sum[2];
-      }
+      solve_compute<TPB, GEN, false>(d, sin_, false, bt, fE, fG, sred, fft, nullptr, sum);
+    }
+    // ring entry r2 was read at the previous step by every tile (they have all passed the
+    // barrier since) and is deposited into at the next one (after the next barrier)
+    for (int f = cl0 + (int)threadIdx.x; f < cl1; f += TPB) {
+      if constexpr (MODE == kFP32)
+        gst(gp<float>(d.acc) + acc_off(d, r2, 0) + f, 0.0f);
+      else
+        gst(gp(d.acc) + acc_off(d, r2, 0) + f, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
       if (v[u])
-        push_particle<MODE, T, true, true, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
-                                                  w[u], Ks, Ms, Cs, Us);
+        push_particle<MODE, T, true, GEN, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
+                                                 w[u], Ks, Ms, Cs, Us);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Ks = wave_sum(Ks);
     Ms = wave_sum(Ms);
     Cs = wave_sum(Cs);
-    Us = wave_sum(Us);
+    if constexpr (GEN) Us = wave_sum(Us);
     if (lane == 0) {
       red[4 * wid] = Ks;
       red[4 * wid + 1] = Ms;
@@ -148,13 +201,14 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
         kb += red[4 * ww];
         mb += red[4 * ww + 1];
         cbs += red[4 * ww + 2];
-        ub += red[4 * ww + 3];
+        if constexpr (GEN) ub += red[4 * ww + 3];
       }
       VPG double* slot = gp(d.kin) + ((size_t)r0 * d.kin_cap + tl.local) * kKinFields;
       gst(slot, kb);
       gst(slot + 1, mb);
       gst(slot + 2, cbs);
       gst(slot + 3, ub);
+      if (first) sc->pend[r1] = 1;
     }
     flush<MODE, TPB>(d, sacc, r1, tl.local % d.acc_copies);
     if (st + 1 < nsteps) {
@@ -164,8 +218,17 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
         __hip_atomic_fetch_add(arrive + my_group * kArriveStride, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (first) {  // record of step st - 1, field summary of step st
+      double rec_next[3];
+      persist_bookkeeping<TPB, GEN>(d, fE, sred, r0, r2, st > 0 || (pend0 && step0 >= 1),
+                                    step0 + st - 1, rec, rec_next);
+      rec[0] = rec_next[0];
+      rec[1] = rec_next[1];
+      rec[2] = rec_next[2];
+    }
     r0 = r1;
   }
+  if (first && threadIdx.x == 0) sc->step = step0 + nsteps;
 #pragma unroll
   for (int u = 0; u < PPT; ++u)
     if (v[u]) {
@@ -176,10 +239,11 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
 
 #define VP_PERSIST_CASE(M, TB, PP)                                                          \
   if (mode == M && tpb == TB && ppt == PP) {                                                \
-    fn = reinterpret_cast<const void*>(&k_persist<M, TB, PP>);                              \
+    fn = general ? reinterpret_cast<const void*>(&k_persist<M, TB, PP, true>)              \
+                 : reinterpret_cast<const void*>(&k_persist<M, TB, PP, false>);            \
   }
 
-static const void* persist_fn(int mode, int tpb, int ppt) {
+static const void* persist_fn(int mode, int tpb, int ppt, bool general) {
   const void* fn = nullptr;
 #define VP_PERSIST_MODE(M)                                                                  \
   VP_PERSIST_CASE(M, 512, 2) VP_PERSIST_CASE(M, 512, 4) VP_PERSIST_CASE(M, 512, 8)          \
@@ -193,8 +257,8 @@ static const void* persist_fn(int mode, int tpb, int ppt) {
 }
 #undef VP_PERSIST_CASE
 
-int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft) {
-  const void* fn = persist_fn(mode, tpb, ppt);
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general) {
+  const void* fn = persist_fn(mode, tpb, ppt, general);
   if (!fn) return 0;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
   int per_cu = 0, cus = 0, dev = 0;
@@ -205,10 +269,10 @@ int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft) {
 }
 
 hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
-                          int ntiles, int max_ng, bool lds_fft, int phase, int nsteps,
-                          hipStream_t s) {
+                          int ntiles, int max_ng, bool lds_fft, bool general, int phase,
+                          int nsteps, hipStream_t s) {
   if (ntiles <= 0 || nsteps <= 0) return hipSuccess;
-  const void* fn = persist_fn(mode, tpb, ppt);
+  const void* fn = persist_fn(mode, tpb, ppt, general);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
   void* args[] = {(void*)&d_inst, (void*)&d_tiles, (void*)&phase, (void*)&nsteps};

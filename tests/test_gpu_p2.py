@@ -2,8 +2,9 @@
 oracle's P2 functions.  The oracle assembles the P2 stiffness matrix and solves the bordered
 system with the integral gauge, refined in extended precision; the kernels eliminate each
 element's midpoint unknown and solve the P1 system that remains, so the two agree to the
-kernels' float64 rounding: field values within 1e-12 of their scale at every mesh (a NumPy
-model of the condensed solve in float64 is within 5e-15 of the oracle up to Ng 1024), float64
+kernels' float64 rounding: field values within 1e-12 of their scale at every mesh with the
+scan solver (a NumPy model of the condensed solve in float64 is within 5e-15 of the oracle up
+to Ng 1024) and max(1e-12, 1e-17 Ng^2) with the FFT solver, float64
 trajectories 1e-10 (state, absolute) and 1e-10 (histories, relative to their scale).  Float32
 state is held to the oracle's P2 sub-flows with the fused step's float32 storage points.
 Edge cases: the smallest and largest meshes, a ragged tile tail, one particle, monopole-only
@@ -27,8 +28,11 @@ def lattice(ng, nx, nv, alpha=0.05, seed=0):
     return w
 
 
-def field_tol(ng):
-    return 1e-12
+def field_tol(ng, solver="scan"):
+    """The scan solve rounds like a prefix sum (a float64 model of it is within 1e-14 of the
+    oracle up to Ng 1024); the FFT solve divides rounding of the high modes by eigenvalues
+    that fall like 1/Ng^2 (a float64 NumPy model is 1.8e-12 off at Ng 1024, 1.1e-13 at 256)."""
+    return 1e-12 if solver == "scan" else max(1e-12, 1e-17 * ng * ng)
 
 
 def close(a, b, tol):
@@ -66,7 +70,7 @@ def test_field_at_t0(vp, ng, solver):
     sim = vp.Simulation(st, w.L, ng, w.dt, "fp64", hist_cap=4, solver=solver, element_order=2)
     d = sim.diagnostics(0, grid=True)
     f = O.solve_field_p2(st["Q"], st["ps"], st["psi"], w.L, ng)
-    tol = field_tol(ng)
+    tol = field_tol(ng, solver)
     assert d["bt"].shape == (2 * ng,) and d["Phi"].shape == (2 * ng,)
     assert close(d["bt"], np.concatenate([f["btv"], f["btm"]]), tol)
     assert close(d["Phi"], np.concatenate([f["Phv"], f["Phm"]]), tol)
@@ -111,7 +115,8 @@ def test_largest_mesh_trajectory(vp, solver):
     for k, r in zip(FIELDS, ref):
         assert np.allclose(got[k], r, rtol=0, atol=1e-9), k
     d = sim.diagnostics(0, grid=True)
-    assert close(d["E"], fld["E"], field_tol(1024)) and close(d["g"], fld["g"], field_tol(1024))
+    tol = field_tol(1024, solver)
+    assert close(d["E"], fld["E"], tol) and close(d["g"], fld["g"], tol)
     sim.close()
 
 

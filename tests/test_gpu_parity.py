@@ -45,7 +45,7 @@ def test_library_loaded_from_tree(vp):
     with open("/proc/self/maps") as f:
         maps = f.read()
     assert lib_path in maps
-    assert vp.load_library().vp_abi_version() == vp._lib.VP_ABI_VERSION == 7
+    assert vp.load_library().vp_abi_version() == vp._lib.VP_ABI_VERSION == 8
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
@@ -226,7 +226,7 @@ def test_fp32_fused_history_matches_storage_reference(vp, prec):
     print(f"\n[precision] {prec} fused path vs float32-storage reference: W rel L2 = {errW:.3e}, "
           f"H rel L2 = {errH:.3e}")
     assert errW < 1e-5 and errH < 1e-5, (errW, errH)
-    s = np_state(eng)
+    s = {k: v.astype(np.float64) for k, v in eng.state_numpy(0).items()}  # owed half-kick applied
     for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
         assert rel_l2(s[k], r) < 1e-5, k
 
