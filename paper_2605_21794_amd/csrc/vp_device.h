@@ -83,19 +83,14 @@ __device__ __forceinline__ T ntld(const VPG T* p) { return __builtin_nontemporal
 template <typename T>
 __device__ __forceinline__ void ntst(VPG T* p, T v) { __builtin_nontemporal_store(v, p); }
 
-// Element index of x = Q * Ng / L: floor, clamped to [0, Ng-1] (NaN maps to 0), so an LDS
-// index is always in range whatever the state holds.
+// Element index of x = Q * Ng / L: floor, clamped to [0, Ng-1] (NaN maps to 0: fmax returns
+// the number when one operand is NaN), so an LDS index is always in range whatever the state
+// holds.  Branch-free, so the particles of one thread interleave.
 __device__ __forceinline__ int cell_of(double x, int ng) {
-  const double f = floor(x);
-  if (!(f >= 0.0)) return 0;
-  if (f >= (double)(ng - 1)) return ng - 1;
-  return (int)f;
+  return (int)fmin(fmax(floor(x), 0.0), (double)(ng - 1));
 }
 __device__ __forceinline__ int cell_of_f(float x, int ng) {
-  const float f = floorf(x);
-  if (!(f >= 0.0f)) return 0;
-  if (f >= (float)(ng - 1)) return ng - 1;
-  return (int)f;
+  return (int)fminf(fmaxf(floorf(x), 0.0f), (float)(ng - 1));
 }
 __device__ __forceinline__ double frac01(double x, int i) {
   double s = x - (double)i;

@@ -57,12 +57,12 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       const int loc = (k0 + u) * TPB + (int)threadIdx.x;
       g.v[u] = (k0 + u < ppt) && (loc < tl.count);
       g.idx[u] = tl.begin + loc;
+      // a lane past the end of the tile holds an all-zero particle (see run_group)
+      g.q[u] = g.p[u] = g.a[u] = g.b[u] = g.w[u] = T(0);
       if (g.v[u]) {
         g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
         if constexpr (DIP) {
           g.a[u] = ntld(qsp + g.idx[u]); g.b[u] = ntld(psp + g.idx[u]);
-        } else {
-          g.a[u] = T(0); g.b[u] = T(0);
         }
       }
     }
@@ -114,15 +114,22 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
     }
   }
 
+  // Every lane pushes all its particles without a branch: an all-zero particle (a lane past
+  // the end of the tile) deposits +0 and adds 0 to the kinetic sums, so the particles'
+  // dependency chains interleave; only the stores test the lane.
   auto run_group = [&](Group& g) {
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
-      if (!g.v[u]) continue;
       T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
       push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms,
                                            Cs, Us);
-      ntst(Qp + g.idx[u], Q); ntst(Pp + g.idx[u], P);
-      if constexpr (DIP) { ntst(qsp + g.idx[u], qs); ntst(psp + g.idx[u], ps); }
+      g.q[u] = Q; g.p[u] = P; g.a[u] = qs; g.b[u] = ps;
+    }
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if (!g.v[u]) continue;
+      ntst(Qp + g.idx[u], g.q[u]); ntst(Pp + g.idx[u], g.p[u]);
+      if constexpr (DIP) { ntst(qsp + g.idx[u], g.a[u]); ntst(psp + g.idx[u], g.b[u]); }
     }
   };
 

@@ -105,12 +105,15 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   if (sc->frozen) return;  // fixed for the launch: all tiles of the instance leave together
   const bool first = tl.local == 0;
 
+  // A lane past the end of the tile holds an all-zero particle: its deposit adds +0 and its
+  // kinetic sums 0, so every lane runs the push without a branch (only the stores test it).
   T q[PPT], p[PPT], a[PPT], b[PPT], w[PPT];
   bool v[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     const int loc = u * TPB + (int)threadIdx.x;
     v[u] = loc < tl.count;
+    q[u] = p[u] = a[u] = b[u] = w[u] = T(0);
     if (v[u]) {
       const long long i = tl.begin + loc;
       q[u] = ntld(Qp + i); p[u] = ntld(Pp + i); a[u] = ntld(qsp + i);
@@ -178,9 +181,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
-      if (v[u])
-        push_particle<MODE, T, true, GEN, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
-                                                 w[u], Ks, Ms, Cs, Us);
+      push_particle<MODE, T, true, GEN, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
+                                               w[u], Ks, Ms, Cs, Us);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

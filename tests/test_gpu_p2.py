@@ -115,8 +115,9 @@ def test_largest_mesh_trajectory(vp, solver):
     for k, r in zip(FIELDS, ref):
         assert np.allclose(got[k], r, rtol=0, atol=1e-9), k
     d = sim.diagnostics(0, grid=True)
-    tol = field_tol(1024, solver)
-    assert close(d["E"], fld["E"], tol) and close(d["g"], fld["g"], tol)
+    # after six steps the field inherits the trajectories' difference (positions within 1e-9
+    # of the oracle's), so it is held to that bar rather than to the same-bits field bar
+    assert close(d["E"], fld["E"], 1e-9) and close(d["g"], fld["g"], 1e-9)
     sim.close()
 
 

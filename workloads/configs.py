@@ -74,12 +74,15 @@ class Workload:
             return bump_on_tail_profile(p.get("alpha", 0.04), p.get("k", 0.3))
         raise ValueError(self.kind)
 
-    def state(self, dtype=np.float64) -> dict:
+    def state(self, dtype=np.float64, moments: bool = False) -> dict:
+        """The initial state; moments=True adds each cell's second moments (Mqq, Mqp, Mpp)
+        for particles with moments of degree 2 (k = 3)."""
         rng = None
         if self.rng_seedseq is not None:
             rng = np.random.default_rng(self.rng_seedseq)
         st = make_lattice(self.L, self.nx, self.nv, self.vmin, self.vmax, self.profile(),
-                          seed=self.seed, jx=self.jx, jv=self.jv, rng=rng, order=self.order)
+                          seed=self.seed, jx=self.jx, jv=self.jv, rng=rng, order=self.order,
+                          moments=moments)
         return cast_state(st, dtype)
 
 

@@ -68,8 +68,11 @@ def bump_on_tail_profile(alpha: float = 0.04, k: float = 0.3):
 
 def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
                  seed: int = 0, jx: float = 1.0, jv: float = 1.0, rng=None,
-                 order: str = "random"):
-    """Return dict(Q, P, qs, ps, psi) of float64 arrays with nx*nv decorated particles."""
+                 order: str = "random", moments: bool = False):
+    """Return dict(Q, P, qs, ps, psi) of float64 arrays with nx*nv decorated particles.
+    With moments=True also the centred second moments of each cell about its centre (the
+    k = 3 particle): Mqq = int_C f0 (L/pi)^2 sin^2(pi (Q - x)/L), Mqp = int_C f0 c (P - v)
+    with the first moment's periodic displacement c, Mpp = int_C f0 (P - v)^2."""
     X, V = profile
     dx = float(L) / nx
     dv = (float(vmax) - float(vmin)) / nv
@@ -99,6 +102,8 @@ def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
     th = 2.0 * math.pi / L
     ps = np.empty_like(Q)
     qs = np.empty_like(Q)
+    if moments:
+        Mqq, Mqp, Mpp = np.empty_like(Q), np.empty_like(Q), np.empty_like(Q)
     rows = max(1, (1 << 21) // max(1, nx))      # bound the (rows, nx, 8) temporaries
     for r0 in range(0, nv, rows):
         r1 = min(nv, r0 + rows)
@@ -108,8 +113,16 @@ def make_lattice(L: float, nx: int, nv: int, vmin: float, vmax: float, profile,
         # q* = -Ix0 * int V(v) (P - v) dv; P varies per particle
         dvp = P[r0:r1, :, None] - vn[r0:r1, None, :]
         qs[r0:r1] = -Ix0[None, :] * np.sum(Vw[r0:r1, None, :] * dvp, axis=2)
+        if moments:
+            dq2 = (L / math.pi) ** 2 * np.sin(0.5 * th * (Q[r0:r1, :, None] - xn[None, :, :])) ** 2
+            Mqq[r0:r1] = Iv0[r0:r1, None] * np.sum(Xw[None, :, :] * dq2, axis=2)
+            cx = (L / (2.0 * math.pi)) * np.sum(Xw[None, :, :] * sx, axis=2)
+            Mqp[r0:r1] = cx * np.sum(Vw[r0:r1, None, :] * dvp, axis=2)
+            Mpp[r0:r1] = Ix0[None, :] * np.sum(Vw[r0:r1, None, :] * dvp * dvp, axis=2)
 
     out = {"Q": Q, "P": P, "qs": qs, "ps": ps, "psi": psi}
+    if moments:
+        out.update(Mqq=Mqq, Mqp=Mqp, Mpp=Mpp)
     if perm is None:
         return {k: v.reshape(-1).copy() for k, v in out.items()}
     return {k: v.reshape(-1)[perm].copy() for k, v in out.items()}
