@@ -381,6 +381,23 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
  * k, or NULL) receives each centre's v.  Every batch index is checked on the device before
  * use (VP_ERR_ARG if any lies outside [0, m)).  Synchronises the stream.  Errors:
  * VP_ERR_ARG, VP_ERR_HIP. */
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): vp_cluster_markers without the workspace
+ * argument.  The workspace is the library's own file-scope device array of
+ * VP_CLUSTER_STATIC_BYTES (16 MiB), one per device, held until the process ends; the call
+ * allocates nothing.  Same arguments, outputs and results as vp_cluster_markers (bit for
+ * bit); the starting indices are checked on the device.  Refused with VP_ERR_ARG when
+ * vp_cluster_workspace_bytes(m, k) exceeds VP_CLUSTER_STATIC_BYTES (400k markers into 40k
+ * clusters fit).  Every call clears the part of the array it uses first.  Calls that
+ * overlap on one device (two streams, two threads) share the array and race: serialise
+ * them.  Synchronises `stream`.  Errors: VP_ERR_ARG, VP_ERR_HIP. */
+#define VP_CLUSTER_STATIC_BYTES (16u << 20)
+vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const double* wm,
+                                    int64_t m, int32_t k, const int32_t* init_idx, int32_t iters,
+                                    double L, void* stream, double* Q, double* P, double* qs,
+                                    double* ps, double* psi, int32_t* assign_out,
+                                    int32_t* n_out);
+
 vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
                                                size_t* bytes_out);
 vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,

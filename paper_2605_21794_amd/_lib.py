@@ -85,6 +85,10 @@ SIGNATURES = {
                                      POINTER(c_int32)]),
     "vp_cluster_minibatch_workspace_bytes": (c_int32, [c_int64, c_int32, c_int32,
                                                        POINTER(c_size_t)]),
+    "vp_cluster_markers_static": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                                            c_void_p, c_int32, c_double, c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                            POINTER(c_int32)]),
     "vp_cluster_markers_minibatch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32,
                                                c_void_p, c_void_p, c_int32, c_int32, c_double,
                                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -995,6 +995,45 @@ vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const
   return cluster_impl(Qm, Pm, wm, m, k, init_idx, batch_idx, batch, nbatch, 0, L, workspace,
                       stream, Q, P, qs, ps, psi, assign_out, absorbed_out, n_out);
 }
+vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const double* wm,
+                                    int64_t m, int32_t k, const int32_t* init_idx, int32_t iters,
+                                    double L, void* stream, double* Q, double* P, double* qs,
+                                    double* ps, double* psi, int32_t* assign_out,
+                                    int32_t* n_out) {
+  VP_TRY(cluster_check(m, k));
+  if (!Qm || !Pm || !wm || !init_idx || !Q || !P || !qs || !ps || !psi || !n_out)
+    return fail(VP_ERR_ARG, "NULL argument");
+  const void* dptr[9] = {Qm, Pm, wm, Q, P, qs, ps, psi, init_idx};
+  for (int i = 0; i < 9; ++i)
+    if (!aligned(dptr[i], i < 8 ? 8 : 4)) return fail(VP_ERR_ARG, "argument %d misaligned", i);
+  if (assign_out && !aligned(assign_out, 4)) return fail(VP_ERR_ARG, "assign_out misaligned");
+  if (!(iters >= 0)) return fail(VP_ERR_ARG, "iters must be >= 0");
+  if (!(L > 0.0) || !std::isfinite(L)) return fail(VP_ERR_ARG, "L must be positive and finite");
+  const vpk::ClusterWs lay = vpk::cluster_layout(m, k);
+  if (lay.total > (size_t)VP_CLUSTER_STATIC_BYTES)
+    return fail(VP_ERR_ARG,
+                "%lld markers into %d clusters need %zu bytes of workspace; the static workspace "
+                "holds %zu (vp_cluster_markers takes a workspace of any size)",
+                (long long)m, k, lay.total, (size_t)VP_CLUSTER_STATIC_BYTES);
+  void* ws = nullptr;
+  VP_HIP(vpk::cluster_static_workspace(&ws));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the array keeps the previous call's contents: this call's part starts cleared
+  VP_HIP(vpk::launch_fill_zero(ws, lay.total, s));
+  // every starting marker index must address a marker (counted on the device)
+  int bad = 0;
+  VP_HIP(vpk::cluster_count_bad(init_idx, k, m, ws, lay, &bad, s));
+  if (bad) return fail(VP_ERR_ARG, "%d starting indices outside [0, %lld)", bad, (long long)m);
+  double mm[2] = {0.0, 0.0};
+  VP_HIP(vpk::cluster_p_range(Pm, m, ws, lay, mm, s));
+  if (!std::isfinite(mm[0]) || !std::isfinite(mm[1])) return fail(VP_ERR_ARG, "non-finite marker velocities");
+  int n = 0;
+  VP_HIP(vpk::cluster_run(Qm, Pm, wm, m, k, init_idx, nullptr, 0, 0, iters, L, mm[0], mm[1], ws,
+                          lay, Q, P, qs, ps, psi, assign_out, nullptr, &n, s));
+  *n_out = n;
+  return VP_OK;
+}
+
 
 vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   if (!h || !bytes_out) return fail(VP_ERR_ARG, "NULL argument");

@@ -19,6 +19,8 @@
 
 #include "vp_internal.h"
 
+#include <mutex>
+
 #include <math.h>
 
 namespace vpk {
@@ -546,6 +548,33 @@ ClusterWs cluster_layout(long long m, int k, int batch) {
   w.bad = o;     o = a256(o + sizeof(int));
   w.total = o;
   return w;
+}
+
+// ---------------------------------------------------------------- allocation-free workspace
+// The workspace of vp_cluster_markers_static.  A file-scope device array: each device the
+// library runs on holds its own copy for the life of the process.  In host code the array's
+// name is only a stand-in for the symbol, never a device address: its address on a device
+// comes from hipGetSymbolAddress, taken once per device with that device current and kept.
+static __device__ __align__(256) unsigned char scratch[VP_CLUSTER_STATIC_BYTES];
+
+hipError_t cluster_static_workspace(void** ptr_out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptrs[dev] = p;
+  }
+  *ptr_out = ptrs[dev];
+  return hipSuccess;
 }
 
 hipError_t cluster_count_bad(const int* idx, long long n, long long m, void* ws,

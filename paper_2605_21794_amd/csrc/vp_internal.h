@@ -160,6 +160,9 @@ hipError_t cluster_count_bad(const int* idx, long long n, long long m, void* ws,
 // Velocity range of the markers (synchronises the stream).
 hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
                            double* host_minmax, hipStream_t s);
+// The library's own workspace of vp_cluster_markers_static on the current device (a file-scope
+// device array of VP_CLUSTER_STATIC_BYTES, its address looked up once per device).
+hipError_t cluster_static_workspace(void** ptr_out);
 // nbatch mini-batch updates (batches of `batch` marker indices, batch_idx[t * batch ..]),
 // then Lloyd iterations, final assignment, moments and compaction; *host_n = decorated
 // particles written; absorbed_out (k doubles, or NULL) = the weight each centre absorbed in
