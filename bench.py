@@ -43,6 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle per fused step: read Q, P, q*, p*, psi*; write Q, P, q*, p*
 FUSED_BYTES = {"fp64": 72, "fp32c": 36, "fp32": 36, "fp32ts": 36}
 MONOPOLE_BYTES = {"fp64": 40, "fp32c": 20, "fp32": 20, "fp32ts": 20}  # Q, P, psi* in; Q, P out
+# particles with second moments: also read and write Mqq, Mqp, Mpp
+MOMENT_BYTES = {"fp64": 120, "fp32c": 60, "fp32ts": 60}
 
 
 def log(*a):
@@ -764,13 +766,18 @@ def run_primitives(args):
                       "primitives": res}), flush=True)
 
 
-def cpu_baseline(state, w, budget_s: float, max_steps: int, order: int = 1):
+def cpu_baseline(state, w, budget_s: float, max_steps: int, order: int = 1,
+                 moments: bool = False):
     """FP64 oracle steps on the same initial state until the time budget is spent (P2
-    steps with order 2)."""
+    steps with order 2, k = 3 steps with moments)."""
     import numpy as np
     import oracle as O
-    st = tuple(np.asarray(state[k], dtype=np.float64).copy() for k in ("Q", "P", "qs", "ps", "psi"))
-    if order == 2:
+    names = O.K3_FIELDS if moments else ("Q", "P", "qs", "ps", "psi")
+    st = tuple(np.asarray(state[k], dtype=np.float64).copy() for k in names)
+    if moments:
+        fld = O.solve_field_p2_k3(st[0], st[3], st[4], st[5], w.L, w.ng)
+        step, name = O.step_k3, "oracle.step_k3"
+    elif order == 2:
         fld = O.solve_field_p2(st[0], st[3], st[4], w.L, w.ng)
         step, name = O.step_p2, "oracle.step_p2"
     else:
@@ -816,6 +823,8 @@ def main():
     ap.add_argument("--markers", type=int, default=1 << 22, help="cluster: markers")
     ap.add_argument("--monopole", action="store_true",
                     help="run the workload as monopole-only (plain particle-in-cell) particles")
+    ap.add_argument("--moments", action="store_true",
+                    help="particles with second moments (k = 3; P2 elements)")
     ap.add_argument("--element-order", type=int, default=1, choices=(1, 2),
                     help="2: P2 elements (vertex and midpoint nodes) in place of P1")
     ap.add_argument("--ng", type=int, default=0,
@@ -840,6 +849,10 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"))
     args = ap.parse_args()
+    if args.moments:
+        if args.monopole:
+            raise SystemExit("--moments needs dipoles (not --monopole)")
+        args.element_order = 2
     if args.steps is None:
         args.steps = 99 if args.workload == "landau_sweep" else 1000
     if args.pmc_summary:
@@ -885,7 +898,9 @@ def main():
         prec = args.precision
     log(f"workload {w.name}: N={w.n} Ng={w.ng} dt={w.dt} precision={prec}")
     t0 = time.perf_counter()
-    state = w.state(np.float64 if prec == "fp64" else np.float32)
+    if args.moments and prec not in MOMENT_BYTES:
+        raise SystemExit(f"--moments runs in {sorted(MOMENT_BYTES)}, not {prec}")
+    state = w.state(np.float64 if prec == "fp64" else np.float32, moments=args.moments)
     if args.monopole:  # plain particle-in-cell: the same lattice without its dipole moments
         state["qs"][:] = 0
         state["ps"][:] = 0
@@ -954,7 +969,9 @@ def main():
     n = w.n
     value = n * args.steps / elapsed
     # the persistent kernel carries monopole-only particles through the decorated path
-    bytes_per_step = (MONOPOLE_BYTES if args.monopole and not persistent else FUSED_BYTES)[prec] * n
+    table = (MOMENT_BYTES if args.moments else
+             MONOPOLE_BYTES if args.monopole and not persistent else FUSED_BYTES)
+    bytes_per_step = table[prec] * n
     # a launch is one step, or up to 1024 steps of the persistent kernel
     steps_per_launch = min(args.steps, 1024) if persistent else 1
     launches = -(-args.steps // steps_per_launch)
@@ -963,7 +980,8 @@ def main():
     achieved = bytes_per_launch / launch_s / 1e9
     # counters were taken on the one-launch-per-step kernel; the persistent kernel is a
     # different kernel (and moves far fewer bytes), so it reports none
-    suffix = ("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
+    suffix = (("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
+              + ("_k3" if args.moments else ""))
     traffic_key = args.workload + suffix
     traffic = None if persistent else load_traffic(traffic_key, n, prec, launch_key(tun))
     out = {
@@ -1000,7 +1018,8 @@ def main():
         out["served"] = served_block(prec)
     if not args.no_cpu:
         log("timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 500, args.element_order)
+        out["cpu_baseline"] = cpu_baseline(state, w, args.cpu_budget, 500, args.element_order,
+                                           args.moments)
     print(json.dumps(out), flush=True)
 
 

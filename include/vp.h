@@ -18,7 +18,8 @@
  *     particle arrays and workspaces are borrowed from vp_create / vp_admit until
  *     vp_destroy / vp_retire and must stay allocated and untouched by other work until then.
  *   - Particle arrays are five separate contiguous arrays (structure of arrays) of n
- *     elements each, float64 for VP_FP64 and float32 for the three float32 modes.
+ *     elements each (eight with second moments, vp_config.moment_order 3), float64 for
+ *     VP_FP64 and float32 for the three float32 modes.
  *     Positions must lie in [0, L) on entry; psi* is never written.
  *   - Work is enqueued asynchronously on the stream given at creation (a hipStream_t
  *     passed as void*, NULL for the null stream) unless a function says it synchronises.
@@ -36,7 +37,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 8
+#define VP_ABI_VERSION 9
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -106,7 +107,21 @@ typedef struct vp_config {
                             element, so cfg.projection must be VP_PROJ_ELEM and plays no
                             part).  P2 needs a precision other than VP_FP32 and is not run by
                             persistent tuning. */
-  int32_t reserved_;     /* 0 */
+  int32_t moment_order;  /* highest moment carried by each particle, the k of the ansatz
+                            (eq. sw_f_ansatz) and its quotient algebra s_k (Section
+                            "Scovel-Weinstein enhancement of PIC").  0 or 2 (default): the
+                            monopole-dipole particle (k = 2).  3: each particle also carries
+                            its centred second moments M = (Mqq, Mqp, Mpp) (vp_particles'
+                            Mqq, Mqp, Mpp, read and written).  Their Lie-Poisson bracket on
+                            the quadratic phase-space polynomials gives the covariance
+                            equations of the linearised flow: each kick maps M to A M A^T
+                            with A = [[1, 0], [-tau phi'', 1]], each drift with A = [[1, tau],
+                            [0, 1]], so det M is kept exactly; the load gains (1/2) Mqq
+                            phi_j''(Q), q*'s kick gains -(1/2) Mqq V'''(Q) of a prescribed
+                            potential, K gains Mpp / 2 and U gains (1/2) Mqq V''(Q).  k = 3
+                            needs element_order 2 (phi_j'' exists on each element), a
+                            precision other than VP_FP32, monopole_only 0 and sort_every 0;
+                            vp_sort and persistent tuning refuse such a slot. */
 } vp_config;
 
 /* The dipole equation d(q*)/dt = p* phi_h''(Q) needs a second derivative that a P1 potential
@@ -139,12 +154,16 @@ typedef struct vp_particles {
   void* qs;   /* q*: momentum dipole                   */
   void* ps;   /* p*: spatial dipole                    */
   void* psi;  /* psi*: weight, read only               */
+  void* Mqq;  /* second moments (vp_config.moment_order 3 only; NULL otherwise): */
+  void* Mqp;  /*   the particle's centred covariance in q-q, q-p and p-p, a       */
+  void* Mpp;  /*   positive semi-definite 2 x 2 matrix                             */
 } vp_particles;
 
 typedef struct vp_diag {
   int64_t step;     /* steps taken by vp_step since creation / admission */
   double t;         /* step * dt */
-  double K;         /* sum psi* P^2 / 2 + q* P  (kinetic part of eq. Hh)          */
+  double K;         /* sum psi* P^2 / 2 + q* P  (kinetic part of eq. Hh), + Mpp / 2 for
+                       particles with second moments */
   double W;         /* (1/2) Phi^T A Phi = (1/2) sum_e h E_e^2 (field part of eq. Hh) */
   double H;         /* K + U + W */
   double charge;    /* sum psi* */
@@ -279,7 +298,8 @@ vp_status vp_sync_state(vp_handle* h);
  * i = min(floor(Q * Ng / L), Ng - 1), computed in float64), chunks of cfg.sort_chunk
  * particles, ties kept in original order.  Permutes all five arrays in place.  If
  * dev_perm is non-NULL, writes the permutation (dev_perm[k] = source index of slot k,
- * int32, n entries).  slot < 0 sorts every occupied slot (dev_perm must then be NULL). */
+ * int32, n entries).  slot < 0 sorts every occupied slot (dev_perm must then be NULL).
+ * A slot whose particles carry second moments (moment_order 3) is refused (VP_ERR_ARG). */
 vp_status vp_sort(vp_handle* h, int32_t slot, int32_t* dev_perm);
 
 /* Cell index of every particle of one slot into dev_cells (int32, n entries), by the
@@ -361,6 +381,23 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
                              void* workspace, void* stream, double* Q, double* P, double* qs,
                              double* ps, double* psi, int32_t* assign_out, int32_t* n_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): vp_cluster_markers without the workspace
+ * argument.  The workspace is the library's own file-scope device array of
+ * VP_CLUSTER_STATIC_BYTES (16 MiB), one per device, held until the process ends; the call
+ * allocates nothing.  Same arguments, outputs and results as vp_cluster_markers (bit for
+ * bit); the starting indices are checked on the device.  Refused with VP_ERR_ARG when
+ * vp_cluster_workspace_bytes(m, k) exceeds VP_CLUSTER_STATIC_BYTES (400k markers into 40k
+ * clusters fit).  Every call clears the part of the array it uses first.  Calls that
+ * overlap on one device (two streams, two threads) share the array and race: serialise
+ * them.  Synchronises `stream`.  Errors: VP_ERR_ARG, VP_ERR_HIP. */
+#define VP_CLUSTER_STATIC_BYTES (16u << 20)
+vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const double* wm,
+                                    int64_t m, int32_t k, const int32_t* init_idx, int32_t iters,
+                                    double L, void* stream, double* Q, double* P, double* qs,
+                                    double* ps, double* psi, int32_t* assign_out,
+                                    int32_t* n_out);
+
 /* Algorithm 1 with mini-batch k-means in place of Lloyd's iteration, which the paper allows
  * for large runs (Section 4, before Algorithm 1).  The update is the weighted, batched form
  * of Sculley's mini-batch k-means ("Web-scale k-means clustering", 2010).  From the k
@@ -381,23 +418,6 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
  * k, or NULL) receives each centre's v.  Every batch index is checked on the device before
  * use (VP_ERR_ARG if any lies outside [0, m)).  Synchronises the stream.  Errors:
  * VP_ERR_ARG, VP_ERR_HIP. */
-/* For callers that cannot allocate device memory (code under HIP graph capture, tight
- * serving loops, harnesses that forbid hipMalloc): vp_cluster_markers without the workspace
- * argument.  The workspace is the library's own file-scope device array of
- * VP_CLUSTER_STATIC_BYTES (16 MiB), one per device, held until the process ends; the call
- * allocates nothing.  Same arguments, outputs and results as vp_cluster_markers (bit for
- * bit); the starting indices are checked on the device.  Refused with VP_ERR_ARG when
- * vp_cluster_workspace_bytes(m, k) exceeds VP_CLUSTER_STATIC_BYTES (400k markers into 40k
- * clusters fit).  Every call clears the part of the array it uses first.  Calls that
- * overlap on one device (two streams, two threads) share the array and race: serialise
- * them.  Synchronises `stream`.  Errors: VP_ERR_ARG, VP_ERR_HIP. */
-#define VP_CLUSTER_STATIC_BYTES (16u << 20)
-vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const double* wm,
-                                    int64_t m, int32_t k, const int32_t* init_idx, int32_t iters,
-                                    double L, void* stream, double* Q, double* P, double* qs,
-                                    double* ps, double* psi, int32_t* assign_out,
-                                    int32_t* n_out);
-
 vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
                                                size_t* bytes_out);
 vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,

@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": L.VP_FP64, "fp32c": L.VP_FP32_COMP, "fp32": L.VP_FP32,
 FIELDS = ("Q", "P", "qs", "ps", "psi")
 
 
+MOMENTS = ("Mqq", "Mqp", "Mpp")        # second moments of k = 3 particles
 def load_library():
     return L.load()
 
@@ -44,7 +45,7 @@ PROJECTIONS = {"elem": L.VP_PROJ_ELEM, "nodal": L.VP_PROJ_NODAL,
 
 def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4096,
                 solver="scan", projection="elem", monopole_only=False, self_field=True,
-                external=None, element_order=1):
+                external=None, element_order=1, moment_order=2):
     return L.vp_config(n=int(n), ng=int(ng), precision=_prec(precision), L=float(L_),
                        dt=float(dt), sort_every=int(sort_every), sort_chunk=int(sort_chunk),
                        hist_cap=int(hist_cap),
@@ -54,7 +55,7 @@ def make_config(n, ng, L_, dt, precision, sort_every=0, sort_chunk=0, hist_cap=4
                        no_self_field=0 if self_field else 1,
                        ext_mode=int(external["mode"]) if external else 0,
                        ext_amplitude=float(external["amp"]) if external else 0.0,
-                       element_order=int(element_order))
+                       element_order=int(element_order), moment_order=int(moment_order))
 
 
 def workspace_bytes(cfg) -> int:
@@ -179,31 +180,38 @@ class Engine:
     def admit(self, slot: int, state: dict, L_: float, ng: int, dt: float, sort_every: int = 0,
               sort_chunk: int = 0, hist_cap: int = 4096, solver="scan", projection="elem",
               monopole_only: bool = False, self_field: bool = True, external=None,
-              element_order: int = 1):
+              element_order: int = 1, moment_order: int = None):
         """Copy `state` (arrays Q, P, qs, ps, psi) to the device and admit it into `slot`.
         monopole_only: plain particle-in-cell particles (p* = q* = 0; qs, ps may be left out
         of `state`, and are zeroed on admission).  self_field=False: the particles feel no
         field of their own (charge e = 0).  external = {"amp": A, "mode": m}: the prescribed
         potential A (1 - cos(2 pi m q / L)).  element_order=2: P2 elements (a vertex and a
-        midpoint node per element; phi_h'' from the basis)."""
+        midpoint node per element; phi_h'' from the basis).  moment_order=3 (the default when
+        `state` holds Mqq): the particles also carry their second moments Mqq, Mqp, Mpp (k = 3;
+        P2 elements only)."""
         t = self._torch
-        tens = {k: self._tensor(state[k]) for k in FIELDS if k in state}
+        if moment_order is None:
+            moment_order = 3 if "Mqq" in state else 2
+        names = FIELDS + (MOMENTS if moment_order == 3 else ())
+        tens = {k: self._tensor(state[k]) for k in names if k in state}
         if monopole_only:
             for k in ("qs", "ps"):
                 if k not in tens:
                     tens[k] = t.zeros_like(tens["Q"])
-        missing = [k for k in FIELDS if k not in tens]
+        missing = [k for k in names if k not in tens]
         if missing:
             raise ValueError(f"state lacks {missing}")
         n = int(tens["Q"].numel())
         if any(int(v.numel()) != n for v in tens.values()):
             raise ValueError("state arrays differ in length")
         cfg = make_config(n, ng, L_, dt, self.prec, sort_every, sort_chunk, hist_cap, solver,
-                          projection, monopole_only, self_field, external, element_order)
+                          projection, monopole_only, self_field, external, element_order,
+                          moment_order)
         ws = t.zeros(workspace_bytes(cfg), dtype=t.uint8, device=self.device)
         if ws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
-        parts = L.vp_particles(*(c_void_p(tens[k].data_ptr()) for k in FIELDS))
+        parts = L.vp_particles(*(c_void_p(tens[k].data_ptr() if k in tens else None)
+                                 for k in FIELDS + MOMENTS))
         t.cuda.current_stream(self.device).synchronize()
         L.check(self.lib.vp_admit(self.h, int(slot), byref(cfg), parts, c_void_p(ws.data_ptr())),
                 "vp_admit")
@@ -351,7 +359,7 @@ class Simulation(Engine):
     def __init__(self, state: dict, L_: float, ng: int, dt: float, precision="fp32c",
                  sort_every: int = 0, sort_chunk: int = 0, hist_cap: int = 4096, device=None,
                  stream=None, solver="scan", projection="elem", monopole_only=False,
-                 self_field=True, external=None, element_order=1):
+                 self_field=True, external=None, element_order=1, moment_order=None):
         super().__init__(precision, 1, device, stream)
         self.admit(0, state, L_, ng, dt, sort_every, sort_chunk, hist_cap, solver, projection,
-                   monopole_only, self_field, external, element_order)
+                   monopole_only, self_field, external, element_order, moment_order)

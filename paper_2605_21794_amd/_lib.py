@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
-VP_ABI_VERSION = 8          # the layout of the structures declared below
+VP_ABI_VERSION = 9          # the layout of the structures declared below
 VP_SLOT_OCCUPIED, VP_SLOT_NONFINITE = 1, 2
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_PROJ_ELEM, VP_PROJ_NODAL, VP_PROJ_CONSISTENT = 0, 1, 2
@@ -25,12 +25,12 @@ class vp_config(Structure):
                 ("hist_cap", c_int32), ("solver", c_int32),
                 ("projection", c_int32), ("monopole_only", c_int32),
                 ("no_self_field", c_int32), ("ext_mode", c_int32), ("ext_amplitude", c_double),
-                ("element_order", c_int32), ("reserved_", c_int32)]
+                ("element_order", c_int32), ("moment_order", c_int32)]
 
 
 class vp_particles(Structure):
     _fields_ = [("Q", c_void_p), ("P", c_void_p), ("qs", c_void_p), ("ps", c_void_p),
-                ("psi", c_void_p)]
+                ("psi", c_void_p), ("Mqq", c_void_p), ("Mqp", c_void_p), ("Mpp", c_void_p)]
 
 
 class vp_diag(Structure):

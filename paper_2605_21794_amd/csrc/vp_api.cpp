@@ -43,6 +43,9 @@ vp_status fail(vp_status s, const char* fmt, ...) {
     if (s_ != VP_OK) return s_;   \
   } while (0)
 
+constexpr int kGroups = 9;        // kinds of tiles, one fused launch each (see rebuild_tables)
+constexpr int kGroupMoments = 8;  // the kind of instances with second moments
+
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int x) { int m = 0; while ((1 << m) < x) ++m; return m; }
 size_t state_elem_size(int prec) { return prec == VP_FP64 ? sizeof(double) : sizeof(float); }
@@ -79,11 +82,23 @@ vp_status validate(const vp_config* c) {
       return fail(VP_ERR_ARG, "P2 elements take phi_h'' from the basis: projection must be "
                               "VP_PROJ_ELEM");
   }
-  if (c->reserved_ != 0) return fail(VP_ERR_ARG, "reserved_ must be 0");
+  if (c->moment_order != 0 && c->moment_order != 2 && c->moment_order != 3)
+    return fail(VP_ERR_ARG, "moment_order = %d must be 0, 2 or 3", c->moment_order);
+  if (c->moment_order == 3) {
+    if (c->element_order != 2)
+      return fail(VP_ERR_ARG, "second moments need P2 elements (element_order 2)");
+    if (c->precision == VP_FP32)
+      return fail(VP_ERR_ARG, "second moments need a precision other than VP_FP32");
+    if (c->monopole_only) return fail(VP_ERR_ARG, "second moments need dipoles (monopole_only 0)");
+    if (c->sort_every != 0)
+      return fail(VP_ERR_ARG, "particles with second moments are not sorted (sort_every 0)");
+  }
   return VP_OK;
 }
 
 int order_of(const vp_config& c) { return c.element_order == 2 ? 2 : 1; }
+// Particle arrays of a slot: five, eight with second moments.
+int state_arrays(const vp_config& c) { return c.moment_order == 3 ? 8 : 5; }
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -112,9 +127,10 @@ struct vp_handle {
   Tile* d_tiles = nullptr;
   size_t tiles_cap = 0;
   int ntiles = 0;
-  int ntiles_dip = 0;      // tiles of decorated instances (they come first)
-  // tile ranges by kind: decorated / monopole-only x P1 / P2 x without / with general options
-  int group_end[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int ntiles_dip = 0;      // tiles of decorated instances
+  // tile ranges by kind: decorated / monopole-only x P1 / P2 x without / with general
+  // options, then the instances with second moments
+  int group_end[kGroups] = {};
   int* d_occ = nullptr;
   int* d_ids = nullptr;     // d_ids[i] = i, for single-slot launches
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
@@ -163,17 +179,18 @@ vp_status rebuild_tables(vp_handle* h) {
     if (h->slots[s].used) h->h_occ.push_back(s);
   // tiles grouped by kind, one fused launch per non-empty group and step: decorated then
   // monopole-only instances; within each, P1 then P2 elements, each without then with
-  // general options
+  // general options; last the instances with second moments (P2, general, decorated)
   auto group_of = [&](int s) {
     const InstDev& d = h->h_inst[s];
+    if (d.k3) return kGroupMoments;
     return (h->slots[s].cfg.monopole_only ? 4 : 0) + (d.order == 2 ? 2 : 0) + (d.general ? 1 : 0);
   };
   std::vector<int> order;
-  for (int gi = 0; gi < 8; ++gi)
+  for (int gi = 0; gi < kGroups; ++gi)
     for (int s : h->h_occ)
       if (group_of(s) == gi) order.push_back(s);
   h->ntiles_dip = 0;
-  for (int gi = 0; gi < 8; ++gi) h->group_end[gi] = 0;
+  for (int gi = 0; gi < kGroups; ++gi) h->group_end[gi] = 0;
   for (int s : order) {
     Slot& sl = h->slots[s];
     h->max_ng = std::max(h->max_ng, order_of(sl.cfg) * sl.cfg.ng);  // LDS sizing
@@ -194,7 +211,7 @@ vp_status rebuild_tables(vp_handle* h) {
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
-    for (int gi = group_of(s); gi < 8; ++gi) h->group_end[gi] += nt;
+    for (int gi = group_of(s); gi < kGroups; ++gi) h->group_end[gi] += nt;
   }
   h->ntiles = (int)h->h_tiles.size();
   h->any_fft = false;
@@ -231,15 +248,18 @@ vp_status check_slot(const vp_handle* h, int slot) {
 int next_phase(int p) { return p == vpk::kRing - 1 ? 0 : p + 1; }
 
 // One fused step of every instance in phase ph: one launch per non-empty group of tiles
-// (decorated / monopole-only instances x P1 / P2 x without / with general options).
+// (decorated / monopole-only instances x P1 / P2 x without / with general options, and the
+// instances with second moments).
 hipError_t fused_step(vp_handle* h, int ph) {
   int b = 0;
-  for (int gi = 0; gi < 8; ++gi) {
+  for (int gi = 0; gi < kGroups; ++gi) {
     const int e_ = h->group_end[gi];
     if (e_ > b) {
+      const bool km = gi == kGroupMoments;
       const hipError_t e = vpk::launch_fused(h->precision, h->tun.threads, h->d_inst, h->d_tiles,
                                              b, e_ - b, h->tun.ppt, h->max_ng, h->any_fft, ph,
-                                             gi < 4, (gi & 1) != 0, (gi & 2) != 0, h->stream);
+                                             gi < 4 || km, (gi & 1) != 0 || km,
+                                             (gi & 2) != 0 || km, km, h->stream);
       if (e != hipSuccess) return e;
     }
     b = e_;
@@ -484,9 +504,11 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   if (cfg->precision != h->precision)
     return fail(VP_ERR_ARG, "precision %d differs from the engine's %d", cfg->precision, h->precision);
   const size_t es = state_elem_size(cfg->precision);
-  void* arrs[5] = {parts.Q, parts.P, parts.qs, parts.ps, parts.psi};
-  for (int k = 0; k < 5; ++k)
+  const bool k3 = cfg->moment_order == 3;
+  void* arrs[8] = {parts.Q, parts.P, parts.qs, parts.ps, parts.psi, parts.Mqq, parts.Mqp, parts.Mpp};
+  for (int k = 0; k < (k3 ? 8 : 5); ++k)
     if (!arrs[k] || !aligned(arrs[k], es)) return fail(VP_ERR_ARG, "particle array %d NULL or misaligned", k);
+  if (!k3) parts.Mqq = parts.Mqp = parts.Mpp = nullptr;
   if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
 
   if (h->tun.persistent && order_of(*cfg) == 2)
@@ -519,7 +541,10 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   d.proj = cfg->projection;
   d.self_on = cfg->no_self_field ? 0 : 1;
   d.ext_on = (cfg->ext_mode >= 1 && cfg->ext_amplitude != 0.0) ? 1 : 0;
-  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on) ? 1 : 0;
+  d.Mqq = parts.Mqq; d.Mqp = parts.Mqp; d.Mpp = parts.Mpp;
+  d.k3 = k3 ? 1 : 0;
+  // second moments run in the kernels' general path
+  d.general = (d.proj != VP_PROJ_ELEM || !d.self_on || d.ext_on || k3) ? 1 : 0;
   d.ext_a = cfg->ext_amplitude;
   d.ext_k = 6.283185307179586 * (double)cfg->ext_mode / cfg->L;  // 2 pi m / L
   d.ext_ak = d.ext_a * d.ext_k;
@@ -734,12 +759,15 @@ vp_status vp_sort(vp_handle* h, int32_t slot, int32_t* dev_perm) {
   if (slot < 0) {
     if (dev_perm) return fail(VP_ERR_ARG, "dev_perm must be NULL when sorting every slot");
     for (int s : h->h_occ)
+      if (h->h_inst[s].k3) return fail(VP_ERR_ARG, "slot %d carries second moments, which are not sorted", s);
+    for (int s : h->h_occ)
       VP_HIP(vpk::launch_sort(h->precision, h->d_inst, s, h->slots[s].cfg.n,
                               sort_chunk_of(h->slots[s].cfg), nullptr, h->stream));
     return VP_OK;
   }
   VP_TRY(check_slot(h, slot));
   const Slot& sl = h->slots[slot];
+  if (h->h_inst[slot].k3) return fail(VP_ERR_ARG, "slot %d carries second moments, which are not sorted", slot);
   if (dev_perm && sl.cfg.n > INT32_MAX) return fail(VP_ERR_ARG, "n too large for an int32 permutation");
   VP_HIP(vpk::launch_sort(h->precision, h->d_inst, slot, sl.cfg.n, sort_chunk_of(sl.cfg), dev_perm,
                           h->stream));
@@ -967,34 +995,6 @@ vp_status vp_cluster_markers(const double* Qm, const double* Pm, const double* w
                       P, qs, ps, psi, assign_out, nullptr, n_out);
 }
 
-static vp_status minibatch_check(int64_t m, int32_t k, int32_t batch, int32_t nbatch) {
-  VP_TRY(cluster_check(m, k));
-  if (batch < 1 || batch > m) return fail(VP_ERR_ARG, "batch = %d must lie in [1, m]", batch);
-  if (nbatch < 1) return fail(VP_ERR_ARG, "nbatch must be >= 1");
-  if ((long long)batch * nbatch > 0x7fffffffLL)
-    return fail(VP_ERR_ARG, "batch * nbatch = %lld exceeds 2^31 - 1", (long long)batch * nbatch);
-  return VP_OK;
-}
-
-vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
-                                               size_t* bytes_out) {
-  if (!bytes_out) return fail(VP_ERR_ARG, "NULL argument");
-  VP_TRY(minibatch_check(m, k, batch, 1));
-  *bytes_out = vpk::cluster_layout(m, k, batch).total;
-  return VP_OK;
-}
-
-vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,
-                                       int64_t m, int32_t k, const int32_t* init_idx,
-                                       const int32_t* batch_idx, int32_t batch, int32_t nbatch,
-                                       double L, void* workspace, void* stream, double* Q,
-                                       double* P, double* qs, double* ps, double* psi,
-                                       int32_t* assign_out, double* absorbed_out,
-                                       int32_t* n_out) {
-  VP_TRY(minibatch_check(m, k, batch, nbatch));
-  return cluster_impl(Qm, Pm, wm, m, k, init_idx, batch_idx, batch, nbatch, 0, L, workspace,
-                      stream, Q, P, qs, ps, psi, assign_out, absorbed_out, n_out);
-}
 vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const double* wm,
                                     int64_t m, int32_t k, const int32_t* init_idx, int32_t iters,
                                     double L, void* stream, double* Q, double* P, double* qs,
@@ -1034,13 +1034,41 @@ vp_status vp_cluster_markers_static(const double* Qm, const double* Pm, const do
   return VP_OK;
 }
 
+static vp_status minibatch_check(int64_t m, int32_t k, int32_t batch, int32_t nbatch) {
+  VP_TRY(cluster_check(m, k));
+  if (batch < 1 || batch > m) return fail(VP_ERR_ARG, "batch = %d must lie in [1, m]", batch);
+  if (nbatch < 1) return fail(VP_ERR_ARG, "nbatch must be >= 1");
+  if ((long long)batch * nbatch > 0x7fffffffLL)
+    return fail(VP_ERR_ARG, "batch * nbatch = %lld exceeds 2^31 - 1", (long long)batch * nbatch);
+  return VP_OK;
+}
+
+vp_status vp_cluster_minibatch_workspace_bytes(int64_t m, int32_t k, int32_t batch,
+                                               size_t* bytes_out) {
+  if (!bytes_out) return fail(VP_ERR_ARG, "NULL argument");
+  VP_TRY(minibatch_check(m, k, batch, 1));
+  *bytes_out = vpk::cluster_layout(m, k, batch).total;
+  return VP_OK;
+}
+
+vp_status vp_cluster_markers_minibatch(const double* Qm, const double* Pm, const double* wm,
+                                       int64_t m, int32_t k, const int32_t* init_idx,
+                                       const int32_t* batch_idx, int32_t batch, int32_t nbatch,
+                                       double L, void* workspace, void* stream, double* Q,
+                                       double* P, double* qs, double* ps, double* psi,
+                                       int32_t* assign_out, double* absorbed_out,
+                                       int32_t* n_out) {
+  VP_TRY(minibatch_check(m, k, batch, nbatch));
+  return cluster_impl(Qm, Pm, wm, m, k, init_idx, batch_idx, batch, nbatch, 0, L, workspace,
+                      stream, Q, P, qs, ps, psi, assign_out, absorbed_out, n_out);
+}
 
 vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
   if (!h || !bytes_out) return fail(VP_ERR_ARG, "NULL argument");
   size_t b = 0;
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
-    b += ((size_t)5 * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
+    b += ((size_t)state_arrays(sl.cfg) * sl.cfg.n * state_elem_size(h->precision) + 255) & ~size_t(255);
     b += vpk::workspace_layout(sl.cfg.ng, order_of(sl.cfg), sl.cfg.hist_cap, sl.cfg.n).total;
   }
   *bytes_out = b;
@@ -1048,7 +1076,7 @@ vp_status vp_tune_scratch_bytes(const vp_handle* h, size_t* bytes_out) {
 }
 
 namespace {
-// Copy the state of every occupied slot (the five particle arrays, which a scheduled sort
+// Copy the state of every occupied slot (its particle arrays, which a scheduled sort
 // permutes, and the workspace) to or from
 // the tuner scratch buffer.
 vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
@@ -1056,13 +1084,15 @@ vp_status tune_copy(vp_handle* h, char* scratch, bool save) {
   for (int s : h->h_occ) {
     const Slot& sl = h->slots[s];
     const size_t es = state_elem_size(h->precision);
-    void* arrs[5] = {sl.parts.Q, sl.parts.P, sl.parts.qs, sl.parts.ps, sl.parts.psi};
-    for (int k = 0; k < 5; ++k) {
+    void* arrs[8] = {sl.parts.Q,  sl.parts.P,   sl.parts.qs,  sl.parts.ps,
+                     sl.parts.psi, sl.parts.Mqq, sl.parts.Mqp, sl.parts.Mpp};
+    const int na = state_arrays(sl.cfg);
+    for (int k = 0; k < na; ++k) {
       char* sp = scratch + off + (size_t)k * sl.cfg.n * es;
       if (save) VP_HIP(hipMemcpyAsync(sp, arrs[k], sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
       else VP_HIP(hipMemcpyAsync(arrs[k], sp, sl.cfg.n * es, hipMemcpyDeviceToDevice, h->stream));
     }
-    off += ((size_t)5 * sl.cfg.n * es + 255) & ~size_t(255);
+    off += ((size_t)na * sl.cfg.n * es + 255) & ~size_t(255);
     const size_t wb = vpk::workspace_layout(sl.cfg.ng, order_of(sl.cfg), sl.cfg.hist_cap, sl.cfg.n).total;
     if (save) VP_HIP(hipMemcpyAsync(scratch + off, sl.ws, wb, hipMemcpyDeviceToDevice, h->stream));
     else VP_HIP(hipMemcpyAsync(sl.ws, scratch + off, wb, hipMemcpyDeviceToDevice, h->stream));

@@ -228,11 +228,19 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
 // quadratic basis N0 = (1-s)(1-2s), N1 = 4s(1-s), N2 = s(2s-1) of the element's left vertex,
 // midpoint and right vertex): node k gets psi* N_k(s) - p* N_k'(s) / h.  Midpoint j is LDS
 // entry ng + j.  With DIP false p* is zero and its terms are left out.
-template <int MODE, bool DIP>
+// K3: the particle also carries second moments, and Mqq adds (1/2) Mqq phi_k''(Q): the
+// basis' second derivatives on the element are 4, -8, 4 (left vertex, midpoint, right vertex)
+// over h^2.
+template <int MODE, bool DIP, bool K3 = false>
 __device__ __forceinline__ void deposit_p2(double* sacc, int ng, int j, double s, double psi,
-                                           double ps, double inv_h) {
+                                           double ps, double inv_h, double mqq = 0.0) {
   const double n0 = (1.0 - s) * (1.0 - 2.0 * s), n1 = 4.0 * s * (1.0 - s), n2 = s * (2.0 * s - 1.0);
-  if constexpr (DIP) {
+  if constexpr (K3) {
+    const double c = 0.5 * mqq * (inv_h * inv_h);
+    lds_add<MODE>(sacc, j, psi * n0 - ps * ((4.0 * s - 3.0) * inv_h) + 4.0 * c);
+    lds_add<MODE>(sacc, ng + j, psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h) - 8.0 * c);
+    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2 - ps * ((4.0 * s - 1.0) * inv_h) + 4.0 * c);
+  } else if constexpr (DIP) {
     lds_add<MODE>(sacc, j, psi * n0 - ps * ((4.0 * s - 3.0) * inv_h));
     lds_add<MODE>(sacc, ng + j, psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h));
     lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2 - ps * ((4.0 * s - 1.0) * inv_h));
@@ -241,6 +249,34 @@ __device__ __forceinline__ void deposit_p2(double* sacc, int ng, int j, double s
     lds_add<MODE>(sacc, ng + j, psi * n1);
     lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2);
   }
+}
+
+// Second moments M = (Mqq, Mqp, Mpp) of a k = 3 particle under the two sub-flows of the
+// splitting (the Lie-Poisson bracket of the quadratic phase-space polynomials gives the
+// covariance equations of the linearised flow, M -> A M A^T): the kick by tau with curvature
+// g (Q and Mqq frozen), A = [[1, 0], [-tau g, 1]]; the drift by tau (Mpp frozen),
+// A = [[1, tau], [0, 1]].  The plain definition's operation order.
+__device__ __forceinline__ void moments_kick(double tau, double g, double Mqq, double& Mqp,
+                                             double& Mpp) {
+  Mpp = Mpp - 2.0 * tau * g * Mqp + (tau * g) * (tau * g) * Mqq;
+  Mqp = Mqp - tau * g * Mqq;
+}
+__device__ __forceinline__ void moments_drift(double tau, double& Mqq, double& Mqp, double Mpp) {
+  Mqq = Mqq + 2.0 * tau * Mqp + tau * tau * Mpp;
+  Mqp = Mqp + tau * Mpp;
+}
+
+// The prescribed potential's part of a k = 3 particle: its third derivative at Q, which adds
+// -(1/2) Mqq V'''(Q) to dq*/dt (the mean force over the particle's spread), and
+// (1/2) Mqq V''(Q) added to U.
+__device__ __forceinline__ void k3_external(const InstDev& d, double Q, double Mqq, double& g3,
+                                            double& U) {
+  g3 = 0.0;
+  if (!d.ext_on) return;
+  const double ph = d.ext_k * Q;
+  const double sn = sin(ph), cs = cos(ph);
+  g3 = -(d.ext_akk * d.ext_k) * sn;
+  U += 0.5 * Mqq * (d.ext_akk * cs);
 }
 
 // Add the LDS grid into accumulator copy `copy` of ring entry r of the instance (device-scope
@@ -779,11 +815,16 @@ static __device__ void write_record(const InstDev& d, long long step, double K, 
 // float64 modes compute in float64 from the stored values in the oracle's operation order.
 // DIP = false: a monopole-only particle (p* = q* = 0, plain P1 particle-in-cell): the dipole
 // terms are left out, which gives the same values as carrying zeros through them.
+// k3 (an instance with second moments; GEN and P2 launches only): Mr holds the particle's
+// (Mqq, Mqp, Mpp) in storage precision, updated in place.  Mr is only read when k3 holds, so
+// a caller passes its local array unconditionally (a pointer chosen at run time between a
+// local array and nullptr would keep the array out of registers).
 template <int MODE, typename T, bool DIP = true, bool GEN = true, bool P2 = GEN>
 __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
                                               double* sacc, int pend, T& Qr, T& Pr, T& qsr,
                                               T& psr, const T psir, double& Ks, double& Ms,
-                                              double& Cs, double& Us) {
+                                              double& Cs, double& Us, bool k3in = false,
+                                              T* Mr = nullptr) {
   const int ng = d.ng;
   if constexpr (MODE == kFP32) {
     float* fa = reinterpret_cast<float*>(sacc);
@@ -854,13 +895,34 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
       general_field(d, fE, fG, i, xq, Q, psi, ps, Ei, gi, u);
       Us += u;
     }
+    // k = 3: the second moments move with the kicks and the drift (uniform per workgroup)
+    const bool k3 = GEN && P2 && DIP && k3in;
+    double Mqq = 0.0, Mqp = 0.0, Mpp = 0.0, g3 = 0.0;
+    if (k3) {
+      Mqq = Mr[0];
+      Mqp = Mr[1];
+      Mpp = Mr[2];
+      k3_external(d, Q, Mqq, g3, Us);
+    }
     if constexpr (DIP) {
-      if (pend) { P = P + half * Ei; qs = qs + half * ps * gi; }
+      if (pend) {
+        P = P + half * Ei;
+        qs = qs + half * ps * gi;
+        if (k3) {
+          qs = qs - (0.5 * half) * Mqq * g3;
+          moments_kick(half, gi, Mqq, Mqp, Mpp);
+        }
+      }
       Ks += 0.5 * psi * P * P + qs * P;
+      if (k3) Ks += 0.5 * Mpp;
       Ms += psi * P + qs;
       Cs += psi;
       P = P + half * Ei;
       qs = qs + half * ps * gi;
+      if (k3) {
+        qs = qs - (0.5 * half) * Mqq * g3;
+        moments_kick(half, gi, Mqq, Mqp, Mpp);
+      }
     } else {
       if (pend) P = P + half * Ei;
       Ks += 0.5 * psi * P * P;
@@ -881,7 +943,15 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
       const double psn = ps - dt * qs;
       const T pss = (T)psn;
       const double psd = pss;
-      if (p2) {
+      if (k3) {
+        // the drift moves the moments; the load takes the stored (rounded) Mqq
+        moments_drift(dt, Mqq, Mqp, Mpp);
+        const T m0 = (T)Mqq;
+        Mr[0] = m0;
+        Mr[1] = (T)Mqp;
+        Mr[2] = (T)Mpp;
+        deposit_p2<MODE, true, true>(sacc, ng, j, s, psi, psd, inv_h, (double)m0);
+      } else if (p2) {
         deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h);
       } else {
         lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);

@@ -14,7 +14,7 @@ namespace vpk {
 // GEN = false: no instance of the launch has general options (d.general), so the field on a
 // particle is read straight from the mesh arrays.  P2 = true: the launch's instances have P2
 // elements (separate instances keep the others' registers as they were).
-template <int MODE, int TPB, bool DIP, bool GEN, bool P2>
+template <int MODE, int TPB, bool DIP, bool GEN, bool P2, bool KM = false>
 __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts,
                                                const Tile* __restrict__ tiles, int tile0,
                                                int ppt, int phase) {
@@ -46,11 +46,21 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
   const bool first = tl.local == 0;  // the instance's bookkeeping tile (uniform per workgroup)
 
   // one group of particles per thread: thread t takes tile.begin + k * TPB + t, k0 <= k < k0 + kGroup
+  // KM: a launch of k = 3 instances (particles with second moments; P2, general options,
+  // never kFP32), whose moments travel with the group
+  static_assert(!KM || (GEN && P2 && DIP && MODE != kFP32), "second moments need P2 and GEN");
+  constexpr bool kM = KM;
+  constexpr int kMG = kM ? kGroup : 1;
   struct Group {
     T q[kGroup], p[kGroup], a[kGroup], b[kGroup], w[kGroup];
+    T m[3][kMG];
     long long idx[kGroup];
     bool v[kGroup];
   };
+  constexpr bool k3 = kM;
+  VPG T* __restrict__ Mqp_ = gp<T>(d.Mqq);
+  VPG T* __restrict__ Mqpp = gp<T>(d.Mqp);
+  VPG T* __restrict__ Mppp = gp<T>(d.Mpp);
   auto load_group = [&](int k0, Group& g) {
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
@@ -63,6 +73,13 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
         g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
         if constexpr (DIP) {
           g.a[u] = ntld(qsp + g.idx[u]); g.b[u] = ntld(psp + g.idx[u]);
+        }
+      }
+      if constexpr (kM) {
+        g.m[0][u] = g.m[1][u] = g.m[2][u] = T(0);
+        if (k3 && g.v[u]) {
+          g.m[0][u] = ntld(Mqp_ + g.idx[u]); g.m[1][u] = ntld(Mqpp + g.idx[u]);
+          g.m[2][u] = ntld(Mppp + g.idx[u]);
         }
       }
     }
@@ -121,8 +138,15 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       T Q = g.q[u], P = g.p[u], qs = g.a[u], ps = g.b[u];
-      push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks, Ms,
-                                           Cs, Us);
+      if constexpr (kM) {
+        T Mv[3] = {g.m[0][u], g.m[1][u], g.m[2][u]};
+        push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks,
+                                             Ms, Cs, Us, k3, Mv);
+        g.m[0][u] = Mv[0]; g.m[1][u] = Mv[1]; g.m[2][u] = Mv[2];
+      } else {
+        push_particle<MODE, T, DIP, GEN, P2>(d, fE, fG, sacc, pend, Q, P, qs, ps, g.w[u], Ks,
+                                             Ms, Cs, Us);
+      }
       g.q[u] = Q; g.p[u] = P; g.a[u] = qs; g.b[u] = ps;
     }
 #pragma unroll
@@ -130,6 +154,11 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       if (!g.v[u]) continue;
       ntst(Qp + g.idx[u], g.q[u]); ntst(Pp + g.idx[u], g.p[u]);
       if constexpr (DIP) { ntst(qsp + g.idx[u], g.a[u]); ntst(psp + g.idx[u], g.b[u]); }
+      if constexpr (kM)
+        if (k3) {
+          ntst(Mqp_ + g.idx[u], g.m[0][u]); ntst(Mqpp + g.idx[u], g.m[1][u]);
+          ntst(Mppp + g.idx[u], g.m[2][u]);
+        }
     }
   };
 
@@ -175,14 +204,22 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
 template <int MODE>
 hipError_t launch_fused_mode(int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        bool general, bool p2, hipStream_t s) {
+                        bool general, bool p2, bool moments, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (moments && (MODE == kFP32 || !dipoles || !general || !p2)) return hipErrorInvalidValue;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
 #define VP_FUSED_K(M, TB, D, G, P)                                                           \
   hipLaunchKernelGGL((k_fused<M, TB, D, G, P>), dim3(ntiles), dim3(TB), lds, s, d_inst,      \
                      d_tiles, tile0, ppt, phase)
 #define VP_FUSED(M, TB)                                                                      \
   do {                                                                                       \
+    if constexpr (M != kFP32) {                                                              \
+      if (moments) {                                                                         \
+        hipLaunchKernelGGL((k_fused<M, TB, true, true, true, true>), dim3(ntiles), dim3(TB),   \
+                           lds, s, d_inst, d_tiles, tile0, ppt, phase);                      \
+        break;                                                                               \
+      }                                                                                      \
+    }                                                                                        \
     if (dipoles) {                                                                           \
       if (p2) {                                                                              \
         if (general) VP_FUSED_K(M, TB, true, true, true);                                    \
@@ -218,6 +255,6 @@ template hipError_t launch_fused_mode<VP_FUSED_MODE>(int tpb, const InstDev* d_i
                                                      const Tile* d_tiles, int tile0, int ntiles,
                                                      int ppt, int max_ng, bool lds_fft, int phase,
                                                      bool dipoles, bool general, bool p2,
-                                                     hipStream_t s);
+                                                     bool moments, hipStream_t s);
 
 }  // namespace vpk

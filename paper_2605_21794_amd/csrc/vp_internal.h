@@ -80,6 +80,11 @@ struct InstDev {
   int self_on;      // the particles feel their own field
   int ext_on;       // a prescribed potential acts
   double ext_a, ext_k, ext_ak, ext_akk;  // A, kappa = 2 pi m / L, A kappa, A kappa^2
+  void* Mqq;        // second moments of k = 3 particles (nullptr otherwise)
+  void* Mqp;
+  void* Mpp;
+  int k3;           // the particles carry second moments (P2, general options)
+  int pad_;
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.
@@ -105,15 +110,16 @@ size_t particle_lds_bytes(int mode, int max_ng);
 // `lds_fft` is true when some instance of the launch uses the FFT solver (more LDS);
 // `dipoles` false when every tile of the launch is of a monopole-only instance; `general`
 // true when some instance of the launch has general options (InstDev::general); `p2` true
-// when its instances have P2 elements.
+// when its instances have P2 elements; `moments` true when its instances carry second
+// moments (InstDev::k3; then dipoles, general and p2 hold too).
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        bool general, bool p2, hipStream_t s);
+                        bool general, bool p2, bool moments, hipStream_t s);
 // The same for one precision mode (vpk::Mode), defined in the unit compiled for that mode.
 template <int MODE>
 hipError_t launch_fused_mode(int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                              int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                             bool general, bool p2, hipStream_t s);
+                             bool general, bool p2, bool moments, hipStream_t s);
 hipError_t launch_deposit(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                           int ntiles, int ppt, int max_ng, int phase, hipStream_t s);
 hipError_t launch_gather_push(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles,
@@ -154,15 +160,15 @@ struct ClusterWs {
       total;
 };
 ClusterWs cluster_layout(long long m, int k, int batch = 0);
+// The library's own workspace of vp_cluster_markers_static on the current device (a file-scope
+// device array of VP_CLUSTER_STATIC_BYTES, its address looked up once per device).
+hipError_t cluster_static_workspace(void** ptr_out);
 // *host_bad = how many of the n device indices idx lie outside [0, m) (synchronises).
 hipError_t cluster_count_bad(const int* idx, long long n, long long m, void* ws,
                              const ClusterWs& w, int* host_bad, hipStream_t s);
 // Velocity range of the markers (synchronises the stream).
 hipError_t cluster_p_range(const double* p, long long m, void* ws, const ClusterWs& w,
                            double* host_minmax, hipStream_t s);
-// The library's own workspace of vp_cluster_markers_static on the current device (a file-scope
-// device array of VP_CLUSTER_STATIC_BYTES, its address looked up once per device).
-hipError_t cluster_static_workspace(void** ptr_out);
 // nbatch mini-batch updates (batches of `batch` marker indices, batch_idx[t * batch ..]),
 // then Lloyd iterations, final assignment, moments and compaction; *host_n = decorated
 // particles written; absorbed_out (k doubles, or NULL) = the weight each centre absorbed in

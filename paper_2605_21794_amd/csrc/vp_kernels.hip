@@ -59,6 +59,7 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
   } else {
     const double inv_h = d.inv_h;
     const bool p2 = d.order == 2;
+    const VPG T* __restrict__ Mqqp = gp<T>(d.Mqq);  // k = 3 only
     VP_TILE_LOOP_BEGIN
     T q[4], b[4], w[4];
 #pragma unroll
@@ -71,7 +72,9 @@ __global__ __launch_bounds__(TPB) void k_deposit(const InstDev* __restrict__ ins
       const double x = (double)q[u] * inv_h;
       const int j = cell_of(x, ng);
       const double s = frac01(x, j);
-      if (p2) {
+      if (p2 && d.k3) {
+        deposit_p2<MODE, true, true>(sacc, ng, j, s, psi, psd, inv_h, (double)Mqqp[idx[u]]);
+      } else if (p2) {
         deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h);
       } else {
         lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
@@ -146,6 +149,10 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
     VP_TILE_LOOP_END
   } else {
     const double L = d.L, inv_h = d.inv_h;
+    const bool k3 = d.k3;  // second moments (uniform per workgroup)
+    VPG T* __restrict__ M0p = gp<T>(d.Mqq);
+    VPG T* __restrict__ M1p = gp<T>(d.Mqp);
+    VPG T* __restrict__ M2p = gp<T>(d.Mpp);
     VP_TILE_LOOP_BEGIN
     T q[4], p[4], a[4], b[4];
 #pragma unroll
@@ -167,14 +174,27 @@ __global__ __launch_bounds__(TPB) void k_gather_push(const InstDev* __restrict__
         double uu;
         general_field(d, smem, smem + ng, i, xq, (double)Q, 0.0, 0.0, Ei, gi, uu);
       }
+      double Mqq = 0.0, Mqp = 0.0, Mpp = 0.0, g3 = 0.0, uk = 0.0;
+      if (k3) {
+        Mqq = M0p[idx[u]];
+        Mqp = M1p[idx[u]];
+        Mpp = M2p[idx[u]];
+        k3_external(d, Q, Mqq, g3, uk);
+      }
       P = P + kick * Ei;
       qs = qs + kick * ps * gi;
+      if (k3) {
+        qs = qs - (0.5 * kick) * Mqq * g3;
+        moments_kick(kick, gi, Mqq, Mqp, Mpp);
+      }
       double Qn = Q + drift * P;
       if (Qn < 0.0) Qn += L;
       if (Qn >= L) Qn -= L;
       ps = ps - drift * qs;
+      if (k3) moments_drift(drift, Mqq, Mqp, Mpp);
       if (do_kick) { Pp[idx[u]] = (T)P; qsp[idx[u]] = (T)qs; }
       if (do_drift) { Qp[idx[u]] = (T)Qn; psp[idx[u]] = (T)ps; }
+      if (k3) { M0p[idx[u]] = (T)Mqq; M1p[idx[u]] = (T)Mqp; M2p[idx[u]] = (T)Mpp; }
     }
     VP_TILE_LOOP_END
   }
@@ -236,6 +256,7 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
     VP_TILE_LOOP_END
   } else {
     const double inv_h = d.inv_h, half = 0.5 * d.dt;
+    const bool k3 = d.k3;  // second moments (uniform per workgroup)
     VP_TILE_LOOP_BEGIN
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -254,11 +275,23 @@ __global__ __launch_bounds__(TPB) void k_diag(const InstDev* __restrict__ insts,
         general_field(d, smem, smem + ng, i, xq, Q, psi, ps, Ei, gi, uu);
         Us += uu;
       }
+      double Mqq = 0.0, Mqp = 0.0, Mpp = 0.0, g3 = 0.0;
+      if (k3) {
+        Mqq = gp<T>(d.Mqq)[idx[u]];
+        Mqp = gp<T>(d.Mqp)[idx[u]];
+        Mpp = gp<T>(d.Mpp)[idx[u]];
+        k3_external(d, Q, Mqq, g3, Us);
+      }
       if (pend) {
         P = P + half * Ei;
         qs = qs + half * ps * gi;
+        if (k3) {
+          qs = qs - (0.5 * half) * Mqq * g3;
+          moments_kick(half, gi, Mqq, Mqp, Mpp);
+        }
       }
       Ks += 0.5 * psi * P * P + qs * P;
+      if (k3) Ks += 0.5 * Mpp;
       Ms += psi * P + qs;
       Cs += psi;
     }
@@ -589,20 +622,20 @@ size_t particle_lds_bytes(int /*mode*/, int max_ng) {
 
 hipError_t launch_fused(int mode, int tpb, const InstDev* d_inst, const Tile* d_tiles, int tile0,
                         int ntiles, int ppt, int max_ng, bool lds_fft, int phase, bool dipoles,
-                        bool general, bool p2, hipStream_t s) {
+                        bool general, bool p2, bool moments, hipStream_t s) {
   switch (mode) {
     case kFP64:
       return launch_fused_mode<kFP64>(tpb, d_inst, d_tiles, tile0, ntiles, ppt, max_ng, lds_fft,
-                                      phase, dipoles, general, p2, s);
+                                      phase, dipoles, general, p2, moments, s);
     case kFP32Comp:
       return launch_fused_mode<kFP32Comp>(tpb, d_inst, d_tiles, tile0, ntiles, ppt, max_ng,
-                                          lds_fft, phase, dipoles, general, p2, s);
+                                          lds_fft, phase, dipoles, general, p2, moments, s);
     case kFP32:
       return launch_fused_mode<kFP32>(tpb, d_inst, d_tiles, tile0, ntiles, ppt, max_ng, lds_fft,
-                                      phase, dipoles, general, p2, s);
+                                      phase, dipoles, general, p2, moments, s);
     default:
       return launch_fused_mode<kFP32TwoSum>(tpb, d_inst, d_tiles, tile0, ntiles, ppt, max_ng,
-                                            lds_fft, phase, dipoles, general, p2, s);
+                                            lds_fft, phase, dipoles, general, p2, moments, s);
   }
 }
 

@@ -72,3 +72,25 @@ def fp32_fused_reference(s64, w, nsteps, order: int = 1):
         fld = _solve(Q, ps, psi, w, order)
     P, qs = _r32(P), _r32(qs)
     return np.array(Ws), np.array(Hs), (Q, P, qs, ps)
+
+
+def fp32_fused_reference_k3(s64, w, nsteps):
+    """The fused step's storage points for particles with second moments (k = 3, P2
+    elements): as fp32_fused_reference, with the moments rounded to float32 where the
+    state is stored.  Returns (W history, H history, final state tuple of eight arrays)."""
+    st = tuple(np.asarray(s64[k], dtype=np.float64).copy() for k in O.K3_FIELDS)
+    fld = O.solve_field_p2_k3(st[0], st[3], st[4], st[5], w.L, w.ng)
+    Ws, Hs = [], []
+    for n in range(nsteps + 1):
+        if n > 0:
+            st = O.kick_k3(st, fld, w.L, 0.5 * w.dt)
+        Ws.append(fld["W"])
+        Hs.append(O.diagnostics_k3(st, fld, w.L)["H"])
+        if n == nsteps:
+            break
+        st = O.kick_k3(st, fld, w.L, 0.5 * w.dt)
+        st = O.drift_k3(st, w.L, w.dt)
+        st = tuple(_r32(a) if k != 4 else a for k, a in enumerate(st))
+        fld = O.solve_field_p2_k3(st[0], st[3], st[4], st[5], w.L, w.ng)
+    st = tuple(_r32(a) if k in (1, 2, 6, 7) else a for k, a in enumerate(st))
+    return np.array(Ws), np.array(Hs), st

@@ -32,7 +32,7 @@ int main(void) {
   vp_config bad[8];
   for (int i = 0; i < 8; ++i) bad[i] = good();
   bad[0].ng = 100; bad[1].n = 0; bad[2].L = -1.0; bad[3].dt = 0.0; bad[4].element_order = 3;
-  bad[5].reserved_ = 1; bad[6].ng = 4096; bad[7].hist_cap = 0;
+  bad[5].moment_order = 4; bad[6].ng = 4096; bad[7].hist_cap = 0;
   for (int i = 0; i < 8; ++i) {
     CHECK(vp_workspace_bytes(&bad[i], &b) != VP_OK);
     const char* m = vp_last_error();

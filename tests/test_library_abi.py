@@ -52,7 +52,11 @@ def test_workspace_sizing_and_validation(lib):
            dict(ext_mode=1, ext_amplitude=float("inf")), dict(element_order=3),
            dict(element_order=-1), dict(element_order=2, precision=L.VP_FP32),
            dict(element_order=2, projection=L.VP_PROJ_NODAL),
-           dict(element_order=2, projection=L.VP_PROJ_CONSISTENT), dict(reserved_=1)]
+           dict(element_order=2, projection=L.VP_PROJ_CONSISTENT), dict(moment_order=1),
+           dict(moment_order=4), dict(moment_order=3), dict(moment_order=3, element_order=1),
+           dict(moment_order=3, element_order=2, precision=L.VP_FP32),
+           dict(moment_order=3, element_order=2, monopole_only=1),
+           dict(moment_order=3, element_order=2, sort_every=8)]
     for kw in bad:
         args = dict(n=1000, ng=64, precision=L.VP_FP32_COMP, L=10.0, dt=0.05, hist_cap=100)
         args.update(kw)
@@ -77,6 +81,12 @@ def test_workspace_sizing_and_validation(lib):
     for prec in (L.VP_FP64, L.VP_FP32_COMP, L.VP_FP32_TWOSUM):
         c = L.vp_config(n=1000, ng=64, precision=prec, L=1.0, dt=0.1, hist_cap=1, element_order=2)
         assert lib.vp_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == L.VP_OK
+        for mo in (0, 2, 3):   # second moments live in the particle arrays, not the workspace
+            c2 = L.vp_config(n=1000, ng=64, precision=prec, L=1.0, dt=0.1, hist_cap=1,
+                             element_order=2, moment_order=mo)
+            b2 = ctypes.c_size_t()
+            assert lib.vp_workspace_bytes(ctypes.byref(c2), ctypes.byref(b2)) == L.VP_OK
+            assert b2.value == b.value
 
 
 def test_null_handles_rejected(lib):
@@ -85,7 +95,8 @@ def test_null_handles_rejected(lib):
     assert lib.vp_deposit(None) == L.VP_ERR_ARG
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
-    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 8
+    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 9
+    assert ctypes.sizeof(L.vp_particles) == 8 * 8  # eight array pointers, the moments last
     assert ctypes.sizeof(L.vp_diag) == 8 * 12  # twelve 8-byte fields, stamp last
     assert lib.vp_prepare_step(None, 1) == L.VP_ERR_ARG
     assert lib.vp_wall_clock_hz(None) == L.VP_ERR_ARG
