@@ -1025,3 +1025,7 @@ def main():
 
 if __name__ == "__main__":
     main()
+    # explicit teardown while the HIP runtime and any attached profiler are alive: every
+    # engine closed, the device idle (nothing of the library is left for interpreter shutdown)
+    import paper_2605_21794_amd as _vp
+    _vp.close_all()

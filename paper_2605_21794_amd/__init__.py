@@ -14,7 +14,9 @@ GPU raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from ctypes import byref, c_double, c_int32, c_int64, c_size_t, c_void_p
 
 import numpy as np
@@ -25,11 +27,35 @@ from ._lib import VPError  # noqa: F401
 PRECISIONS = {"fp64": L.VP_FP64, "fp32c": L.VP_FP32_COMP, "fp32": L.VP_FP32,
               "fp32ts": L.VP_FP32_TWOSUM}
 FIELDS = ("Q", "P", "qs", "ps", "psi")
-
-
 MOMENTS = ("Mqq", "Mqp", "Mpp")        # second moments of k = 3 particles
+
+
 def load_library():
     return L.load()
+
+
+# Engines still open when the interpreter starts to exit are closed by close_all(), which
+# atexit runs before the interpreter tears its objects down: every handle, graph and device
+# table of the library is released while the HIP runtime (and any tool attached to it, such
+# as a profiler) is fully alive, never from a destructor during shutdown.
+_open_engines = weakref.WeakSet()
+
+
+def close_all():
+    """Close every open Engine (and Simulation), after the device has finished its work."""
+    engines = list(_open_engines)
+    if not engines:
+        return
+    try:
+        import torch
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for e in engines:
+        e.close()
+
+
+atexit.register(close_all)
 
 
 def _prec(p) -> int:
@@ -169,6 +195,7 @@ class Engine:
                 "vp_engine_create")
         self.h = h
         self.slots = {}
+        _open_engines.add(self)
 
     # ---------------------------------------------------------------- slots
     def _tensor(self, a):
@@ -345,6 +372,7 @@ class Engine:
         if getattr(self, "h", None):
             self.lib.vp_destroy(self.h)
             self.h = None
+        _open_engines.discard(self)
 
     def __del__(self):
         try:
