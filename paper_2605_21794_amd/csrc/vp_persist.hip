@@ -20,28 +20,35 @@ namespace vpk {
 // What no other tile needs is kept off the path between the barriers: every tile clears its
 // own slice of the ring entry the next step deposits into, and the instance's first tile
 // writes the record of step n-1 and the field summary of step n after it has counted its
-// arrival for step n, while the others are still on their way.
+// arrival for step n, while the others are still on their way.  That bookkeeping reads LDS
+// only: the first tile copies the Fourier weights of E1 to LDS once per launch, and issues
+// the loads of the previous pass's per-tile kinetic sums together with the solve's loads,
+// parking the per-thread partials in LDS after the solve (device-scope loads after the
+// arrival would hold it past the others' release).
 // GEN = false: no instance of the launch has general options (fewer registers).
 constexpr unsigned kSpinLimit = 1u << 22;
 
 // The first tile's bookkeeping after step n (every thread of the workgroup calls it): the
 // field summary of the field in LDS (W, E1; the same per-thread partials, wave trees and
 // wave order as the solve's), into rec_next and the instance's field-summary ring entry r0;
-// and, when write_rec, the record of integer step rec_step with the kinetic sums of ring
-// entry kin_r (every tile's slot is complete: they were stored before the barrier this
-// workgroup passed at the start of step n) and the field summary rec of that step.
+// and, when write_rec, the record of integer step rec_step with the kinetic sums of the
+// previous pass (skin: each solving thread's partial sums, field f of thread t at
+// f * kSolveThreads + t, as load_kin forms them from the per-tile slots) and the field
+// summary rec of that step.  tw: the Fourier weights (d.tw) in LDS.
 template <int TPB, bool GEN>
-__device__ void persist_bookkeeping(const InstDev& d, const double* fE, double* sred, int r0,
-                                    int kin_r, bool write_rec, long long rec_step,
-                                    const double (&rec)[3], double (&rec_next)[3]) {
+__device__ void persist_bookkeeping(const InstDev& d, const double* fE, const double* tw,
+                                    const double* skin, double* sred, int r0, bool write_rec,
+                                    long long rec_step, const double (&rec)[3],
+                                    double (&rec_next)[3]) {
   const int ng = d.ng, tid = threadIdx.x;
   const int per = solve_per(ng), j0 = tid * per;
   const bool solver_thread = tid < kSolveThreads;
   double kin[kKinFields] = {0.0, 0.0, 0.0, 0.0};
-  if (write_rec && solver_thread) load_kin<true, GEN ? kKinFields : 3>(d, kin_r, kin);
+  if (write_rec && solver_thread)
+#pragma unroll
+    for (int f = 0; f < kKinFields; ++f) kin[f] = skin[f * kSolveThreads + tid];
   double wp = 0.0, er = 0.0, ei = 0.0;
   if (solver_thread && j0 < ng) {
-    const VPG double* tw = gp(d.tw);
     const int halfn = ng >> 1;
     for (int k = 0; k < per; ++k) {
       const int e = j0 + k, t = e & (halfn - 1);
@@ -87,6 +94,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   extern __shared__ double smem[];
   __shared__ double red[4 * (TPB / 64)];
   __shared__ double sred[kSolveRed];
+  __shared__ double stw[VP_MAX_NG];                     // first tile: Fourier weights of E1
+  __shared__ double skin[kKinFields * kSolveThreads];  // first tile: previous pass's partials
   using T = typename StateType<MODE>::T;
   const Tile tl = tiles[blockIdx.x];
   const InstDev& d = insts[tl.inst];
@@ -122,6 +131,10 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   }
   const int pend0 = sc->pend[phase0];
   int pend = pend0;
+  if (first) {  // visible at the first step's solve barriers
+    const VPG double* twg = gp(d.tw);
+    for (int j = threadIdx.x; j < ng; j += TPB) stw[j] = twg[j];
+  }
   long long step0 = 0;
   double rec[3] = {0.0, 0.0, 0.0};  // field summary of the previous integer step (first tile)
   if (first) {
@@ -165,12 +178,21 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
     SolveIn sin_;
     solve_load<MODE, true, GEN, false>(d, r0, false, sin_);
+    // the first tile's record of step st - 1 sums ring entry r2, which every tile finished
+    // before the barrier just passed: its loads go out with the solve's
+    const bool write_rec = st > 0 || (pend0 && step0 >= 1);
+    double kinv[kKinFields] = {0.0, 0.0, 0.0, 0.0};
+    if (first && write_rec && threadIdx.x < kSolveThreads)
+      load_kin<true, GEN ? kKinFields : 3>(d, r2, kinv);
     for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
     double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
     {
       double sum[7];
       solve_compute<TPB, GEN, false>(d, sin_, false, bt, fE, fG, sred, fft, nullptr, sum);
     }
+    if (first && threadIdx.x < kSolveThreads)  // read after the arrival's barrier
+#pragma unroll
+      for (int f = 0; f < kKinFields; ++f) skin[f * kSolveThreads + threadIdx.x] = kinv[f];
     // ring entry r2 was read at the previous step by every tile (they have all passed the
     // barrier since) and is deposited into at the next one (after the next barrier)
     for (int f = cl0 + (int)threadIdx.x; f < cl1; f += TPB) {
@@ -222,8 +244,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
     if (first) {  // record of step st - 1, field summary of step st
       double rec_next[3];
-      persist_bookkeeping<TPB, GEN>(d, fE, sred, r0, r2, st > 0 || (pend0 && step0 >= 1),
-                                    step0 + st - 1, rec, rec_next);
+      persist_bookkeeping<TPB, GEN>(d, fE, stw, skin, sred, r0, write_rec, step0 + st - 1, rec,
+                                    rec_next);
       rec[0] = rec_next[0];
       rec[1] = rec_next[1];
       rec[2] = rec_next[2];
