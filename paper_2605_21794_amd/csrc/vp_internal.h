@@ -28,8 +28,9 @@ constexpr int kConsTapsMax = 65;
 constexpr int cons_taps(int ng) { return ng <= 64 ? ng : kConsTapsMax; }
 constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
 
-constexpr int kArriveGroups = 8;   // arrival counters per instance (one per XCD)
-constexpr int kArriveStride = 32;  // unsigned words between counters (128 bytes)
+constexpr int kArriveGroups = 16;  // arrival counters per instance
+constexpr int kReleaseFlags = 8;   // copies of an instance's release flag
+constexpr int kArriveStride = 32;  // unsigned words between counters and flags (128 bytes)
 
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
@@ -40,11 +41,16 @@ struct InstScal {
   int nonfinite;                            // set when a diagnostic came out NaN or Inf
   int frozen;                               // nonfinite as of the start of a persistent launch
   int timeout;                              // a persistent launch's wait gave up (error)
-  // Workgroup arrivals in a persistent launch: tile t of the instance counts on group
-  // t mod kArriveGroups, each group's counter on a 128-byte line of its own.  Workgroups are
-  // handed to the 8 XCDs in turn, so a group collects the arrivals of one XCD, and a waiting
-  // workgroup reads the 8 counters at once instead of contending on one.
+  // The barrier between the steps of a persistent launch, a two-level tree: tile t of the
+  // instance counts its arrival on group counter t mod G (G = min(kArriveGroups, tiles));
+  // the tile that completes a group counts on `top`, and the tile that completes `top`
+  // writes the step's number into every release flag.  A waiting tile polls flag
+  // t mod kReleaseFlags with one lane.  Each counter and flag has a 128-byte line of its own,
+  // so the polls of the waiting tiles are spread over kReleaseFlags lines and leave the
+  // counters to the arrivals.
   alignas(128) unsigned arrive[kArriveGroups * kArriveStride];
+  alignas(128) unsigned top[kArriveStride];
+  alignas(128) unsigned release[kReleaseFlags * kArriveStride];
 };
 
 // Device descriptor of one instance (one slot of an engine).

@@ -458,6 +458,8 @@ __global__ void k_slot_scalars(const InstDev* __restrict__ insts, const int* __r
   } else if (op == kScalPersistStart) {
     sc->frozen = sc->nonfinite;
     for (int gr = 0; gr < kArriveGroups; ++gr) sc->arrive[gr * kArriveStride] = 0u;
+    sc->top[0] = 0u;
+    for (int f = 0; f < kReleaseFlags; ++f) sc->release[f * kArriveStride] = 0u;
   }
 }
 

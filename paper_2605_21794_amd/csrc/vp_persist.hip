@@ -8,10 +8,10 @@ namespace vpk {
 // nsteps fused steps in one cooperative launch (every workgroup resident at once).  The
 // particles of each tile stay in registers from the first step to the last.  Between steps
 // every workgroup of an instance waits until all of the instance's tiles have flushed the
-// previous step: each tile counts its arrival on one of kArriveGroups counters (tile index
-// mod kArriveGroups, which collects one XCD's tiles) and one lane per counter polls all of
-// them at once, with a bounded spin (after kSpinLimit polls the instance is flagged and the
-// wait ends, so every wave finishes).  Data other workgroups of the launch wrote (the load
+// previous step, through the two-level arrival tree of InstScal: group counters, a top
+// counter, and release flags written by the tile that completes the top counter; one lane
+// of each waiting tile polls one flag, with a bounded spin (after kSpinLimit polls the
+// instance is flagged and the wait ends, so every wave finishes).  Data other workgroups of the launch wrote (the load
 // vector, the per-tile kinetic sums, the cleared ring entry) is read and written at device
 // scope.  The ring protocol, the records and the arithmetic are those of k_fused, so nsteps
 // persistent steps equal nsteps fused launches.  P2 instances are not taken (the host
@@ -143,14 +143,13 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     rec[1] = sc->e1r[ring_prev(phase0)];
     rec[2] = sc->e1i[ring_prev(phase0)];
   }
-  VPG unsigned* arrive = sc->arrive;
-  // The tiles of the instance that count on arrival group g (lane g of the first wave waits
-  // for them): local indices congruent to g mod kArriveGroups.
-  const int my_group = tl.local & (kArriveGroups - 1);
-  const unsigned group_tiles =
-      threadIdx.x < kArriveGroups
-          ? (unsigned)((d.ntiles - (int)threadIdx.x + kArriveGroups - 1) / kArriveGroups)
-          : 0u;
+  // this tile's arrival group (local indices congruent mod ngroups), its size, and the
+  // release flag it polls
+  const int ngroups = min(kArriveGroups, d.ntiles);
+  const int my_group = tl.local % ngroups;
+  const unsigned group_tiles = (unsigned)((d.ntiles - my_group + ngroups - 1) / ngroups);
+  VPG unsigned* const my_counter = sc->arrive + my_group * kArriveStride;
+  VPG unsigned* const my_flag = sc->release + (tl.local & (kReleaseFlags - 1)) * kArriveStride;
   // this tile's slice of a ring entry's copies, cleared for the step after next
   const int ncl = d.acc_copies * ng;
   const int cl_per = (ncl + d.ntiles - 1) / d.ntiles;
@@ -162,11 +161,10 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     __asm__ __volatile__("" ::: "memory");
     const int r1 = ring_next(r0), r2 = ring_prev(r0);
     if (st > 0) {  // wait for every tile of the instance to finish the previous step
-      if (threadIdx.x < kArriveGroups) {  // one lane per arrival group, all groups at once
-        const unsigned target = (unsigned)st * group_tiles;
-        VPG unsigned* c = arrive + threadIdx.x * kArriveStride;
+      if (threadIdx.x == 0) {
         unsigned it = 0;
-        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(my_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               (unsigned)st) {
           __builtin_amdgcn_s_sleep(1);
           if (++it > kSpinLimit) {
             __hip_atomic_store(&sc->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -238,9 +236,19 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     if (st + 1 < nsteps) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's flush, slot and clear are performed
       __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(arrive + my_group * kArriveStride, 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0) {  // count the arrival; the last of all releases step st + 1
+        const unsigned e = (unsigned)(st + 1);
+        const unsigned old = __hip_atomic_fetch_add(my_counter, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == e * group_tiles) {
+          const unsigned g = __hip_atomic_fetch_add(sc->top, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+          if (g + 1u == e * (unsigned)ngroups)
+            for (int f = 0; f < kReleaseFlags; ++f)
+              __hip_atomic_store(sc->release + f * kArriveStride, e, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
     }
     if (first) {  // record of step st - 1, field summary of step st
       double rec_next[3];
