@@ -707,7 +707,9 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
       }
     }
   }
-  __syncthreads();  // bt, E and the summary totals complete
+  // g below reads only b~, complete since the scan's barrier (the FFT path's first): this
+  // barrier is for the summary totals, the FFT's E (written by one wave) and phi
+  if (want_sum || use_fft || phi) __syncthreads();  // bt, E and the summary totals complete
   if (want_sum) {
     sum[0] = 0.5 * d.h * solve_total(red, 3);
     sum[1] = solve_total(red, 4) / (double)ng;
@@ -819,12 +821,19 @@ static __device__ void write_record(const InstDev& d, long long step, double K, 
 // (Mqq, Mqp, Mpp) in storage precision, updated in place.  Mr is only read when k3 holds, so
 // a caller passes its local array unconditionally (a pointer chosen at run time between a
 // local array and nullptr would keep the array out of registers).
-template <int MODE, typename T, bool DIP = true, bool GEN = true, bool P2 = GEN>
+// PEND: 1 or 0 when the caller knows the (uniform) pending flag at compile time, -1 to test
+// `pend`.  CELL (float64 modes, P1 without general options): *cellr holds the element of Qr
+// on entry (the element the previous push deposited at, from the same stored position) and
+// receives the element of the drifted position; the gather then skips recomputing it.
+template <int MODE, typename T, bool DIP = true, bool GEN = true, bool P2 = GEN, int PEND = -1,
+          bool CELL = false>
 __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE, const double* fG,
                                               double* sacc, int pend, T& Qr, T& Pr, T& qsr,
                                               T& psr, const T psir, double& Ks, double& Ms,
                                               double& Cs, double& Us, bool k3in = false,
-                                              T* Mr = nullptr) {
+                                              T* Mr = nullptr, int* cellr = nullptr) {
+  static_assert(!CELL || (!GEN && !P2 && MODE != kFP32), "CELL: float64 modes, P1, no general options");
+  const bool pending = PEND < 0 ? pend != 0 : PEND == 1;
   const int ng = d.ng;
   if constexpr (MODE == kFP32) {
     float* fa = reinterpret_cast<float*>(sacc);
@@ -846,7 +855,7 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
       Us += u;
     }
     if constexpr (DIP) {
-      if (pend) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
+      if (pending) { P = P + hf * Ei; qs = qs + hf * ps * gi; }
       const double Pd = P, qd = qs, wd = psi;
       Ks += 0.5 * wd * Pd * Pd + qd * Pd;
       Ms += wd * Pd + qd;
@@ -854,7 +863,7 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
       P = P + hf * Ei;
       qs = qs + hf * ps * gi;
     } else {
-      if (pend) P = P + hf * Ei;
+      if (pending) P = P + hf * Ei;
       const double Pd = P, wd = psi;
       Ks += 0.5 * wd * Pd * Pd;
       Ms += wd * Pd;
@@ -881,8 +890,8 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const double L = d.L, inv_h = d.inv_h, dt = d.dt, half = 0.5 * d.dt;
     const double Q = Qr, psi = psir;
     double P = Pr, qs = qsr, ps = psr;
-    const double xq = Q * inv_h;
-    const int i = cell_of(xq, ng);
+    const double xq = CELL ? 0.0 : Q * inv_h;
+    const int i = CELL ? *cellr : cell_of(xq, ng);
     double Ei, gi;
     if (!GEN || !d.general) {
       Ei = fE[i];
@@ -905,7 +914,7 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
       k3_external(d, Q, Mqq, g3, Us);
     }
     if constexpr (DIP) {
-      if (pend) {
+      if (pending) {
         P = P + half * Ei;
         qs = qs + half * ps * gi;
         if (k3) {
@@ -924,7 +933,7 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
         moments_kick(half, gi, Mqq, Mqp, Mpp);
       }
     } else {
-      if (pend) P = P + half * Ei;
+      if (pending) P = P + half * Ei;
       Ks += 0.5 * psi * P * P;
       Ms += psi * P;
       Cs += psi;
@@ -938,6 +947,7 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
     const double x = Qd * inv_h;
     const int j = cell_of(x, ng);
     const double s = frac01(x, j);
+    if constexpr (CELL) *cellr = j;
     const bool p2 = P2 && d.order == 2;
     if constexpr (DIP) {
       const double psn = ps - dt * qs;

@@ -129,6 +129,12 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       b[u] = ntld(psp + i); w[u] = ntld(psip + i);
     }
   }
+  // float64 modes without general options carry each particle's element from one step's
+  // deposit to the next step's gather
+  constexpr bool kCell = !GEN && MODE != kFP32;
+  int cell[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) cell[u] = kCell ? cell_of((double)q[u] * d.inv_h, ng) : 0;
   const int pend0 = sc->pend[phase0];
   int pend = pend0;
   if (first) {  // visible at the first step's solve barriers
@@ -201,8 +207,9 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
-      push_particle<MODE, T, true, GEN, false>(d, fE, fG, sacc, pend, q[u], p[u], a[u], b[u],
-                                               w[u], Ks, Ms, Cs, Us);
+      push_particle<MODE, T, true, GEN, false, -1, kCell>(d, fE, fG, sacc, pend, q[u], p[u], a[u],
+                                                          b[u], w[u], Ks, Ms, Cs, Us, false,
+                                                          nullptr, &cell[u]);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
