@@ -92,6 +92,12 @@ __device__ __forceinline__ int cell_of(double x, int ng) {
 __device__ __forceinline__ int cell_of_f(float x, int ng) {
   return (int)fminf(fmaxf(floorf(x), 0.0f), (float)(ng - 1));
 }
+// 2^-m exactly (0 <= m <= 1022): x * inv_pow2(m) equals x / 2^m bit for bit, without the
+// division's instruction sequence.
+__device__ __forceinline__ double inv_pow2(int m) {
+  return __longlong_as_double((long long)(1023 - m) << 52);
+}
+
 __device__ __forceinline__ double frac01(double x, int i) {
   double s = x - (double)i;
   s = s < 0.0 ? 0.0 : s;
@@ -598,7 +604,8 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     for (int j = tid; j < ng; j += TPB) fft[2 * ng + j] = tw_g[j];
   }
   __syncthreads();
-  const double mean = solve_total(red, 0) / (double)ng;
+  const double inv_ng = inv_pow2(d.log2ng);  // ng is a power of two
+  const double mean = solve_total(red, 0) * inv_ng;
 
   double S[kSolvePer];
   double tot = 0.0, wsum = 0.0, wmid = 0.0;
@@ -639,7 +646,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     __syncthreads();
     if (act) {
       for (int w = 0; w < wid; ++w) off += red[kSolveWaves + w];
-      const double C = -solve_total(red, 2) / (double)ng;
+      const double C = -solve_total(red, 2) * inv_ng;
 #pragma unroll
       for (int k = 0; k < kSolvePer; ++k)
         if (k < per) {
@@ -679,7 +686,6 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
       __builtin_amdgcn_wave_barrier();
       bit_reverse_wave(re, im, ng, m, lane);
       fft_wave(re, im, ng, m, tw, true, lane);
-      const double inv_ng = 1.0 / (double)ng;
       for (int j = lane; j < ng; j += 64) re[j] = re[j] * inv_ng;  // Phi
       __builtin_amdgcn_wave_barrier();
       const double inv_h = d.inv_h;
@@ -712,8 +718,8 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
   if (want_sum || use_fft || phi) __syncthreads();  // bt, E and the summary totals complete
   if (want_sum) {
     sum[0] = 0.5 * d.h * solve_total(red, 3);
-    sum[1] = solve_total(red, 4) / (double)ng;
-    sum[2] = solve_total(red, 5) / (double)ng;
+    sum[1] = solve_total(red, 4) * inv_ng;
+    sum[2] = solve_total(red, 5) * inv_ng;
     sum[3] = solve_total(red, 6);
     sum[4] = solve_total(red, 7);
     sum[5] = solve_total(red, 8);
@@ -765,7 +771,7 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
     __syncthreads();
     if (act) {
       for (int w = 0; w < wid; ++w) poff += red[kSolveWaves + w];
-      const double Pm = solve_total(red, 2) / (double)ng;
+      const double Pm = solve_total(red, 2) * inv_ng;
 #pragma unroll
       for (int k = 0; k < kSolvePer; ++k)
         if (k < per) phi[j0 + k] = -d.h * ((P[k] + poff) - Pm);

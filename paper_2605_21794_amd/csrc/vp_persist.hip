@@ -71,8 +71,8 @@ __device__ void persist_bookkeeping(const InstDev& d, const double* fE, const do
   }
   __syncthreads();
   rec_next[0] = 0.5 * d.h * solve_total(sred, 3);
-  rec_next[1] = solve_total(sred, 4) / (double)ng;
-  rec_next[2] = solve_total(sred, 5) / (double)ng;
+  rec_next[1] = solve_total(sred, 4) * inv_pow2(d.log2ng);
+  rec_next[2] = solve_total(sred, 5) * inv_pow2(d.log2ng);
   if (tid == 0) {
     if (write_rec)
       write_record(d, rec_step, solve_total(sred, 6), solve_total(sred, 7),
