@@ -78,23 +78,31 @@ def launch_key(tun: dict) -> list:
     return [int(tun["threads"]), int(tun["ppt"]), int(tun["acc_copies"])]
 
 
-def pmc_path(workload: str, launch: list) -> str:
-    """Committed counter summary of the fused kernel for one workload and launch shape."""
+def kernel_of(tun: dict) -> str:
+    """The step kernel a tuning runs: the persistent one or one fused launch per step."""
+    return "k_persist" if int(tun.get("persistent", 0)) else "k_fused"
+
+
+def pmc_path(workload: str, launch: list, kernel: str = "k_fused") -> str:
+    """Committed counter summary of a step kernel for one workload and launch shape."""
     t, p, c = launch
-    return os.path.join(ROOT, "profiles", f"pmc_k_fused_{workload}_{t}x{p}x{c}.json")
+    return os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{t}x{p}x{c}.json")
 
 
-def load_traffic(workload: str, n: int, precision: str, launch: list):
-    """HBM bytes per fused-kernel launch from the committed rocprofv3 PMC summary, or None
-    when there is none, when the kernel source changed since the counters were taken, or
-    when this run's particle count, precision or launch shape is not the one they were
-    taken at (the bytes scale with the storage type, the grid traffic with the shape)."""
-    p = pmc_path(workload, launch)
+def load_traffic(workload: str, n: int, precision: str, launch: list, kernel: str = "k_fused",
+                 steps_per_launch: int = 1):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3 PMC summary, or
+    None when there is none, when the kernel source changed since the counters were taken,
+    or when this run's particle count, precision, launch shape or steps per launch is not
+    the one they were taken at (the bytes scale with the storage type, the grid traffic
+    with the shape, and a persistent launch's with its steps)."""
+    p = pmc_path(workload, launch, kernel)
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
     if (rec.get("kernel_src_sha") != kernel_src_sha() or rec.get("n") != n
-            or rec.get("precision") != precision or rec.get("launch") != list(launch)):
+            or rec.get("precision") != precision or rec.get("launch") != list(launch)
+            or rec.get("steps_per_launch", 1) != steps_per_launch):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -150,12 +158,15 @@ def base_workload(name: str) -> str:
     return name
 
 
-def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precision, launch):
-    """Write profiles/pmc_k_fused_<workload>_<shape>.json: FETCH_SIZE + WRITE_SIZE per launch,
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precision, launch,
+                kernel="k_fused", steps_per_launch=1):
+    """Write profiles/pmc_<kernel>_<workload>_<shape>.json: FETCH_SIZE + WRITE_SIZE per launch,
     each scaled by the ratio of known bytes to what the same counter reads for a copy.
-    `precision` and `launch` (threads, ppt, copies) name the counter runs' settings."""
-    fetch_kib, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", "k_fused")
-    write_kib, nw = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", "k_fused")
+    `precision`, `launch` (threads, ppt, copies) and `steps_per_launch` (1 for k_fused; the
+    steps of the one persistent launch of the counter runs for k_persist) name the counter
+    runs' settings."""
+    fetch_kib, nf = _per_dispatch(_counter_rows(fetch_dir), "FETCH_SIZE", kernel)
+    write_kib, nw = _per_dispatch(_counter_rows(write_dir), "WRITE_SIZE", kernel)
     # the copy kernel is the largest dispatch in its run (torch launches a few small ones too)
     cf_rows = _counter_rows(cfetch_dir)
     cw_rows = _counter_rows(cwrite_dir)
@@ -166,8 +177,8 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precisio
     fetch_b = fetch_kib * 1024.0 * f_scale
     write_b = write_kib * 1024.0 * w_scale
     w, _ = make_workload(base_workload(workload))
-    rec = {"kernel": "k_fused", "workload": workload, "n": w.n,
-           "precision": precision, "launch": list(launch),
+    rec = {"kernel": kernel, "workload": workload, "n": w.n,
+           "precision": precision, "launch": list(launch), "steps_per_launch": steps_per_launch,
            "kernel_src_sha": kernel_src_sha(),
            "fetch_kib_per_dispatch": fetch_kib, "write_kib_per_dispatch": write_kib,
            "dispatches": [nf, nw],
@@ -175,8 +186,9 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precisio
            "fetch_scale": f_scale, "write_scale": w_scale,
            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
            "traffic_bytes_per_launch": fetch_b + write_b,
-           "traffic_bytes_per_particle": (fetch_b + write_b) / w.n}
-    out = pmc_path(workload, launch)
+           "traffic_bytes_per_particle": (fetch_b + write_b) / w.n,
+           "traffic_bytes_per_update": (fetch_b + write_b) / (w.n * steps_per_launch)}
+    out = pmc_path(workload, launch, kernel)
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -858,8 +870,10 @@ def main():
     if args.pmc_summary:
         if not args.launch:
             raise SystemExit("--pmc-summary needs --launch: the shape the counter runs used")
+        tun = parse_launch(args.launch)
+        kern = kernel_of(tun)
         pmc_summary(*args.pmc_summary, args.workload, args.precision or "fp32c",
-                    launch_key(parse_launch(args.launch)))
+                    launch_key(tun), kern, args.steps if kern == "k_persist" else 1)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -978,12 +992,13 @@ def main():
     bytes_per_launch = bytes_per_step * steps_per_launch
     launch_s = ev0.elapsed_time(ev1) * 1e-3 / launches
     achieved = bytes_per_launch / launch_s / 1e9
-    # counters were taken on the one-launch-per-step kernel; the persistent kernel is a
-    # different kernel (and moves far fewer bytes), so it reports none
+    # counters of the kernel that ran, at this run's shape (and, for the persistent kernel,
+    # its steps per launch: its particles stay on chip between the steps of one launch)
     suffix = (("_monopole" if args.monopole else "") + ("_p2" if args.element_order == 2 else "")
               + ("_k3" if args.moments else ""))
     traffic_key = args.workload + suffix
-    traffic = None if persistent else load_traffic(traffic_key, n, prec, launch_key(tun))
+    traffic = load_traffic(traffic_key, n, prec, launch_key(tun), kernel_of(tun),
+                           steps_per_launch)
     out = {
         "metric": METRIC,
         "value": value,

@@ -202,7 +202,10 @@ typedef struct vp_handle vp_handle;
 vp_status vp_workspace_bytes(const vp_config* cfg, size_t* bytes_out);
 
 /* Single-instance handle: an engine with one slot, slot 0 admitted with (cfg, parts,
- * workspace).  Enqueues the initial deposit and Poisson solve (field at t = 0).
+ * workspace).  The instance is the paper's problem statement (Section 5, "Discretization
+ * in space and time"): the decorated-particle tuple of Section 4 per particle, a periodic
+ * mesh of cfg->ng elements over [0, cfg->L), the time step cfg->dt.  Enqueues the initial
+ * deposit and Poisson solve (field at t = 0, eqs. rhs-assembly and lin-sys).
  * workspace: device memory of vp_workspace_bytes(cfg) bytes, 256-byte aligned.
  * stream: hipStream_t as void*.  Errors: VP_ERR_ARG (cfg, null or misaligned pointers),
  * VP_ERR_HIP. */
@@ -269,7 +272,9 @@ vp_status vp_gather_push(vp_handle* h, double kick, double drift);
 
 /* ---------------------------------------------------------------- fused stepping */
 
-/* Advance every occupied slot by nsteps kick-drift-kick steps.  One fused kernel launch per
+/* Advance every occupied slot by nsteps kick-drift-kick steps of the discrete Hamiltonian
+ * system (eq. Hh with the equations of motion of eq. sw-evolution; the leapfrog of
+ * Section 5 taken as the splitting into the field and kinetic parts).  One fused kernel launch per
  * step and kind of instance (decorated or monopole-only, P1 or P2, with or without general
  * options; a single launch when all instances are of one kind): every workgroup solves the
  * field of the current positions from the load vector the
@@ -278,7 +283,9 @@ vp_status vp_gather_push(vp_handle* h, double kick, double drift);
  * load vector; optionally replayed from captured HIP graphs.  Equals the primitive
  * composition up to rounding.  Leaves a pending half-kick (P, q* at t + dt/2); every state
  * read-back must go through vp_sync_state, vp_retire or vp_diagnostics (which accounts for
- * it). */
+ * it).  With vp_tuning.persistent, up to 1024 steps run in one cooperative launch whose
+ * workgroups keep their particles in registers and wait for one another between steps;
+ * the arithmetic and the results are those of the fused launches. */
 vp_status vp_step(vp_handle* h, int32_t nsteps);
 /* (vp_step) An instance whose diagnostics come out NaN or Inf is frozen from the next step
  * on: its state, step counter and history stop where they are, vp_diagnostics and

@@ -87,12 +87,47 @@ def test_committed_counters_name_their_settings():
     """Every committed counter summary records the precision and launch shape it was taken
     at, so that no other run reports its bytes."""
     import glob
-    files = glob.glob(os.path.join(ROOT, "profiles", "pmc_k_fused_*.json"))
+    files = glob.glob(os.path.join(ROOT, "profiles", "pmc_k_*.json"))
     assert files
     for f in files:
         rec = json.load(open(f))
+        assert rec["kernel"] in ("k_fused", "k_persist"), f
         assert rec["precision"] in ("fp64", "fp32c", "fp32ts", "fp32"), f
         assert len(rec["launch"]) == 3 and all(isinstance(v, int) for v in rec["launch"]), f
-        assert os.path.basename(f) == os.path.basename(bench.pmc_path(rec["workload"],
-                                                                      rec["launch"])), f
+        assert os.path.basename(f) == os.path.basename(
+            bench.pmc_path(rec["workload"], rec["launch"], rec["kernel"])), f
+        if rec["kernel"] == "k_persist":
+            assert rec["steps_per_launch"] >= 1, f
+
+
+def test_pmc_summary_of_the_persistent_kernel(tmp_path, monkeypatch):
+    """A persistent launch runs many steps: its summary names the kernel and its steps per
+    launch, and a run with another step count reports none of its bytes."""
+    src = tmp_path / "paper_2605_21794_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "vp_kernels.hip").write_text("// kernel source stand-in\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    k = "void vpk::k_persist<1, 1024, 4, false>(...)"
+    _write_counters(tmp_path / "f", "FETCH_SIZE", [(1, k, 300.0), (2, "k_fused<1>", 9e9)])
+    _write_counters(tmp_path / "w", "WRITE_SIZE", [(1, k, 700.0)])
+    gib_kib = (1 << 30) / 1024.0
+    _write_counters(tmp_path / "cf", "FETCH_SIZE", [(1, "copy", gib_kib / 2)])
+    _write_counters(tmp_path / "cw", "WRITE_SIZE", [(1, "copy", gib_kib)])
+    bench.pmc_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                      str(tmp_path / "cw"), "two_stream", "fp32c", [1024, 4, 4],
+                      "k_persist", 1000)
+    rec = json.load(open(tmp_path / "profiles" / "pmc_k_persist_two_stream_1024x4x4.json"))
+    assert rec["kernel"] == "k_persist" and rec["steps_per_launch"] == 1000
+    assert rec["dispatches"] == [1, 1]
+    tb = (2 * 300.0 + 700.0) * 1024.0
+    assert rec["traffic_bytes_per_launch"] == pytest.approx(tb)
+    assert rec["traffic_bytes_per_update"] == pytest.approx(tb / (rec["n"] * 1000))
+    n, shape = rec["n"], [1024, 4, 4]
+    assert bench.load_traffic("two_stream", n, "fp32c", shape, "k_persist", 1000) == \
+        pytest.approx(tb)
+    assert bench.load_traffic("two_stream", n, "fp32c", shape, "k_persist", 20) is None
+    assert bench.load_traffic("two_stream", n, "fp32c", shape, "k_fused", 1) is None
+    assert bench.kernel_of({"persistent": 1}) == "k_persist"
+    assert bench.kernel_of({"persistent": 0}) == "k_fused"
 

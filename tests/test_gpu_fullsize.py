@@ -174,3 +174,66 @@ def test_p2_two_stream_full_size_fp32c(vp):
     W1 = sim.diagnostics(0)["W"]
     assert abs(W1 - fld1["W"]) <= 1e-5 * fld1["W"]
     sim.close()
+
+
+@pytest.mark.parametrize("copies", [4, 8])
+def test_two_stream_full_size_persistent_steps(vp, copies):
+    """The bench's default workload (N = 2^20, Ng 512, fp32c) in the persistent shapes its
+    autotuner picks (1024 threads x 4 particles per thread, 256 workgroups, 4 or 8 copies).
+
+    * One persistent launch of one step: the particle update is bit-exact against the
+      oracle's kick and drift on the device's own initial field, the field of the stepped
+      state within 1e-5 of the oracle's on the same bits, the cell indices bit-exact.
+    * Then 30 more steps in one persistent launch: the field-energy and energy histories
+      against the float32-storage reference of the fused step (the oracle's sub-flows in
+      float64, stored in float32 where the kernel stores), relative L2 1e-5, and the final
+      state against it (rel-L2 1e-5)."""
+    from fp32_reference import fp32_fused_reference
+    w = W.two_stream()
+    st = w.state(np.float32)
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=64)
+    sim.set_tuning(threads=1024, ppt=4, acc_copies=copies, persistent=1)
+    assert sim.get_tuning()["persistent"] == 1
+    f0 = sim.diagnostics(0, grid=True)
+    sim.step(1)
+    check_slot(sim, 0, st, f0, w)
+    more = 30
+    sim.step(more)
+    n = 1 + more
+    hist = sim.history(0, 0, n) + [sim.diagnostics(0)]
+    assert [h["step"] for h in hist] == list(range(n + 1))
+    s64 = {k: v.astype(np.float64) for k, v in st.items()}
+    Wr, Hr, (Q, P, qs, ps) = fp32_fused_reference(s64, w, n)
+    assert rel_l2([h["W"] for h in hist], Wr) < 1e-5
+    assert rel_l2([h["H"] for h in hist], Hr) < 1e-5
+    got = sim.state_numpy(0)
+    for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
+        assert rel_l2(got[k], r) < 1e-5, k
+    sim.close()
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_two_stream_full_size_fp64_run_against_oracle(vp, persistent):
+    """The two-stream workload at full size in float64 (N = 2^20, Ng 512), 33 steps against
+    the oracle's run from the same bits: graph-replayed fused launches (512 threads x 4,
+    8 copies, graphs of 3 steps, so every ring phase is replayed) or one persistent launch
+    (1024 x 4, 4 copies).  The two sides differ in summation order only: state within
+    1e-11 (absolute), W, K and H histories within 1e-10 (relative L2)."""
+    w = W.two_stream()
+    st = w.state(np.float64)
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=64)
+    if persistent:
+        sim.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    else:
+        sim.set_tuning(threads=512, ppt=4, acc_copies=8, use_graph=1, graph_steps=3)
+    nsteps = 33
+    sim.step(nsteps)
+    hist = sim.history(0, 0, nsteps) + [sim.diagnostics(0)]
+    got = sim.state_numpy(0)
+    ref_state, _, ref_hist = O.run(*(st[k] for k in ("Q", "P", "qs", "ps", "psi")),
+                                   w.L, w.ng, w.dt, nsteps)
+    for k, r in zip(("Q", "P", "qs", "ps", "psi"), ref_state):
+        assert np.max(np.abs(got[k] - r)) <= 1e-11, k
+    for key in ("W", "K", "H"):
+        assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
+    sim.close()
