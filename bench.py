@@ -7,22 +7,25 @@
     python bench.py --workload sw_vs_pic         particle count against accuracy, decorated
                                                  particles against plain particle-in-cell
     python bench.py --workload cluster           k-means initialisation from markers
-    python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies)
+    python bench.py --launch 1024,8,1 --no-tune ...   fixed launch shape (threads, ppt, acc copies
+                                                 [, persistent [, wave_reduce]])
+    python bench.py --order lattice ...               lattice particle order instead of random
     python bench.py --copy-calibration                one device copy of a known size (for PMC scaling)
-    python bench.py --pmc-summary F_DIR W_DIR COPY_F_DIR COPY_W_DIR --workload W --launch T,PPT,C
+    python bench.py --pmc-summary F_DIR W_DIR COPY_F_DIR COPY_W_DIR --workload W --launch T,PPT,C[,1]
 
 One step = one pass of the whole hot path over the batch of particles: the Poisson solve of
-the previous deposit (every workgroup of the fused kernel solves it in its prologue),
-pending half-kick, kinetic diagnostics, half-kick, drift, deposit.  --monopole runs the same
-workload as plain particle-in-cell particles (p* = q* = 0, 20 bytes per update);
---element-order 2 runs it with P2 elements (the same 36 bytes per update, a load vector of
-2 Ng nodes).  Default workload: the two-stream instability, N = 2^20 decorated particles,
-Ng = 512, dt = 0.05, FP32 state with compensated deposition.
+the previous deposit (every workgroup of the step kernel solves it), pending half-kick,
+kinetic diagnostics, half-kick, drift, deposit.  --monopole runs the same workload as plain
+particle-in-cell particles (p* = q* = 0, 20 bytes per update); --element-order 2 runs it
+with P2 elements (the same 36 bytes per update, a load vector of 2 Ng nodes).  Default
+workload: the two-stream instability, N = 2^20 decorated particles, Ng = 512, dt = 0.05,
+FP32 state with compensated deposition.
 
 Prints ONE JSON line on stdout.  `value` = N * K / wall time of the K timed steps
-(particle state resident in HBM, graph-replayed steps).  `roofline` divides the fused
-kernel's algorithmic bytes by its average launch duration, taken with HIP events on the
-library's stream around the timed region (one fused launch per step).
+(particle state resident in HBM; graph-replayed fused launches, or persistent launches of
+up to 1024 steps when the autotuner keeps that kernel).  `roofline` divides the step
+kernel's algorithmic bytes per launch by its average launch duration, taken with HIP events
+on the library's stream around the timed region.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -195,11 +198,13 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, precisio
 
 
 def parse_launch(text: str) -> dict:
-    """threads,ppt,acc_copies[,persistent] -> tuning fields."""
+    """threads,ppt,acc_copies[,persistent[,wave_reduce]] -> tuning fields."""
     v = [int(x) for x in text.split(",")]
     out = {"threads": v[0], "ppt": v[1], "acc_copies": v[2]}
     if len(v) > 3:
         out["persistent"] = v[3]
+    if len(v) > 4:
+        out["wave_reduce"] = v[4]
     return out
 
 
@@ -832,6 +837,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="sort particles by cell every this many steps (0: never)")
     ap.add_argument("--sort-chunk", type=int, default=0, help="particles per sorted chunk")
+    ap.add_argument("--order", default="random", choices=("random", "lattice"),
+                    help="particle order in memory of the lattice workloads")
     ap.add_argument("--markers", type=int, default=1 << 22, help="cluster: markers")
     ap.add_argument("--monopole", action="store_true",
                     help="run the workload as monopole-only (plain particle-in-cell) particles")
@@ -908,9 +915,10 @@ def main():
     import paper_2605_21794_amd as vp
 
     w, prec = make_workload(args.workload)
+    w.order = args.order
     if args.precision:
         prec = args.precision
-    log(f"workload {w.name}: N={w.n} Ng={w.ng} dt={w.dt} precision={prec}")
+    log(f"workload {w.name}: N={w.n} Ng={w.ng} dt={w.dt} precision={prec} order={w.order}")
     t0 = time.perf_counter()
     if args.moments and prec not in MOMENT_BYTES:
         raise SystemExit(f"--moments runs in {sorted(MOMENT_BYTES)}, not {prec}")
@@ -1016,7 +1024,7 @@ def main():
             "workload": w.name + suffix, "n": n, "ng": w.ng, "element_order": args.element_order,
             "L": w.L, "dt": w.dt,
             "precision": prec, "instances": 1, "launch": tun, "timed_launches": timed_launches,
-            "sort_every": args.sort_every, "sort_chunk": args.sort_chunk,
+            "sort_every": args.sort_every, "sort_chunk": args.sort_chunk, "order": args.order,
             "state_finite_after_run": finite, "t_end": diag["t"],
         },
         "roofline": {

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define VP_ABI_VERSION 9
+#define VP_ABI_VERSION 10
 #define VP_MIN_NG 8
 #define VP_MAX_NG 1024
 #define VP_MAX_SORT_CHUNK_F32 4096 /* particles per sorted chunk, float32 state */
@@ -191,6 +191,14 @@ typedef struct vp_tuning {
                          * particles held in registers between steps (threads 512 or 1024,
                          * ppt 2, 4 or 8; every tile must be resident at once, else
                          * vp_set_tuning returns VP_ERR_ARG); 0: one launch per step */
+  int32_t wave_reduce;  /* VP_FP32_TWOSUM only (the other modes ignore it): 1: the deposit
+                         * of the fused and persistent steps first combines, within each
+                         * wavefront, the loads of neighbouring lanes whose particles lie in
+                         * the same element (a segmented sum over each run, then one
+                         * compare-and-swap per run and node); it pays when particles that are
+                         * neighbours in memory are neighbours in space (sorted by cell,
+                         * vp_config.sort_every, or bunched).  0: one update per particle and
+                         * node.  Results differ in summation order only. */
 } vp_tuning;
 
 typedef struct vp_handle vp_handle;

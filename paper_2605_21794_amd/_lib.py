@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvp.so")
 
 VP_OK, VP_ERR_ARG, VP_ERR_HIP, VP_ERR_NONFINITE, VP_ERR_STATE, VP_ERR_RANGE = range(6)
 VP_FP64, VP_FP32_COMP, VP_FP32, VP_FP32_TWOSUM = 0, 1, 2, 3
-VP_ABI_VERSION = 9          # the layout of the structures declared below
+VP_ABI_VERSION = 10         # the layout of the structures declared below
 VP_SLOT_OCCUPIED, VP_SLOT_NONFINITE = 1, 2
 VP_SOLVE_SCAN, VP_SOLVE_FFT = 0, 1
 VP_PROJ_ELEM, VP_PROJ_NODAL, VP_PROJ_CONSISTENT = 0, 1, 2
@@ -45,7 +45,8 @@ class vp_diag(Structure):
 
 class vp_tuning(Structure):
     _fields_ = [("threads", c_int32), ("ppt", c_int32), ("acc_copies", c_int32),
-                ("use_graph", c_int32), ("graph_steps", c_int32), ("persistent", c_int32)]
+                ("use_graph", c_int32), ("graph_steps", c_int32), ("persistent", c_int32),
+                ("wave_reduce", c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -136,7 +136,7 @@ struct vp_handle {
   long long* d_status = nullptr;  // 2 per slot: step, nonfinite (vp_slot_status)
   int max_ng = VP_MIN_NG;   // largest ng of the slots, doubled for P2 (sizes the launches' LDS)
   bool any_fft = false;     // some slot uses the FFT solver (fused launches need more LDS)
-  vp_tuning tun{1024, 4, 4, 1, 33, 0};
+  vp_tuning tun{1024, 4, 4, 1, 33, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t step_graph[vpk::kRing] = {nullptr, nullptr, nullptr};  // one step at phase p
@@ -210,6 +210,7 @@ vp_status rebuild_tables(vp_handle* h) {
     if (nt > d.kin_cap) return fail(VP_ERR_STATE, "slot %d: %d tiles exceed the kinetic-sum ring (%d)", s, nt, d.kin_cap);
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
+    d.seg = h->tun.wave_reduce;
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
     for (int gi = group_of(s); gi < kGroups; ++gi) h->group_end[gi] += nt;
   }
@@ -867,6 +868,7 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
     return fail(VP_ERR_ARG, "ppt must be 1, 2, 4, 8, 16, 32 or 64");
   if (t->acc_copies < 1 || t->acc_copies > VP_MAX_ACC_COPIES) return fail(VP_ERR_ARG, "acc_copies out of range");
   if (t->graph_steps < 1 || t->graph_steps > 256) return fail(VP_ERR_ARG, "graph_steps out of range");
+  if (t->wave_reduce != 0 && t->wave_reduce != 1) return fail(VP_ERR_ARG, "wave_reduce must be 0 or 1");
   if (t->persistent) {
     if (!(t->threads == 512 || t->threads == 1024) || !(t->ppt == 2 || t->ppt == 4 || t->ppt == 8))
       return fail(VP_ERR_ARG, "persistent steps need threads 512 or 1024 and ppt 2, 4 or 8");
@@ -1139,44 +1141,55 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
           for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 1});
       }
   vp_status st = VP_OK;
-  for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
-    {
-      vp_tuning t = orig;
-      t.threads = cands[ci].threads;
-      t.ppt = cands[ci].ppt;
-      t.acc_copies = cands[ci].acc;
-      t.persistent = cands[ci].persistent;
-      t.use_graph = (h->stream != nullptr) ? 1 : 0;
-      t.graph_steps = std::min(steps_per_trial, 256);
-      st = vp_set_tuning(h, &t);
-      if (st == VP_ERR_ARG && t.persistent) {  // this shape cannot keep every tile resident
-        st = VP_OK;
-        continue;
-      }
-      if (st != VP_OK) break;
-      // one untimed graph build + warm-up pass, then the timed steps
-      st = vp_step(h, t.graph_steps);
-      if (st != VP_OK) break;
-      if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(VP_ERR_HIP, "event record"); break; }
-      st = vp_step(h, steps_per_trial);
-      if (st != VP_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = fail(VP_ERR_HIP, "event timing");
-        break;
-      }
-      const double us = 1000.0 * ms / steps_per_trial;
-      if (us < best_us) {
-        best_us = us;
-        best = t;
-      }
-      h->slots = saved;
-      h->phase = saved_phase;
-      h->field_stale = saved_fs;
-      h->acc_stale = saved_as;
-      if (st == VP_OK) st = tune_copy(h, scratch, false);
+  // one trial: set the shape, one untimed graph build + warm-up pass, the timed steps, then
+  // the saved state back.  Returns false when a persistent shape cannot keep every tile
+  // resident (skipped); st carries any error.
+  auto trial = [&](vp_tuning t) -> bool {
+    t.use_graph = (h->stream != nullptr) ? 1 : 0;
+    t.graph_steps = std::min(steps_per_trial, 256);
+    st = vp_set_tuning(h, &t);
+    if (st == VP_ERR_ARG && t.persistent) {  // this shape cannot keep every tile resident
+      st = VP_OK;
+      return false;
     }
+    if (st != VP_OK) return false;
+    st = vp_step(h, t.graph_steps);
+    if (st != VP_OK) return false;
+    if (hipEventRecord(e0, h->stream) != hipSuccess) { st = fail(VP_ERR_HIP, "event record"); return false; }
+    st = vp_step(h, steps_per_trial);
+    if (st != VP_OK) return false;
+    float ms = 0.f;
+    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(VP_ERR_HIP, "event timing");
+      return false;
+    }
+    const double us = 1000.0 * ms / steps_per_trial;
+    if (us < best_us) {
+      best_us = us;
+      best = t;
+    }
+    h->slots = saved;
+    h->phase = saved_phase;
+    h->field_stale = saved_fs;
+    h->acc_stale = saved_as;
+    st = tune_copy(h, scratch, false);
+    return true;
+  };
+  for (size_t ci = 0; ci < cands.size() && st == VP_OK; ++ci) {
+    vp_tuning t = orig;
+    t.threads = cands[ci].threads;
+    t.ppt = cands[ci].ppt;
+    t.acc_copies = cands[ci].acc;
+    t.persistent = cands[ci].persistent;
+    t.wave_reduce = 0;
+    trial(t);
+  }
+  // the wavefront-combined deposit (compensated float32 pairs only), at the fastest shape
+  if (st == VP_OK && best_us < 1e300 && h->precision == VP_FP32_TWOSUM) {
+    vp_tuning t = best;
+    t.wave_reduce = 1;
+    trial(t);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

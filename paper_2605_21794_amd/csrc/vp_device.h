@@ -230,6 +230,54 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
   }
 }
 
+// Deposit of one particle's NV nodal contributions c[k] into nodes node[k] of element j.
+// In the compensated float32 mode, with `seg` (vp_tuning.wave_reduce, uniform per
+// workgroup), the wavefront first combines the contributions of neighbouring lanes that hit
+// the same element: lanes whose left neighbour has the same element continue a run; a
+// segmented inclusive sum over each run (Hillis-Steele over lane shuffles, clipped at the
+// run's first lane) leaves the run's totals in its last lane, which alone commits them to
+// the LDS grid.  Runs arise when particles that are neighbours in memory are neighbours in
+// space (sorted by cell, or bunched in a lattice order); when fewer than kSegMin lanes
+// continue a run the lanes update the grid one by one, as without `seg`.  The combination
+// needs every lane of the wavefront active (checked; otherwise the per-lane updates).  Sums
+// differ from the per-lane updates in their order only.  The float64 LDS add takes
+// same-node lanes faster than the scan would (measured), so the modes that accumulate in
+// float64 always update per lane; the (hi, lo) pairs pay a compare-and-swap per update.
+constexpr int kSegMin = 8;
+template <int MODE, int NV>
+__device__ __forceinline__ void deposit_nodes(double* sacc, bool seg, int j, const int (&node)[NV],
+                                              double (&c)[NV]) {
+  if (MODE == kFP32TwoSum && seg && __builtin_amdgcn_read_exec() == ~0ull) {
+    // element of lane - 1 (lane 0: -1, never an element), by a DPP wavefront shift
+    const int jp = __builtin_amdgcn_update_dpp(-1, j, 0x138, 0xf, 0xf, false);
+    const unsigned long long cont = __ballot(jp == j);
+    if (__popcll(cont) >= kSegMin) {
+      const int lane = __lane_id();
+      int rs = (jp == j) ? 0 : lane;  // first lane of this lane's run, by a max-scan
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(rs, off);
+        if (lane >= off) rs = max(rs, t);
+      }
+      for (int off = 1; off < 64; off <<= 1) {
+        double t[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[k] = __shfl_up(c[k], off);
+        if (lane - off >= rs)
+#pragma unroll
+          for (int k = 0; k < NV; ++k) c[k] += t[k];
+      }
+      // element of lane + 1 (lane 63: -1): the run's last lane holds its totals
+      const int jn = __builtin_amdgcn_update_dpp(-1, j, 0x130, 0xf, 0xf, false);
+      if (jn != j)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds_add<MODE>(sacc, node[k], c[k]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) lds_add<MODE>(sacc, node[k], c[k]);
+}
+
 // P2 load of one particle at local coordinate s of element j (eq. galerkin with the
 // quadratic basis N0 = (1-s)(1-2s), N1 = 4s(1-s), N2 = s(2s-1) of the element's left vertex,
 // midpoint and right vertex): node k gets psi* N_k(s) - p* N_k'(s) / h.  Midpoint j is LDS
@@ -239,22 +287,26 @@ __device__ __forceinline__ void lds_add(double* sacc, int j, double c) {
 // over h^2.
 template <int MODE, bool DIP, bool K3 = false>
 __device__ __forceinline__ void deposit_p2(double* sacc, int ng, int j, double s, double psi,
-                                           double ps, double inv_h, double mqq = 0.0) {
+                                           double ps, double inv_h, double mqq = 0.0,
+                                           bool seg = false) {
   const double n0 = (1.0 - s) * (1.0 - 2.0 * s), n1 = 4.0 * s * (1.0 - s), n2 = s * (2.0 * s - 1.0);
+  const int node[3] = {j, ng + j, (j + 1) & (ng - 1)};
+  double c[3];
   if constexpr (K3) {
-    const double c = 0.5 * mqq * (inv_h * inv_h);
-    lds_add<MODE>(sacc, j, psi * n0 - ps * ((4.0 * s - 3.0) * inv_h) + 4.0 * c);
-    lds_add<MODE>(sacc, ng + j, psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h) - 8.0 * c);
-    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2 - ps * ((4.0 * s - 1.0) * inv_h) + 4.0 * c);
+    const double m = 0.5 * mqq * (inv_h * inv_h);
+    c[0] = psi * n0 - ps * ((4.0 * s - 3.0) * inv_h) + 4.0 * m;
+    c[1] = psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h) - 8.0 * m;
+    c[2] = psi * n2 - ps * ((4.0 * s - 1.0) * inv_h) + 4.0 * m;
   } else if constexpr (DIP) {
-    lds_add<MODE>(sacc, j, psi * n0 - ps * ((4.0 * s - 3.0) * inv_h));
-    lds_add<MODE>(sacc, ng + j, psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h));
-    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2 - ps * ((4.0 * s - 1.0) * inv_h));
+    c[0] = psi * n0 - ps * ((4.0 * s - 3.0) * inv_h);
+    c[1] = psi * n1 - ps * ((4.0 - 8.0 * s) * inv_h);
+    c[2] = psi * n2 - ps * ((4.0 * s - 1.0) * inv_h);
   } else {
-    lds_add<MODE>(sacc, j, psi * n0);
-    lds_add<MODE>(sacc, ng + j, psi * n1);
-    lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * n2);
+    c[0] = psi * n0;
+    c[1] = psi * n1;
+    c[2] = psi * n2;
   }
+  deposit_nodes<MODE, 3>(sacc, seg, j, node, c);
 }
 
 // Second moments M = (Mqq, Mqp, Mpp) of a k = 3 particle under the two sub-flows of the
@@ -966,20 +1018,22 @@ __device__ __forceinline__ void push_particle(const InstDev& d, const double* fE
         Mr[0] = m0;
         Mr[1] = (T)Mqp;
         Mr[2] = (T)Mpp;
-        deposit_p2<MODE, true, true>(sacc, ng, j, s, psi, psd, inv_h, (double)m0);
+        deposit_p2<MODE, true, true>(sacc, ng, j, s, psi, psd, inv_h, (double)m0, d.seg != 0);
       } else if (p2) {
-        deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h);
+        deposit_p2<MODE, true>(sacc, ng, j, s, psi, psd, inv_h, 0.0, d.seg != 0);
       } else {
-        lds_add<MODE>(sacc, j, psi * (1.0 - s) + psd * inv_h);
-        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s - psd * inv_h);
+        const int node[2] = {j, (j + 1) & (ng - 1)};
+        double c[2] = {psi * (1.0 - s) + psd * inv_h, psi * s - psd * inv_h};
+        deposit_nodes<MODE, 2>(sacc, d.seg != 0, j, node, c);
       }
       qsr = (T)qs; psr = pss;
     } else {
       if (p2) {
-        deposit_p2<MODE, false>(sacc, ng, j, s, psi, 0.0, inv_h);
+        deposit_p2<MODE, false>(sacc, ng, j, s, psi, 0.0, inv_h, 0.0, d.seg != 0);
       } else {
-        lds_add<MODE>(sacc, j, psi * (1.0 - s));
-        lds_add<MODE>(sacc, (j + 1) & (ng - 1), psi * s);
+        const int node[2] = {j, (j + 1) & (ng - 1)};
+        double c[2] = {psi * (1.0 - s), psi * s};
+        deposit_nodes<MODE, 2>(sacc, d.seg != 0, j, node, c);
       }
     }
     Qr = Qs; Pr = (T)P;

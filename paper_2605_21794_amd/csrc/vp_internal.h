@@ -90,7 +90,8 @@ struct InstDev {
   void* Mqp;
   void* Mpp;
   int k3;           // the particles carry second moments (P2, general options)
-  int pad_;
+  int seg;          // the fused and persistent deposits combine runs of equal elements
+                    // within each wavefront first (vp_tuning.wave_reduce)
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.

@@ -45,7 +45,7 @@ def test_library_loaded_from_tree(vp):
     with open("/proc/self/maps") as f:
         maps = f.read()
     assert lib_path in maps
-    assert vp.load_library().vp_abi_version() == vp._lib.VP_ABI_VERSION == 9
+    assert vp.load_library().vp_abi_version() == vp._lib.VP_ABI_VERSION == 10
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])

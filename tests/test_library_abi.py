@@ -95,7 +95,7 @@ def test_null_handles_rejected(lib):
     assert lib.vp_deposit(None) == L.VP_ERR_ARG
     assert lib.vp_destroy(None) == L.VP_OK
     assert lib.vp_status_string(L.VP_ERR_RANGE) == b"history record out of range"
-    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 9
+    assert lib.vp_abi_version() == L.VP_ABI_VERSION == 10
     assert ctypes.sizeof(L.vp_particles) == 8 * 8  # eight array pointers, the moments last
     assert ctypes.sizeof(L.vp_diag) == 8 * 12  # twelve 8-byte fields, stamp last
     assert lib.vp_prepare_step(None, 1) == L.VP_ERR_ARG
