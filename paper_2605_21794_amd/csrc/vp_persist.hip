@@ -20,71 +20,65 @@ namespace vpk {
 // What no other tile needs is kept off the path between the barriers: every tile clears its
 // own slice of the ring entry the next step deposits into, and the instance's first tile
 // writes the record of step n-1 and the field summary of step n after it has counted its
-// arrival for step n, while the others are still on their way.  That bookkeeping reads LDS
-// only: the first tile copies the Fourier weights of E1 to LDS once per launch, and issues
-// the loads of the previous pass's per-tile kinetic sums together with the solve's loads,
-// parking the per-thread partials in LDS after the solve (device-scope loads after the
-// arrival would hold it past the others' release).
+// arrival for step n, while the others are still on their way.  That bookkeeping is done by
+// the tile's first wavefront alone, with no workgroup barrier (its last wavefront polls the
+// release meanwhile), and reads LDS only: the first tile copies the Fourier weights of E1 to
+// LDS once per launch, and issues the loads of the previous pass's per-tile kinetic sums
+// together with the solve's loads, parking the per-thread partials in LDS after the solve
+// (device-scope loads after the arrival would hold it past the others' release).
 // GEN = false: no instance of the launch has general options (fewer registers).
 constexpr unsigned kSpinLimit = 1u << 22;
 
-// The first tile's bookkeeping after step n (every thread of the workgroup calls it): the
-// field summary of the field in LDS (W, E1; the same per-thread partials, wave trees and
-// wave order as the solve's), into rec_next and the instance's field-summary ring entry r0;
-// and, when write_rec, the record of integer step rec_step with the kinetic sums of the
-// previous pass (skin: each solving thread's partial sums, field f of thread t at
+// The first tile's bookkeeping after step n, by its first wavefront alone (no workgroup
+// barrier, so the tile's other waves go on to the next step's wait): the field summary of
+// the field in LDS (W, E1), into rec and the instance's field-summary ring entry r0; and,
+// when write_rec, the record of integer step rec_step with the kinetic sums of the previous
+// pass (skin: each solving thread's partial sums, field f of thread t at
 // f * kSolveThreads + t, as load_kin forms them from the per-tile slots) and the field
-// summary rec of that step.  tw: the Fourier weights (d.tw) in LDS.
-template <int TPB, bool GEN>
+// summary rec of that step.  Each lane takes nodes and partials lane, lane + 64, ... in
+// order, then one wave tree per quantity: a fixed order.  tw: the Fourier weights (d.tw) in
+// LDS.  rec is read and updated in every lane (the wave trees leave the totals in all).
+template <bool GEN>
 __device__ void persist_bookkeeping(const InstDev& d, const double* fE, const double* tw,
-                                    const double* skin, double* sred, int r0, bool write_rec,
-                                    long long rec_step, const double (&rec)[3],
-                                    double (&rec_next)[3]) {
-  const int ng = d.ng, tid = threadIdx.x;
-  const int per = solve_per(ng), j0 = tid * per;
-  const bool solver_thread = tid < kSolveThreads;
+                                    const double* skin, int r0, bool write_rec,
+                                    long long rec_step, double (&rec)[3]) {
+  const int ng = d.ng, lane = threadIdx.x & 63;
   double kin[kKinFields] = {0.0, 0.0, 0.0, 0.0};
-  if (write_rec && solver_thread)
+  if (write_rec)
+    for (int t = lane; t < kSolveThreads; t += 64)
 #pragma unroll
-    for (int f = 0; f < kKinFields; ++f) kin[f] = skin[f * kSolveThreads + tid];
+      for (int f = 0; f < kKinFields; ++f) kin[f] += skin[f * kSolveThreads + t];
   double wp = 0.0, er = 0.0, ei = 0.0;
-  if (solver_thread && j0 < ng) {
-    const int halfn = ng >> 1;
-    for (int k = 0; k < per; ++k) {
-      const int e = j0 + k, t = e & (halfn - 1);
-      const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
-      const double c = sg * tw[2 * t], sn = sg * tw[2 * t + 1];
-      const double Ee = fE[e];
-      wp += Ee * Ee;
-      er += Ee * c;
-      ei -= Ee * sn;
-    }
+  const int halfn = ng >> 1;
+  for (int e = lane; e < ng; e += 64) {
+    const int t = e & (halfn - 1);
+    const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
+    const double c = sg * tw[2 * t], sn = sg * tw[2 * t + 1];
+    const double Ee = fE[e];
+    wp += Ee * Ee;
+    er += Ee * c;
+    ei -= Ee * sn;
   }
-  if (solver_thread) {
-    solve_wave_total(wp, sred, 3);
-    solve_wave_total(er, sred, 4);
-    solve_wave_total(ei, sred, 5);
-    solve_wave_total(kin[0], sred, 6);
-    solve_wave_total(kin[1], sred, 7);
-    solve_wave_total(kin[2], sred, 8);
-    solve_wave_total(kin[3], sred, 9);
-  }
-  __syncthreads();
-  rec_next[0] = 0.5 * d.h * solve_total(sred, 3);
-  rec_next[1] = solve_total(sred, 4) * inv_pow2(d.log2ng);
-  rec_next[2] = solve_total(sred, 5) * inv_pow2(d.log2ng);
-  if (tid == 0) {
+  wp = wave_sum(wp);
+  er = wave_sum(er);
+  ei = wave_sum(ei);
+#pragma unroll
+  for (int f = 0; f < kKinFields; ++f) kin[f] = wave_sum(kin[f]);
+  const double W = 0.5 * d.h * wp;
+  const double e1r = er * inv_pow2(d.log2ng), e1i = ei * inv_pow2(d.log2ng);
+  if (lane == 0) {
     if (write_rec)
-      write_record(d, rec_step, solve_total(sred, 6), solve_total(sred, 7),
-                   solve_total(sred, 8), GEN ? solve_total(sred, 9) : 0.0, rec[0], rec[1],
+      write_record(d, rec_step, kin[0], kin[1], kin[2], GEN ? kin[3] : 0.0, rec[0], rec[1],
                    rec[2]);
     VPG InstScal* sc = gp(d.scal);
-    sc->W[r0] = rec_next[0];
-    sc->e1r[r0] = rec_next[1];
-    sc->e1i[r0] = rec_next[2];
-    if (!isfinite(rec_next[0])) sc->nonfinite = 1;
+    sc->W[r0] = W;
+    sc->e1r[r0] = e1r;
+    sc->e1i[r0] = e1i;
+    if (!isfinite(W)) sc->nonfinite = 1;
   }
-  __syncthreads();  // sred is reused by the next solve
+  rec[0] = W;
+  rec[1] = e1r;
+  rec[2] = e1i;
 }
 
 template <int MODE, int TPB, int PPT, bool GEN>
@@ -167,7 +161,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     __asm__ __volatile__("" ::: "memory");
     const int r1 = ring_next(r0), r2 = ring_prev(r0);
     if (st > 0) {  // wait for every tile of the instance to finish the previous step
-      if (threadIdx.x == 0) {
+      // polled by the last wave: the first wave may still be in the first tile's bookkeeping
+      if (threadIdx.x == TPB - 64) {
         unsigned it = 0;
         while (__hip_atomic_load(my_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                (unsigned)st) {
@@ -257,14 +252,8 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
         }
       }
     }
-    if (first) {  // record of step st - 1, field summary of step st
-      double rec_next[3];
-      persist_bookkeeping<TPB, GEN>(d, fE, stw, skin, sred, r0, write_rec, step0 + st - 1, rec,
-                                    rec_next);
-      rec[0] = rec_next[0];
-      rec[1] = rec_next[1];
-      rec[2] = rec_next[2];
-    }
+    if (first && threadIdx.x < 64)  // record of step st - 1, field summary of step st
+      persist_bookkeeping<GEN>(d, fE, stw, skin, r0, write_rec, step0 + st - 1, rec);
     r0 = r1;
   }
   if (first && threadIdx.x == 0) sc->step = step0 + nsteps;
