@@ -29,7 +29,7 @@ constexpr int cons_taps(int ng) { return ng <= 64 ? ng : kConsTapsMax; }
 constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
 
 constexpr int kArriveGroups = 16;  // arrival counters per instance
-constexpr int kReleaseFlags = 8;   // copies of an instance's release flag
+constexpr int kReleaseFlags = 32;  // copies of an instance's release flag
 constexpr int kArriveStride = 32;  // unsigned words between counters and flags (128 bytes)
 
 // Per-instance scalars living in the instance workspace.

@@ -238,18 +238,22 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     if (st + 1 < nsteps) {
       __builtin_amdgcn_s_waitcnt(0);  // this wave's flush, slot and clear are performed
       __syncthreads();
-      if (threadIdx.x == 0) {  // count the arrival; the last of all releases step st + 1
+      if (threadIdx.x < 64) {  // count the arrival; the last of all releases step st + 1
         const unsigned e = (unsigned)(st + 1);
-        const unsigned old = __hip_atomic_fetch_add(my_counter, 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1u == e * group_tiles) {
-          const unsigned g = __hip_atomic_fetch_add(sc->top, 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-          if (g + 1u == e * (unsigned)ngroups)
-            for (int f = 0; f < kReleaseFlags; ++f)
-              __hip_atomic_store(sc->release + f * kArriveStride, e, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+        unsigned rel = 0;
+        if (threadIdx.x == 0) {
+          const unsigned old = __hip_atomic_fetch_add(my_counter, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+          if (old + 1u == e * group_tiles) {
+            const unsigned g = __hip_atomic_fetch_add(sc->top, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (g + 1u == e * (unsigned)ngroups) rel = 1;
+          }
         }
+        if (__shfl(rel, 0))  // the flags are written by the whole wavefront
+          for (int f = threadIdx.x; f < kReleaseFlags; f += 64)
+            __hip_atomic_store(sc->release + f * kArriveStride, e, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     if (first && threadIdx.x < 64)  // record of step st - 1, field summary of step st
