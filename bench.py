@@ -1036,6 +1036,11 @@ def main():
             "direct_launch_us": direct_us,
         },
     }
+    if persistent:
+        out["roofline"]["note"] = (
+            "persistent kernel: each thread keeps its particles in registers for all the steps "
+            "of a launch; achieved counts the algorithmic bytes per update, traffic the bytes "
+            "the counters measured per launch")
     sim.close()
     if not args.no_served:
         out["served"] = served_block(prec)
