@@ -67,13 +67,19 @@ __global__ __launch_bounds__(TPB) void k_fused(const InstDev* __restrict__ insts
       const int loc = (k0 + u) * TPB + (int)threadIdx.x;
       g.v[u] = (k0 + u < ppt) && (loc < tl.count);
       g.idx[u] = tl.begin + loc;
-      // a lane past the end of the tile holds an all-zero particle (see run_group)
-      g.q[u] = g.p[u] = g.a[u] = g.b[u] = g.w[u] = T(0);
-      if (g.v[u]) {
-        g.q[u] = ntld(Qp + g.idx[u]); g.p[u] = ntld(Pp + g.idx[u]); g.w[u] = ntld(psip + g.idx[u]);
-        if constexpr (DIP) {
-          g.a[u] = ntld(qsp + g.idx[u]); g.b[u] = ntld(psp + g.idx[u]);
-        }
+      // every lane loads (a lane past the end of the tile reads the tile's last particle, so
+      // no load is under a branch); such a lane then holds an all-zero particle (run_group)
+      const long long li = tl.begin + (g.v[u] ? loc : tl.count - 1);
+      const T z = T(0);
+      const T lq = ntld(Qp + li), lp = ntld(Pp + li), lw = ntld(psip + li);
+      g.q[u] = g.v[u] ? lq : z;
+      g.p[u] = g.v[u] ? lp : z;
+      g.w[u] = g.v[u] ? lw : z;
+      g.a[u] = g.b[u] = z;
+      if constexpr (DIP) {
+        const T la = ntld(qsp + li), lb = ntld(psp + li);
+        g.a[u] = g.v[u] ? la : z;
+        g.b[u] = g.v[u] ? lb : z;
       }
       if constexpr (kM) {
         g.m[0][u] = g.m[1][u] = g.m[2][u] = T(0);
