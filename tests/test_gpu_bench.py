@@ -69,3 +69,22 @@ def test_p2_bench_line():
     assert d["config"]["workload"] == "two_stream_p2" and d["config"]["element_order"] == 2
     assert d["value"] > 0
     assert (d["roofline"]["traffic"] is not None) == committed_counters_current("two_stream_p2")
+
+
+def test_persistent_bench_line():
+    """The persistent kernel's line: one launch of the timed steps, the algorithmic bytes of
+    all of them over that launch's duration, the note on what they count, and no counter
+    traffic for a step count the counters were not taken at."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--no-tune", "--launch",
+                        "1024,4,4,1", "--steps", "100", "--warmup", "9", "--no-cpu",
+                        "--no-served"], capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = json.loads([ln for ln in r.stdout.splitlines() if ln.strip()][-1])
+    assert d["config"]["timed_launches"] == "persistent launches"
+    rf = d["roofline"]
+    assert rf["kernel"] == "k_persist" and rf["steps_per_launch"] == 100
+    assert rf["bytes_per_launch"] == 36 * (1 << 20) * 100
+    assert rf["achieved"] == pytest.approx(rf["bytes_per_launch"] / (rf["kernel_us"] * 1e-6) / 1e9)
+    assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"])
+    assert "registers" in rf["note"]
+    assert rf["traffic"] is None
