@@ -400,6 +400,11 @@ def run_served(args):
 
     torch.cuda.set_device(0)
     srv = Server(precision=prec, max_slots=args.slots, chunk=args.chunk)
+    if args.launch:
+        srv.backend.engine.set_tuning(**parse_launch(args.launch))
+    if args.use_graph is not None:
+        srv.backend.engine.set_tuning(use_graph=args.use_graph)
+    log(f"served: engine tuning {srv.backend.engine.get_tuning()}")
     full_budget = srv.budget
     w0 = base[0][1]
     srv.run([Job(state=states[0], L=w0.L, ng=w0.ng, dt=w0.dt, horizon=66, name="warm")])
@@ -694,7 +699,7 @@ def run_precision_study(args):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     modes = {}
-    for prec in ("fp64", "fp32c", "fp32ts", "fp32"):
+    for prec in args.modes.split(","):
         st = {k: (v.astype(np.float64) if prec == "fp64" else v) for k, v in st32.items()}
         sim = vp.Simulation(st, w.L, w.ng, w.dt, prec, hist_cap=steps + 8, stream=stream)
         if args.launch:
@@ -723,10 +728,11 @@ def run_precision_study(args):
         sim.close()
     oracle = {"H_drift_max_rel": float(np.max(np.abs(col["H"] - col["H"][0])) / abs(col["H"][0])),
               "momentum_drift_max": float(np.max(np.abs(col["momentum"] - col["momentum"][0])))}
-    out = {"metric": METRIC, "value": modes["fp32c"]["updates_per_s"],
+    head = "fp32c" if "fp32c" in modes else next(iter(modes))
+    out = {"metric": METRIC, "value": modes[head]["updates_per_s"],
            "unit": "decorated-particle updates/s", "n_gpus": 1, "steps": steps, "warmup": 0,
-           "ms_per_step": modes["fp32c"]["ms"] / steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": arith_dtype("fp32c"),
+           "ms_per_step": modes[head]["ms"] / steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": arith_dtype(head),
            "data": "synthetic", "config": {"workload": "landau_nonlinear", "n": w.n, "ng": w.ng, "dt": w.dt,
                       "study": "precision"},
            "precision_study": modes, "oracle": oracle}
@@ -850,6 +856,8 @@ def main():
                     help="sw_vs_pic: mesh elements (default 128 for P1, 32 for P2)")
     ap.add_argument("--primitives", action="store_true",
                     help="time vp_deposit and vp_gather_push on their own")
+    ap.add_argument("--modes", default="fp64,fp32c,fp32ts,fp32",
+                    help="precision study: the modes to run, in order")
     ap.add_argument("--precision-study", action="store_true",
                     help="landau_nonlinear in every precision mode against the stored oracle")
     ap.add_argument("--jobs", type=int, default=128, help="served: jobs in the stream")
@@ -860,6 +868,8 @@ def main():
                     help="served: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=64, help="served: engine slots")
     ap.add_argument("--chunk", type=int, default=33, help="served: steps between decisions")
+    ap.add_argument("--use-graph", type=int, default=None, choices=(0, 1),
+                    help="served: replay captured graphs (1) or launch directly (0)")
     ap.add_argument("--budget-gib", type=float, default=None,
                     help="served: device bytes cap (default: 1/32 GiB for the capped runs)")
     ap.add_argument("--launch", default=None,
