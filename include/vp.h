@@ -105,8 +105,7 @@ typedef struct vp_config {
                             integral(phi_h) = 0 (eq. galerkin), E = -phi_h' is linear on each
                             element and phi_h'' is read from the basis itself (constant per
                             element, so cfg.projection must be VP_PROJ_ELEM and plays no
-                            part).  P2 needs a precision other than VP_FP32 and is not run by
-                            persistent tuning. */
+                            part).  P2 needs a precision other than VP_FP32. */
   int32_t moment_order;  /* highest moment carried by each particle, the k of the ansatz
                             (eq. sw_f_ansatz) and its quotient algebra s_k (Section
                             "Scovel-Weinstein enhancement of PIC").  0 or 2 (default): the

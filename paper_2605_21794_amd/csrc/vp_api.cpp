@@ -344,6 +344,13 @@ bool any_general(const vp_handle* h) {
   return false;
 }
 
+// Some occupied slot has P2 elements (the persistent kernel then takes its P2 instance).
+bool any_p2(const vp_handle* h) {
+  for (int s : h->h_occ)
+    if (h->h_inst[s].order == 2) return true;
+  return false;
+}
+
 // k steps as cooperative persistent launches (particles in registers between steps).
 vp_status advance_persistent(vp_handle* h, int k) {
   while (k > 0) {
@@ -351,7 +358,8 @@ vp_status advance_persistent(vp_handle* h, int k) {
     VP_HIP(vpk::launch_slot_scalars(h->d_inst, h->d_occ, (int)h->h_occ.size(), vpk::kScalPersistStart,
                                     h->phase, h->stream));
     VP_HIP(vpk::launch_persist(h->precision, h->tun.threads, h->tun.ppt, h->d_inst, h->d_tiles, h->ntiles,
-                               h->max_ng, h->any_fft, any_general(h), h->phase, c, h->stream));
+                               h->max_ng, h->any_fft, any_general(h), any_p2(h), h->phase, c,
+                               h->stream));
     h->phase = (h->phase + c) % vpk::kRing;
     k -= c;
   }
@@ -512,8 +520,8 @@ vp_status vp_admit(vp_handle* h, int32_t slot, const vp_config* cfg, vp_particle
   if (!k3) parts.Mqq = parts.Mqp = parts.Mpp = nullptr;
   if (!workspace || !aligned(workspace, 256)) return fail(VP_ERR_ARG, "workspace NULL or not 256-byte aligned");
 
-  if (h->tun.persistent && order_of(*cfg) == 2)
-    return fail(VP_ERR_ARG, "P2 elements are not run by persistent tuning");
+  if (h->tun.persistent && cfg->moment_order == 3)
+    return fail(VP_ERR_ARG, "particles with second moments are not run by persistent tuning");
   const vpk::WsLayout w = vpk::workspace_layout(cfg->ng, order_of(*cfg), cfg->hist_cap, cfg->n);
   char* ws = static_cast<char*>(workspace);
   InstDev d{};
@@ -873,8 +881,9 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
     if (!(t->threads == 512 || t->threads == 1024) || !(t->ppt == 2 || t->ppt == 4 || t->ppt == 8))
       return fail(VP_ERR_ARG, "persistent steps need threads 512 or 1024 and ppt 2, 4 or 8");
     for (int s : h->h_occ)
-      if (order_of(h->slots[s].cfg) == 2)
-        return fail(VP_ERR_ARG, "slot %d has P2 elements, which persistent steps do not run", s);
+      if (h->h_inst[s].k3)
+        return fail(VP_ERR_ARG, "slot %d has particles with second moments, which persistent "
+                                "steps do not run", s);
   }
   const vp_tuning old = h->tun;
   h->tun = *t;
@@ -883,7 +892,7 @@ vp_status vp_set_tuning(vp_handle* h, const vp_tuning* t) {
   VP_TRY(rebuild_tables(h));
   if (h->tun.persistent) {
     const int cap = vpk::persist_capacity(h->precision, h->tun.threads, h->tun.ppt, h->max_ng,
-                                          h->any_fft, any_general(h));
+                                          h->any_fft, any_general(h), any_p2(h));
     if (h->ntiles > cap) {
       const int need = h->ntiles;
       h->tun = old;
@@ -1137,7 +1146,7 @@ vp_status vp_tune(vp_handle* h, void* dev_scratch, int32_t steps_per_trial, vp_t
           return t;
         }();
         if (tiles_needed <= vpk::persist_capacity(h->precision, th, pp, h->max_ng, h->any_fft,
-                                                  any_general(h)))
+                                                  any_general(h), any_p2(h)))
           for (int ac : {1, 2, 4, 8}) cands.push_back({th, pp, ac, 1});
       }
   vp_status st = VP_OK;

@@ -139,11 +139,13 @@ hipError_t launch_diag(int mode, int tpb, const InstDev* d_inst, const Tile* d_t
 // Persistent form of the fused step: nsteps steps in one cooperative launch, the particles
 // of each tile held in registers between steps (ppt per thread, 2, 4 or 8).  Every tile of
 // the launch must be resident at once: persist_capacity gives how many workgroups can be.
-// `general`: some instance of the launch has general options (InstDev::general).
+// `general`: some instance of the launch has general options (InstDev::general); `p2`:
+// some instance has P2 elements (never with second moments).
 hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
-                          int ntiles, int max_ng, bool lds_fft, bool general, int phase,
+                          int ntiles, int max_ng, bool lds_fft, bool general, bool p2, int phase,
                           int nsteps, hipStream_t s);
-int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general);
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general,
+                     bool p2);
 // Solve the listed slots from ring entry `phase` and write the field arrays (materialise).
 hipError_t launch_solve(int mode, const InstDev* d_inst, const int* d_slots, int nslots,
                         int max_ng, bool lds_fft, int phase, hipStream_t s);

@@ -11,7 +11,8 @@ namespace vpk {
 // previous step, through the two-level arrival tree of InstScal: group counters, a top
 // counter, and release flags written by the tile that completes the top counter; one lane
 // of each waiting tile polls one flag, with a bounded spin (after kSpinLimit polls the
-// instance is flagged and the wait ends, so every wave finishes).  Data other workgroups of the launch wrote (the load
+// instance is flagged, the wait ends and that tile waits no more in this launch, so every
+// wave finishes within one such period).  Data other workgroups of the launch wrote (the load
 // vector, the per-tile kinetic sums, the cleared ring entry) is read and written at device
 // scope.  The ring protocol, the records and the arithmetic are those of k_fused, so nsteps
 // persistent steps equal nsteps fused launches.  P2 instances are not taken (the host
@@ -38,10 +39,10 @@ constexpr unsigned kSpinLimit = 1u << 22;
 // summary rec of that step.  Each lane takes nodes and partials lane, lane + 64, ... in
 // order, then one wave tree per quantity: a fixed order.  tw: the Fourier weights (d.tw) in
 // LDS.  rec is read and updated in every lane (the wave trees leave the totals in all).
-template <bool GEN>
-__device__ void persist_bookkeeping(const InstDev& d, const double* fE, const double* tw,
-                                    const double* skin, int r0, bool write_rec,
-                                    long long rec_step, double (&rec)[3]) {
+template <bool GEN, bool P2>
+__device__ void persist_bookkeeping(const InstDev& d, const double* fE, const double* fG,
+                                    const double* tw, const double* skin, int r0,
+                                    bool write_rec, long long rec_step, double (&rec)[3]) {
   const int ng = d.ng, lane = threadIdx.x & 63;
   double kin[kKinFields] = {0.0, 0.0, 0.0, 0.0};
   if (write_rec)
@@ -58,6 +59,13 @@ __device__ void persist_bookkeeping(const InstDev& d, const double* fE, const do
     wp += Ee * Ee;
     er += Ee * c;
     ei -= Ee * sn;
+  }
+  if (P2 && d.order == 2) {
+    // the field is linear on a P2 element: W gains (1/2) h (3/16) sum b~_m^2 over the
+    // midpoint loads, b~_m = -(2h/3) g_e
+    double gm = 0.0;
+    for (int e = lane; e < ng; e += 64) gm += fG[e] * fG[e];
+    wp += 0.1875 * ((4.0 / 9.0) * d.h * d.h) * gm;
   }
   wp = wave_sum(wp);
   er = wave_sum(er);
@@ -81,7 +89,7 @@ __device__ void persist_bookkeeping(const InstDev& d, const double* fE, const do
   rec[2] = e1i;
 }
 
-template <int MODE, int TPB, int PPT, bool GEN>
+template <int MODE, int TPB, int PPT, bool GEN, bool P2>
 __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ insts,
                                                  const Tile* __restrict__ tiles, int phase0,
                                                  int nsteps) {
@@ -99,11 +107,12 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   VPG T* __restrict__ qsp = gp<T>(d.qs);
   VPG T* __restrict__ psp = gp<T>(d.ps);
   const VPG T* __restrict__ psip = gp<T>(d.psi);
+  const int nacc = P2 ? d.nacc : ng;  // load-vector nodes (2 ng for a P2 instance)
   double* fE = smem;
   double* fG = smem + ng;
   double* sacc = smem + 2 * ng;
-  double* bt = smem + 3 * ng;
-  double* fft = smem + 4 * ng;
+  double* bt = sacc + nacc;
+  double* fft = bt + ng;
   VPG InstScal* sc = gp(d.scal);
   if (sc->frozen) return;  // fixed for the launch: all tiles of the instance leave together
   const bool first = tl.local == 0;
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   }
   // float64 modes without general options carry each particle's element from one step's
   // deposit to the next step's gather
-  constexpr bool kCell = !GEN && MODE != kFP32;
+  constexpr bool kCell = !GEN && !P2 && MODE != kFP32;
   int cell[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) cell[u] = kCell ? cell_of((double)q[u] * d.inv_h, ng) : 0;
@@ -151,10 +160,11 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   VPG unsigned* const my_counter = sc->arrive + my_group * kArriveStride;
   VPG unsigned* const my_flag = sc->release + (tl.local & (kReleaseFlags - 1)) * kArriveStride;
   // this tile's slice of a ring entry's copies, cleared for the step after next
-  const int ncl = d.acc_copies * ng;
+  const int ncl = d.acc_copies * nacc;
   const int cl_per = (ncl + d.ntiles - 1) / d.ntiles;
   const int cl0 = min(ncl, tl.local * cl_per), cl1 = min(ncl, cl0 + cl_per);
 
+  bool gave_up = false;  // the poller's wait timed out: it waits no more, the launch drains
   int r0 = phase0;
   for (int st = 0; st < nsteps; ++st) {
     // nothing is hoisted out of the step loop: keeps the step's registers per step
@@ -164,30 +174,30 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       // polled by the last wave: the first wave may still be in the first tile's bookkeeping
       if (threadIdx.x == TPB - 64) {
         unsigned it = 0;
-        while (__hip_atomic_load(my_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-               (unsigned)st) {
+        while (!gave_up && __hip_atomic_load(my_flag, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) < (unsigned)st) {
           __builtin_amdgcn_s_sleep(1);
           if (++it > kSpinLimit) {
             __hip_atomic_store(&sc->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+            gave_up = true;
           }
         }
       }
       __syncthreads();
     }
     SolveIn sin_;
-    solve_load<MODE, true, GEN, false>(d, r0, false, sin_);
+    solve_load<MODE, true, GEN, P2>(d, r0, false, sin_);
     // the first tile's record of step st - 1 sums ring entry r2, which every tile finished
     // before the barrier just passed: its loads go out with the solve's
     const bool write_rec = st > 0 || (pend0 && step0 >= 1);
     double kinv[kKinFields] = {0.0, 0.0, 0.0, 0.0};
     if (first && write_rec && threadIdx.x < kSolveThreads)
       load_kin<true, GEN ? kKinFields : 3>(d, r2, kinv);
-    for (int j = threadIdx.x; j < ng; j += TPB) sacc[j] = 0.0;
+    for (int j = threadIdx.x; j < nacc; j += TPB) sacc[j] = 0.0;
     double Ks = 0.0, Ms = 0.0, Cs = 0.0, Us = 0.0;
     {
       double sum[7];
-      solve_compute<TPB, GEN, false>(d, sin_, false, bt, fE, fG, sred, fft, nullptr, sum);
+      solve_compute<TPB, GEN, P2>(d, sin_, false, bt, fE, fG, sred, fft, nullptr, sum);
     }
     if (first && threadIdx.x < kSolveThreads)  // read after the arrival's barrier
 #pragma unroll
@@ -202,9 +212,9 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
-      push_particle<MODE, T, true, GEN, false, -1, kCell>(d, fE, fG, sacc, pend, q[u], p[u], a[u],
-                                                          b[u], w[u], Ks, Ms, Cs, Us, false,
-                                                          nullptr, &cell[u]);
+      push_particle<MODE, T, true, GEN, P2, -1, kCell>(d, fE, fG, sacc, pend, q[u], p[u], a[u],
+                                                       b[u], w[u], Ks, Ms, Cs, Us, false,
+                                                       nullptr, &cell[u]);
     pend = 1;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       }
     }
     if (first && threadIdx.x < 64)  // record of step st - 1, field summary of step st
-      persist_bookkeeping<GEN>(d, fE, stw, skin, r0, write_rec, step0 + st - 1, rec);
+      persist_bookkeeping<GEN, P2>(d, fE, fG, stw, skin, r0, write_rec, step0 + st - 1, rec);
     r0 = r1;
   }
   if (first && threadIdx.x == 0) sc->step = step0 + nsteps;
@@ -271,11 +281,19 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
 
 #define VP_PERSIST_CASE(M, TB, PP)                                                          \
   if (mode == M && tpb == TB && ppt == PP) {                                                \
-    fn = general ? reinterpret_cast<const void*>(&k_persist<M, TB, PP, true>)              \
-                 : reinterpret_cast<const void*>(&k_persist<M, TB, PP, false>);            \
+    if (p2) {                                                                               \
+      if constexpr (M != kFP32)                                                             \
+        fn = general ? reinterpret_cast<const void*>(&k_persist<M, TB, PP, true, true>)     \
+                     : reinterpret_cast<const void*>(&k_persist<M, TB, PP, false, true>);   \
+    } else {                                                                                \
+      fn = general ? reinterpret_cast<const void*>(&k_persist<M, TB, PP, true, false>)      \
+                   : reinterpret_cast<const void*>(&k_persist<M, TB, PP, false, false>);    \
+    }                                                                                       \
   }
 
-static const void* persist_fn(int mode, int tpb, int ppt, bool general) {
+// p2: some instance of the launch has P2 elements (float32 naive state has none); such a
+// launch takes the P2 instance of the kernel, which runs the P1 instances too.
+static const void* persist_fn(int mode, int tpb, int ppt, bool general, bool p2) {
   const void* fn = nullptr;
 #define VP_PERSIST_MODE(M)                                                                  \
   VP_PERSIST_CASE(M, 512, 2) VP_PERSIST_CASE(M, 512, 4) VP_PERSIST_CASE(M, 512, 8)          \
@@ -289,8 +307,9 @@ static const void* persist_fn(int mode, int tpb, int ppt, bool general) {
 }
 #undef VP_PERSIST_CASE
 
-int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general) {
-  const void* fn = persist_fn(mode, tpb, ppt, general);
+int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool general,
+                     bool p2) {
+  const void* fn = persist_fn(mode, tpb, ppt, general, p2);
   if (!fn) return 0;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
   int per_cu = 0, cus = 0, dev = 0;
@@ -301,10 +320,10 @@ int persist_capacity(int mode, int tpb, int ppt, int max_ng, bool lds_fft, bool 
 }
 
 hipError_t launch_persist(int mode, int tpb, int ppt, const InstDev* d_inst, const Tile* d_tiles,
-                          int ntiles, int max_ng, bool lds_fft, bool general, int phase,
+                          int ntiles, int max_ng, bool lds_fft, bool general, bool p2, int phase,
                           int nsteps, hipStream_t s) {
   if (ntiles <= 0 || nsteps <= 0) return hipSuccess;
-  const void* fn = persist_fn(mode, tpb, ppt, general);
+  const void* fn = persist_fn(mode, tpb, ppt, general, p2);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = fused_lds_doubles(lds_fft) * (size_t)max_ng * sizeof(double);
   void* args[] = {(void*)&d_inst, (void*)&d_tiles, (void*)&phase, (void*)&nsteps};

@@ -41,6 +41,12 @@ def close(a, b, tol):
     return float(np.max(np.abs(a - b))) <= tol * max(1e-300, float(np.max(np.abs(b))))
 
 
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
 def oracle_run(st, L, ng, dt, nsteps, **kw):
     return O.run_p2(*(np.asarray(st[k], dtype=np.float64) for k in FIELDS), L, ng, dt, nsteps,
                     **kw)
@@ -188,9 +194,11 @@ def test_one_particle_and_retire(vp):
     eng.close()
 
 
-def test_engine_mixing_p1_and_p2(vp):
-    """P1 and P2 instances of different meshes in one engine (one launch per kind of tile):
-    each on its own oracle trajectory."""
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_engine_mixing_p1_and_p2(vp, persistent):
+    """P1 and P2 instances of different meshes in one engine (one launch per kind of tile, or
+    one persistent launch for all of them, in the kernel instance with P2 elements and
+    general options): each on its own oracle trajectory."""
     specs = [dict(ng=64, order=1), dict(ng=32, order=2), dict(ng=16, order=2, mono=True),
              dict(ng=128, order=2, solver="fft"), dict(ng=32, order=1, ext={"amp": 0.2, "mode": 1})]
     eng = vp.Engine("fp64", max_slots=len(specs))
@@ -205,7 +213,7 @@ def test_engine_mixing_p1_and_p2(vp):
         eng.admit(s, st, w.L, w.ng, w.dt, hist_cap=16, solver=sp.get("solver", "scan"),
                   monopole_only=sp.get("mono", False), external=sp.get("ext"),
                   element_order=sp["order"])
-    eng.set_tuning(threads=512, ppt=2, acc_copies=2, graph_steps=3)
+    eng.set_tuning(threads=512, ppt=2, acc_copies=2, graph_steps=3, persistent=persistent)
     eng.step(9)
     for s, (sp, (w, st)) in enumerate(zip(specs, sts)):
         if sp["order"] == 2:
@@ -278,13 +286,44 @@ def test_refused_configurations(vp):
         vp.Simulation(st, w.L, w.ng, w.dt, "fp64", element_order=3)
     sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", element_order=2)
     with pytest.raises(vp.VPError):
-        sim.set_tuning(threads=512, ppt=2, persistent=1)
+        sim.set_tuning(threads=256, ppt=2, persistent=1)  # persistent steps: 512 or 1024
     assert sim.get_tuning()["persistent"] == 0
     sim.step(2)                                   # still steps after the refusal
     sim.close()
-    eng = vp.Engine("fp64", max_slots=2)
-    eng.admit(0, st, w.L, w.ng, w.dt)
-    eng.set_tuning(threads=512, ppt=2, persistent=1)
-    with pytest.raises(vp.VPError):
-        eng.admit(1, st, w.L, w.ng, w.dt, element_order=2)
-    eng.close()
+
+
+@pytest.mark.parametrize("threads,ppt,copies", [(1024, 4, 4), (512, 2, 2)])
+def test_persistent_trajectory_matches_oracle(vp, threads, ppt, copies):
+    """P2 instances in persistent launches (particles in registers between steps), a ragged
+    tail, float64 against the oracle's P2 run (state 1e-10, histories 1e-10 of scale)."""
+    w = lattice(32, 128, 40, alpha=0.1)
+    st = {k: v[:-37] for k, v in w.state().items()}
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=64, element_order=2)
+    sim.set_tuning(threads=threads, ppt=ppt, acc_copies=copies, persistent=1)
+    assert sim.get_tuning()["persistent"] == 1
+    sim.step(7)
+    sim.step(13)                                  # two launches: the ring carries over
+    check_run(sim, st, w.L, w.ng, w.dt, 20)
+    sim.close()
+
+
+def test_persistent_full_size_two_stream_fp32c(vp):
+    """The `--element-order 2` workload at full size (2^20, Ng 512, fp32c) in persistent
+    launches (1024 x 4, 4 copies), 31 steps against the P2 float32-storage reference:
+    W and H histories and the final state within 1e-5."""
+    from fp32_reference import fp32_fused_reference
+    w = W.two_stream()
+    st = w.state(np.float32)
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c", hist_cap=64, element_order=2)
+    sim.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    n = 31
+    sim.step(n)
+    hist = sim.history(0, 0, n) + [sim.diagnostics(0)]
+    s64 = {k: v.astype(np.float64) for k, v in st.items()}
+    Wr, Hr, (Q, P, qs, ps) = fp32_fused_reference(s64, w, n, order=2)
+    assert rel(np.array([h["W"] for h in hist]), Wr) < 1e-5
+    assert rel(np.array([h["H"] for h in hist]), Hr) < 1e-5
+    got = sim.state_numpy(0)
+    for k, r in (("Q", Q), ("P", P), ("qs", qs), ("ps", ps)):
+        assert rel(got[k], r) < 1e-5, k
+    sim.close()
