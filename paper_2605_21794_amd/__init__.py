@@ -330,6 +330,18 @@ class Engine:
             L.check(st, "vp_history")
         return [arr[i].as_dict() for i in range(int(count))]
 
+    def history_array(self, slot: int, first: int, count: int, allow_nonfinite: bool = False):
+        """The same records as history(), as one numpy structured array (a field per
+        vp_diag member; no per-record Python objects)."""
+        arr = (L.vp_diag * max(1, int(count)))()
+        st = self.lib.vp_history(self.h, int(slot), int(first), int(count), arr)
+        if not (allow_nonfinite and st == L.VP_ERR_NONFINITE):
+            L.check(st, "vp_history")
+        dt = np.dtype([(k, np.int64 if k == "step" else np.float64)
+                       for k, _ in L.vp_diag._fields_])
+        assert dt.itemsize == ctypes.sizeof(L.vp_diag)
+        return np.frombuffer(arr, dtype=dt, count=int(count)).copy()
+
     # ---------------------------------------------------------------- tuning
     def get_tuning(self) -> dict:
         tu = L.vp_tuning()

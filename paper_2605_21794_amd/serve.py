@@ -179,12 +179,12 @@ class Server:
                     # others during the fused launch of the following step), so the stamps of
                     # records 0 .. done-2 bracket done-2 steps
                     done = min(job.steps_done, self.backend.frozen_step(slot))
-                    recs = self.backend.records(slot, done) if done > 0 else []
-                    st_s = [r["stamp_s"] for r in recs[:max(0, done - 1)]]
+                    st_s = self.backend.record_stamps(slot, done) if done > 0 else []
+                    st_s = st_s[:max(0, done - 1)]
                     job.step_latency_s = list(np.diff(st_s)) if len(st_s) > 1 else []
                     record_samples.extend(job.step_latency_s)
                     if self.keep_history:
-                        job.history = recs
+                        job.history = self.backend.records(slot, done) if done > 0 else []
                 job.result = self.backend.diagnostics(slot)
                 st = self.backend.retire(slot)
                 job.final_state = st if self.keep_state else None
@@ -257,6 +257,12 @@ class GpuBackend:
     def frozen_step(self, slot: int) -> int:
         """Steps the slot has taken (a frozen instance stops counting)."""
         return int(self.engine.slot_status()[slot][0])
+
+    def record_stamps(self, slot: int, count: int):
+        """The device clock stamps of records 0 .. count-1 of a slot, in seconds (one numpy
+        array, read without building a record object per step)."""
+        return self.engine.history_array(slot, 0, count, allow_nonfinite=True)["stamp"] / \
+            self.clock_hz
 
     def records(self, slot: int, count: int) -> list:
         """Per-step records 0 .. count-1 of a slot, each with its stamp in seconds."""
