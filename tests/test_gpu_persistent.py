@@ -109,3 +109,60 @@ def test_persistent_rejects_shapes_that_do_not_fit(vp):
     assert sim.get_tuning()["persistent"] == 1
     sim.step(3)
     assert sim.diagnostics(0)["step"] == 3
+
+
+def test_persistent_runs_past_one_launch(vp):
+    """1030 steps in one call are two cooperative launches (1024 steps, then 6), the second
+    starting at ring phase 1024 mod 3; the history ring (64 records) wraps 16 times.  A ragged
+    last tile (7680 particles in tiles of 4096).  dt = 0.01 keeps the run (t = 10.3) inside
+    the ansatz's validity.  The bars are about a thousand times what permuting the particles
+    alone (a different summation order) gives in the oracle over these steps: 4e-14 in the
+    state, 1e-14 in the W history."""
+    w = W.landau_linear(seed=4, nx=96, nv=80, ng=64)
+    w.params["alpha"] = 0.2
+    dt = 0.01
+    st = w.state()
+    sim = vp.Simulation(st, w.L, w.ng, dt, "fp64", hist_cap=64)
+    sim.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    sim.step(1030)
+    sim.step(5)                                   # continues from the odd phase
+    nsteps = 1035
+    got = sim.state_numpy(0)
+    hist = sim.history(0, nsteps - 60, 60) + [sim.diagnostics(0)]
+    ref_state, _, ref_hist = O.run(*(np.asarray(st[k], dtype=np.float64) for k in FIELDS),
+                                   w.L, w.ng, dt, nsteps)
+    for k, r in zip(FIELDS, ref_state):
+        assert np.allclose(got[k], r, rtol=0, atol=1e-10), k
+    assert [h["step"] for h in hist] == list(range(nsteps - 60, nsteps + 1))
+    ref_tail = ref_hist[nsteps - 60:]              # the oracle's record i is step i
+    for key in ("W", "K", "H"):
+        assert rel_l2([h[key] for h in hist], [h[key] for h in ref_tail]) < 1e-11, key
+    with pytest.raises(vp.VPError) as e:
+        sim.history(0, nsteps - 70, 10)           # overwritten records
+    assert e.value.status == vp._lib.VP_ERR_RANGE
+    sim.close()
+
+
+@pytest.mark.parametrize("n", [1, 7, 257])
+def test_persistent_edge_sizes(vp, n):
+    """n = 1 and n below one wavefront in a persistent launch: one tile, most lanes empty;
+    a particle at 0 and one on a node."""
+    L, ng = 3.0, 16
+    rng = np.random.default_rng(n)
+    st = {"Q": rng.uniform(0, L, n), "P": rng.normal(size=n), "qs": 0.01 * rng.normal(size=n),
+          "ps": 0.01 * rng.normal(size=n), "psi": rng.uniform(0.1, 1, n)}
+    st["Q"][0] = 0.0
+    if n > 1:
+        st["Q"][1] = 5 * L / ng
+    sim = vp.Simulation(st, L, ng, 0.05, "fp64", hist_cap=16)
+    sim.set_tuning(threads=512, ppt=2, acc_copies=1, persistent=1)
+    sim.step(5)
+    got = sim.state_numpy(0)
+    ref_state, _, ref_hist = O.run(*(np.asarray(st[k], dtype=np.float64) for k in FIELDS),
+                                   L, ng, 0.05, 5)
+    for k, r in zip(FIELDS, ref_state):
+        assert np.allclose(got[k], r, rtol=0, atol=1e-11), k
+    hist = sim.history(0, 0, 5) + [sim.diagnostics(0)]
+    for key in ("W", "K", "H"):
+        assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
+    sim.close()
