@@ -65,14 +65,42 @@ KERNEL_SOURCES = ("vp_device.h", "vp_internal.h", "vp_kernels.hip", "vp_fused.hi
                   "vp_persist.hip")
 
 
+def code_tokens(text: str) -> str:
+    """C/C++ source text with its comments removed and every run of whitespace made one
+    space (string and character literals kept as written): what the compiler sees, so that
+    an edit of comments or layout alone leaves a counter reading valid."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_src_sha() -> str:
+    """Hash of the kernels' code (comments and layout left out)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2605_21794_amd", "csrc")
     for name in KERNEL_SOURCES:
         p = os.path.join(d, name)
         if os.path.exists(p):
             h.update(name.encode())
-            h.update(open(p, "rb").read())
+            h.update(code_tokens(open(p, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

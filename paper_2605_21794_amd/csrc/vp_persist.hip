@@ -15,8 +15,9 @@ namespace vpk {
 // wave finishes within one such period).  Data other workgroups of the launch wrote (the load
 // vector, the per-tile kinetic sums, the cleared ring entry) is read and written at device
 // scope.  The ring protocol, the records and the arithmetic are those of k_fused, so nsteps
-// persistent steps equal nsteps fused launches.  P2 instances are not taken (the host
-// refuses persistent tuning for them).
+// persistent steps equal nsteps fused launches.  A launch with a P2 instance takes the P2
+// instance of the kernel (which runs its P1 instances too); particles with second moments
+// are not taken (the host refuses persistent tuning for them).
 //
 // What no other tile needs is kept off the path between the barriers: every tile clears its
 // own slice of the ring entry the next step deposits into, and the instance's first tile

@@ -44,7 +44,7 @@ def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
     dispatch summed first), each scaled by known bytes over the copy's reading."""
     src = tmp_path / "paper_2605_21794_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "vp_kernels.hip").write_text("// kernel source stand-in\n")
+    (src / "vp_kernels.hip").write_text("// kernel source stand-in\nint k = 1;\n")
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     k = "void vpk::k_fused<1, 512, true, false, false>(...)"
@@ -74,7 +74,10 @@ def test_pmc_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert bench.load_traffic("two_stream", n, "fp64", shape) is None
     assert bench.load_traffic("two_stream", n, "fp32c", [1024, 4, 8]) is None
     assert bench.load_traffic("two_stream", n, "fp32c", [512, 4, 4]) is None
-    (src / "vp_kernels.hip").write_text("// edited\n")
+    (src / "vp_kernels.hip").write_text("// a comment edited\nint k = 1;  /* and one added */\n")
+    assert bench.load_traffic("two_stream", n, "fp32c", shape) == pytest.approx(
+        rec["traffic_bytes_per_launch"])
+    (src / "vp_kernels.hip").write_text("// kernel source stand-in\nint k = 2;\n")
     assert bench.load_traffic("two_stream", n, "fp32c", shape) is None
 
 
@@ -105,7 +108,7 @@ def test_pmc_summary_of_the_persistent_kernel(tmp_path, monkeypatch):
     launch, and a run with another step count reports none of its bytes."""
     src = tmp_path / "paper_2605_21794_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "vp_kernels.hip").write_text("// kernel source stand-in\n")
+    (src / "vp_kernels.hip").write_text("// kernel source stand-in\nint k = 1;\n")
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     k = "void vpk::k_persist<1, 1024, 4, false>(...)"
@@ -131,3 +134,14 @@ def test_pmc_summary_of_the_persistent_kernel(tmp_path, monkeypatch):
     assert bench.kernel_of({"persistent": 1}) == "k_persist"
     assert bench.kernel_of({"persistent": 0}) == "k_fused"
 
+
+def test_source_hash_ignores_comments_and_layout():
+    """The counters' source hash follows the code only: comments and whitespace may change,
+    string literals and code may not."""
+    base = 'int a = 1; /* x */ const char* s = "a // b";\nint f() { return a; } // tail\n'
+    same = ('int a = 1;\n// one more comment\nconst char* s = "a // b";  int f() {\n'
+            '    return a;  /* inside */\n}\n')
+    assert bench.code_tokens(base) == bench.code_tokens(same)
+    assert bench.code_tokens(base) != bench.code_tokens(base.replace('"a // b"', '"a  b"'))
+    assert bench.code_tokens(base) != bench.code_tokens(base.replace("return a", "return -a"))
+    assert bench.code_tokens("char c = '/'; int x; // y") == "char c = '/'; int x;"
