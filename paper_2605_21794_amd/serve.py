@@ -123,7 +123,9 @@ class Server:
         self.keep_state = keep_state
         self.retire_nonfinite = retire_nonfinite
         self.keep_history = keep_history
-        self.device_records = hasattr(self.backend, "records")
+        # a backend with device records gives their stamps as one array (record_stamps) and,
+        # for keep_history, the records themselves (records)
+        self.device_records = hasattr(self.backend, "record_stamps")
 
     def run(self, jobs: list, sleep=time.sleep) -> Report:
         for j in jobs:
@@ -183,7 +185,7 @@ class Server:
                     st_s = st_s[:max(0, done - 1)]
                     job.step_latency_s = list(np.diff(st_s)) if len(st_s) > 1 else []
                     record_samples.extend(job.step_latency_s)
-                    if self.keep_history:
+                    if self.keep_history and hasattr(self.backend, "records"):
                         job.history = self.backend.records(slot, done) if done > 0 else []
                 job.result = self.backend.diagnostics(slot)
                 st = self.backend.retire(slot)

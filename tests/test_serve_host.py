@@ -157,3 +157,57 @@ def test_weighted_percentiles():
     r = _weighted_pcts([3.0, 1.0, 2.0], [1, 98, 1])
     assert r["p50"] == 1.0 and r["max"] == 3.0
     assert _weighted_pcts([5.0, 7.0], [1, 1])["p99"] == 7.0
+
+
+class RecordingBackend(FakeBackend):
+    """FakeBackend with device records: the k steps of a chunk write the records of integer
+    steps dev_step .. dev_step+k-1, stamped evenly over the chunk's fake time."""
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.stamps = {}
+
+    def admit(self, slot, job):
+        super().admit(slot, job)
+        self.stamps[slot] = []
+
+    def step(self, k):
+        t0 = self.clock.t
+        before = dict(self.dev_step)
+        dt = super().step(k)
+        for s in self.resident:
+            n_new = self.dev_step[s] - before[s]
+            self.stamps[s].extend(t0 + (i + 1) * dt / k for i in range(n_new))
+        return dt
+
+    def frozen_step(self, slot):
+        return self.dev_step[slot]
+
+    def record_stamps(self, slot, count):
+        assert count <= len(self.stamps[slot])
+        return np.asarray(self.stamps[slot][:count])
+
+    def retire(self, slot):
+        self.stamps.pop(slot)
+        return super().retire(slot)
+
+
+def test_step_latency_from_device_record_stamps():
+    """With device records the per-step latency samples are the differences of consecutive
+    record stamps (records 0 .. done-2 of each job), not chunk means: here each step costs
+    1e-5 s per 1000 resident particles, so every sample is 2e-5 s while both jobs are
+    resident and 1e-5 s once one is left."""
+    clk = FakeClock()
+    be = RecordingBackend(clk, max_slots=2)
+    jobs = make_jobs([("a", 1000, 25, 0.0), ("b", 1000, 12, 0.0)])
+    rep = Server(backend=be, chunk=10, clock=clk).run(jobs, sleep=clk.sleep)
+    assert rep.step_latency_source == "device records"
+    a, b = rep.jobs
+    assert len(a.step_latency_s) == 25 - 2 and len(b.step_latency_s) == 12 - 2
+    assert np.allclose(b.step_latency_s, 2e-5)
+    # job a: 12 steps with b resident, then 13 alone; the step that straddles b's
+    # retirement is stamped at the first step of the next chunk
+    assert np.allclose(a.step_latency_s[:11], 2e-5)
+    assert np.allclose(a.step_latency_s[11:], 1e-5)
+    assert rep.step_latency_us["max"] == pytest.approx(20.0)
+    assert rep.step_latency_us["p50"] == pytest.approx(20.0)
