@@ -307,6 +307,19 @@ def test_persistent_trajectory_matches_oracle(vp, threads, ppt, copies):
     sim.close()
 
 
+def test_persistent_at_the_largest_grid(vp):
+    """P2 at Ng = 1024 (a 2048-node load vector) in persistent launches: float64 against the
+    oracle's P2 run, a ragged tail, two launches."""
+    w = lattice(1024, 2048, 16, alpha=0.1, seed=3)
+    st = {k: v[:-5] for k, v in w.state().items()}
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=32, element_order=2)
+    sim.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    sim.step(5)
+    sim.step(4)
+    check_run(sim, st, w.L, w.ng, w.dt, 9)
+    sim.close()
+
+
 def test_persistent_full_size_two_stream_fp32c(vp):
     """The `--element-order 2` workload at full size (2^20, Ng 512, fp32c) in persistent
     launches (1024 x 4, 4 copies), 31 steps against the P2 float32-storage reference:

@@ -166,3 +166,25 @@ def test_persistent_edge_sizes(vp, n):
     for key in ("W", "K", "H"):
         assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
     sim.close()
+
+
+@pytest.mark.parametrize("solver", ["scan", "fft"])
+def test_persistent_at_the_largest_grid(vp, solver):
+    """Ng = 1024 (the largest grid), 2^15 - 11 particles (a ragged tail), two launches
+    (7 and 6 steps), float64 against the oracle."""
+    w = W.landau_linear(seed=6, nx=2048, nv=16, ng=1024)
+    w.params["alpha"] = 0.1
+    st = {k: v[:-11] for k, v in w.state().items()}
+    sim = vp.Simulation(st, w.L, w.ng, w.dt, "fp64", hist_cap=32, solver=solver)
+    sim.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    sim.step(7)
+    sim.step(6)
+    nsteps = 13
+    got = sim.state_numpy(0)
+    hist = sim.history(0, 0, nsteps) + [sim.diagnostics(0)]
+    ref_state, _, ref_hist = oracle_run(st, w, nsteps)
+    for k, r in zip(FIELDS, ref_state):
+        assert np.allclose(got[k], r, rtol=0, atol=1e-11), k
+    for key in ("W", "K", "H"):
+        assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
+    sim.close()
