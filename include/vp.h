@@ -292,7 +292,11 @@ vp_status vp_gather_push(vp_handle* h, double kick, double drift);
  * read-back must go through vp_sync_state, vp_retire or vp_diagnostics (which accounts for
  * it).  With vp_tuning.persistent, up to 1024 steps run in one cooperative launch whose
  * workgroups keep their particles in registers and wait for one another between steps;
- * the arithmetic and the results are those of the fused launches. */
+ * the arithmetic and the results are those of the fused launches.  Each wait between
+ * steps is bounded: after 2^22 polls (fewer when the environment variable
+ * VP_PERSIST_SPIN_LIMIT, read when the handle is created, gives a smaller count; for tests
+ * of this path) the instance is flagged, its tiles wait no more in that launch, and
+ * vp_diagnostics reports VP_ERR_HIP for it from then on (its state is not valid). */
 vp_status vp_step(vp_handle* h, int32_t nsteps);
 /* (vp_step) An instance whose diagnostics come out NaN or Inf is frozen from the next step
  * on: its state, step counter and history stop where they are, vp_diagnostics and

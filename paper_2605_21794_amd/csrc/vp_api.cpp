@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -147,6 +148,7 @@ struct vp_handle {
   int phase = 0;            // ring phase of the next fused launch (step count mod kRing)
   bool field_stale = false; // fused steps ran since the field arrays were last written
   bool acc_stale = false;   // a drift ran since the ring entry of `phase` was deposited
+  unsigned spin_limit = vpk::kSpinLimit;  // polls of a persistent wait (VP_PERSIST_SPIN_LIMIT)
 };
 
 namespace {
@@ -211,6 +213,7 @@ vp_status rebuild_tables(vp_handle* h) {
     d.ntiles = nt;
     d.acc_copies = std::max(1, std::min(h->tun.acc_copies, nt));
     d.seg = h->tun.wave_reduce;
+    d.spin_limit = h->spin_limit;
     if (!sl.cfg.monopole_only) h->ntiles_dip += nt;
     for (int gi = group_of(s); gi < kGroups; ++gi) h->group_end[gi] += nt;
   }
@@ -487,6 +490,13 @@ vp_status vp_engine_create(int32_t precision, int32_t max_slots, void* stream, v
   h->stream = static_cast<hipStream_t>(stream);
   h->slots.resize(max_slots);
   h->h_inst.assign(max_slots, InstDev{});
+  // fewer polls for a persistent wait, for tests of its time-out path (never more than the
+  // default; anything that does not parse as a smaller count leaves the default)
+  if (const char* env = std::getenv("VP_PERSIST_SPIN_LIMIT")) {
+    char* end = nullptr;
+    const unsigned long v = std::strtoul(env, &end, 10);
+    if (end != env && *end == '\0' && v < vpk::kSpinLimit) h->spin_limit = (unsigned)v;
+  }
   std::vector<int> ids(max_slots);
   for (int i = 0; i < max_slots; ++i) ids[i] = i;
   hipError_t e = hipMalloc(&h->d_inst, max_slots * sizeof(InstDev));

@@ -31,6 +31,10 @@ constexpr int cons_off(int ng) { return ng <= 64 ? 0 : -(kConsTapsMax / 2); }
 constexpr int kArriveGroups = 16;  // arrival counters per instance
 constexpr int kReleaseFlags = 32;  // copies of an instance's release flag
 constexpr int kArriveStride = 32;  // unsigned words between counters and flags (128 bytes)
+// Polls of a persistent launch's wait before it gives up (the instance is then flagged and the
+// launch drains).  A handle may be created with fewer (the VP_PERSIST_SPIN_LIMIT environment
+// variable), which tests of the time-out path use; never more.
+constexpr unsigned kSpinLimit = 1u << 22;
 
 // Per-instance scalars living in the instance workspace.
 struct InstScal {
@@ -92,6 +96,7 @@ struct InstDev {
   int k3;           // the particles carry second moments (P2, general options)
   int seg;          // the fused and persistent deposits combine runs of equal elements
                     // within each wavefront first (vp_tuning.wave_reduce)
+  unsigned spin_limit;  // polls before a persistent wait gives up (<= kSpinLimit)
 };
 
 // A run of consecutive particles of one instance, processed by one workgroup.

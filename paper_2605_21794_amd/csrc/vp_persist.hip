@@ -10,7 +10,7 @@ namespace vpk {
 // every workgroup of an instance waits until all of the instance's tiles have flushed the
 // previous step, through the two-level arrival tree of InstScal: group counters, a top
 // counter, and release flags written by the tile that completes the top counter; one lane
-// of each waiting tile polls one flag, with a bounded spin (after kSpinLimit polls the
+// of each waiting tile polls one flag, with a bounded spin (after d.spin_limit polls the
 // instance is flagged, the wait ends and that tile waits no more in this launch, so every
 // wave finishes within one such period).  Data other workgroups of the launch wrote (the load
 // vector, the per-tile kinetic sums, the cleared ring entry) is read and written at device
@@ -29,7 +29,6 @@ namespace vpk {
 // together with the solve's loads, parking the per-thread partials in LDS after the solve
 // (device-scope loads after the arrival would hold it past the others' release).
 // GEN = false: no instance of the launch has general options (fewer registers).
-constexpr unsigned kSpinLimit = 1u << 22;
 
 // The first tile's bookkeeping after step n, by its first wavefront alone (no workgroup
 // barrier, so the tile's other waves go on to the next step's wait): the field summary of
@@ -166,6 +165,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   const int cl0 = min(ncl, tl.local * cl_per), cl1 = min(ncl, cl0 + cl_per);
 
   bool gave_up = false;  // the poller's wait timed out: it waits no more, the launch drains
+  const unsigned spin_limit = min(d.spin_limit, kSpinLimit);
   int r0 = phase0;
   for (int st = 0; st < nsteps; ++st) {
     // nothing is hoisted out of the step loop: keeps the step's registers per step
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
         while (!gave_up && __hip_atomic_load(my_flag, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT) < (unsigned)st) {
           __builtin_amdgcn_s_sleep(1);
-          if (++it > kSpinLimit) {
+          if (++it > spin_limit) {
             __hip_atomic_store(&sc->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             gave_up = true;
           }

@@ -188,3 +188,36 @@ def test_persistent_at_the_largest_grid(vp, solver):
     for key in ("W", "K", "H"):
         assert rel_l2([h[key] for h in hist], [h[key] for h in ref_hist]) < 1e-10, key
     sim.close()
+
+
+def test_persistent_wait_time_out_is_reported(vp, monkeypatch):
+    """The bounded wait between persistent steps, forced from the host: a handle created
+    with VP_PERSIST_SPIN_LIMIT = 0 gives up at its first unanswered poll, so every tile
+    stops waiting in that launch and the launch drains (no wave is left spinning); the
+    instance is flagged and reported with VP_ERR_HIP.  A handle created after it, with the
+    default limit, steps the same state normally."""
+    w = W.two_stream(nx=512, nv=512, ng=64)        # 2^18 particles, 64 tiles of 4096
+    st = w.state(np.float32)
+    monkeypatch.setenv("VP_PERSIST_SPIN_LIMIT", "0")
+    bad = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c")
+    monkeypatch.delenv("VP_PERSIST_SPIN_LIMIT")
+    bad.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    status = None
+    try:
+        bad.step(40)
+        bad.diagnostics(0)
+    except vp.VPError as e:
+        status = e.status
+    assert status == vp._lib.VP_ERR_HIP
+    bad.close()
+    good = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c")
+    ref = vp.Simulation(st, w.L, w.ng, w.dt, "fp32c")
+    good.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=1)
+    ref.set_tuning(threads=1024, ppt=4, acc_copies=4, persistent=0)
+    good.step(40)
+    ref.step(40)
+    dg, dr = good.diagnostics(0), ref.diagnostics(0)
+    for key in ("W", "K", "H"):
+        assert abs(dg[key] - dr[key]) <= 1e-5 * abs(dr[key]), key
+    good.close()
+    ref.close()
