@@ -398,6 +398,27 @@ __device__ __forceinline__ double wave_bcast63(double x) {
 // Sum over the 64 lanes; every lane gets the same total.
 __device__ __forceinline__ double wave_sum(double v) { return wave_bcast63(wave_incl_scan(v)); }
 
+// wave_sum of N values at once: each step of the scan is taken for all N values before the
+// next, so one value's DPP latency overlaps the others'; every value gets exactly the
+// additions, in the order, that wave_sum gives it.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x111, 0xf, true>(v[i]);   // row_shr:1
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x112, 0xf, true>(v[i]);   // row_shr:2
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x114, 0xf, true>(v[i]);   // row_shr:4
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x118, 0xf, true>(v[i]);   // row_shr:8
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x142, 0xa, false>(v[i]);  // row_bcast:15
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_move<0x143, 0xc, false>(v[i]);  // row_bcast:31
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_bcast63(v[i]);
+}
+
 // Exclusive prefix over lanes of one value per lane.
 __device__ __forceinline__ double wave_excl_scan(double v, int /*lane*/) {
   return wave_incl_scan(v) - v;
@@ -833,11 +854,13 @@ __device__ void solve_compute(const InstDev& d, const SolveIn& in, bool want_sum
 }
 
 // Record of integer step `step` (kinetic and potential sums of that step's pass, field
-// summary of its field) into the history ring; flags non-finite values.  One thread.
-static __device__ void write_record(const InstDev& d, long long step, double K, double mom, double chg,
-                             double U, double W, double e1r, double e1i) {
+// summary of its field) into slot `slot` of the history ring, which the caller keeps equal
+// to step mod hist_cap; flags non-finite values.  One thread.
+static __device__ void write_record_at(const InstDev& d, int slot, long long step, double K,
+                                       double mom, double chg, double U, double W, double e1r,
+                                       double e1i) {
   if (!d.self_on) W = e1r = e1i = 0.0;  // no field of their own acts on the particles
-  VPG double* r = gp(d.hist) + (size_t)(step % d.hist_cap) * kHistFields;
+  VPG double* r = gp(d.hist) + (size_t)slot * kHistFields;
   r[0] = (double)step;
   r[1] = (double)step * d.dt;
   r[2] = K;
@@ -851,6 +874,11 @@ static __device__ void write_record(const InstDev& d, long long step, double K, 
   r[10] = U;
   r[11] = (double)wall_clock64();  // device constant-rate clock when the record is written
   if (!isfinite(K) || !isfinite(W) || !isfinite(U)) gp(d.scal)->nonfinite = 1;
+}
+// The same, the slot computed here.
+static __device__ void write_record(const InstDev& d, long long step, double K, double mom,
+                                    double chg, double U, double W, double e1r, double e1i) {
+  write_record_at(d, (int)(step % d.hist_cap), step, K, mom, chg, U, W, e1r, e1i);
 }
 
 // ------------------------------------------------------------------ particle passes

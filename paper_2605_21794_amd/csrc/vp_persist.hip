@@ -36,48 +36,55 @@ namespace vpk {
 // when write_rec, the record of integer step rec_step with the kinetic sums of the previous
 // pass (skin: each solving thread's partial sums, field f of thread t at
 // f * kSolveThreads + t, as load_kin forms them from the per-tile slots) and the field
-// summary rec of that step.  Each lane takes nodes and partials lane, lane + 64, ... in
-// order, then one wave tree per quantity: a fixed order.  tw: the Fourier weights (d.tw) in
-// LDS.  rec is read and updated in every lane (the wave trees leave the totals in all).
+// summary rec of that step, into history slot rec_slot (rec_step mod hist_cap).  Each lane
+// takes nodes and partials lane, lane + 64, ... in order, then one wave tree per quantity: a
+// fixed order.  The node loop is unrolled by four (the loads of four nodes go out together;
+// the additions keep their order) and the seven trees run side by side (wave_sum_n): this
+// wave's work delays the tile's next step.  tw: the Fourier weights (d.tw) in LDS.  rec is
+// read and updated in every lane (the wave trees leave the totals in all).
 template <bool GEN, bool P2>
 __device__ void persist_bookkeeping(const InstDev& d, const double* fE, const double* fG,
                                     const double* tw, const double* skin, int r0,
-                                    bool write_rec, long long rec_step, double (&rec)[3]) {
+                                    bool write_rec, long long rec_step, int rec_slot,
+                                    double (&rec)[3]) {
   const int ng = d.ng, lane = threadIdx.x & 63;
-  double kin[kKinFields] = {0.0, 0.0, 0.0, 0.0};
+  // v: W's sum, E1 real and imaginary, then the kinetic fields
+  double v[3 + kKinFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (write_rec)
-    for (int t = lane; t < kSolveThreads; t += 64)
 #pragma unroll
-      for (int f = 0; f < kKinFields; ++f) kin[f] += skin[f * kSolveThreads + t];
-  double wp = 0.0, er = 0.0, ei = 0.0;
+    for (int k = 0; k < kSolveThreads / 64; ++k)
+#pragma unroll
+      for (int f = 0; f < kKinFields; ++f) v[3 + f] += skin[f * kSolveThreads + lane + 64 * k];
   const int halfn = ng >> 1;
-  for (int e = lane; e < ng; e += 64) {
-    const int t = e & (halfn - 1);
-    const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
-    const double c = sg * tw[2 * t], sn = sg * tw[2 * t + 1];
-    const double Ee = fE[e];
-    wp += Ee * Ee;
-    er += Ee * c;
-    ei -= Ee * sn;
+  for (int base = 0; base < ng; base += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + 64 * u + lane;
+      if (e < ng) {
+        const int t = e & (halfn - 1);
+        const double sg = (e < halfn) ? 1.0 : -1.0;  // cos / sin of theta + pi
+        const double c = sg * tw[2 * t], sn = sg * tw[2 * t + 1];
+        const double Ee = fE[e];
+        v[0] += Ee * Ee;
+        v[1] += Ee * c;
+        v[2] -= Ee * sn;
+      }
+    }
   }
   if (P2 && d.order == 2) {
     // the field is linear on a P2 element: W gains (1/2) h (3/16) sum b~_m^2 over the
     // midpoint loads, b~_m = -(2h/3) g_e
     double gm = 0.0;
     for (int e = lane; e < ng; e += 64) gm += fG[e] * fG[e];
-    wp += 0.1875 * ((4.0 / 9.0) * d.h * d.h) * gm;
+    v[0] += 0.1875 * ((4.0 / 9.0) * d.h * d.h) * gm;
   }
-  wp = wave_sum(wp);
-  er = wave_sum(er);
-  ei = wave_sum(ei);
-#pragma unroll
-  for (int f = 0; f < kKinFields; ++f) kin[f] = wave_sum(kin[f]);
-  const double W = 0.5 * d.h * wp;
-  const double e1r = er * inv_pow2(d.log2ng), e1i = ei * inv_pow2(d.log2ng);
+  wave_sum_n(v);
+  const double W = 0.5 * d.h * v[0];
+  const double e1r = v[1] * inv_pow2(d.log2ng), e1i = v[2] * inv_pow2(d.log2ng);
   if (lane == 0) {
     if (write_rec)
-      write_record(d, rec_step, kin[0], kin[1], kin[2], GEN ? kin[3] : 0.0, rec[0], rec[1],
-                   rec[2]);
+      write_record_at(d, rec_slot, rec_step, v[3], v[4], v[5], GEN ? v[6] : 0.0, rec[0],
+                      rec[1], rec[2]);
     VPG InstScal* sc = gp(d.scal);
     sc->W[r0] = W;
     sc->e1r[r0] = e1r;
@@ -146,8 +153,10 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
   }
   long long step0 = 0;
   double rec[3] = {0.0, 0.0, 0.0};  // field summary of the previous integer step (first tile)
+  int rec_slot = 0;                 // (step0 + st - 1) mod hist_cap at step st (first tile)
   if (first) {
     step0 = sc->step;
+    rec_slot = (int)(((step0 - 1) % d.hist_cap + d.hist_cap) % d.hist_cap);
     rec[0] = sc->W[ring_prev(phase0)];
     rec[1] = sc->e1r[ring_prev(phase0)];
     rec[2] = sc->e1i[ring_prev(phase0)];
@@ -268,7 +277,9 @@ __global__ __launch_bounds__(TPB) void k_persist(const InstDev* __restrict__ ins
       }
     }
     if (first && threadIdx.x < 64)  // record of step st - 1, field summary of step st
-      persist_bookkeeping<GEN, P2>(d, fE, fG, stw, skin, r0, write_rec, step0 + st - 1, rec);
+      persist_bookkeeping<GEN, P2>(d, fE, fG, stw, skin, r0, write_rec, step0 + st - 1,
+                                   rec_slot, rec);
+    if (++rec_slot == d.hist_cap) rec_slot = 0;
     r0 = r1;
   }
   if (first && threadIdx.x == 0) sc->step = step0 + nsteps;
